@@ -1,0 +1,434 @@
+"""Plain FP64 CPU oracle for Gauss-Newton (preconditioned implicit CG) and ALS CP decomposition.
+
+TEST INFRASTRUCTURE. This module is the reference that the GPU library is checked against.
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may import it; the
+product path never does. It shares no code with the GPU library: it is NumPy/SciPy only and
+imports nothing from the GPU package.
+
+It follows N. Singh, L. Ma, H. Yang, E. Solomonik, "Comparison of Accuracy and Scalability of
+Gauss-Newton and Alternating Least Squares for CP Decomposition" (arXiv:1910.12331). Equation
+numbers refer to that paper: (1) the Khatri-Rao product P^(n), (2) the Hadamard product of Grams
+Gamma^(n), (3) the objective f, (4) the Jacobian tensor, (5) the blocks of J^T J, (6) the
+generalised Gamma^(n,p), (7) the implicit matrix-vector contraction. Algorithm 1 is CP-GN,
+Algorithm 2 is CP-CG, Listing 1 is the per-pair einsum form of the matrix-vector product.
+
+Conventions: a tensor is a C-order float64 ndarray of shape (s_1, ..., s_N); a factor list holds
+N arrays A[n] of shape (s_n, R). Everything is computed in float64 in the order the paper
+states it; library primitives (matmul, einsum, Cholesky) serve as single steps.
+
+Readings of the paper that are not literal (each is listed in the design notes as well):
+  * Algorithm 2 divides beta by sum <W,Q>; the standard preconditioned-CG ratio
+    sum <R_new,Z_new> / sum <R_old,Z_old> is used instead (the literal ratio does not converge).
+  * The varying-lambda schedule (Section 3.2) gives no constants; they are parameters here.
+  * The relative residual (Section 5) is evaluated directly, as ||X - [[A]]||_F / ||X||_F.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+
+__all__ = [
+    "full", "unfold", "khatri_rao", "mttkrp", "mttkrp_loops", "grams", "gamma", "gamma_set",
+    "objective", "gradient", "jtj_matvec", "preconditioner", "pcg", "PCGResult", "gn_step",
+    "GNStepStats", "LambdaSchedule", "als_sweep", "residual", "residual_expansion", "gn", "als",
+    "jacobian", "jtj_dense", "flatten_factors", "unflatten_factors", "OracleError",
+]
+
+
+class OracleError(RuntimeError):
+    """Raised where the method has no defined result (singular normal equations, breakdown)."""
+
+
+# --------------------------------------------------------------------------------------------
+# CP model and MTTKRP (Section 2.2)
+# --------------------------------------------------------------------------------------------
+
+def full(A):
+    """Reconstruction [[A(1),...,A(N)]] = sum_r a_r(1) o ... o a_r(N)  (Section 2.2).
+
+    Written as the sum over components of outer products, one component at a time.
+    """
+    dims = [a.shape[0] for a in A]
+    rank = A[0].shape[1]
+    out = np.zeros(dims)
+    for r in range(rank):
+        term = A[0][:, r]
+        for a in A[1:]:
+            term = np.multiply.outer(term, a[:, r])
+        out += term
+    return out
+
+
+def unfold(X, n):
+    """Mode-n matricization X_(n) of shape (s_n, prod_{m != n} s_m)  (Section 2.1).
+
+    The column index runs over the remaining modes in increasing mode order with the last
+    mode fastest, which is the ordering the Khatri-Rao product of eq. (1) produces.
+    """
+    return np.moveaxis(X, n, 0).reshape(X.shape[n], -1)
+
+
+def khatri_rao(mats):
+    """Column-wise Kronecker product A(1) (.) A(2) (.) ... : column r is a_r(1) kron a_r(2) ...
+    (Section 2.1). The first matrix's row index varies slowest."""
+    rank = mats[0].shape[1]
+    out = np.ones((1, rank))
+    for m in mats:
+        out = np.einsum("ir,jr->ijr", out, m).reshape(-1, rank)
+    return out
+
+
+def mttkrp(X, A, n):
+    """M(n) = X_(n) P(n), with P(n) the Khatri-Rao product of all factors but A(n), eq. (1)."""
+    others = [A[m] for m in range(len(A)) if m != n]
+    return unfold(X, n) @ khatri_rao(others)
+
+
+def mttkrp_loops(X, A, n):
+    """Element-wise MTTKRP by explicit loops (tiny inputs only):
+    M[k, r] = sum over all indices i with i_n = k of X[i] * prod_{m != n} A(m)[i_m, r]."""
+    rank = A[0].shape[1]
+    M = np.zeros((X.shape[n], rank))
+    for idx in itertools.product(*[range(s) for s in X.shape]):
+        for r in range(rank):
+            prod = X[idx]
+            for m, im in enumerate(idx):
+                if m != n:
+                    prod *= A[m][im, r]
+            M[idx[n], r] += prod
+    return M
+
+
+# --------------------------------------------------------------------------------------------
+# Grams and Gamma matrices, eqs. (2) and (6)
+# --------------------------------------------------------------------------------------------
+
+def grams(A):
+    """S(i) = A(i)^T A(i) for every mode (Section 2.2)."""
+    return [a.T @ a for a in A]
+
+
+def gamma(S, n, p):
+    """Gamma(n,p) = Hadamard product of S(m) over m not in {n, p}, eq. (6).
+
+    With n == p this is Gamma(n) of eq. (2). An empty product (N = 2, n != p) is the all-ones
+    matrix, the identity of the Hadamard product.
+    """
+    rank = S[0].shape[0]
+    out = np.ones((rank, rank))
+    for m in range(len(S)):
+        if m != n and m != p:
+            out = out * S[m]
+    return out
+
+
+def gamma_set(S):
+    N = len(S)
+    return [[gamma(S, n, p) for p in range(N)] for n in range(N)]
+
+
+# --------------------------------------------------------------------------------------------
+# Objective, gradient, J^T J (Section 3)
+# --------------------------------------------------------------------------------------------
+
+def objective(X, A):
+    """f = 1/2 ||X - [[A]]||_F^2, eq. (3)."""
+    d = X - full(A)
+    return 0.5 * float(np.sum(d * d))
+
+
+def gradient(X, A):
+    """G(n) = A(n) Gamma(n,n) - M(n) for every mode, all at the same point (Algorithm 1)."""
+    N = len(A)
+    S = grams(A)
+    return [A[n] @ gamma(S, n, n) - mttkrp(X, A, n) for n in range(N)]
+
+
+def jtj_matvec(A, W, lam=0.0, Gam=None):
+    """Q(n) = lam W(n) + sum_p MatVec(A(n), A(p), Gamma(n,p), W(p))  (Algorithm 2, eq. (7)).
+
+    Each (n, p) term is the Listing 1 contraction written out literally:
+      n == p:  U[k,r] = sum_z Gamma(n,n)[r,z] W(n)[k,z]
+      n != p:  U[k,r] = sum_{l,z} A(n)[k,z] A(p)[l,r] Gamma(n,p)[r,z] W(p)[l,z]
+    """
+    N = len(A)
+    if Gam is None:
+        Gam = gamma_set(grams(A))
+    Q = []
+    for n in range(N):
+        U = lam * W[n]
+        for p in range(N):
+            if n == p:
+                U = U + np.einsum("rz,kz->kr", Gam[n][p], W[p])
+            else:
+                U = U + np.einsum("kz,lr,rz,lz->kr", A[n], A[p], Gam[n][p], W[p], optimize=True)
+        Q.append(U)
+    return Q
+
+
+def preconditioner(Gam, lam):
+    """P_inv(n) = (Gamma(n,n) + lam I)^-1 for every mode, built from a Cholesky factor
+    (Algorithm 2, Section 3.3). Raises OracleError when the shifted matrix is not SPD."""
+    out = []
+    for n in range(len(Gam)):
+        g = Gam[n][n] + lam * np.eye(Gam[n][n].shape[0])
+        try:
+            c = scipy.linalg.cho_factor(g, lower=True)
+        except np.linalg.LinAlgError as e:
+            raise OracleError(f"Gamma({n},{n}) + lambda I is not positive definite") from e
+        out.append(scipy.linalg.cho_solve(c, np.eye(g.shape[0])))
+    return out
+
+
+def _fro(m):
+    return math.sqrt(float(np.sum(m * m)))
+
+
+def _inner(a, b):
+    return float(np.sum(a * b))
+
+
+@dataclass
+class PCGResult:
+    V: list
+    iters: int
+    res_norm_sum: float      # sum_n ||R(n)||_F at exit
+    grad_norm_sum: float     # sum_n ||G(n)||_F
+    alpha_last: float = 0.0
+    beta_last: float = 0.0
+    history: list = field(default_factory=list)
+
+
+def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None):
+    """Algorithm 2 (CP-CG): preconditioned implicit CG for (J^T J + lam I) V = -G.
+
+    Steps, in the paper's order: P_inv(n) = (Gamma(n,n) + lam I)^-1; V = 0; R = -G;
+    Z = R P_inv; W = Z. While sum ||R(n)|| > eps_cg sum ||G(n)|| (and fewer than ``maxiter``
+    iterations): Q = lam W + MatVec(W); alpha = sum<R,Z> / sum<W,Q>; V += alpha W;
+    R -= alpha Q; Z = R P_inv; beta = sum<R,Z>_new / sum<R,Z>_old; W = Z + beta W.
+
+    beta uses the standard preconditioned-CG ratio (the printed denominator sum<W,Q> is read as
+    a typo). A non-positive curvature sum<W,Q> <= 0 raises OracleError.
+    """
+    N = len(A)
+    if Gam is None:
+        Gam = gamma_set(grams(A))
+    P = preconditioner(Gam, lam)
+    V = [np.zeros_like(g) for g in G]
+    R = [-g for g in G]
+    Z = [R[n] @ P[n] for n in range(N)]
+    W = [z.copy() for z in Z]
+    gsum = sum(_fro(g) for g in G)
+    rz = sum(_inner(R[n], Z[n]) for n in range(N))
+    rsum = sum(_fro(r) for r in R)
+    it = 0
+    alpha = beta = 0.0
+    hist = []
+    while rsum > eps_cg * gsum and it < maxiter:
+        Q = jtj_matvec(A, W, lam, Gam)
+        wq = sum(_inner(W[n], Q[n]) for n in range(N))
+        if not wq > 0.0:
+            raise OracleError("CG breakdown: sum <W,Q> <= 0")
+        alpha = rz / wq
+        for n in range(N):
+            V[n] = V[n] + alpha * W[n]
+            R[n] = R[n] - alpha * Q[n]
+            Z[n] = R[n] @ P[n]
+        rz_new = sum(_inner(R[n], Z[n]) for n in range(N))
+        beta = rz_new / rz
+        for n in range(N):
+            W[n] = Z[n] + beta * W[n]
+        rz = rz_new
+        rsum = sum(_fro(r) for r in R)
+        it += 1
+        hist.append(dict(alpha=alpha, beta=beta, res_norm_sum=rsum))
+    return PCGResult(V=V, iters=it, res_norm_sum=rsum, grad_norm_sum=gsum,
+                     alpha_last=alpha, beta_last=beta, history=hist)
+
+
+@dataclass
+class GNStepStats:
+    cg_iters: int
+    grad_norm_sum: float
+    cg_res_norm_sum: float
+    alpha_last: float
+    beta_last: float
+    lam: float
+    update_norm: float
+
+
+def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20):
+    """One loop body of Algorithm 1 (CP-GN): all M(n) at the current point, Gamma(n,p),
+    G(n) = A(n) Gamma(n,n) - M(n), V = CP-CG(G, A, Gamma, eps_cg, lam), A(n) += V(n).
+
+    Returns (new factors, GNStepStats). The input list is not modified.
+    """
+    N = len(A)
+    S = grams(A)
+    Gam = gamma_set(S)
+    M = [mttkrp(X, A, n) for n in range(N)]
+    G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
+    res = pcg(G, A, lam, eps_cg, maxiter, Gam)
+    newA = [A[n] + res.V[n] for n in range(N)]
+    upd = math.sqrt(sum(float(np.sum(v * v)) for v in res.V))
+    return newA, GNStepStats(cg_iters=res.iters, grad_norm_sum=res.grad_norm_sum,
+                             cg_res_norm_sum=res.res_norm_sum, alpha_last=res.alpha_last,
+                             beta_last=res.beta_last, lam=lam, update_norm=upd)
+
+
+class LambdaSchedule:
+    """Varying damping of Section 3.2: start at the upper threshold, divide by mu each step
+    until the lower threshold is reached, then multiply by mu until the upper threshold is
+    reached, and repeat. ``value`` is the lambda for the current step; ``advance`` moves on."""
+
+    def __init__(self, lam0=1e-4, lo=1e-10, hi=1e-4, mu=2.0):
+        if not (mu > 1.0 and 0.0 < lo <= hi):
+            raise ValueError("need mu > 1 and 0 < lo <= hi")
+        self.value = float(lam0)
+        self.lo, self.hi, self.mu = float(lo), float(hi), float(mu)
+        self.down = True
+
+    def advance(self):
+        if self.down:
+            self.value /= self.mu
+            if self.value <= self.lo:
+                self.down = False
+        else:
+            self.value *= self.mu
+            if self.value >= self.hi:
+                self.down = True
+        return self.value
+
+    def state(self):
+        return dict(value=self.value, down=self.down, lo=self.lo, hi=self.hi, mu=self.mu)
+
+
+# --------------------------------------------------------------------------------------------
+# ALS (Section 2.2)
+# --------------------------------------------------------------------------------------------
+
+def als_sweep(X, A, lam=0.0):
+    """One CP-ALS sweep, modes in increasing order (Gauss-Seidel): Gamma(n) from the current
+    Grams, M(n) with the latest factors, A(n) = M(n) (Gamma(n) + lam I)^-1 by a Cholesky solve
+    of the normal equations. Returns new factors; raises OracleError if Gamma(n)+lam I is not
+    SPD."""
+    A = [a.copy() for a in A]
+    N = len(A)
+    for n in range(N):
+        S = grams(A)
+        g = gamma(S, n, n) + lam * np.eye(A[n].shape[1])
+        M = mttkrp(X, A, n)
+        try:
+            c = scipy.linalg.cho_factor(g, lower=True)
+        except np.linalg.LinAlgError as e:
+            raise OracleError(f"Gamma({n}) + lambda I is not positive definite") from e
+        A[n] = scipy.linalg.cho_solve(c, M.T).T
+    return A
+
+
+# --------------------------------------------------------------------------------------------
+# Residual (Section 5)
+# --------------------------------------------------------------------------------------------
+
+def residual(X, A):
+    """Direct relative residual r = ||X - [[A]]||_F / ||X||_F (Section 5); fitness = 1 - r.
+
+    Returns (||X - [[A]]||_F, ||X||_F). The squares are summed with math.fsum."""
+    d = (X - full(A)).ravel()
+    x = X.ravel()
+    return math.sqrt(math.fsum(d * d)), math.sqrt(math.fsum(x * x))
+
+
+def residual_expansion(X, A):
+    """||X - [[A]]||^2 by the expansion ||X||^2 - 2 <M(1), A(1)> + sum_{r,z} prod_m S(m)[r,z].
+    Cancels catastrophically near an exact fit; kept only to characterise that form."""
+    S = grams(A)
+    had = np.ones_like(S[0])
+    for s in S:
+        had = had * s
+    xx = float(np.sum(X * X))
+    cross = float(np.sum(mttkrp(X, A, 0) * A[0]))
+    return xx - 2.0 * cross + float(np.sum(had)), math.sqrt(xx)
+
+
+# --------------------------------------------------------------------------------------------
+# Drivers (Algorithm 1 outer loop; ALS loop)
+# --------------------------------------------------------------------------------------------
+
+def gn(X, A0, schedule=None, eps_cg=1e-3, maxiter=20, target=1e-10, maxsteps=200, log=None):
+    """Algorithm 1 driver: GN steps until the direct relative residual <= target or maxsteps.
+    lambda for step k is the schedule's value at step k (advanced after every step)."""
+    sched = schedule or LambdaSchedule()
+    A = [a.copy() for a in A0]
+    hist = []
+    for step in range(maxsteps):
+        num, den = residual(X, A)
+        if num / den <= target:
+            break
+        A, st = gn_step(X, A, sched.value, eps_cg, maxiter)
+        sched.advance()
+        rec = dict(step=step, lam=st.lam, cg_iters=st.cg_iters, grad_norm_sum=st.grad_norm_sum)
+        hist.append(rec)
+        if log is not None:
+            log(rec)
+    num, den = residual(X, A)
+    return A, hist, num / den
+
+
+def als(X, A0, lam=0.0, target=1e-10, maxsweeps=500):
+    A = [a.copy() for a in A0]
+    hist = []
+    for sweep in range(maxsweeps):
+        num, den = residual(X, A)
+        hist.append(num / den)
+        if num / den <= target:
+            break
+        A = als_sweep(X, A, lam)
+    num, den = residual(X, A)
+    return A, hist, num / den
+
+
+# --------------------------------------------------------------------------------------------
+# Brute force for tiny inputs: explicit Jacobian, eq. (4)
+# --------------------------------------------------------------------------------------------
+
+def flatten_factors(A):
+    return np.concatenate([a.ravel() for a in A])
+
+
+def unflatten_factors(v, dims, rank):
+    out, off = [], 0
+    for s in dims:
+        out.append(v[off:off + s * rank].reshape(s, rank))
+        off += s * rank
+    return out
+
+
+def jacobian(A):
+    """Explicit Jacobian of the residual X - [[A]] with respect to all factor entries, eq. (4):
+    j(n)[i_1..i_N, k, r] = -(prod_{m != n} A(m)[i_m, r]) delta(i_n, k).
+    Rows run over tensor entries in C order, columns over (n, k, r) in factor order."""
+    dims = [a.shape[0] for a in A]
+    rank = A[0].shape[1]
+    ncols = sum(dims) * rank
+    rows = int(np.prod(dims))
+    J = np.zeros((rows, ncols))
+    offs = np.cumsum([0] + [s * rank for s in dims])
+    for row, idx in enumerate(itertools.product(*[range(s) for s in dims])):
+        for n, k in enumerate(idx):
+            for r in range(rank):
+                prod = 1.0
+                for m, im in enumerate(idx):
+                    if m != n:
+                        prod *= A[m][im, r]
+                J[row, offs[n] + k * rank + r] = -prod
+    return J
+
+
+def jtj_dense(A):
+    J = jacobian(A)
+    return J.T @ J
