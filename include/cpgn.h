@@ -1,0 +1,177 @@
+/*
+ * cpgn.h -- C ABI of libcpgn.so: Gauss-Newton (preconditioned implicit CG) and ALS for dense
+ * CP decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow N. Singh, L. Ma, H. Yang, E. Solomonik, "Comparison of Accuracy and
+ * Scalability of Gauss-Newton and Alternating Least Squares for CP Decomposition"
+ * (arXiv:1910.12331). Equation numbers refer to that paper: (1) Khatri-Rao product P^(n),
+ * (2) Gamma^(n), (3) objective f, (4) Jacobian, (5) blocks of J^T J, (6) Gamma^(n,p),
+ * (7) implicit matrix-vector contraction; Algorithm 1 is CP-GN and Algorithm 2 is CP-CG.
+ *
+ * Memory and ownership
+ *   - X is a DEVICE pointer to a dense C-order tensor of shape dims[0] x ... x dims[N-1]
+ *     (last index fastest).
+ *   - A, G, W, Q are HOST arrays of N DEVICE pointers; entry n points to a row-major
+ *     dims[n] x rank matrix (rank contiguous). Modes may have different sizes, hence the
+ *     per-mode pointers.
+ *   - Every buffer, including the workspace `ws`, is allocated and owned by the caller. The
+ *     library allocates nothing, keeps no mutable global state and is re-entrant per stream.
+ *     Query the workspace size with cp_workspace_bytes; the workspace must be 256-byte
+ *     aligned. Its contents need not be initialised and are clobbered.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every call only
+ *     enqueues work on that stream and returns without waiting.
+ *
+ * Error behaviour
+ *   - The return value reports errors detectable on the host before anything is enqueued:
+ *     CP_EINVAL (bad order/rank/dims/mode/method, null pointer, misaligned workspace),
+ *     CP_EUNSUPPORTED (dtype combination), CP_EWORKSPACE (workspace too small), CP_EHIP (a
+ *     launch failed). Nothing has been enqueued when a non-zero value is returned, except for
+ *     CP_EHIP.
+ *   - Failures found on the device (a non-SPD Cholesky pivot, CG breakdown <W,Q> <= 0,
+ *     non-finite values) are written as a status code into device memory (the `status` field
+ *     of cp_gn_stats, or `status_dev`); the caller reads it after synchronising the stream.
+ *     On such a failure the factors are left unchanged.
+ *
+ * Precision
+ *   - x_dtype must equal f_dtype and be CP_F64 or CP_F32. The tensor contraction (MTTKRP,
+ *     reconstruction) runs on the matrix cores in that precision with accumulation in the same
+ *     precision; Grams, Gamma matrices, the CG vectors and scalars, Cholesky factors and all
+ *     norms and inner products are kept in FP64 on the device.
+ */
+#ifndef CPGN_H
+#define CPGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CP_MAX_ORDER 8
+#define CP_ABI_VERSION 1
+
+typedef enum { CP_F64 = 0, CP_F32 = 1 } cp_dtype;
+
+/* Return / device status codes. */
+enum {
+  CP_OK = 0,
+  CP_EINVAL = -1,
+  CP_EUNSUPPORTED = -2,
+  CP_EWORKSPACE = -3,
+  CP_EHIP = -4,
+  CP_ENOTSPD = -5,      /* Gamma(n,n) + lambda I (or Gamma(n) + lambda I in ALS) not SPD  */
+  CP_EBREAKDOWN = -6,   /* CG curvature sum <W,Q> <= 0                                     */
+  CP_ENONFINITE = -7    /* a NaN or Inf appeared in the gradient or the CG recurrences      */
+};
+
+/* Workspace queries: one per entry point. */
+enum {
+  CP_OP_MTTKRP = 0,
+  CP_OP_GN_GRADIENT = 1,
+  CP_OP_GN_JTJ_MATVEC = 2,
+  CP_OP_GN_STEP = 3,
+  CP_OP_ALS_SWEEP = 4,
+  CP_OP_RESIDUAL = 5
+};
+
+/* Residual methods for cp_residual. */
+enum { CP_RESIDUAL_DIRECT = 0, CP_RESIDUAL_EXPANSION = 1 };
+
+typedef struct {
+  int32_t order;                 /* N, 2 <= N <= CP_MAX_ORDER                               */
+  int32_t rank;                  /* R >= 1                                                  */
+  int64_t dims[CP_MAX_ORDER];    /* s_1..s_N, each >= 1; entries past N are ignored         */
+  int32_t x_dtype;               /* cp_dtype of X                                           */
+  int32_t f_dtype;               /* cp_dtype of the factor matrices and per-mode outputs    */
+} cp_problem;
+
+typedef struct {
+  double lambda;                 /* Tikhonov damping of J^T J + lambda I (>= 0), Section 3.2 */
+  double cg_tol;                 /* eps_cg: CG runs while sum||R(n)|| > eps_cg sum||G(n)||   */
+  int32_t cg_maxiter;            /* cap on CG iterations (>= 0)                              */
+  uint32_t flags;                /* reserved, must be 0                                      */
+} cp_gn_params;
+
+/* Written to DEVICE memory by cp_gn_step. */
+typedef struct {
+  int32_t status;                /* CP_OK or a device status code                           */
+  int32_t cg_iters;              /* CG iterations taken                                     */
+  double grad_norm_sum;          /* sum_n ||G(n)||_F at the start of the step               */
+  double cg_res_norm_sum;        /* sum_n ||R(n)||_F when CG stopped                        */
+  double alpha_last;             /* last CG step length (0 if no iteration)                 */
+  double beta_last;              /* last CG direction coefficient (0 if no iteration)       */
+  double update_norm;            /* sqrt(sum_n ||V(n)||_F^2) of the applied update          */
+} cp_gn_stats;
+
+/* Size in bytes of the workspace entry point `op` needs for this problem. */
+int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes);
+
+/*
+ * MTTKRP, Section 2.2: M = X_(n) P^(n), with P^(n) the Khatri-Rao product of every factor but
+ * A^(n) (eq. (1)); elementwise M[k,r] = sum over indices i with i_n = k of
+ * X[i] * prod_{m != n} A^(m)[i_m, r].
+ *   mode: n, 0-based. M: device, dims[mode] x rank, f_dtype, written.
+ */
+int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int mode, void* M,
+              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of f (eq. (3)) for every mode at one point, Algorithm 1:
+ * G^(n) = A^(n) Gamma^(n,n) - M^(n), with Gamma^(n,n) the Hadamard product of the Grams
+ * S^(m) = A^(m)T A^(m), m != n (eq. (2)).
+ *   G: N device pointers, dims[n] x rank, f_dtype, written.
+ *   grad_norm_sum_dev: device double, receives sum_n ||G^(n)||_F (may be NULL).
+ */
+int cp_gn_gradient(const cp_problem* prob, const void* X, const void* const* A, void* const* G,
+                   double* grad_norm_sum_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Damped Gauss-Newton matrix-vector product, Algorithm 2 with eqs. (5)-(7):
+ * Q^(n) = lambda W^(n) + sum_p sum_{l,z} h^(n,p)_{krlz} W^(p)_{lz}, i.e. Q = (J^T J + lambda I) W.
+ *   W: N device pointers (input), Q: N device pointers (output), both dims[n] x rank, f_dtype.
+ */
+int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* const* W,
+                     double lambda, void* const* Q, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * One loop body of Algorithm 1 (CP-GN): all MTTKRPs at the current point, Grams and Gamma
+ * matrices, G^(n), then Algorithm 2 (CP-CG) on (J^T J + lambda I) V = -G with the block
+ * preconditioner (Gamma^(n,n) + lambda I)^-1 (Section 3.3), then A^(n) += V^(n).
+ * CG uses beta = sum<R,Z>_new / sum<R,Z>_old (standard preconditioned CG).
+ *   A: N device pointers, read and overwritten in place (f_dtype).
+ *   params: HOST pointer. stats: DEVICE pointer to one cp_gn_stats.
+ */
+int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_gn_params* params,
+               cp_gn_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * One ALS sweep, Section 2.2: for n = 0..N-1 in order, A^(n) = M^(n) (Gamma^(n) + lambda I)^-1
+ * with M^(n) computed from the latest factors; the inverse comes from an FP64 Cholesky factor.
+ *   A: N device pointers, read and overwritten in place. lambda >= 0 (0 = plain ALS).
+ *   status_dev: device int32 receiving CP_OK or CP_ENOTSPD (may be NULL).
+ */
+int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double lambda,
+                 int32_t* status_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Residual norms, Section 5 (relative residual r = ||X - [[A]]||_F / ||X||_F, fitness 1 - r).
+ *   method CP_RESIDUAL_DIRECT: streams X once and rebuilds [[A]] tile by tile.
+ *   method CP_RESIDUAL_EXPANSION: ||X||^2 - 2<M^(1),A^(1)> + sum_{r,z} prod_m S^(m)_{rz}; cheap
+ *     but it cancels catastrophically near an exact fit (a negative square is clamped to 0).
+ *   out_dev: device double[2]: out_dev[0] = ||X - [[A]]||_F, out_dev[1] = ||X||_F.
+ */
+int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int method,
+                double* out_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* cp_status_string(int status);
+
+/* CP_ABI_VERSION of the built library. */
+int cp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPGN_H */

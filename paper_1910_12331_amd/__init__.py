@@ -1,0 +1,13 @@
+"""MI355X-native Gauss-Newton (preconditioned implicit CG) and ALS for dense CP decomposition.
+
+The compute path is libcpgn.so (HIP kernels for gfx950 behind the C ABI in include/cpgn.h);
+this package is its Python binding.
+"""
+from . import _lib
+from .api import (CpError, Workspace, als_sweep, gn_gradient, gn_step, jtj_matvec, mttkrp,
+                  read_stats, residual, stats_buffer)
+from .optim import ALS, DampingSchedule, GaussNewton, GNConfig
+
+__all__ = ["CpError", "Workspace", "als_sweep", "gn_gradient", "gn_step", "jtj_matvec", "mttkrp",
+           "read_stats", "residual", "stats_buffer", "ALS", "DampingSchedule", "GaussNewton",
+           "GNConfig"]

@@ -1,0 +1,76 @@
+"""ctypes declarations of the libcpgn.so C ABI (include/cpgn.h). Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpgn.so")
+
+MAX_ORDER = 8
+CP_F64, CP_F32 = 0, 1
+CP_OK, CP_EINVAL, CP_EUNSUPPORTED, CP_EWORKSPACE, CP_EHIP = 0, -1, -2, -3, -4
+CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
+OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL = range(6)
+RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
+
+EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
+           "cp_als_sweep", "cp_residual", "cp_status_string", "cp_abi_version"]
+
+
+class CpProblem(C.Structure):
+    _fields_ = [("order", C.c_int32), ("rank", C.c_int32), ("dims", C.c_int64 * MAX_ORDER),
+                ("x_dtype", C.c_int32), ("f_dtype", C.c_int32)]
+
+
+class CpGnParams(C.Structure):
+    _fields_ = [("lam", C.c_double), ("cg_tol", C.c_double), ("cg_maxiter", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class CpGnStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cg_iters", C.c_int32), ("grad_norm_sum", C.c_double),
+                ("cg_res_norm_sum", C.c_double), ("alpha_last", C.c_double),
+                ("beta_last", C.c_double), ("update_norm", C.c_double)]
+
+
+PTRS = C.c_void_p * MAX_ORDER
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcpgn.so and declare its signatures. Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1910_12331_amd.build`")
+    lib = C.CDLL(path)
+    vp, sz, i32 = C.c_void_p, C.c_size_t, C.c_int
+    P = C.POINTER
+    lib.cp_abi_version.restype = i32
+    lib.cp_abi_version.argtypes = []
+    lib.cp_status_string.restype = C.c_char_p
+    lib.cp_status_string.argtypes = [i32]
+    lib.cp_workspace_bytes.restype = i32
+    lib.cp_workspace_bytes.argtypes = [P(CpProblem), i32, P(sz)]
+    lib.cp_mttkrp.restype = i32
+    lib.cp_mttkrp.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
+    lib.cp_gn_gradient.restype = i32
+    lib.cp_gn_gradient.argtypes = [P(CpProblem), vp, PTRS, PTRS, vp, vp, sz, vp]
+    lib.cp_gn_jtj_matvec.restype = i32
+    lib.cp_gn_jtj_matvec.argtypes = [P(CpProblem), PTRS, PTRS, C.c_double, PTRS, vp, sz, vp]
+    lib.cp_gn_step.restype = i32
+    lib.cp_gn_step.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, sz, vp]
+    lib.cp_als_sweep.restype = i32
+    lib.cp_als_sweep.argtypes = [P(CpProblem), vp, PTRS, C.c_double, vp, vp, sz, vp]
+    lib.cp_residual.restype = i32
+    lib.cp_residual.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
+    if lib.cp_abi_version() != 1:
+        raise RuntimeError("libcpgn.so ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().cp_status_string(int(code)).decode()

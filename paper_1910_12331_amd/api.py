@@ -1,0 +1,210 @@
+"""Python entry points over the libcpgn.so C ABI.
+
+Tensors are torch tensors resident on the GPU; this module only checks them, hands their
+device pointers and the current HIP stream to the library, and allocates the workspace with
+torch. Every step of the computation runs in the library's HIP kernels; there is no CPU
+fallback, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Sequence
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.CP_F64, torch.float32: L.CP_F32}
+
+
+class CpError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {L.status_string(code)} (code {code})")
+        self.code = code
+
+
+def _check(rc: int, where: str):
+    if rc != L.CP_OK:
+        raise CpError(rc, where)
+
+
+def _problem(X: torch.Tensor, rank: int) -> L.CpProblem:
+    if X.dtype not in _DT:
+        raise TypeError(f"unsupported tensor dtype {X.dtype}")
+    if X.dim() < 2 or X.dim() > L.MAX_ORDER:
+        raise ValueError("tensor order must be between 2 and 8")
+    p = L.CpProblem()
+    p.order = X.dim()
+    p.rank = int(rank)
+    for i, s in enumerate(X.shape):
+        p.dims[i] = int(s)
+    p.x_dtype = p.f_dtype = _DT[X.dtype]
+    return p
+
+
+def _problem_from_factors(A: Sequence[torch.Tensor]) -> L.CpProblem:
+    p = L.CpProblem()
+    p.order = len(A)
+    p.rank = int(A[0].shape[1])
+    for i, a in enumerate(A):
+        p.dims[i] = int(a.shape[0])
+    p.x_dtype = p.f_dtype = _DT[A[0].dtype]
+    return p
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _ptrs(ts: Sequence[torch.Tensor]):
+    arr = L.PTRS()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _factors(A, X_or_dims, dtype, rank, name="A"):
+    dims = X_or_dims
+    if len(A) != len(dims):
+        raise ValueError(f"{name} must hold one matrix per mode")
+    for n, a in enumerate(A):
+        _dev(a, f"{name}[{n}]", dtype, (dims[n], rank))
+    return A
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Workspace:
+    """Caches one device workspace per (problem, op); grows on demand."""
+
+    def __init__(self):
+        self._buf = None
+
+    def get(self, prob: L.CpProblem, op: int, device) -> tuple[int, int]:
+        n = C.c_size_t(0)
+        _check(L.load().cp_workspace_bytes(C.byref(prob), op, C.byref(n)), "cp_workspace_bytes")
+        need = int(n.value) + 256
+        if self._buf is None or self._buf.numel() < need or self._buf.device != device:
+            self._buf = torch.empty(need, dtype=torch.uint8, device=device)
+        base = self._buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        return aligned, int(n.value)
+
+
+_default_ws = Workspace()
+
+
+def _ws(prob, op, device, ws):
+    return (ws or _default_ws).get(prob, op, device)
+
+
+def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=None):
+    """M = X_(mode) P^(mode) (Section 2.2, eq. (1)); returns a dims[mode] x R tensor."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, X.dtype, R)
+    prob = _problem(X, R)
+    if out is None:
+        out = torch.empty((X.shape[mode], R), dtype=X.dtype, device=X.device)
+    _dev(out, "out", X.dtype, (X.shape[mode], R))
+    w, nb = _ws(prob, L.OP_MTTKRP, X.device, ws)
+    _check(L.load().cp_mttkrp(C.byref(prob), X.data_ptr(), _ptrs(A), int(mode), out.data_ptr(), w, nb,
+                              _stream()), "cp_mttkrp")
+    return out
+
+
+def gn_gradient(X: torch.Tensor, A: Sequence[torch.Tensor], ws=None):
+    """G(n) = A(n) Gamma(n,n) - M(n) for every mode (Algorithm 1). Returns (G list, sum ||G||)."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, X.dtype, R)
+    prob = _problem(X, R)
+    G = [torch.empty_like(a) for a in A]
+    gsum = torch.empty(1, dtype=torch.float64, device=X.device)
+    w, nb = _ws(prob, L.OP_GN_GRADIENT, X.device, ws)
+    _check(L.load().cp_gn_gradient(C.byref(prob), X.data_ptr(), _ptrs(A), _ptrs(G), gsum.data_ptr(),
+                                   w, nb, _stream()), "cp_gn_gradient")
+    return G, gsum
+
+
+def jtj_matvec(A: Sequence[torch.Tensor], W: Sequence[torch.Tensor], lam: float = 0.0, ws=None):
+    """Q = (J^T J + lam I) W through the implicit contractions of eq. (7)."""
+    R = int(A[0].shape[1])
+    dims = [a.shape[0] for a in A]
+    _factors(A, dims, A[0].dtype, R)
+    _factors(W, dims, A[0].dtype, R, "W")
+    prob = _problem_from_factors(A)
+    Q = [torch.empty_like(w) for w in W]
+    w, nb = _ws(prob, L.OP_GN_JTJ_MATVEC, A[0].device, ws)
+    _check(L.load().cp_gn_jtj_matvec(C.byref(prob), _ptrs(A), _ptrs(W), float(lam), _ptrs(Q), w, nb,
+                                     _stream()), "cp_gn_jtj_matvec")
+    return Q
+
+
+STATS_FIELDS = ("status", "cg_iters", "grad_norm_sum", "cg_res_norm_sum", "alpha_last",
+                "beta_last", "update_norm")
+
+
+def stats_buffer(device) -> torch.Tensor:
+    return torch.zeros(C.sizeof(L.CpGnStats), dtype=torch.uint8, device=device)
+
+
+def read_stats(buf: torch.Tensor) -> dict:
+    raw = bytes(buf.cpu().numpy().tobytes())
+    s = L.CpGnStats.from_buffer_copy(raw)
+    return {f: getattr(s, f) for f in STATS_FIELDS}
+
+
+def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
+            cg_maxiter: int = 20, stats=None, ws=None):
+    """One Algorithm 1 step in place on A; returns the device stats buffer (cp_gn_stats)."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, X.dtype, R)
+    prob = _problem(X, R)
+    prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter), 0)
+    if stats is None:
+        stats = stats_buffer(X.device)
+    w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
+    _check(L.load().cp_gn_step(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm), stats.data_ptr(),
+                               w, nb, _stream()), "cp_gn_step")
+    return stats
+
+
+def als_sweep(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float = 0.0, status=None, ws=None):
+    """One ALS sweep in place on A (Section 2.2); returns the device int32 status."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, X.dtype, R)
+    prob = _problem(X, R)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    w, nb = _ws(prob, L.OP_ALS_SWEEP, X.device, ws)
+    _check(L.load().cp_als_sweep(C.byref(prob), X.data_ptr(), _ptrs(A), float(lam), status.data_ptr(),
+                                 w, nb, _stream()), "cp_als_sweep")
+    return status
+
+
+def residual(X: torch.Tensor, A: Sequence[torch.Tensor], method: int = L.RESIDUAL_DIRECT, out=None,
+             ws=None):
+    """Device tensor [||X - [[A]]||_F, ||X||_F] (Section 5)."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, X.dtype, R)
+    prob = _problem(X, R)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=X.device)
+    w, nb = _ws(prob, L.OP_RESIDUAL, X.device, ws)
+    _check(L.load().cp_residual(C.byref(prob), X.data_ptr(), _ptrs(A), int(method), out.data_ptr(),
+                                w, nb, _stream()), "cp_residual")
+    return out

@@ -1,0 +1,438 @@
+// C ABI of libcpgn.so: argument validation, workspace carving and launch sequencing for
+// Gauss-Newton (Algorithms 1 and 2 of Singh, Ma, Yang, Solomonik, arXiv:1910.12331) and
+// ALS (Section 2.2). Every call enqueues on the caller's stream and returns; FP64 CG scalars
+// stay on the device, so a whole Gauss-Newton step runs without a host synchronisation.
+#include <math.h>
+#include <string.h>
+
+#include "cpgn_internal.h"
+
+namespace cpgn {
+
+// Launchers defined in the other translation units.
+void launch_gram2(const Dims&, const double*, const double*, double*, int, const CgState*, hipStream_t);
+void launch_gamma(const Dims&, const double*, double*, hipStream_t);
+void launch_ycore(const Dims&, const double*, const double*, double*, const CgState*, hipStream_t);
+int rowmm_blocks(const Dims&);
+void launch_cg_axpy(const Dims&, double*, double*, const double*, const double*, double*,
+                    const CgState*, hipStream_t);
+void launch_cg_wupdate(int64_t, double*, const double*, const CgState*, hipStream_t);
+void launch_fill(int64_t, double*, double, hipStream_t);
+void launch_to64(const Dims&, const PerMode<const void*>&, int, double*, hipStream_t);
+void launch_fin_grad(const Dims&, int, const double*, CgState*, double, double*, hipStream_t);
+void launch_state_reset(CgState*, hipStream_t);
+void launch_fin_cginit(const Dims&, int, const double*, CgState*, hipStream_t);
+void launch_fin_alpha(const Dims&, int, const double*, CgState*, hipStream_t);
+void launch_fin_beta(const Dims&, int, const double*, const double*, CgState*, hipStream_t);
+void launch_gn_apply(const Dims&, double*, const double*, const PerMode<void*>&, int, double*,
+                     const CgState*, hipStream_t);
+void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stats*, hipStream_t);
+void launch_status_out(const CgState*, int32_t*, hipStream_t);
+size_t spd_inv_lds(int);
+int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
+                   hipStream_t);
+int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t);
+int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
+void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
+                                   const double*, double*, hipStream_t);
+int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipStream_t, bool);
+
+void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_plan(const cp_problem* prob, Plan* p) {
+  if (!prob || !p) return CP_EINVAL;
+  if (prob->order < 2 || prob->order > kMaxOrder || prob->rank < 1) return CP_EINVAL;
+  if (prob->x_dtype != prob->f_dtype) return CP_EUNSUPPORTED;
+  if (prob->x_dtype != CP_F64 && prob->x_dtype != CP_F32) return CP_EUNSUPPORTED;
+  *p = Plan{};
+  p->N = prob->order;
+  p->R = prob->rank;
+  if (p->R > (1 << 20)) return CP_EINVAL;
+  p->Rp = (p->R + 15) / 16 * 16;
+  p->NBt = p->Rp / 16;
+  p->dtype = prob->x_dtype;
+  p->esz = p->dtype == CP_F64 ? 8 : 4;
+  p->total = 1;
+  for (int n = 0; n < p->N; ++n) {
+    const int64_t s = prob->dims[n];
+    if (s < 1) return CP_EINVAL;
+    if (p->total > ((int64_t)1 << 50) / s) return CP_EINVAL;
+    p->s[n] = s;
+    p->total *= s;
+    p->sum_s += s;
+    p->max_s = s > p->max_s ? s : p->max_s;
+  }
+  p->qc_last = (p->s[p->N - 1] + 15) / 16;
+  p->qc_prev = (p->s[p->N - 2] + 15) / 16;
+  int64_t part = p->qc_last * 16 * p->Rp;   // residual's packed last factor reuses this region
+  for (int n = 0; n < p->N; ++n) {
+    int RT, SW, rpt;
+    mttkrp_splits(*p, n, &RT, &SW, &rpt);
+    const int64_t e = (int64_t)SW * RT * rpt * p->Rp;
+    part = e > part ? e : part;
+  }
+  p->part_elems = part;
+  const int64_t RR = (int64_t)p->R * p->R;
+  const size_t vec = (size_t)p->sum_s * p->R * 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  p->off_apad = take((size_t)p->sum_s * p->Rp * p->esz);
+  p->off_fpk_last = take((size_t)p->qc_last * p->NBt * 256 * p->esz);
+  p->off_fpk_prev = take((size_t)p->qc_prev * p->NBt * 256 * p->esz);
+  p->off_part = take((size_t)part * p->esz);
+  p->off_m64 = take(vec);
+  p->off_a64 = take(vec);
+  p->off_s = take((size_t)p->N * RR * 8);
+  p->off_gam = take((size_t)p->N * p->N * RR * 8);
+  p->off_pinv = take((size_t)p->N * RR * 8);
+  p->off_g = take(vec);
+  p->off_v = take(vec);
+  p->off_r = take(vec);
+  p->off_z = take(vec);
+  p->off_w = take(vec);
+  p->off_q = take(vec);
+  p->off_bp = take((size_t)p->N * RR * 8);
+  p->off_y = take((size_t)p->N * RR * 8);
+  p->off_red = take((size_t)2 * p->N * kRedSlots * 8);
+  p->off_state = take(sizeof(CgState));
+  p->bytes = off;
+  return CP_OK;
+}
+
+Dims make_dims(const Plan& p) {
+  Dims d{};
+  d.N = p.N;
+  d.R = p.R;
+  d.Rp = p.Rp;
+  d.off[0] = 0;
+  for (int n = 0; n < p.N; ++n) {
+    d.s[n] = p.s[n];
+    d.off[n + 1] = d.off[n] + p.s[n];
+  }
+  return d;
+}
+
+// Pointers into a carved workspace.
+struct Ws {
+  char* base;
+  double *m64, *a64, *S, *gam, *pinv, *g, *v, *r, *z, *w, *q, *bp, *y, *red_dot, *red_nrm;
+  CgState* st;
+};
+
+static Ws carve(const Plan& p, void* ws) {
+  Ws w{};
+  w.base = (char*)ws;
+  w.m64 = (double*)(w.base + p.off_m64);
+  w.a64 = (double*)(w.base + p.off_a64);
+  w.S = (double*)(w.base + p.off_s);
+  w.gam = (double*)(w.base + p.off_gam);
+  w.pinv = (double*)(w.base + p.off_pinv);
+  w.g = (double*)(w.base + p.off_g);
+  w.v = (double*)(w.base + p.off_v);
+  w.r = (double*)(w.base + p.off_r);
+  w.z = (double*)(w.base + p.off_z);
+  w.w = (double*)(w.base + p.off_w);
+  w.q = (double*)(w.base + p.off_q);
+  w.bp = (double*)(w.base + p.off_bp);
+  w.y = (double*)(w.base + p.off_y);
+  w.red_dot = (double*)(w.base + p.off_red);
+  w.red_nrm = w.red_dot + (size_t)p.N * kRedSlots;
+  w.st = (CgState*)(w.base + p.off_state);
+  return w;
+}
+
+static int check_ws(const Plan& p, void* ws, size_t ws_bytes) {
+  if (!ws) return CP_EINVAL;
+  if ((uintptr_t)ws % 256 != 0) return CP_EINVAL;
+  if (ws_bytes < p.bytes) return CP_EWORKSPACE;
+  return CP_OK;
+}
+
+static int check_ptrs(const Plan& p, const void* const* A) {
+  if (!A) return CP_EINVAL;
+  for (int n = 0; n < p.N; ++n)
+    if (!A[n]) return CP_EINVAL;
+  return CP_OK;
+}
+
+static int hip_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CP_OK : CP_EHIP;
+}
+
+// Gradient of Algorithm 1 into w.g (and R = -G into w.r); fills the per-mode norm partials and
+// resets the CG state (gsum, eps). Requires prepared factors (Apad, Fpk, A64).
+static void gradient_core(const Plan& p, const Dims& d, const void* X, const Ws& w, double eps,
+                          const PerMode<void*>& cast_g, double* gsum_out, hipStream_t st) {
+  launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
+  launch_gamma(d, w.S, w.gam, st);
+  int64_t off = 0;
+  for (int n = 0; n < p.N; ++n) {
+    launch_mttkrp(p, X, n, w.base, w.m64 + off * p.R, nullptr, st);
+    off += p.s[n];
+  }
+  const int64_t RR = (int64_t)p.R * p.R;
+  RowMM a{};
+  a.in = w.m64;
+  a.cin = -1.0;
+  a.l1 = w.a64;
+  a.t1 = w.gam;
+  a.t1_stride = (int64_t)(p.N + 1) * RR;
+  a.out = w.g;
+  a.out2 = w.r;
+  a.out2_scale = -1.0;
+  a.red_nrm = w.red_nrm;
+  a.cast_out = cast_g;
+  a.cast_dtype = p.dtype;
+  a.mode_only = -1;
+  launch_rowmm(d, a, nullptr, st);
+  launch_fin_grad(d, rowmm_blocks(d), w.red_nrm, w.st, eps, gsum_out, st);
+}
+
+// Q = lambda W + sum_p MatVec (eq. (7)) on FP64 packed vectors; writes <W,Q> partials.
+static void matvec_core(const Plan& p, const Dims& d, const Ws& w, const double* W, double lambda,
+                        double* Q, const PerMode<void*>& cast_q, bool use_state, hipStream_t st) {
+  const int64_t RR = (int64_t)p.R * p.R;
+  const CgState* cs = use_state ? w.st : nullptr;
+  launch_gram2(d, w.a64, W, w.bp, -1, cs, st);
+  launch_ycore(d, w.gam, w.bp, w.y, cs, st);
+  RowMM a{};
+  a.in = W;
+  a.cin = lambda;
+  a.l1 = W;
+  a.t1 = w.gam;
+  a.t1_stride = (int64_t)(p.N + 1) * RR;
+  a.l2 = w.a64;
+  a.t2 = w.y;
+  a.t2_stride = RR;
+  a.out = Q;
+  a.dotw = W;
+  a.red_dot = w.red_dot;
+  a.cast_out = cast_q;
+  a.cast_dtype = p.dtype;
+  a.mode_only = -1;
+  launch_rowmm(d, a, cs, st);
+}
+
+}  // namespace cpgn
+
+using namespace cpgn;
+
+extern "C" {
+
+int cp_abi_version(void) { return CP_ABI_VERSION; }
+
+const char* cp_status_string(int s) {
+  switch (s) {
+    case CP_OK: return "ok";
+    case CP_EINVAL: return "invalid argument";
+    case CP_EUNSUPPORTED: return "unsupported dtype combination or size";
+    case CP_EWORKSPACE: return "workspace too small";
+    case CP_EHIP: return "HIP launch error";
+    case CP_ENOTSPD: return "matrix not symmetric positive definite (Cholesky pivot <= 0)";
+    case CP_EBREAKDOWN: return "CG breakdown (sum <W,Q> <= 0)";
+    case CP_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes) {
+  if (!bytes) return CP_EINVAL;
+  if (op < CP_OP_MTTKRP || op > CP_OP_RESIDUAL) return CP_EINVAL;
+  Plan p;
+  const int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  *bytes = p.bytes;
+  return CP_OK;
+}
+
+int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int mode, void* M,
+              void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !M || mode < 0 || mode >= p.N) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, false);
+  launch_mttkrp(p, X, mode, ws, nullptr, M, st);
+  return hip_status();
+}
+
+int cp_gn_gradient(const cp_problem* prob, const void* X, const void* const* A, void* const* G,
+                   double* grad_norm_sum_dev, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ptrs(p, (const void* const*)G)) ||
+      (rc = check_ws(p, ws, ws_bytes)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, true);
+  PerMode<void*> cg{};
+  for (int n = 0; n < p.N; ++n) cg.p[n] = G[n];
+  gradient_core(p, d, X, w, 0.0, cg, grad_norm_sum_dev, st);
+  return hip_status();
+}
+
+int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* const* W,
+                     double lambda, void* const* Q, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ptrs(p, W)) ||
+      (rc = check_ptrs(p, (const void* const*)Q)) || (rc = check_ws(p, ws, ws_bytes)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  PerMode<const void*> src{};
+  for (int n = 0; n < p.N; ++n) src.p[n] = A[n];
+  launch_to64(d, src, p.dtype, w.a64, st);
+  for (int n = 0; n < p.N; ++n) src.p[n] = W[n];
+  launch_to64(d, src, p.dtype, w.w, st);
+  launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
+  launch_gamma(d, w.S, w.gam, st);
+  PerMode<void*> cq{};
+  for (int n = 0; n < p.N; ++n) cq.p[n] = Q[n];
+  matvec_core(p, d, w, w.w, lambda, w.q, cq, false, st);
+  return hip_status();
+}
+
+int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_gn_params* prm,
+               cp_gn_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !prm || !stats) return CP_EINVAL;
+  if (!(prm->lambda >= 0.0) || !isfinite(prm->lambda) || !(prm->cg_tol >= 0.0) ||
+      !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 || prm->flags != 0)
+    return CP_EINVAL;
+  if (spd_inv_lds(p.R) > 160 * 1024) return CP_EUNSUPPORTED;
+  if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  const int64_t RR = (int64_t)p.R * p.R;
+  const int64_t cnt = p.sum_s * p.R;
+  const int nb = rowmm_blocks(d);
+
+  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+  PerMode<void*> none{};
+  gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
+  // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
+  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st);
+  // CG initialisation: V = 0, R = -G (written by the gradient), Z = R P_inv, W = Z.
+  launch_fill(cnt, w.v, 0.0, st);
+  {
+    RowMM a{};
+    a.l1 = w.r;
+    a.t1 = w.pinv;
+    a.t1_stride = RR;
+    a.out = w.z;
+    a.out2 = w.w;
+    a.out2_scale = 1.0;
+    a.dotw = w.r;
+    a.red_dot = w.red_dot;
+    a.mode_only = -1;
+    launch_rowmm(d, a, w.st, st);
+  }
+  launch_fin_cginit(d, nb, w.red_dot, w.st, st);
+  PerMode<void*> none2{};
+  for (int it = 0; it < prm->cg_maxiter; ++it) {
+    matvec_core(p, d, w, w.w, prm->lambda, w.q, none2, true, st);
+    launch_fin_alpha(d, nb, w.red_dot, w.st, st);
+    launch_cg_axpy(d, w.v, w.r, w.w, w.q, w.red_nrm, w.st, st);
+    RowMM a{};
+    a.l1 = w.r;
+    a.t1 = w.pinv;
+    a.t1_stride = RR;
+    a.out = w.z;
+    a.dotw = w.r;
+    a.red_dot = w.red_dot;
+    a.mode_only = -1;
+    launch_rowmm(d, a, w.st, st);
+    launch_fin_beta(d, nb, w.red_dot, w.red_nrm, w.st, st);
+    launch_cg_wupdate(cnt, w.w, w.z, w.st, st);
+  }
+  PerMode<void*> aout{};
+  for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
+  launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
+  launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
+  return hip_status();
+}
+
+int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double lambda,
+                 int32_t* status_dev, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !(lambda >= 0.0) || !isfinite(lambda)) return CP_EINVAL;
+  if (spd_inv_lds(p.R) > 160 * 1024) return CP_EUNSUPPORTED;
+  if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  const int64_t RR = (int64_t)p.R * p.R;
+  launch_state_reset(w.st, st);
+  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+  launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
+  int64_t off = 0;
+  for (int n = 0; n < p.N; ++n) {
+    launch_gamma(d, w.S, w.gam, st);
+    double* m64n = w.m64 + off * p.R;
+    launch_mttkrp(p, X, n, ws, m64n, nullptr, st);
+    launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, n, 1, w.st, st);
+    RowMM a{};
+    a.l1 = w.m64;
+    a.t1 = w.pinv;
+    a.t1_stride = RR;
+    a.cast_out.p[n] = A[n];
+    a.cast_dtype = p.dtype;
+    a.mode_only = n;
+    a.skip_if_status = 1;
+    launch_rowmm(d, a, w.st, st);
+    // refresh the padded/packed copies, the FP64 copy and the Gram of the updated mode
+    launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+    launch_gram2(d, w.a64, w.a64, w.S, n, nullptr, st);
+    off += p.s[n];
+  }
+  if (status_dev) launch_status_out(w.st, status_dev, st);
+  return hip_status();
+}
+
+int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int method,
+                double* out_dev, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !out_dev) return CP_EINVAL;
+  if (method != CP_RESIDUAL_DIRECT && method != CP_RESIDUAL_EXPANSION) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, method == CP_RESIDUAL_EXPANSION);
+  if (method == CP_RESIDUAL_DIRECT) {
+    launch_residual_direct(p, X, ws, out_dev, st);
+  } else {
+    launch_mttkrp(p, X, 0, ws, w.m64, nullptr, st);
+    launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
+    int nblocks = 0;
+    launch_sumsq(p, X, w.red_dot, st, &nblocks);
+    launch_fin_residual_expansion(d, nblocks, w.red_dot, w.m64, w.a64, w.S, out_dev, st);
+  }
+  return hip_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,775 @@
+// FP64 kernels for the small dense parts of one Gauss-Newton step and one ALS sweep
+// (Singh, Ma, Yang, Solomonik, arXiv:1910.12331): Grams S = A^T A and the Hadamard products
+// Gamma(n,p) of eqs. (2) and (6); row-block times R x R products (gradient of Algorithm 1,
+// the implicit J^T J product of eq. (7), the preconditioner apply of Algorithm 2, the ALS
+// solve); the CG vector recurrences with device-resident FP64 scalars; the Cholesky-based
+// explicit inverse (Gamma(n,n) + lambda I)^-1 of Section 3.3.
+//
+// Packed layout: the per-mode [s_n, R] matrices of one kind (factors, gradient, CG vectors)
+// are stored back to back as one [sum_n s_n, R] FP64 array; Dims::off[n] is mode n's first
+// row. Every reduction writes one partial per workgroup and is finished by a single
+// workgroup in a fixed order, so results do not depend on scheduling.
+#include "cpgn_internal.h"
+
+namespace cpgn {
+
+// ------------------------------------------------------------------------------------------
+// Deterministic block reduction of two doubles (fixed tree over 256 threads).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sa[256], sb[256];
+  const int t = threadIdx.x;
+  sa[t] = a;
+  sb[t] = b;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      sa[t] += sa[t + w];
+      sb[t] += sb[t + w];
+    }
+    __syncthreads();
+  }
+  a = sa[0];
+  b = sb[0];
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool state_done(const CgState* st) {
+  return *(volatile const int32_t*)&st->done != 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// C(n) = X(n)^T Y(n) for every mode (R x R, FP64). 16x16 output tile per workgroup, rows of
+// X and Y staged through LDS 16 at a time. Used for the Grams (Y = X) and for the CG
+// projections B(p) = A(p)^T W(p).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram2(Dims d, const double* __restrict__ Xp,
+                                               const double* __restrict__ Yp, double* __restrict__ C,
+                                               int mode_only, const CgState* st) {
+  if (st && state_done(st)) return;
+  const int n = mode_only >= 0 ? mode_only : blockIdx.z;
+  const int R = d.R;
+  const int tiles = (R + 15) / 16;
+  const int r0 = 16 * (blockIdx.x % tiles), z0 = 16 * (blockIdx.x / tiles);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double xs[16][17], ys[16][17];
+  const double* X = Xp + d.off[n] * R;
+  const double* Y = Yp + d.off[n] * R;
+  const int64_t s = d.s[n];
+  double acc = 0.0;
+  for (int64_t k0 = 0; k0 < s; k0 += 16) {
+    const int64_t k = k0 + ty;
+    xs[ty][tx] = (k < s && r0 + tx < R) ? X[k * R + r0 + tx] : 0.0;
+    ys[ty][tx] = (k < s && z0 + tx < R) ? Y[k * R + z0 + tx] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc += xs[kk][ty] * ys[kk][tx];
+    __syncthreads();
+  }
+  if (r0 + ty < R && z0 + tx < R) C[((int64_t)n * R + r0 + ty) * R + z0 + tx] = acc;
+}
+
+// Gam[n][p] = Hadamard product of S(m) over m not in {n, p} (all-ones when empty), eq. (6).
+__global__ void k_gamma(Dims d, const double* __restrict__ S, double* __restrict__ Gam) {
+  const int R = d.R, N = d.N;
+  const int64_t RR = (int64_t)R * R;
+  const int64_t total = (int64_t)N * N * RR;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx % RR;
+    const int np = (int)(idx / RR);
+    const int n = np / N, p = np % N;
+    double v = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != n && m != p) v *= S[m * RR + e];
+    Gam[idx] = v;
+  }
+}
+
+// Y(n)[r][z] = sum_{p != n} Gam[n][p][r][z] * B(p)[r][z]  (the R x R core of eq. (7)).
+__global__ void k_ycore(Dims d, const double* __restrict__ Gam, const double* __restrict__ B,
+                        double* __restrict__ Y, const CgState* st) {
+  if (st && state_done(st)) return;
+  const int R = d.R, N = d.N;
+  const int64_t RR = (int64_t)R * R;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)N * RR;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(idx / RR);
+    const int64_t e = idx - n * RR;
+    double v = 0.0;
+    for (int p = 0; p < N; ++p)
+      if (p != n) v += Gam[((int64_t)n * N + p) * RR + e] * B[p * RR + e];
+    Y[idx] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-block times small matrices, all modes in one launch (grid.y = mode):
+//   Out(n)[k][r] = cin * In(n)[k][r] + sum_z L1(n)[k][z] T1(n)[z][r] + sum_z L2(n)[k][z] T2(n)[r][z]
+// T1/T2 are per-mode R x R matrices at T + n * t_stride (t_stride = 0 shares one matrix).
+// Optional: Out2 = out2_scale * Out; a copy of Out in the caller's precision (per-mode
+// pointers); per-workgroup partials of <Out(n), D(n)> and ||Out(n)||^2.
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_rowmm(Dims d, RowMM a, const CgState* st) {
+  if (st && (state_done(st) || (a.skip_if_status && st->status != 0))) return;
+  const int n = a.mode_only >= 0 ? a.mode_only : blockIdx.y;
+  const int R = d.R;
+  const int64_t rows = d.s[n];
+  const int64_t base = d.off[n] * R;
+  const double* T1 = a.t1 ? a.t1 + n * a.t1_stride : nullptr;
+  const double* T2 = a.t2 ? a.t2 + n * a.t2_stride : nullptr;
+  double dot = 0.0, nrm = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * R;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / R;
+    const int r = (int)(e - k * R);
+    const int64_t at = base + e;
+    double v = a.in ? a.cin * a.in[at] : 0.0;
+    if (T1) {
+      const double* L = a.l1 + base + k * R;
+      double s = 0.0;
+      for (int z = 0; z < R; ++z) s += L[z] * T1[(int64_t)z * R + r];
+      v += s;
+    }
+    if (T2) {
+      const double* L = a.l2 + base + k * R;
+      const double* Tr = T2 + (int64_t)r * R;
+      double s = 0.0;
+      for (int z = 0; z < R; ++z) s += L[z] * Tr[z];
+      v += s;
+    }
+    if (a.out) a.out[at] = v;
+    if (a.out2) a.out2[at] = a.out2_scale * v;
+    if (a.cast_out.p[n]) {
+      if (a.cast_dtype == CP_F64) ((double*)a.cast_out.p[n])[e] = v;
+      else ((float*)a.cast_out.p[n])[e] = (float)v;
+    }
+    if (a.dotw) dot += v * a.dotw[at];
+    nrm += v * v;
+  }
+  if (a.red_dot || a.red_nrm) {
+    block_sum2(dot, nrm);
+    if (threadIdx.x == 0) {
+      if (a.red_dot) a.red_dot[n * kRedSlots + blockIdx.x] = dot;
+      if (a.red_nrm) a.red_nrm[n * kRedSlots + blockIdx.x] = nrm;
+    }
+  }
+}
+
+// V += alpha W; R -= alpha Q; partial ||R(n)||^2 per workgroup (grid.y = mode).
+__global__ __launch_bounds__(256) void k_cg_axpy(Dims d, double* __restrict__ V, double* __restrict__ Rv,
+                                                 const double* __restrict__ W,
+                                                 const double* __restrict__ Q, double* red_nrm,
+                                                 const CgState* st) {
+  if (state_done(st)) return;
+  const int n = blockIdx.y;
+  const double alpha = st->alpha;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  double nrm = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    V[base + e] += alpha * W[base + e];
+    const double r = Rv[base + e] - alpha * Q[base + e];
+    Rv[base + e] = r;
+    nrm += r * r;
+  }
+  block_sum2(nrm, dummy);
+  if (threadIdx.x == 0) red_nrm[n * kRedSlots + blockIdx.x] = nrm;
+}
+
+// W = Z + beta W (all modes, flat).
+__global__ void k_cg_wupdate(int64_t cnt, double* __restrict__ W, const double* __restrict__ Z,
+                             const CgState* st) {
+  if (state_done(st)) return;
+  const double beta = st->beta;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    W[e] = Z[e] + beta * W[e];
+}
+
+__global__ void k_fill(int64_t cnt, double* __restrict__ p, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// Per-mode conversion of caller buffers to packed FP64.
+__global__ void k_to64(Dims d, PerMode<const void*> src, int dtype, double* __restrict__ dst) {
+  const int n = blockIdx.y;
+  const int64_t cnt = d.s[n] * d.R, base = d.off[n] * d.R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[base + e] = dtype == CP_F64 ? ((const double*)src.p[n])[e]
+                                    : (double)((const float*)src.p[n])[e];
+}
+
+// ------------------------------------------------------------------------------------------
+// Scalar finishing steps (one workgroup). Partials are summed in index order.
+// ------------------------------------------------------------------------------------------
+__device__ double sum_slots(const double* red, int nblocks) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) a += red[i];
+  block_sum2(a, b);
+  return a;
+}
+
+// Gradient norms: gsum = sum_n sqrt(sum_b nrm[n][b]); resets the CG state.
+__global__ void k_fin_grad(int N, int nblocks, const double* red_nrm, CgState* st, double eps,
+                           double* gsum_out) {
+  double g = 0.0;
+  for (int n = 0; n < N; ++n) g += sqrt(sum_slots(red_nrm + n * kRedSlots, nblocks));
+  if (threadIdx.x == 0) {
+    st->gsum = g;
+    st->rsum = g;
+    st->eps = eps;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->rz = 0.0;
+    st->upd2 = 0.0;
+    st->iters = 0;
+    st->status = isfinite(g) ? CP_OK : CP_ENONFINITE;
+    st->done = st->status != CP_OK ? 1 : 0;
+    if (gsum_out) *gsum_out = g;
+  }
+}
+
+__global__ void k_state_reset(CgState* st) {
+  if (threadIdx.x == 0) {
+    st->gsum = st->rsum = st->alpha = st->beta = st->rz = st->upd2 = 0.0;
+    st->eps = 0.0;
+    st->iters = 0;
+    st->status = CP_OK;
+    st->done = 0;
+  }
+}
+
+// After Z = R P_inv with R = -G: rho = sum <R,Z>; CG runs while rsum > eps * gsum.
+__global__ void k_fin_cginit(int N, int nblocks, const double* red_dot, CgState* st) {
+  if (state_done(st)) return;
+  double rz = 0.0;
+  for (int n = 0; n < N; ++n) rz += sum_slots(red_dot + n * kRedSlots, nblocks);
+  if (threadIdx.x == 0) {
+    st->rz = rz;
+    if (!isfinite(rz)) {
+      st->status = CP_ENONFINITE;
+      st->done = 1;
+    } else if (!(st->rsum > st->eps * st->gsum)) {
+      st->done = 1;
+    }
+  }
+}
+
+// alpha = sum <R,Z> / sum <W,Q>; breakdown when sum <W,Q> <= 0.
+__global__ void k_fin_alpha(int N, int nblocks, const double* red_dot, CgState* st) {
+  if (state_done(st)) return;
+  double wq = 0.0;
+  for (int n = 0; n < N; ++n) wq += sum_slots(red_dot + n * kRedSlots, nblocks);
+  if (threadIdx.x == 0) {
+    if (!isfinite(wq)) {
+      st->status = CP_ENONFINITE;
+      st->done = 1;
+    } else if (!(wq > 0.0)) {
+      st->status = CP_EBREAKDOWN;
+      st->done = 1;
+    } else {
+      st->alpha = st->rz / wq;
+    }
+  }
+}
+
+// beta = sum <R,Z>_new / sum <R,Z>_old; stop test on sum_n ||R(n)||_F.
+__global__ void k_fin_beta(int N, int nblocks, const double* red_dot, const double* red_nrm,
+                           CgState* st) {
+  if (state_done(st)) return;
+  double rz = 0.0, rs = 0.0;
+  for (int n = 0; n < N; ++n) {
+    rz += sum_slots(red_dot + n * kRedSlots, nblocks);
+    rs += sqrt(sum_slots(red_nrm + n * kRedSlots, nblocks));
+  }
+  if (threadIdx.x == 0) {
+    st->beta = rz / st->rz;
+    st->rz = rz;
+    st->rsum = rs;
+    st->iters += 1;
+    if (!isfinite(rz) || !isfinite(rs)) {
+      st->status = CP_ENONFINITE;
+      st->done = 1;
+    } else if (!(rs > st->eps * st->gsum)) {
+      st->done = 1;
+    }
+  }
+}
+
+// A64 += V (when the step did not fail), write the caller's factors, ||V||, and the stats.
+__global__ __launch_bounds__(256) void k_gn_apply(Dims d, double* __restrict__ A64,
+                                                  const double* __restrict__ V,
+                                                  PerMode<void*> Aout, int dtype, double* red_nrm,
+                                                  const CgState* st) {
+  const int n = blockIdx.y;
+  const bool ok = st->status == CP_OK;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  double nrm = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = ok ? V[base + e] : 0.0;
+    nrm += v * v;
+    if (ok) {
+      const double a = A64[base + e] + v;
+      A64[base + e] = a;
+      if (dtype == CP_F64) ((double*)Aout.p[n])[e] = a;
+      else ((float*)Aout.p[n])[e] = (float)a;
+    }
+  }
+  block_sum2(nrm, dummy);
+  if (threadIdx.x == 0) red_nrm[n * kRedSlots + blockIdx.x] = nrm;
+}
+
+__global__ void k_gn_stats(int N, int nblocks, const double* red_nrm, const CgState* st,
+                           cp_gn_stats* out) {
+  double u = 0.0;
+  for (int n = 0; n < N; ++n) u += sum_slots(red_nrm + n * kRedSlots, nblocks);
+  if (threadIdx.x == 0) {
+    out->status = st->status;
+    out->cg_iters = st->iters;
+    out->grad_norm_sum = st->gsum;
+    out->cg_res_norm_sum = st->rsum;
+    out->alpha_last = st->alpha;
+    out->beta_last = st->beta;
+    out->update_norm = sqrt(u);
+  }
+}
+
+__global__ void k_status_out(const CgState* st, int32_t* out) {
+  if (threadIdx.x == 0) *out = st->status;
+}
+
+// ------------------------------------------------------------------------------------------
+// P = (G + lambda I)^-1 for an R x R SPD matrix, one workgroup per matrix, in LDS:
+// right-looking Cholesky G + lambda I = L L^T in place (pivots must be positive), then L^-1
+// by forward elimination overwriting L column by column, then P = L^-T L^-1.
+// A non-positive pivot records CP_ENOTSPD and marks the state done.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spd_inv(int R, const double* __restrict__ Gin,
+                                                 int64_t g_stride, double lambda,
+                                                 double* __restrict__ Pout, int64_t p_stride,
+                                                 int first_mode, CgState* st) {
+  extern __shared__ double sm[];
+  double* a = sm;               // R x R
+  double* tmp = sm + R * R;     // R
+  __shared__ int fail;
+  const int n = first_mode + blockIdx.x;
+  const double* G = Gin + n * g_stride;
+  double* P = Pout + n * p_stride;
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (st->status != CP_OK) return;
+  if (t == 0) fail = 0;
+  for (int e = t; e < R * R; e += nt) a[e] = G[e] + ((e / R) == (e % R) ? lambda : 0.0);
+  __syncthreads();
+  // Cholesky, lower triangle.
+  for (int j = 0; j < R; ++j) {
+    const double djj = a[j * R + j];
+    if (!(djj > 0.0) || !isfinite(djj)) {
+      if (t == 0) fail = 1;
+      break;
+    }
+    const double ljj = sqrt(djj);
+    __syncthreads();
+    for (int i = j + 1 + t; i < R; i += nt) a[i * R + j] /= ljj;
+    if (t == 0) a[j * R + j] = ljj;
+    __syncthreads();
+    const int m = R - j - 1;
+    for (int e = t; e < m * m; e += nt) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) a[i * R + k] -= a[i * R + j] * a[k * R + j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (fail) {
+    if (t == 0) {
+      st->status = CP_ENOTSPD;
+      st->done = 1;
+    }
+    return;
+  }
+  // In-place inverse of L: after step j, rows i > j hold e_i - sum_{k<=j} L[i][k] Linv[k][:].
+  for (int j = 0; j < R; ++j) {
+    const double inv = 1.0 / a[j * R + j];
+    __syncthreads();
+    for (int i = j + 1 + t; i < R; i += nt) tmp[i] = a[i * R + j];
+    for (int k = t; k < j; k += nt) a[j * R + k] *= inv;
+    __syncthreads();
+    if (t == 0) a[j * R + j] = inv;
+    __syncthreads();
+    const int m = R - j - 1, w = j + 1;
+    for (int e = t; e < m * w; e += nt) {
+      const int i = j + 1 + e / w, k = e % w;
+      const double cur = (k == j) ? 0.0 : a[i * R + k];
+      a[i * R + k] = cur - tmp[i] * a[j * R + k];
+    }
+    __syncthreads();
+  }
+  // P = Linv^T Linv: P[i][c] = sum_{k >= max(i,c)} Linv[k][i] Linv[k][c].
+  for (int e = t; e < R * R; e += nt) {
+    const int i = e / R, c = e % R;
+    const int k0 = i > c ? i : c;
+    double s = 0.0;
+    for (int k = k0; k < R; ++k) s += a[k * R + i] * a[k * R + c];
+    P[e] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Direct residual ||X - [[A]]||_F^2 and ||X||_F^2 (Section 5). The reconstruction tile
+// Xt[o][k] = sum_r KRP(o, r) A(N)[k, r] (o runs over all modes but the last) is built on the
+// matrix cores: the Khatri-Rao rows of a 16*MB-row tile stay in registers as A operands, the
+// last factor is streamed in a packed B-operand layout, and each reconstructed 16x16 tile is
+// compared with X in FP64.
+// ------------------------------------------------------------------------------------------
+template <typename T> struct ResCfg;
+template <> struct ResCfg<float> { static constexpr int MB = 4; };
+template <> struct ResCfg<double> { static constexpr int MB = 2; };
+
+struct ResArgs {
+  const void* X;
+  const void* apad[kMaxOrder];  // [s_m][Rp] compute precision
+  const void* bpk;              // [K/16][RS][64]: A(N)[16kb + lane%16][4s + lane/16]
+  int64_t O, K, KB;
+  int64_t s[kMaxOrder];
+  int N, Rp;
+  double* red;                  // [2][kRedSlots]
+};
+
+template <typename T, int NBR>
+__global__ __launch_bounds__(256, 2) void k_residual(ResArgs a) {
+  constexpr int MB = ResCfg<T>::MB;
+  constexpr int RS = 4 * NBR;
+  typedef typename Mfma<T>::v4 v4;
+  const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const T* X = (const T*)a.X;
+  const T* B = (const T*)a.bpk;
+  double d2 = 0.0, x2 = 0.0;
+  for (int64_t tile = wave; tile * 16 * MB < a.O; tile += nwaves) {
+    const int64_t o0 = tile * 16 * MB;
+    T ar[MB][RS];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t o = o0 + 16 * mb + m;
+#pragma unroll
+      for (int s = 0; s < RS; ++s) ar[mb][s] = (o < a.O) ? T(1) : T(0);
+      if (o < a.O) {
+        int64_t rem = o;
+        for (int q = a.N - 2; q >= 0; --q) {
+          const int64_t idx = rem % a.s[q];
+          rem /= a.s[q];
+          const T* row = (const T*)a.apad[q] + idx * a.Rp + g;
+#pragma unroll
+          for (int s = 0; s < RS; ++s) ar[mb][s] *= row[4 * s];
+        }
+      }
+    }
+    for (int64_t kb = 0; kb < a.KB; ++kb) {
+      T br[RS];
+#pragma unroll
+      for (int s = 0; s < RS; ++s) br[s] = B[(kb * RS + s) * kWave + lane];
+      const int64_t k = kb * 16 + m;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < RS; ++s) acc = Mfma<T>::mac(ar[mb][s], br[s], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t o = o0 + 16 * mb + Mfma<T>::out_row(lane, v);
+          if (o < a.O && k < a.K) {
+            const double x = (double)X[o * a.K + k];
+            const double df = x - (double)acc[v];
+            d2 += df * df;
+            x2 += x * x;
+          }
+        }
+      }
+    }
+  }
+  block_sum2(d2, x2);
+  if (threadIdx.x == 0) {
+    a.red[blockIdx.x] = d2;
+    a.red[kRedSlots + blockIdx.x] = x2;
+  }
+}
+
+// Pack the last factor for the residual B operand: bpk[kb][s][lane] = A[16kb + m][4s + g].
+template <typename T>
+__global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, int64_t KB,
+                            T* __restrict__ bpk) {
+  const int RS = Rp / 4;
+  const int64_t total = KB * RS * kWave;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(e % kWave);
+    const int64_t rest = e / kWave;
+    const int s = (int)(rest % RS);
+    const int64_t kb = rest / RS;
+    const int64_t k = 16 * kb + (lane & 15);
+    bpk[e] = k < K ? apad_last[k * Rp + 4 * s + (lane >> 4)] : T(0);
+  }
+}
+
+// Fallback for R > 128: one thread per tensor entry, scalar FP64 reconstruction.
+template <typename T>
+__global__ void k_residual_scalar(ResArgs a, int R) {
+  const T* X = (const T*)a.X;
+  double d2 = 0.0, x2 = 0.0;
+  const int64_t total = a.O * a.K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t idx[kMaxOrder];
+    int64_t rem = e;
+    for (int q = a.N - 1; q >= 0; --q) {
+      idx[q] = rem % a.s[q];
+      rem /= a.s[q];
+    }
+    double xt = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double p = 1.0;
+      for (int q = 0; q < a.N; ++q) p *= (double)((const T*)a.apad[q])[idx[q] * a.Rp + r];
+      xt += p;
+    }
+    const double x = (double)X[e];
+    d2 += (x - xt) * (x - xt);
+    x2 += x * x;
+  }
+  block_sum2(d2, x2);
+  if (threadIdx.x == 0) {
+    a.red[blockIdx.x] = d2;
+    a.red[kRedSlots + blockIdx.x] = x2;
+  }
+}
+
+// sum of squares of X (for the expansion form).
+template <typename T>
+__global__ void k_sumsq(const T* __restrict__ X, int64_t total, double* red) {
+  double x2 = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)X[e];
+    x2 += x * x;
+  }
+  block_sum2(x2, dummy);
+  if (threadIdx.x == 0) red[kRedSlots + blockIdx.x] = x2;
+}
+
+__global__ void k_fin_residual_direct(int nblocks, const double* red, double* out) {
+  const double d2 = sum_slots(red, nblocks);
+  const double x2 = sum_slots(red + kRedSlots, nblocks);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(d2);
+    out[1] = sqrt(x2);
+  }
+}
+
+// ||X||^2 - 2 <M(1), A(1)> + sum_{r,z} prod_m S(m)[r][z]; a negative value is clamped to 0.
+__global__ void k_fin_residual_expansion(Dims d, int nblocks, const double* red,
+                                         const double* M0, const double* A64, const double* S,
+                                         double* out) {
+  const double x2 = sum_slots(red + kRedSlots, nblocks);
+  double cross = 0.0, had = 0.0;
+  const int64_t n0 = d.s[0] * d.R;
+  for (int64_t e = threadIdx.x; e < n0; e += blockDim.x) cross += M0[e] * A64[e];
+  const int64_t RR = (int64_t)d.R * d.R;
+  for (int64_t e = threadIdx.x; e < RR; e += blockDim.x) {
+    double p = 1.0;
+    for (int m = 0; m < d.N; ++m) p *= S[m * RR + e];
+    had += p;
+  }
+  block_sum2(cross, had);
+  if (threadIdx.x == 0) {
+    const double r2 = x2 - 2.0 * cross + had;
+    out[0] = sqrt(r2 > 0.0 ? r2 : 0.0);
+    out[1] = sqrt(x2);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host launchers used by the API layer
+// ------------------------------------------------------------------------------------------
+int grid1(int64_t n, int cap) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+void launch_gram2(const Dims& d, const double* X, const double* Y, double* C, int mode_only,
+                  const CgState* st, hipStream_t s) {
+  const int tiles = (d.R + 15) / 16;
+  dim3 grid(tiles * tiles, 1, mode_only >= 0 ? 1 : d.N);
+  hipLaunchKernelGGL(k_gram2, grid, dim3(256), 0, s, d, X, Y, C, mode_only, st);
+}
+
+void launch_gamma(const Dims& d, const double* S, double* Gam, hipStream_t s) {
+  hipLaunchKernelGGL(k_gamma, dim3(grid1((int64_t)d.N * d.N * d.R * d.R, 256)), dim3(256), 0, s,
+                     d, S, Gam);
+}
+
+void launch_ycore(const Dims& d, const double* Gam, const double* B, double* Y, const CgState* st,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_ycore, dim3(grid1((int64_t)d.N * d.R * d.R, 256)), dim3(256), 0, s, d, Gam,
+                     B, Y, st);
+}
+
+int rowmm_blocks(const Dims& d) {
+  int64_t mx = 0;
+  for (int n = 0; n < d.N; ++n) mx = d.s[n] > mx ? d.s[n] : mx;
+  return grid1(mx * d.R, 256);
+}
+
+void launch_rowmm(const Dims& d, const RowMM& a, const CgState* st, hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), a.mode_only >= 0 ? 1 : d.N);
+  hipLaunchKernelGGL(k_rowmm, grid, dim3(256), 0, s, d, a, st);
+}
+
+void launch_cg_axpy(const Dims& d, double* V, double* Rv, const double* W, const double* Q,
+                    double* red_nrm, const CgState* st, hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), d.N);
+  hipLaunchKernelGGL(k_cg_axpy, grid, dim3(256), 0, s, d, V, Rv, W, Q, red_nrm, st);
+}
+
+void launch_cg_wupdate(int64_t cnt, double* W, const double* Z, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_wupdate, dim3(grid1(cnt, 1024)), dim3(256), 0, s, cnt, W, Z, st);
+}
+
+void launch_fill(int64_t cnt, double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(grid1(cnt, 1024)), dim3(256), 0, s, cnt, p, v);
+}
+
+void launch_to64(const Dims& d, const PerMode<const void*>& src, int dtype, double* dst,
+                 hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), d.N);
+  hipLaunchKernelGGL(k_to64, grid, dim3(256), 0, s, d, src, dtype, dst);
+}
+
+void launch_fin_grad(const Dims& d, int nblocks, const double* red_nrm, CgState* st, double eps,
+                     double* gsum_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_grad, dim3(1), dim3(256), 0, s, d.N, nblocks, red_nrm, st, eps,
+                     gsum_out);
+}
+
+void launch_state_reset(CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st);
+}
+
+void launch_fin_cginit(const Dims& d, int nblocks, const double* red_dot, CgState* st,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cginit, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, st);
+}
+
+void launch_fin_alpha(const Dims& d, int nblocks, const double* red_dot, CgState* st,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, st);
+}
+
+void launch_fin_beta(const Dims& d, int nblocks, const double* red_dot, const double* red_nrm,
+                     CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, red_nrm, st);
+}
+
+void launch_gn_apply(const Dims& d, double* A64, const double* V, const PerMode<void*>& Aout,
+                     int dtype, double* red_nrm, const CgState* st, hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), d.N);
+  hipLaunchKernelGGL(k_gn_apply, grid, dim3(256), 0, s, d, A64, V, Aout, dtype, red_nrm, st);
+}
+
+void launch_gn_stats(const Dims& d, int nblocks, const double* red_nrm, const CgState* st,
+                     cp_gn_stats* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gn_stats, dim3(1), dim3(256), 0, s, d.N, nblocks, red_nrm, st, out);
+}
+
+void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, st, out);
+}
+
+size_t spd_inv_lds(int R) { return ((size_t)R * R + R) * sizeof(double); }
+
+int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
+                   int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s) {
+  const size_t lds = spd_inv_lds(R);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_spd_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_spd_inv, dim3(count), dim3(256), lds, s, R, G, g_stride, lambda, P,
+                     p_stride, first_mode, st);
+  return (int)hipGetLastError();
+}
+
+template <typename T>
+static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out, hipStream_t s) {
+  constexpr int MB = ResCfg<T>::MB;
+  ResArgs a{};
+  a.X = X;
+  int64_t off = 0;
+  for (int m = 0; m < p.N; ++m) {
+    a.apad[m] = ws + p.off_apad + off * p.esz;
+    a.s[m] = p.s[m];
+    off += p.s[m] * p.Rp;
+  }
+  a.N = p.N;
+  a.Rp = p.Rp;
+  a.K = p.s[p.N - 1];
+  a.O = p.total / a.K;
+  a.KB = (a.K + 15) / 16;
+  a.red = (double*)(ws + p.off_red);
+  if (p.R <= 128) {
+    // the packed last factor reuses the MTTKRP partial region
+    a.bpk = ws + p.off_part;
+    hipLaunchKernelGGL(k_pack_last<T>, dim3(grid1(a.KB * p.Rp / 4 * kWave, 1024)), dim3(256), 0,
+                       s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part));
+    const int64_t tiles = (a.O + 16 * MB - 1) / (16 * MB);
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > kRedSlots) blocks = kRedSlots;
+    switch (p.NBt) {
+#define CPGN_RES(k) \
+  case k: hipLaunchKernelGGL((k_residual<T, k>), dim3(blocks), dim3(256), 0, s, a); break;
+      CPGN_RES(1) CPGN_RES(2) CPGN_RES(3) CPGN_RES(4) CPGN_RES(5) CPGN_RES(6) CPGN_RES(7)
+      CPGN_RES(8)
+#undef CPGN_RES
+      default: break;
+    }
+    hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, (int)blocks, a.red, out);
+  } else {
+    const int blocks = grid1(p.total, kRedSlots);
+    hipLaunchKernelGGL(k_residual_scalar<T>, dim3(blocks), dim3(256), 0, s, a, p.R);
+    hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, blocks, a.red, out);
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_residual_direct(const Plan& p, const void* X, void* ws, double* out, hipStream_t s) {
+  if (p.dtype == CP_F32) return launch_residual_t<float>(p, X, (char*)ws, out, s);
+  return launch_residual_t<double>(p, X, (char*)ws, out, s);
+}
+
+int launch_sumsq(const Plan& p, const void* X, double* red, hipStream_t s, int* nblocks) {
+  const int blocks = grid1(p.total, kRedSlots);
+  if (p.dtype == CP_F32)
+    hipLaunchKernelGGL(k_sumsq<float>, dim3(blocks), dim3(256), 0, s, (const float*)X, p.total, red);
+  else
+    hipLaunchKernelGGL(k_sumsq<double>, dim3(blocks), dim3(256), 0, s, (const double*)X, p.total,
+                       red);
+  *nblocks = blocks;
+  return (int)hipGetLastError();
+}
+
+void launch_fin_residual_expansion(const Dims& d, int nblocks, const double* red, const double* M0,
+                                   const double* A64, const double* S, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_residual_expansion, dim3(1), dim3(256), 0, s, d, nblocks, red, M0, A64,
+                     S, out);
+}
+
+}  // namespace cpgn

@@ -1,0 +1,93 @@
+"""Optimizer objects with a step() member, as the paper structures its ALS and Gauss-Newton
+drivers (Section 4): each step() is one ALS sweep or one Gauss-Newton iteration, executed by
+libcpgn.so on the GPU."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import api
+
+
+class DampingSchedule:
+    """Varying Tikhonov damping of Section 3.2: begin at the upper threshold, divide by mu after
+    every step until the lower threshold is reached, then multiply by mu until the upper one is
+    reached again, and so on. `value` is the damping for the coming step."""
+
+    def __init__(self, start=1e-4, lower=1e-10, upper=1e-4, mu=2.0):
+        if not (mu > 1.0 and 0.0 < lower <= upper):
+            raise ValueError("need mu > 1 and 0 < lower <= upper")
+        self.value, self.lower, self.upper, self.mu = float(start), float(lower), float(upper), float(mu)
+        self.decreasing = True
+
+    def advance(self) -> float:
+        if self.decreasing:
+            self.value = self.value / self.mu
+            if self.value <= self.lower:
+                self.decreasing = False
+        else:
+            self.value = self.value * self.mu
+            if self.value >= self.upper:
+                self.decreasing = True
+        return self.value
+
+    def state_dict(self):
+        return dict(value=self.value, lower=self.lower, upper=self.upper, mu=self.mu,
+                    decreasing=self.decreasing)
+
+    def load_state_dict(self, d):
+        self.value, self.lower, self.upper, self.mu = d["value"], d["lower"], d["upper"], d["mu"]
+        self.decreasing = d["decreasing"]
+
+
+@dataclass
+class GNConfig:
+    cg_tol: float = 1e-3
+    cg_maxiter: int = 20
+    schedule: DampingSchedule | None = None
+
+
+class GaussNewton:
+    """Algorithm 1 (CP-GN). Factors are updated in place on the device."""
+
+    def __init__(self, X: torch.Tensor, A, config: GNConfig | None = None):
+        self.X, self.A = X, list(A)
+        self.cfg = config or GNConfig()
+        self.schedule = self.cfg.schedule or DampingSchedule()
+        self.ws = api.Workspace()
+        self.stats_buf = api.stats_buffer(X.device)
+        self.steps = 0
+
+    def step(self) -> torch.Tensor:
+        api.gn_step(self.X, self.A, self.schedule.value, self.cfg.cg_tol, self.cfg.cg_maxiter,
+                    stats=self.stats_buf, ws=self.ws)
+        self.schedule.advance()
+        self.steps += 1
+        return self.stats_buf
+
+    def stats(self) -> dict:
+        return api.read_stats(self.stats_buf)
+
+    def residual(self) -> float:
+        r = api.residual(self.X, self.A, ws=self.ws).cpu()
+        return float(r[0] / r[1])
+
+
+class ALS:
+    """Alternating least squares sweeps (Section 2.2)."""
+
+    def __init__(self, X: torch.Tensor, A, lam: float = 0.0):
+        self.X, self.A, self.lam = X, list(A), float(lam)
+        self.ws = api.Workspace()
+        self.status = torch.zeros(1, dtype=torch.int32, device=X.device)
+        self.steps = 0
+
+    def step(self) -> torch.Tensor:
+        api.als_sweep(self.X, self.A, self.lam, status=self.status, ws=self.ws)
+        self.steps += 1
+        return self.status
+
+    def residual(self) -> float:
+        r = api.residual(self.X, self.A, ws=self.ws).cpu()
+        return float(r[0] / r[1])

@@ -1,0 +1,159 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol the
+public header declares, its structs have the header's layout, and argument errors are
+reported before anything is enqueued. Also the host-side damping schedule."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle as O
+from paper_1910_12331_amd import _lib as L
+from paper_1910_12331_amd.optim import DampingSchedule
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cpgn.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert set(names) == set(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (cp_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "cpgn.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(cp_problem), offsetof(cp_problem, dims),'
+        " offsetof(cp_problem, x_dtype), offsetof(cp_problem, f_dtype), sizeof(cp_gn_params));\n"
+        'printf("%zu %zu %zu\\n", sizeof(cp_gn_stats), offsetof(cp_gn_stats, grad_norm_sum),'
+        " offsetof(cp_gn_stats, update_norm));\n"
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    a = list(map(int, lines[0].split()))
+    b = list(map(int, lines[1].split()))
+    assert a == [C.sizeof(L.CpProblem), L.CpProblem.dims.offset, L.CpProblem.x_dtype.offset,
+                 L.CpProblem.f_dtype.offset, C.sizeof(L.CpGnParams)]
+    assert b == [C.sizeof(L.CpGnStats), L.CpGnStats.grad_norm_sum.offset,
+                 L.CpGnStats.update_norm.offset]
+
+
+def prob(dims=(8, 9, 10), rank=5, dt=L.CP_F64):
+    p = L.CpProblem()
+    p.order = len(dims)
+    p.rank = rank
+    for i, s in enumerate(dims):
+        p.dims[i] = s
+    p.x_dtype = p.f_dtype = dt
+    return p
+
+
+def ws_bytes(lib, p, op=L.OP_GN_STEP):
+    n = C.c_size_t(0)
+    rc = lib.cp_workspace_bytes(C.byref(p), op, C.byref(n))
+    return rc, n.value
+
+
+def test_workspace_queries(lib):
+    rc, n = ws_bytes(lib, prob())
+    assert rc == 0 and n > 0 and n % 256 == 0
+    for op in range(6):
+        assert ws_bytes(lib, prob(), op)[0] == 0
+    assert ws_bytes(lib, prob(), 17)[0] == L.CP_EINVAL
+    big = ws_bytes(lib, prob((400, 400, 400), 100, L.CP_F32))[1]
+    assert big < 64 << 20   # the workspace stays small next to the tensor
+
+
+@pytest.mark.parametrize("mut,code", [
+    (lambda p: setattr(p, "order", 1), L.CP_EINVAL),
+    (lambda p: setattr(p, "order", 9), L.CP_EINVAL),
+    (lambda p: setattr(p, "rank", 0), L.CP_EINVAL),
+    (lambda p: p.dims.__setitem__(1, 0), L.CP_EINVAL),
+    (lambda p: setattr(p, "f_dtype", L.CP_F32), L.CP_EUNSUPPORTED),
+    (lambda p: (setattr(p, "x_dtype", 2), setattr(p, "f_dtype", 2)), L.CP_EUNSUPPORTED),
+])
+def test_problem_validation(lib, mut, code):
+    p = prob()
+    mut(p)
+    assert ws_bytes(lib, p)[0] == code
+
+
+def fake_ptrs(n=3):
+    a = L.PTRS()
+    for i in range(n):
+        a[i] = 0x1000 * (i + 1)
+    return a
+
+
+def test_call_validation_without_launch(lib):
+    p = prob()
+    _, need = ws_bytes(lib, p)
+    X, M, ws = C.c_void_p(0x10000), C.c_void_p(0x20000), C.c_void_p(0x40000)
+    A = fake_ptrs()
+    # bad mode, null tensor, null factor, small / misaligned / null workspace
+    assert lib.cp_mttkrp(C.byref(p), X, A, 3, M, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp(C.byref(p), X, A, -1, M, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp(C.byref(p), None, A, 0, M, ws, need, None) == L.CP_EINVAL
+    A0 = fake_ptrs()
+    A0[1] = 0
+    assert lib.cp_mttkrp(C.byref(p), X, A0, 0, M, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, ws, need - 1, None) == L.CP_EWORKSPACE
+    assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, C.c_void_p(0x40010), need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, None, need, None) == L.CP_EINVAL
+    # Gauss-Newton parameters
+    st = C.c_void_p(0x50000)
+    for prm in [L.CpGnParams(-1.0, 1e-3, 20, 0), L.CpGnParams(1e-3, -1.0, 20, 0),
+                L.CpGnParams(1e-3, 1e-3, -1, 0), L.CpGnParams(1e-3, 1e-3, 20, 1),
+                L.CpGnParams(float("nan"), 1e-3, 20, 0)]:
+        assert lib.cp_gn_step(C.byref(p), X, A, C.byref(prm), st, ws, need, None) == L.CP_EINVAL
+    good = L.CpGnParams(1e-3, 1e-3, 20, 0)
+    assert lib.cp_gn_step(C.byref(p), X, A, C.byref(good), None, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_gn_step(C.byref(p), X, A, C.byref(good), st, ws, need // 2, None) == L.CP_EWORKSPACE
+    assert lib.cp_als_sweep(C.byref(p), X, A, -1.0, None, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_residual(C.byref(p), X, A, 2, C.c_void_p(0x60000), ws, need, None) == L.CP_EINVAL
+    assert lib.cp_residual(C.byref(p), X, A, 0, None, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_gn_jtj_matvec(C.byref(p), A, A, -1.0, A, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_gn_gradient(C.byref(p), X, A, L.PTRS(), None, ws, need, None) == L.CP_EINVAL
+    # ranks whose R x R Cholesky does not fit in one workgroup's LDS are refused by GN and ALS
+    pr = prob(rank=200)
+    _, need2 = ws_bytes(lib, pr)
+    assert lib.cp_gn_step(C.byref(pr), X, A, C.byref(good), st, ws, need2, None) == L.CP_EUNSUPPORTED
+
+
+def test_status_strings(lib):
+    for code in range(0, -8, -1):
+        assert len(L.status_string(code)) > 0
+    assert L.status_string(-99) == "unknown status"
+
+
+def test_damping_schedule_matches_oracle_definition():
+    a = DampingSchedule(1e-4, 1e-10, 1e-4, 2.0)
+    b = O.LambdaSchedule(1e-4, 1e-10, 1e-4, 2.0)
+    for _ in range(100):
+        assert a.value == b.value
+        a.advance()
+        b.advance()
+    s = DampingSchedule(1.0, 0.25, 1.0, 2.0)
+    seq = [s.value] + [s.advance() for _ in range(6)]
+    assert seq == [1.0, 0.5, 0.25, 0.5, 1.0, 0.5, 0.25]

@@ -1,0 +1,346 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle on identical seeded inputs.
+
+Tolerances are normwise relative errors ||gpu - ref||_F / ||ref||_F:
+  * FP64 paths: 1e-12 per call.
+  * FP32 paths: the oracle runs in FP64 on the FP32-rounded inputs. MTTKRP 2e-5; quantities
+    that cancel (gradient, residual) are measured against the size of the terms that cancel.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make_problem, planted_tensor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1910_12331_amd as P  # noqa: E402
+
+TOL = {torch.float64: 1e-12, torch.float32: 2e-5}
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rnd_factors(dims, rank, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return [scale * rng.standard_normal((s, rank)) for s in dims]
+
+
+def to_dev(arrs, dt):
+    return [torch.tensor(a, dtype=dt, device="cuda").contiguous() for a in arrs]
+
+
+def rounded(arrs, dt):
+    """What the device sees, in float64 (FP32 inputs are rounded first)."""
+    if dt == torch.float32:
+        return [np.asarray(a, dtype=np.float32).astype(np.float64) for a in arrs]
+    return [np.asarray(a, dtype=np.float64) for a in arrs]
+
+
+def host(ts):
+    return [t.double().cpu().numpy() for t in ts]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P._lib.load()
+    yield
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------------------------ MTTKRP
+MTTKRP_CASES = [
+    ((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4), ((64, 48, 32), 16),
+    ((30, 20, 25), 50), ((24, 20, 18), 100), ((12, 10, 9), 130), ((1, 5, 3), 2), ((5, 1, 3), 2),
+    ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33),
+]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank", MTTKRP_CASES, ids=[f"{d}-R{r}" for d, r in MTTKRP_CASES])
+def test_mttkrp_matches_oracle(dims, rank, dt):
+    rng = np.random.default_rng(sum(dims) + rank)
+    X = rng.standard_normal(dims)
+    A = rnd_factors(dims, rank, 7 + rank)
+    Xh, Ah = rounded([X], dt)[0], rounded(A, dt)
+    Xd, Ad = to_dev([X], dt)[0], to_dev(A, dt)
+    for n in range(len(dims)):
+        M = P.mttkrp(Xd, Ad, n)
+        ref = O.mttkrp(Xh, Ah, n)
+        assert rel(host([M])[0], ref) < TOL[dt], (n, rel(host([M])[0], ref))
+
+
+def test_mttkrp_config2_full_size_fp64():
+    """300^3, R = 50, congruent factors + noise (FP64), every mode against the oracle."""
+    p = make_problem((300, 300, 300), 50, workload=2, kind="congruent", noise=1e-6)
+    Xd = to_dev([p.x], torch.float64)[0]
+    Ad = to_dev(p.init, torch.float64)
+    for n in range(3):
+        M = P.mttkrp(Xd, Ad, n)
+        assert rel(host([M])[0], O.mttkrp(p.x, p.init, n)) < 1e-12
+
+
+def test_mttkrp_400_fp32_closed_form():
+    """400^3, R = 100 FP32 planted tensor: M(n) = B(n) (Hadamard_{m != n} B(m)^T A(m)) holds at
+    any size; checked against that closed form (FP64) on the FP32-rounded factors."""
+    rng = np.random.default_rng(3000)
+    B = [rng.standard_normal((400, 100)).astype(np.float32).astype(np.float64) for _ in range(3)]
+    X = planted_tensor(B).astype(np.float32)
+    A = [rng.standard_normal((400, 100)).astype(np.float32).astype(np.float64) for _ in range(3)]
+    Xd = torch.from_numpy(X).cuda()
+    del X
+    Ad = to_dev(A, torch.float32)
+    for n in range(3):
+        cross = np.ones((100, 100))
+        for m in range(3):
+            if m != n:
+                cross *= B[m].T @ A[m]
+        ref = B[n] @ cross
+        M = P.mttkrp(Xd, Ad, n)
+        # X itself is rounded to FP32 (relative 6e-8 per entry) on top of the FP32 contraction
+        assert rel(host([M])[0], ref) < 2e-5
+
+
+# ------------------------------------------------------------------------------------ gradient
+GRAD_CASES = [((40, 40, 40), 5), ((23, 18, 31), 6), ((9, 7, 8, 6), 3), ((11, 13), 4),
+              ((30, 25, 20), 50)]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank", GRAD_CASES, ids=[f"{d}-R{r}" for d, r in GRAD_CASES])
+def test_gradient_matches_oracle(dims, rank, dt):
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    G, gsum = P.gn_gradient(to_dev([p.x], dt)[0], to_dev(p.init, dt))
+    ref = O.gradient(Xh, Ah)
+    S = O.grams(Ah)
+    scale = [np.linalg.norm(Ah[n] @ O.gamma(S, n, n)) + np.linalg.norm(O.mttkrp(Xh, Ah, n))
+             for n in range(len(dims))]
+    for n, (g, r) in enumerate(zip(host(G), ref)):
+        err = np.linalg.norm(g - r) / scale[n]
+        assert err < TOL[dt], (n, err)
+    refsum = sum(np.linalg.norm(r) for r in ref)
+    assert abs(float(gsum.item()) - refsum) / refsum < (1e-12 if dt == torch.float64 else 1e-4)
+
+
+def test_gradient_config2_fp64():
+    p = make_problem((300, 300, 300), 50, workload=2, kind="congruent", noise=1e-6)
+    G, _ = P.gn_gradient(to_dev([p.x], torch.float64)[0], to_dev(p.init, torch.float64))
+    for g, r in zip(host(G), O.gradient(p.x, p.init)):
+        assert rel(g, r) < 1e-12
+
+
+# ------------------------------------------------------------------------------------ J^T J
+@pytest.mark.parametrize("dims,rank,lam", [((3, 4, 2), 2, 0.0), ((2, 3, 2, 3), 2, 0.3),
+                                           ((4, 3), 3, 1e-2), ((5, 4, 6), 3, 1e-4)])
+def test_jtj_matvec_explicit_jacobian(dims, rank, lam):
+    A = rnd_factors(dims, rank, 11)
+    W = rnd_factors(dims, rank, 12)
+    Q = P.jtj_matvec(to_dev(A, torch.float64), to_dev(W, torch.float64), lam)
+    H = O.jtj_dense(A)
+    w = O.flatten_factors(W)
+    assert rel(O.flatten_factors(host(Q)), H @ w + lam * w) < 1e-12
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank,lam", [((40, 40, 40), 5, 1e-4), ((300, 300, 300), 50, 1e-3),
+                                           ((400, 400, 400), 100, 1e-4), ((17, 9, 12, 8), 7, 0.0)])
+def test_jtj_matvec_matches_oracle(dims, rank, lam, dt):
+    A = rounded(rnd_factors(dims, rank, 13), dt)
+    W = rounded(rnd_factors(dims, rank, 14), dt)
+    Q = P.jtj_matvec(to_dev(A, dt), to_dev(W, dt), lam)
+    ref = O.jtj_matvec(A, W, lam)
+    tol = 1e-12 if dt == torch.float64 else 1e-6   # FP64 inside; only the output is rounded
+    assert rel(O.flatten_factors(host(Q)), O.flatten_factors(ref)) < tol
+
+
+# ------------------------------------------------------------------------------------ GN step
+def oracle_sensitivity(Xh, Ah, lam, eps, maxiter, seed=1):
+    """Change of the oracle's GN update when its input factors move by 1e-15 relative: the
+    rounding-level spread that any implementation with another summation order inherits
+    (large once CG iterates past its rounding floor and loses orthogonality)."""
+    rng = np.random.default_rng(seed)
+    A2 = [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in Ah]
+    v1 = O.flatten_factors([b - a for a, b in zip(Ah, O.gn_step(Xh, Ah, lam, eps, maxiter)[0])])
+    v2 = O.flatten_factors([b - a for a, b in zip(A2, O.gn_step(Xh, A2, lam, eps, maxiter)[0])])
+    return float(np.linalg.norm(v1 - v2) / max(np.linalg.norm(v1), 1e-300))
+
+
+def gn_compare(p, dt, lam, eps, maxiter, tol_v):
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    if tol_v == "sensitivity":
+        tol_v = max(1e-12, 10 * oracle_sensitivity(Xh, Ah, lam, eps, maxiter))
+    Ad = to_dev(p.init, dt)
+    st = P.read_stats(P.gn_step(to_dev([p.x], dt)[0], Ad, lam, eps, maxiter))
+    newA, ref = O.gn_step(Xh, Ah, lam, eps, maxiter)
+    assert st["status"] == 0
+    assert st["cg_iters"] == ref.cg_iters
+    V = [a - b for a, b in zip(host(Ad), Ah)]
+    Vref = [a - b for a, b in zip(newA, Ah)]
+    err = rel(O.flatten_factors(V), O.flatten_factors(Vref))
+    assert err < tol_v, err
+    assert abs(st["grad_norm_sum"] - ref.grad_norm_sum) <= tol_v * ref.grad_norm_sum
+    return st, ref
+
+
+@pytest.mark.parametrize("maxiter", [0, 1, 5, 10])
+def test_gn_step_fixed_iterations_fp64(maxiter):
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float64, 1e-4, 0.0, maxiter, 1e-12)
+
+
+def test_gn_step_past_cg_rounding_floor_fp64():
+    """20 CG iterations with eps_cg = 0 run past convergence; the bar is 10x the oracle's own
+    spread under a 1e-15 perturbation of its input."""
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float64, 1e-4, 0.0, 20, "sensitivity")
+
+
+@pytest.mark.parametrize("dims,rank,lam", [((40, 40, 40), 5, 1e-4), ((23, 18, 31), 6, 1e-2),
+                                           ((9, 7, 8, 6), 3, 1e-3), ((11, 13), 4, 1e-3),
+                                           ((60, 50, 40), 20, 1e-4)])
+def test_gn_step_cg_tolerance_fp64(dims, rank, lam):
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-3)
+    gn_compare(p, torch.float64, lam, 1e-3, 50, 1e-11)
+
+
+def test_gn_step_config2_fp64():
+    p = make_problem((300, 300, 300), 50, workload=2, kind="congruent", noise=1e-6)
+    st, ref = gn_compare(p, torch.float64, 1e-4, 1e-3, 20, 1e-10)
+    assert st["cg_iters"] >= 1
+
+
+def test_gn_step_fp32():
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float32, 1e-4, 0.0, 10, 1e-4)
+
+
+def test_gn_step_zero_gradient_no_iteration():
+    X = torch.zeros((8, 9, 10), dtype=torch.float64, device="cuda")
+    A = [torch.zeros((s, 3), dtype=torch.float64, device="cuda") for s in (8, 9, 10)]
+    st = P.read_stats(P.gn_step(X, A, 1e-3, 1e-3, 20))
+    assert st["status"] == 0 and st["cg_iters"] == 0 and st["update_norm"] == 0.0
+    assert all(float(a.abs().max()) == 0.0 for a in A)
+
+
+def test_gn_step_not_spd_leaves_factors():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((6, 1))
+    A = [np.hstack([a, a]), rng.standard_normal((5, 2)), rng.standard_normal((4, 2))]
+    A[1][:, 1] = A[1][:, 0]
+    A[2][:, 1] = A[2][:, 0]
+    Ad = to_dev(A, torch.float64)
+    before = host(Ad)
+    st = P.read_stats(P.gn_step(to_dev([rng.standard_normal((6, 5, 4))], torch.float64)[0], Ad,
+                                0.0, 1e-3, 20))
+    assert st["status"] == P._lib.CP_ENOTSPD
+    for x, y in zip(host(Ad), before):
+        assert np.array_equal(x, y)
+
+
+def test_gn_step_bitwise_deterministic():
+    p = make_problem((50, 45, 40), 12, workload=0, problem=9, noise=1e-3)
+    outs = []
+    for _ in range(2):
+        Ad = to_dev(p.init, torch.float64)
+        P.gn_step(to_dev([p.x], torch.float64)[0], Ad, 1e-3, 1e-3, 20)
+        outs.append(host(Ad))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------------------------ ALS
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank,lam", [((40, 40, 40), 5, 0.0), ((23, 18, 31), 6, 1e-2),
+                                           ((9, 7, 8, 6), 3, 0.0), ((30, 25, 20), 50, 1e-3)])
+def test_als_sweep_matches_oracle(dims, rank, lam, dt):
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    Ad = to_dev(p.init, dt)
+    status = P.als_sweep(to_dev([p.x], dt)[0], Ad, lam)
+    assert int(status.item()) == 0
+    ref = O.als_sweep(Xh, Ah, lam)
+    tol = 1e-12 if dt == torch.float64 else 1e-4
+    for a, r in zip(host(Ad), ref):
+        assert rel(a, r) < tol
+
+
+def test_als_sweep_config2_fp64():
+    """After the first mode the congruent data make the Grams ill-conditioned (cond ~1e9-1e11),
+    so later modes are held to 10x the oracle's own spread under a 1e-15 input perturbation."""
+    p = make_problem((300, 300, 300), 50, workload=2, kind="congruent", noise=1e-6)
+    Ad = to_dev(p.init, torch.float64)
+    P.als_sweep(to_dev([p.x], torch.float64)[0], Ad, 0.0)
+    ref = O.als_sweep(p.x, p.init)
+    rng = np.random.default_rng(1)
+    ref2 = O.als_sweep(p.x, [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in p.init])
+    for a, r, r2 in zip(host(Ad), ref, ref2):
+        assert rel(a, r) < max(1e-12, 10 * rel(r2, r))
+
+
+# ------------------------------------------------------------------------------------ residual
+RES_CASES = [((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4),
+             ((12, 10, 9), 130), ((24, 20, 18), 100)]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank", RES_CASES, ids=[f"{d}-R{r}" for d, r in RES_CASES])
+def test_residual_matches_oracle(dims, rank, dt):
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-1)
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    out = P.residual(to_dev([p.x], dt)[0], to_dev(p.init, dt)).cpu().numpy()
+    num, den = O.residual(Xh, Ah)
+    tol = 1e-12 if dt == torch.float64 else 1e-5
+    assert abs(out[0] - num) / num < tol and abs(out[1] - den) / den < tol
+    ex = P.residual(to_dev([p.x], dt)[0], to_dev(p.init, dt), method=1).cpu().numpy()
+    e2, _ = O.residual_expansion(Xh, Ah)
+    assert abs(ex[0] ** 2 - e2) / (den * den + abs(e2)) < (1e-12 if dt == torch.float64 else 1e-5)
+
+
+def test_residual_at_planted_solution_fp64():
+    p = make_problem((60, 50, 40), 8, workload=0, problem=1)
+    out = P.residual(to_dev([p.x], torch.float64)[0], to_dev(p.planted, torch.float64)).cpu().numpy()
+    assert out[0] / out[1] < 1e-14
+
+
+# ------------------------------------------------------------------------------------ end to end
+def test_gn_end_to_end_config1():
+    p = make_problem((40, 40, 40), 5, workload=1)
+    X = to_dev([p.x], torch.float64)[0]
+    Ad = to_dev(p.init, torch.float64)
+    opt = P.GaussNewton(X, Ad, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    r = opt.residual()
+    for _ in range(200):
+        if r <= 1e-10:
+            break
+        opt.step()
+        assert opt.stats()["status"] == 0
+        r = opt.residual()
+    assert r <= 1e-10
+    _, hist, rref = O.gn(p.x, p.init, O.LambdaSchedule(1e-4, 1e-10, 1e-4, 2.0), 1e-3, 20, 1e-10, 200)
+    assert rref <= 1e-10 and abs(opt.steps - len(hist)) <= 3
+    num, den = O.residual(p.x, host(Ad))
+    assert num / den <= 1e-10
+
+
+def test_als_end_to_end_config1_monotone():
+    p = make_problem((40, 40, 40), 5, workload=1)
+    X = to_dev([p.x], torch.float64)[0]
+    Ad = to_dev(p.init, torch.float64)
+    opt = P.ALS(X, Ad)
+    last = math.inf
+    for _ in range(300):
+        r = opt.residual()
+        assert r <= last * (1 + 1e-9)
+        last = r
+        if r <= 1e-10:
+            break
+        opt.step()
+    assert last <= 1e-10
