@@ -31,6 +31,8 @@
  *     non-finite values) are written as a status code into device memory (the `status` field
  *     of cp_gn_stats, or `status_dev`); the caller reads it after synchronising the stream.
  *     On such a failure the factors are left unchanged.
+ *   - cp_gn_step and cp_als_sweep need rank <= 128 (their R x R factorizations are held in one
+ *     workgroup's registers) and return CP_EUNSUPPORTED otherwise; the other calls take any rank.
  *
  * Precision
  *   - x_dtype must equal f_dtype and be CP_F64 or CP_F32. The tensor contraction (MTTKRP,

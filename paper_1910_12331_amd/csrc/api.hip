@@ -28,7 +28,7 @@ void launch_gn_apply(const Dims&, double*, const double*, const PerMode<void*>&,
                      const CgState*, hipStream_t);
 void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stats*, hipStream_t);
 void launch_status_out(const CgState*, int32_t*, hipStream_t);
-size_t spd_inv_lds(int);
+int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
                    hipStream_t);
 int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t);
@@ -67,11 +67,19 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->qc_last = (p->s[p->N - 1] + 15) / 16;
   p->qc_prev = (p->s[p->N - 2] + 15) / 16;
   int64_t part = p->qc_last * 16 * p->Rp;   // residual's packed last factor reuses this region
+  int64_t p1 = 0;
   for (int n = 0; n < p->N; ++n) {
-    int RT, SW, rpt;
-    mttkrp_splits(*p, n, &RT, &SW, &rpt);
-    const int64_t e = (int64_t)SW * RT * rpt * p->Rp;
-    part = e > part ? e : part;
+    for (int v = 0; v < 4; ++v) {   // geometry of every launch form (vector loads, tree)
+      const bool dt = v >= 2;
+      if (dt && !(n == 0 && p->N == 3)) continue;
+      const MttkrpGeom g = mttkrp_geom(*p, n, (v & 1) == 1, dt);
+      const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
+      part = e > part ? e : part;
+      if (dt) {
+        const int64_t e1 = g.RT * g.O * g.HS * p->Rp;
+        p1 = e1 > p1 ? e1 : p1;
+      }
+    }
   }
   p->part_elems = part;
   const int64_t RR = (int64_t)p->R * p->R;
@@ -86,6 +94,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_fpk_last = take((size_t)p->qc_last * p->NBt * 256 * p->esz);
   p->off_fpk_prev = take((size_t)p->qc_prev * p->NBt * 256 * p->esz);
   p->off_part = take((size_t)part * p->esz);
+  p->off_p1 = take((size_t)p1 * p->esz);
   p->off_m64 = take(vec);
   p->off_a64 = take(vec);
   p->off_s = take((size_t)p->N * RR * 8);
@@ -172,10 +181,16 @@ static void gradient_core(const Plan& p, const Dims& d, const void* X, const Ws&
                           const PerMode<void*>& cast_g, double* gsum_out, hipStream_t st) {
   launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
   launch_gamma(d, w.S, w.gam, st);
-  int64_t off = 0;
-  for (int n = 0; n < p.N; ++n) {
-    launch_mttkrp(p, X, n, w.base, w.m64 + off * p.R, nullptr, st);
-    off += p.s[n];
+  if (p.N == 3) {
+    // dimension tree: one pass over X gives M(0) and M(1), a second one M(2)
+    launch_mttkrp_pair01(p, X, w.base, w.m64, w.m64 + p.s[0] * p.R, st);
+    launch_mttkrp(p, X, 2, w.base, w.m64 + (p.s[0] + p.s[1]) * p.R, nullptr, st);
+  } else {
+    int64_t off = 0;
+    for (int n = 0; n < p.N; ++n) {
+      launch_mttkrp(p, X, n, w.base, w.m64 + off * p.R, nullptr, st);
+      off += p.s[n];
+    }
   }
   const int64_t RR = (int64_t)p.R * p.R;
   RowMM a{};
@@ -318,7 +333,7 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   if (!(prm->lambda >= 0.0) || !isfinite(prm->lambda) || !(prm->cg_tol >= 0.0) ||
       !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 || prm->flags != 0)
     return CP_EINVAL;
-  if (spd_inv_lds(p.R) > 160 * 1024) return CP_EUNSUPPORTED;
+  if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);
@@ -378,7 +393,7 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
   int rc = make_plan(prob, &p);
   if (rc) return rc;
   if (!X || !(lambda >= 0.0) || !isfinite(lambda)) return CP_EINVAL;
-  if (spd_inv_lds(p.R) > 160 * 1024) return CP_EUNSUPPORTED;
+  if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);

@@ -13,6 +13,7 @@ namespace cpgn {
 constexpr int kWave = 64;
 constexpr int kMaxOrder = CP_MAX_ORDER;
 constexpr int kRedSlots = 1024;   // max blocks contributing to one deterministic reduction
+constexpr int kNumCU = 256;       // compute units of an MI355X (8 XCDs x 32)
 
 // ------------------------------------------------------------------------------------------
 // Matrix-core traits. Lane l of a wavefront supplies A[l%16][l/16] and B[l/16][l%16] to a
@@ -54,7 +55,7 @@ struct Plan {
   int64_t qc_last = 0, qc_prev = 0;    // 16-row chunks of modes N-1 and N-2
   int64_t part_elems = 0;              // MTTKRP partial buffer (elements of compute precision)
   // byte offsets into the workspace
-  size_t off_apad = 0, off_fpk_last = 0, off_fpk_prev = 0, off_part = 0;
+  size_t off_apad = 0, off_fpk_last = 0, off_fpk_prev = 0, off_part = 0, off_p1 = 0;
   size_t off_m64 = 0, off_a64 = 0, off_s = 0, off_gam = 0, off_pinv = 0;
   size_t off_g = 0, off_v = 0, off_r = 0, off_z = 0, off_w = 0, off_q = 0;
   size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0;
@@ -110,6 +111,17 @@ int launch_prepare_factors(const Plan& p, const void* const* A, void* ws, hipStr
                            bool also_a64);
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64_out,
                   void* m_out_fdtype, hipStream_t st);
-int mttkrp_splits(const Plan& p, int mode, int* row_tiles, int* split_wgs, int* rows_per_tile);
+// Work decomposition of one MTTKRP launch (shared by the workspace plan and the launcher).
+struct MttkrpGeom {
+  int MB;                 // 16-row blocks per wavefront tile
+  int rows_per_tile;
+  int64_t RT;             // row tiles
+  int64_t SW;             // workgroups per row tile (4 wavefronts each split the items)
+  int64_t QC, O, nitems;  // inner chunks, outer indices, items = O * QC
+  int64_t HS;             // max wavefronts sharing one outer index within a row tile
+};
+MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt);
+int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
+                         hipStream_t st);
 
 }  // namespace cpgn

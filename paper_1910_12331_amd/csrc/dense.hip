@@ -347,77 +347,110 @@ __global__ void k_status_out(const CgState* st, int32_t* out) {
 // ------------------------------------------------------------------------------------------
 // P = (G + lambda I)^-1 for an R x R SPD matrix, one workgroup per matrix, in LDS:
 // right-looking Cholesky G + lambda I = L L^T in place (pivots must be positive), then L^-1
-// by forward elimination overwriting L column by column, then P = L^-T L^-1.
+// by forward elimination overwriting L, then P = L^-T L^-1. Both sweeps take one barrier per
+// column: the scaling of column (row) j is deferred to step j+1, where nothing reads it, and
+// the column the elimination needs next is copied one step ahead. The 256 threads sweep the
+// trailing triangle as a 16 x 16 grid.
 // A non-positive pivot records CP_ENOTSPD and marks the state done.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spd_inv(int R, const double* __restrict__ Gin,
+// P = (G + lambda I)^-1 for an R x R SPD matrix (R <= 128), one workgroup per matrix, FP64.
+// In-place Gauss-Jordan inversion without pivoting: for an SPD matrix its pivots are the
+// Cholesky pivots (the diagonals of the successive Schur complements), so "pivot > 0" is the
+// same positive-definiteness test, and R steps give the inverse directly. Thread (ty, tx) of
+// the 32 x 32 grid keeps the entries (ty + 32 ai, tx + 32 bk) of the identity-padded matrix in
+// registers; each step publishes the pivot row r and column c through double-buffered LDS (one
+// barrier), applies a_ik -= (c_i / p) r_k to every entry, and sets the pivot row to r / p, the
+// pivot column to -c / p and the pivot to 1 / p (the Gauss-Jordan update).
+// A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done.
+template <int NBK>
+__global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restrict__ Gin,
                                                  int64_t g_stride, double lambda,
                                                  double* __restrict__ Pout, int64_t p_stride,
                                                  int first_mode, CgState* st) {
-  extern __shared__ double sm[];
-  double* a = sm;               // R x R
-  double* tmp = sm + R * R;     // R
-  __shared__ int fail;
+  constexpr int RP = 32 * NBK;
+  __shared__ double colbuf[2][RP], rowbuf[2][RP];
   const int n = first_mode + blockIdx.x;
   const double* G = Gin + n * g_stride;
   double* P = Pout + n * p_stride;
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
   if (st->status != CP_OK) return;
-  if (t == 0) fail = 0;
-  for (int e = t; e < R * R; e += nt) a[e] = G[e] + ((e / R) == (e % R) ? lambda : 0.0);
-  __syncthreads();
-  // Cholesky, lower triangle.
+  double a[NBK][NBK];
+#pragma unroll
+  for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+    for (int bk = 0; bk < NBK; ++bk) {
+      const int i = ty + 32 * ai, k = tx + 32 * bk;
+      a[ai][bk] = (i < R && k < R) ? G[i * R + k] + (i == k ? lambda : 0.0) : (i == k ? 1.0 : 0.0);
+    }
   for (int j = 0; j < R; ++j) {
-    const double djj = a[j * R + j];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (t == 0) fail = 1;
-      break;
+    const int b = j & 1, jb = j >> 5, jt = j & 31;
+    if (ty == jt) {
+#pragma unroll
+      for (int ai = 0; ai < NBK; ++ai)
+        if (ai == jb) {
+#pragma unroll
+          for (int bk = 0; bk < NBK; ++bk) rowbuf[b][tx + 32 * bk] = a[ai][bk];
+        }
     }
-    const double ljj = sqrt(djj);
-    __syncthreads();
-    for (int i = j + 1 + t; i < R; i += nt) a[i * R + j] /= ljj;
-    if (t == 0) a[j * R + j] = ljj;
-    __syncthreads();
-    const int m = R - j - 1;
-    for (int e = t; e < m * m; e += nt) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) a[i * R + k] -= a[i * R + j] * a[k * R + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (fail) {
-    if (t == 0) {
-      st->status = CP_ENOTSPD;
-      st->done = 1;
-    }
-    return;
-  }
-  // In-place inverse of L: after step j, rows i > j hold e_i - sum_{k<=j} L[i][k] Linv[k][:].
-  for (int j = 0; j < R; ++j) {
-    const double inv = 1.0 / a[j * R + j];
-    __syncthreads();
-    for (int i = j + 1 + t; i < R; i += nt) tmp[i] = a[i * R + j];
-    for (int k = t; k < j; k += nt) a[j * R + k] *= inv;
-    __syncthreads();
-    if (t == 0) a[j * R + j] = inv;
-    __syncthreads();
-    const int m = R - j - 1, w = j + 1;
-    for (int e = t; e < m * w; e += nt) {
-      const int i = j + 1 + e / w, k = e % w;
-      const double cur = (k == j) ? 0.0 : a[i * R + k];
-      a[i * R + k] = cur - tmp[i] * a[j * R + k];
+    if (tx == jt) {
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk)
+        if (bk == jb) {
+#pragma unroll
+          for (int ai = 0; ai < NBK; ++ai) colbuf[b][ty + 32 * ai] = a[ai][bk];
+        }
     }
     __syncthreads();
+    const double piv = rowbuf[b][j];
+    if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
+      if (t == 0) {
+        st->status = CP_ENOTSPD;
+        st->done = 1;
+      }
+      return;
+    }
+    const double rp = 1.0 / piv;
+    double u[NBK], v[NBK];
+#pragma unroll
+    for (int q = 0; q < NBK; ++q) {
+      u[q] = colbuf[b][ty + 32 * q] * rp;
+      v[q] = rowbuf[b][tx + 32 * q];
+    }
+    // One FMA per entry; it leaves 0 in the pivot row and column, which their owners then set
+    // to r_k / p, -c_i / p and 1 / p.
+#pragma unroll
+    for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk) a[ai][bk] -= u[ai] * v[bk];
+    if (ty == jt) {
+#pragma unroll
+      for (int ai = 0; ai < NBK; ++ai)
+        if (ai == jb) {
+#pragma unroll
+          for (int bk = 0; bk < NBK; ++bk) a[ai][bk] = v[bk] * rp;
+        }
+    }
+    if (tx == jt) {
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk)
+        if (bk == jb) {
+#pragma unroll
+          for (int ai = 0; ai < NBK; ++ai) a[ai][bk] = -u[ai];
+        }
+    }
+    if (ty == jt && tx == jt) {
+#pragma unroll
+      for (int q = 0; q < NBK; ++q)
+        if (q == jb) a[q][q] = rp;
+    }
   }
-  // P = Linv^T Linv: P[i][c] = sum_{k >= max(i,c)} Linv[k][i] Linv[k][c].
-  for (int e = t; e < R * R; e += nt) {
-    const int i = e / R, c = e % R;
-    const int k0 = i > c ? i : c;
-    double s = 0.0;
-    for (int k = k0; k < R; ++k) s += a[k * R + i] * a[k * R + c];
-    P[e] = s;
-  }
+#pragma unroll
+  for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+    for (int bk = 0; bk < NBK; ++bk) {
+      const int i = ty + 32 * ai, k = tx + 32 * bk;
+      if (i < R && k < R) P[i * R + k] = a[ai][bk];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -692,19 +725,22 @@ void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, st, out);
 }
 
-size_t spd_inv_lds(int R) { return ((size_t)R * R + R) * sizeof(double); }
+// GN and ALS need R <= 128 (the inverse is register-resident in one workgroup).
+int spd_inv_supported(int R) { return R >= 1 && R <= 128; }
 
 int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
                    int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s) {
-  const size_t lds = spd_inv_lds(R);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_spd_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr_set = true;
+  const int nbk = (R + 31) / 32;
+  switch (nbk) {
+#define CPGN_SPD(k)                                                                          \
+  case k:                                                                                    \
+    hipLaunchKernelGGL((k_spd_inv<k>), dim3(count), dim3(1024), 0, s, R, G, g_stride, lambda, \
+                       P, p_stride, first_mode, st);                                         \
+    break;
+    CPGN_SPD(1) CPGN_SPD(2) CPGN_SPD(3) CPGN_SPD(4)
+#undef CPGN_SPD
+    default: return (int)hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_spd_inv, dim3(count), dim3(256), lds, s, R, G, g_stride, lambda, P,
-                     p_stride, first_mode, st);
   return (int)hipGetLastError();
 }
 
@@ -732,7 +768,7 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
                        s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part));
     const int64_t tiles = (a.O + 16 * MB - 1) / (16 * MB);
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > kRedSlots) blocks = kRedSlots;
+    if (blocks > 2 * kNumCU) blocks = 2 * kNumCU;   // one resident round of workgroups
     switch (p.NBt) {
 #define CPGN_RES(k) \
   case k: hipLaunchKernelGGL((k_residual<T, k>), dim3(blocks), dim3(256), 0, s, a); break;

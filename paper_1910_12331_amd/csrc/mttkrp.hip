@@ -21,21 +21,21 @@
 
 namespace cpgn {
 
-template <typename T> struct MttkrpCfg;
-template <> struct MttkrpCfg<float> { static constexpr int MB = 4; };   // 64 output rows
-template <> struct MttkrpCfg<double> { static constexpr int MB = 2; };  // 32 output rows
 
 struct MttkrpArgs {
   const void* X;
   const void* apad[kMaxOrder];  // padded factors [s_m][Rp], compute precision
   const void* fpk;              // packed inner factor [QC][NBt][64 lanes][4]
+  const void* wfac;             // padded factor of the output mode (dimension-tree weights)
+  void* p1;                     // dimension-tree partials [RT][O][HS][Rp]
   void* part;                   // partial tiles [split_wgs][Jpad][Rp]
-  int64_t J, Jpad, s_in, QC, nitems, Rr, nbo;
+  int64_t J, Jpad, s_in, QC, nitems, Rr, nbo, O, HS;
   int64_t outer_size[kMaxOrder];
   int outer_mode[kMaxOrder];
   int n_outer;
   int Rp, NBt, cb0;
   int nsplit;                   // wavefronts along the contraction split (= 4 * gridDim.x)
+  int dt;                       // also emit the outer mode's MTTKRP partials (order 3)
 };
 
 template <typename T, int MB> struct VecLoad;
@@ -46,12 +46,119 @@ template <> struct VecLoad<double, 2> {
   typedef double v __attribute__((ext_vector_type(2)));
 };
 
-template <typename T, bool CASE_B, int NB, bool VEC>
-__global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
-  constexpr int MB = MttkrpCfg<T>::MB;
+
+// X fragments of one item. Case A: one 4-vector per 16-row block (4 contraction substeps);
+// case B: MB consecutive output rows per contraction substep.
+template <typename T, bool CASE_B, int MB> struct XFrag;
+template <typename T, int MB> struct XFrag<T, false, MB> {
+  struct type { typename Mfma<T>::v4 v[MB]; };
+  static __device__ __forceinline__ T get(const type& x, int mb, int t) { return x.v[mb][t]; }
+};
+template <typename T, int MB> struct XFrag<T, true, MB> {
+  struct type { T v[4][MB]; };
+  static __device__ __forceinline__ T get(const type& x, int mb, int t) { return x.v[t][mb]; }
+};
+
+template <bool CASE_B>
+__device__ __forceinline__ int64_t outer_base(const MttkrpArgs& a, int64_t o) {
+  if (CASE_B) return o * a.s_in * a.J;
+  const int64_t aa = o / a.nbo, bo = o - aa * a.nbo;
+  return aa * a.J * a.Rr + bo * a.s_in;
+}
+
+// Khatri-Rao row of the outer modes at outer index o, for this lane's columns.
+template <typename T, int NB>
+__device__ __forceinline__ void outer_row(const MttkrpArgs& a, int64_t o, int m, T (&kro)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) kro[nb] = T(1);
+  int64_t rem = o;
+  for (int d = a.n_outer - 1; d >= 0; --d) {
+    const int64_t sz = a.outer_size[d];
+    const int64_t idx = rem % sz;
+    rem /= sz;
+    const T* row = (const T*)a.apad[a.outer_mode[d]] + idx * a.Rp + 16 * a.cb0 + m;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) kro[nb] *= row[16 * nb];
+  }
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void load_f(const typename Mfma<T>::v4* __restrict__ F,
+                                       const MttkrpArgs& a, int64_t chunk, int lane,
+                                       typename Mfma<T>::v4 (&f)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) f[nb] = F[(chunk * a.NBt + a.cb0 + nb) * kWave + lane];
+}
+
+// Branch-free loads (out-of-range lanes read a clamped in-bounds address and select 0), so
+// the compiler can keep several items' loads in flight across the MFMA sequence.
+template <typename T, bool CASE_B, int MB, bool VEC>
+__device__ __forceinline__ void load_x(const T* __restrict__ X, const MttkrpArgs& a, int64_t base,
+                                       int64_t chunk, int64_t j0, int g, int m,
+                                       typename XFrag<T, CASE_B, MB>::type& x) {
   typedef typename Mfma<T>::v4 v4;
+  const int64_t in0 = chunk * 16 + 4 * g;
+  if constexpr (!CASE_B) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t j = j0 + 16 * mb + m;
+      if constexpr (VEC) {
+        const bool ok = j < a.J && in0 < a.s_in;
+        const v4 w = *(const v4*)(X + (ok ? base + j * a.Rr + in0 : 0));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x.v[mb][t] = ok ? w[t] : T(0);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bool ok = j < a.J && in0 + t < a.s_in;
+          const T w = X[ok ? base + j * a.Rr + in0 + t : 0];
+          x.v[mb][t] = ok ? w : T(0);
+        }
+      }
+    }
+  } else {
+    const int64_t jb = j0 + MB * m;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t inn = in0 + t;
+      if constexpr (VEC) {
+        typedef typename VecLoad<T, MB>::v vv;
+        const bool ok = inn < a.s_in && jb < a.J;
+        const vv w = *(const vv*)(X + (ok ? base + inn * a.J + jb : 0));
+#pragma unroll
+        for (int v = 0; v < MB; ++v) x.v[t][v] = ok ? w[v] : T(0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < MB; ++v) {
+          const bool ok = inn < a.s_in && jb + v < a.J;
+          const T w = X[ok ? base + inn * a.J + jb + v : 0];
+          x.v[t][v] = ok ? w : T(0);
+        }
+      }
+    }
+  }
+}
+
+// Loads of one item: packed inner factor and X fragment.
+template <typename T, bool CASE_B, int MB, int NB> struct ItemBuf {
+  typename Mfma<T>::v4 f[NB];
+  typename XFrag<T, CASE_B, MB>::type x;
+};
+
+// Split index (within a row tile) of the wavefront that owns item t: largest w with
+// floor(nitems * w / S) <= t.
+__host__ __device__ __forceinline__ int64_t owner_split(int64_t t, int64_t nitems, int64_t S) {
+  return ((t + 1) * S - 1) / nitems;
+}
+
+template <typename T, bool CASE_B, int MB, int NB, bool VEC, bool DT>
+__device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
+  // FP64 with many column blocks keeps a single F buffer (registers); F is L2-resident.
+  constexpr bool PF = sizeof(T) == 4 || NB <= 4;
+  typedef typename Mfma<T>::v4 v4;
+  typedef ItemBuf<T, CASE_B, MB, NB> Buf;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, m = lane & 15;
   const int split = blockIdx.x * 4 + wave;
   const int64_t j0 = (int64_t)blockIdx.y * 16 * MB;
@@ -60,86 +167,143 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
   const T* __restrict__ X = (const T*)a.X;
   const v4* __restrict__ F = (const v4*)a.fpk;
 
+  // acc: this wavefront's share of M(n).
+  // Plain form: the B operand is the packed inner factor times the outer Khatri-Rao row kro of
+  //   the current outer index (kept in registers, refreshed when the index changes).
+  // Dimension-tree form (DT): tacc accumulates T = X x_q A(q) for one outer index o; when o
+  //   changes it is folded into acc with kro and, weighted by A(n), summed over the rows into
+  //   the outer mode's partial M(o).
   v4 acc[MB][NB];
+  v4 tacc[DT ? MB : 1][DT ? NB : 1];
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[i][nb] = v4{0, 0, 0, 0};
-
+  if constexpr (DT) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) tacc[i][nb] = v4{0, 0, 0, 0};
+  }
   T kro[NB];
-  int64_t o_cur = -1, base = 0;
-  for (int64_t it = it0; it < it1; ++it) {
-    const int64_t o = it / a.QC;
-    const int64_t chunk = it - o * a.QC;
-    if (o != o_cur) {
-      o_cur = o;
+
+  // Two item buffers in ping-pong: the loads of the next item are in flight while the MFMAs of
+  // the current one run, and no register copy forces them to complete early.
+  auto issue = [&](Buf& b, int64_t chunk, int64_t base) {
+    if constexpr (PF) load_f<T, NB>(F, a, chunk, lane, b.f);
+    load_x<T, CASE_B, MB, VEC>(X, a, base, chunk, j0, g, m, b.x);
+  };
+  auto consume = [&](Buf& b, int64_t chunk) {
+    if constexpr (!PF) load_f<T, NB>(F, a, chunk, lane, b.f);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) kro[nb] = T(1);
-      int64_t rem = o;
-      for (int d = a.n_outer - 1; d >= 0; --d) {
-        const int64_t sz = a.outer_size[d];
-        const int64_t idx = rem % sz;
-        rem /= sz;
-        const T* row = (const T*)a.apad[a.outer_mode[d]] + idx * a.Rp + 16 * a.cb0 + m;
+    for (int t = 0; t < 4; ++t) {
+      T bt[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) kro[nb] *= row[16 * nb];
-      }
-      if (!CASE_B) {
-        const int64_t aa = o / a.nbo, bo = o - aa * a.nbo;
-        base = aa * a.J * a.Rr + bo * a.s_in;
-      } else {
-        base = o * a.s_in * a.J;
-      }
-    }
-    T b[4][NB];
+      for (int nb = 0; nb < NB; ++nb) bt[nb] = DT ? b.f[nb][t] : b.f[nb][t] * kro[nb];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const v4 f = F[(chunk * a.NBt + a.cb0 + nb) * kWave + lane];
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) b[t][nb] = f[t] * kro[nb];
-    }
-    const int64_t in0 = chunk * 16 + 4 * g;
-    if (!CASE_B) {
-      v4 xv[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int64_t j = j0 + 16 * mb + m;
-        const T* p = X + base + j * a.Rr + in0;
-        if (VEC) {
-          xv[mb] = (j < a.J && in0 < a.s_in) ? *(const v4*)p : v4{0, 0, 0, 0};
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) xv[mb][t] = (j < a.J && in0 + t < a.s_in) ? p[t] : T(0);
+        for (int nb = 0; nb < NB; ++nb) {
+          const T x = XFrag<T, CASE_B, MB>::get(b.x, mb, t);
+          if constexpr (DT) tacc[mb][nb] = Mfma<T>::mac(x, bt[nb], tacc[mb][nb]);
+          else acc[mb][nb] = Mfma<T>::mac(x, bt[nb], acc[mb][nb]);
         }
-      }
+    }
+  };
+  // Output row held by element v of block mb in this lane.
+  auto row_of = [&](int mb, int v) -> int64_t {
+    const int i = Mfma<T>::out_row(lane, v);
+    return CASE_B ? j0 + (int64_t)MB * i + mb : j0 + 16 * mb + i;
+  };
+  // DT: fold tacc of outer index o into acc and into the outer mode's partial.
+  auto flush = [&](int64_t o) {
+    if constexpr (DT) {
+      const T* W = (const T*)a.wfac + 16 * a.cb0 + m;
+      const int64_t h = split - owner_split(o * a.QC, a.nitems, a.nsplit);
+      T* P1 = (T*)a.p1 + ((((int64_t)blockIdx.y * a.O + o) * a.HS + h) * a.Rp) + 16 * a.cb0 + m;
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int nb = 0; nb < NB; ++nb) {
+        T sum = T(0);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = Mfma<T>::mac(xv[mb][t], b[t][nb], acc[mb][nb]);
-    } else {
-      const int64_t jb = j0 + MB * m;
+          for (int v = 0; v < 4; ++v) {
+            const int64_t row = row_of(mb, v);
+            const T w = W[(row < a.J ? row : 0) * a.Rp + 16 * nb];
+            const T tv = tacc[mb][nb][v];
+            sum += tv * (row < a.J ? w : T(0));
+            acc[mb][nb][v] += tv * kro[nb];
+          }
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+        if (g == 0) P1[16 * nb] = sum;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t inn = in0 + t;
-        const T* p = X + base + inn * a.J + jb;
-        T xv[MB];
-        if (VEC) {
-          typedef typename VecLoad<T, MB>::v vv;
-          vv w = (inn < a.s_in && jb < a.J) ? *(const vv*)p : vv{};
-#pragma unroll
-          for (int v = 0; v < MB; ++v) xv[v] = w[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < MB; ++v) xv[v] = (inn < a.s_in && jb + v < a.J) ? p[v] : T(0);
-        }
-#pragma unroll
-        for (int v = 0; v < MB; ++v)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[v][nb] = Mfma<T>::mac(xv[v], b[t][nb], acc[v][nb]);
+        for (int mb = 0; mb < MB; ++mb) tacc[mb][nb] = v4{0, 0, 0, 0};
       }
     }
+  };
+
+  // Item position (outer index o, inner chunk, X offset of (o, chunk 0)), advanced without
+  // divisions so that the loop body has no branches besides its own back-edge and the rare,
+  // uniform flush.
+  struct Pos {
+    int64_t o, chunk, bo, base;
+  };
+  auto advance = [&](Pos q) {
+    q.chunk += 1;
+    const bool wrap = q.chunk == a.QC;
+    q.chunk = wrap ? 0 : q.chunk;
+    q.o += wrap ? 1 : 0;
+    if constexpr (CASE_B) {
+      q.base += wrap ? a.s_in * a.J : 0;
+    } else {
+      q.bo += wrap ? 1 : 0;
+      q.base += wrap ? a.s_in : 0;
+      const bool carry = q.bo == a.nbo;
+      q.bo = carry ? 0 : q.bo;
+      q.base += carry ? (a.J - 1) * a.Rr : 0;
+    }
+    return q;
+  };
+
+  Buf b0, b1;
+  Pos p0{0, 0, 0, 0};
+  if (it0 < it1) {
+    p0.o = it0 / a.QC;
+    p0.chunk = it0 - p0.o * a.QC;
+    if constexpr (CASE_B) {
+      p0.base = p0.o * a.s_in * a.J;
+    } else {
+      const int64_t aa = p0.o / a.nbo;
+      p0.bo = p0.o - aa * a.nbo;
+      p0.base = aa * a.J * a.Rr + p0.bo * a.s_in;
+    }
+    outer_row<T, NB>(a, p0.o, m, kro);
+    issue(b0, p0.chunk, p0.base);
+  }
+  // The item after the last one is replaced by the last one (a harmless re-load), so every
+  // iteration issues the same loads; the outer-index change is a rare, uniform branch.
+  for (int64_t it = it0; it < it1; it += 2) {
+    Pos p1 = advance(p0);
+    const bool last0 = it + 1 >= it1;
+    if (last0) p1 = p0;
+    issue(b1, p1.chunk, p1.base);
+    consume(b0, p0.chunk);
+    if (last0 || p1.o != p0.o) {
+      flush(p0.o);
+      if (!last0) outer_row<T, NB>(a, p1.o, m, kro);
+    }
+    if (last0) break;
+    Pos p2 = advance(p1);
+    const bool last1 = it + 2 >= it1;
+    if (last1) p2 = p1;
+    issue(b0, p2.chunk, p2.base);
+    consume(b1, p1.chunk);
+    if (last1 || p2.o != p1.o) {
+      flush(p1.o);
+      if (!last1) outer_row<T, NB>(a, p2.o, m, kro);
+    }
+    p0 = p2;
   }
 
   // Fixed-order sum of the four wavefronts: (w0 + w2) + (w1 + w3).
@@ -183,24 +347,45 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
   }
 }
 
-// M[j, r] = sum over partial tiles, in FP64, fixed order. Writes the FP64 result and/or a copy
-// in the caller's precision.
+// Plain form: one accumulator set, two wavefronts per SIMD. Dimension-tree form: two
+// accumulator sets, one wavefront per SIMD.
+template <typename T, bool CASE_B, int MB, int NB, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
+  mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a);
+}
+
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256, 1) void k_mttkrp_tree(MttkrpArgs a) {
+  mttkrp_body<T, false, MB, NB, true, true>(a);
+}
+
+// M[j, r] = sum over partial tiles, in FP64, fixed order: lane q of an 8-lane group adds the
+// tiles p = q, q+8, q+16, ... and the 8 lane sums are combined in a fixed butterfly.
+// Writes the FP64 result and/or a copy in the caller's precision.
 template <typename T>
-__global__ void k_mttkrp_reduce(const T* __restrict__ part, int nparts, int64_t Jpad, int Rp,
-                                int64_t J, int R, double* __restrict__ m64, void* mout,
-                                int mout_dtype) {
+__global__ __launch_bounds__(256) void k_mttkrp_reduce(const T* __restrict__ part, int nparts,
+                                                       int64_t Jpad, int Rp, int64_t J, int R,
+                                                       double* __restrict__ m64, void* mout,
+                                                       int mout_dtype) {
+  const int q = threadIdx.x & 7;
   const int64_t n = J * R;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t idx = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 3; idx < n;
+       idx += ((int64_t)gridDim.x * blockDim.x) >> 3) {
     const int64_t j = idx / R;
     const int r = (int)(idx - j * R);
-    double s = 0.0;
     const T* p = part + j * Rp + r;
-    for (int q = 0; q < nparts; ++q) s += (double)p[(int64_t)q * Jpad * Rp];
-    if (m64) m64[idx] = s;
-    if (mout) {
-      if (mout_dtype == CP_F64) ((double*)mout)[idx] = s;
-      else ((float*)mout)[idx] = (float)s;
+    const int64_t stride = Jpad * Rp;
+    double s = 0.0;
+    for (int k = q; k < nparts; k += 8) s += (double)p[(int64_t)k * stride];
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (q == 0) {
+      if (m64) m64[idx] = s;
+      if (mout) {
+        if (mout_dtype == CP_F64) ((double*)mout)[idx] = s;
+        else ((float*)mout)[idx] = (float)s;
+      }
     }
   }
 }
@@ -268,33 +453,50 @@ static int grid_for(int64_t n, int block = 256, int cap = 8192) {
   return (int)g;
 }
 
-int mttkrp_splits(const Plan& p, int mode, int* row_tiles, int* split_wgs, int* rows_per_tile) {
-  const int MB = p.dtype == CP_F32 ? MttkrpCfg<float>::MB : MttkrpCfg<double>::MB;
-  const int rpt = 16 * MB;
-  const int64_t J = p.s[mode];
-  const int64_t RT = (J + rpt - 1) / rpt;
-  const int CG = (p.NBt + 7) / 8;
+MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
+  MttkrpGeom g{};
   const bool caseB = mode == p.N - 1;
   const int q = caseB ? p.N - 2 : p.N - 1;
-  const int64_t QC = (p.s[q] + 15) / 16;
-  const int64_t nitems = (p.total / J / p.s[q]) * QC;
-  // aim for about two wavefronts per SIMD on 256 CUs, each with a handful of items
-  int64_t sw = (2048 + 4 * RT * CG - 1) / (4 * RT * CG);
-  const int64_t max_sw = (nitems + 7) / 8;
+  const int64_t J = p.s[mode];
+  g.MB = p.dtype == CP_F64 ? 2 : 4;
+  (void)vec_ok;
+  g.rows_per_tile = 16 * g.MB;
+  g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
+  g.QC = (p.s[q] + 15) / 16;
+  g.O = p.total / J / p.s[q];
+  g.nitems = g.O * g.QC;
+  // One resident round of 4-wave workgroups: two per CU for the plain form (<= 256 registers
+  // per lane), one per CU for the dimension-tree form (two accumulator sets).
+  const int64_t wgs = (int64_t)kNumCU * (dt ? 1 : 2);
+  int64_t sw = wgs / g.RT;
+  const int64_t max_sw = (g.nitems + 7) / 8;
   if (sw > max_sw) sw = max_sw;
   if (sw > kRedSlots) sw = kRedSlots;
   if (sw < 1) sw = 1;
-  *row_tiles = (int)RT;
-  *split_wgs = (int)sw;
-  *rows_per_tile = rpt;
-  return 0;
+  g.SW = sw;
+  const int64_t S = 4 * sw;
+  g.HS = (g.QC * S + g.nitems - 1) / g.nitems + 1;
+  return g;
 }
 
-template <typename T, bool CASE_B, bool VEC>
+template <typename T, bool CASE_B, int MB, bool VEC>
 static void launch_nb(int NB, dim3 grid, hipStream_t st, const MttkrpArgs& a) {
   switch (NB) {
-#define CPGN_NB(k) \
-  case k: hipLaunchKernelGGL((k_mttkrp<T, CASE_B, k, VEC>), grid, dim3(256), 0, st, a); break;
+#define CPGN_NB(k)                                                                         \
+  case k:                                                                                  \
+    hipLaunchKernelGGL((k_mttkrp<T, CASE_B, MB, k, VEC>), grid, dim3(256), 0, st, a); \
+    break;
+    CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4) CPGN_NB(5) CPGN_NB(6) CPGN_NB(7) CPGN_NB(8)
+#undef CPGN_NB
+    default: break;
+  }
+}
+
+template <typename T, int MB>
+static void launch_tree_nb(int NB, dim3 grid, hipStream_t st, const MttkrpArgs& a) {
+  switch (NB) {
+#define CPGN_NB(k)                                                                      \
+  case k: hipLaunchKernelGGL((k_mttkrp_tree<T, MB, k>), grid, dim3(256), 0, st, a); break;
     CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4) CPGN_NB(5) CPGN_NB(6) CPGN_NB(7) CPGN_NB(8)
 #undef CPGN_NB
     default: break;
@@ -302,11 +504,66 @@ static void launch_nb(int NB, dim3 grid, hipStream_t st, const MttkrpArgs& a) {
 }
 
 template <typename T>
+static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipStream_t st,
+                           const MttkrpArgs& a) {
+  if (a.dt) {   // order-3 dimension tree: mode 0 with vector loads only
+    launch_tree_nb<T, sizeof(T) == 8 ? 2 : 4>(NB, grid, st, a);
+    return;
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (caseB) {
+      if (vec) launch_nb<T, true, 2, true>(NB, grid, st, a);
+      else launch_nb<T, true, 2, false>(NB, grid, st, a);
+    } else {
+      if (vec) launch_nb<T, false, 2, true>(NB, grid, st, a);
+      else launch_nb<T, false, 2, false>(NB, grid, st, a);
+    }
+  } else {
+    if (caseB) {
+      if (vec) launch_nb<T, true, 4, true>(NB, grid, st, a);
+      else launch_nb<T, true, 4, false>(NB, grid, st, a);
+    } else if (!vec) {
+      launch_nb<T, false, 4, false>(NB, grid, st, a);
+    } else {
+      launch_nb<T, false, 4, true>(NB, grid, st, a);
+    }
+  }
+}
+
+// M(o)[o][r] = sum over row tiles and over the wavefronts that shared o (fixed order).
+template <typename T>
+__global__ void k_dt_reduce(const T* __restrict__ p1, int64_t RT, int64_t O, int64_t HS, int Rp,
+                            int R, int64_t QC, int64_t nitems, int64_t S, double* __restrict__ m64,
+                            void* mout, int mout_dtype) {
+  const int64_t n = O * R;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = idx / R;
+    const int r = (int)(idx - o * R);
+    const int64_t h_n = owner_split((o + 1) * QC - 1, nitems, S) - owner_split(o * QC, nitems, S) + 1;
+    double s = 0.0;
+    for (int64_t rt = 0; rt < RT; ++rt)
+      for (int64_t h = 0; h < h_n; ++h) s += (double)p1[((rt * O + o) * HS + h) * Rp + r];
+    if (m64) m64[idx] = s;
+    if (mout) {
+      if (mout_dtype == CP_F64) ((double*)mout)[idx] = s;
+      else ((float*)mout)[idx] = (float)s;
+    }
+  }
+}
+
+static bool vec_ok(const Plan& p, int mode, const void* X) {
+  const bool caseB = mode == p.N - 1;
+  const int q = caseB ? p.N - 2 : p.N - 1;
+  const int vw = p.dtype == CP_F64 ? 2 : 4;
+  return ((uintptr_t)X % 16) == 0 && (caseB ? (p.s[mode] % vw == 0) : (p.s[q] % 4 == 0));
+}
+
+template <typename T>
 static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, double* m64,
-                           void* mout, hipStream_t st) {
-  constexpr int MB = MttkrpCfg<T>::MB;
-  int RT, SW, rpt;
-  mttkrp_splits(p, mode, &RT, &SW, &rpt);
+                           void* mout, bool dt, double* m64_outer, hipStream_t st) {
+  const bool vec = vec_ok(p, mode, X);
+  const MttkrpGeom G = mttkrp_geom(p, mode, vec, dt);
   const bool caseB = mode == p.N - 1;
   const int q = caseB ? p.N - 2 : p.N - 1;
   MttkrpArgs a{};
@@ -318,11 +575,15 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   }
   a.fpk = ws + (caseB ? p.off_fpk_prev : p.off_fpk_last);
   a.part = ws + p.off_part;
+  a.wfac = a.apad[mode];
+  a.p1 = ws + p.off_p1;
   a.J = p.s[mode];
-  a.Jpad = (int64_t)RT * rpt;
+  a.Jpad = G.RT * G.rows_per_tile;
   a.s_in = p.s[q];
-  a.QC = (p.s[q] + 15) / 16;
-  a.nitems = (p.total / a.J / a.s_in) * a.QC;
+  a.QC = G.QC;
+  a.nitems = G.nitems;
+  a.O = G.O;
+  a.HS = G.HS;
   a.Rr = 1;
   for (int m = mode + 1; m < p.N; ++m) a.Rr *= p.s[m];
   a.nbo = caseB ? 1 : a.Rr / a.s_in;
@@ -335,30 +596,39 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   }
   a.Rp = p.Rp;
   a.NBt = p.NBt;
-  a.nsplit = 4 * SW;
-  const bool aligned = ((uintptr_t)X % 16) == 0;
-  const bool vec = aligned && (caseB ? (a.J % MB == 0) : (a.s_in % 4 == 0));
+  a.nsplit = (int)(4 * G.SW);
+  a.dt = dt ? 1 : 0;
   for (int cb0 = 0; cb0 < p.NBt; cb0 += 8) {
     const int NB = p.NBt - cb0 < 8 ? p.NBt - cb0 : 8;
     a.cb0 = cb0;
-    dim3 grid(SW, RT);
-    if (caseB) {
-      if (vec) launch_nb<T, true, true>(NB, grid, st, a);
-      else launch_nb<T, true, false>(NB, grid, st, a);
-    } else {
-      if (vec) launch_nb<T, false, true>(NB, grid, st, a);
-      else launch_nb<T, false, false>(NB, grid, st, a);
-    }
+    launch_variant<T>(caseB, vec, G.MB, NB, dim3((unsigned)G.SW, (unsigned)G.RT), st, a);
   }
-  hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(grid_for(a.J * p.R)), dim3(256), 0, st,
-                     (const T*)a.part, SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);
+  hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(grid_for(8 * a.J * p.R)), dim3(256), 0, st,
+                     (const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);
+  if (dt)
+    hipLaunchKernelGGL(k_dt_reduce<T>, dim3(grid_for(G.O * p.R)), dim3(256), 0, st,
+                       (const T*)a.p1, G.RT, G.O, G.HS, p.Rp, p.R, G.QC, G.nitems,
+                       (int64_t)a.nsplit, m64_outer, nullptr, p.dtype);
   return (int)hipGetLastError();
 }
 
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
                   hipStream_t st) {
-  if (p.dtype == CP_F32) return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, st);
-  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, st);
+  if (p.dtype == CP_F32)
+    return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
+  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
+}
+
+// Order 3, one pass over X: M(0) and, through the dimension tree, M(1) (FP64 outputs).
+int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
+                         hipStream_t st) {
+  if (p.N != 3 || !vec_ok(p, 0, X)) {
+    const int rc = launch_mttkrp(p, X, 0, ws, m64_0, nullptr, st);
+    return rc ? rc : launch_mttkrp(p, X, 1, ws, m64_1, nullptr, st);
+  }
+  if (p.dtype == CP_F32)
+    return launch_mttkrp_t<float>(p, X, 0, (char*)ws, m64_0, nullptr, true, m64_1, st);
+  return launch_mttkrp_t<double>(p, X, 0, (char*)ws, m64_0, nullptr, true, m64_1, st);
 }
 
 // Source factors may be the caller's buffers (compute precision) or FP64 copies.
