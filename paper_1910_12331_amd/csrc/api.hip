@@ -36,6 +36,11 @@ int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
 void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
                                    const double*, double*, hipStream_t);
 int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipStream_t, bool);
+size_t cg_slot_bytes(const Plan&);
+int cg_supported(const Plan&);
+int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
+              double*, double*, double*, double*, double*, double*, void*, CgState*, double, int,
+              hipStream_t);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 
@@ -110,6 +115,8 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_y = take((size_t)p->N * RR * 8);
   p->off_red = take((size_t)2 * p->N * kRedSlots * 8);
   p->off_state = take(sizeof(CgState));
+  p->off_w1 = take(vec);
+  p->off_slots = take(cg_slot_bytes(*p));
   p->bytes = off;
   return CP_OK;
 }
@@ -347,6 +354,17 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
   // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
   launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st);
+  if (cg_supported(p)) {
+    // CG: three fused launches per iteration (cp. pcg.hip)
+    launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, w.z, w.w, (double*)(w.base + p.off_w1), w.q,
+              w.bp, w.base + p.off_slots, w.st, prm->lambda, prm->cg_maxiter, st);
+    PerMode<void*> aout{};
+    for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
+    launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
+    launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
+    return hip_status();
+  }
+  // Ranks whose R x R tiles do not fit the fused kernels' LDS: one launch per vector operation.
   // CG initialisation: V = 0, R = -G (written by the gradient), Z = R P_inv, W = Z.
   launch_fill(cnt, w.v, 0.0, st);
   {

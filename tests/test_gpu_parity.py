@@ -203,9 +203,11 @@ def test_gn_step_past_cg_rounding_floor_fp64():
     gn_compare(p, torch.float64, 1e-4, 0.0, 20, "sensitivity")
 
 
+# R = 128 takes the per-operation CG kernels (its R x R tiles exceed the fused kernels' LDS).
 @pytest.mark.parametrize("dims,rank,lam", [((40, 40, 40), 5, 1e-4), ((23, 18, 31), 6, 1e-2),
                                            ((9, 7, 8, 6), 3, 1e-3), ((11, 13), 4, 1e-3),
-                                           ((60, 50, 40), 20, 1e-4)])
+                                           ((60, 50, 40), 20, 1e-4), ((130, 120, 110), 100, 1e-2),
+                                           ((150, 140, 136), 128, 1e-2)])
 def test_gn_step_cg_tolerance_fp64(dims, rank, lam):
     p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-3)
     gn_compare(p, torch.float64, lam, 1e-3, 50, 1e-11)
