@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run each single-mode MTTKRP and one device copy of X of known size "
+                         "(the workload the rocprofv3 counter runs are taken on), then exit")
     return ap.parse_args()
 
 
@@ -70,6 +73,50 @@ def event_time(fn, reps, stream):
     return start.elapsed_time(end) / 1e3 / reps
 
 
+def event_samples(fn, reps, stream):
+    """Per-call durations (s) of fn(), each bracketed by its own pair of HIP events."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    ev[-1].synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(reps)]
+
+
+def mttkrp_times(P, Xd, A, reps, stream):
+    """Median and mean duration of one cp_mttkrp call per mode."""
+    import torch
+    ws = P.Workspace()
+    s, R = Xd.shape[0], A[0].shape[1]
+    out = {}
+    for n in range(Xd.dim()):
+        M = torch.empty((Xd.shape[n], R), dtype=Xd.dtype, device="cuda")
+        for _ in range(3):
+            P.mttkrp(Xd, A, n, out=M, ws=ws)
+        ts = event_samples(lambda: P.mttkrp(Xd, A, n, out=M, ws=ws), reps, stream)
+        out[n] = (float(np.median(ts)), float(np.mean(ts)))
+    return out
+
+
+# HBM traffic of the single-mode MTTKRP at 400^3 R=100 FP32, from two rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE) of `bench.py --profile-kernels`, each divided by what the same
+# counter reads for a device copy of X (256 MB read + 256 MB written), so 1.0 = exact bytes.
+# Valid only for the kernel source it was taken on.
+MTTKRP_TRAFFIC = {
+    "source_sha256": "e9076ae5a8e36ae6937711556dbb0d50b188d0de3edbf5e5d41f3d196da3c8fd",
+    "bytes_per_launch": 308262468,   # mean over the three modes of the main kernel
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1910_12331_amd", "csrc", "mttkrp.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -89,20 +136,37 @@ def main():
     X64, A0, Xd = make_inputs(s, R, np.float32)
     stream = torch.cuda.current_stream()
 
-    # ---- dominant kernel: single-mode MTTKRP (2 s^3 R flops per call), HIP events
     A = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
-    ws = P.Workspace()
-    outs = [torch.empty((s, R), dtype=torch.float32, device="cuda") for _ in range(3)]
-    mt = {}
-    for n in range(3):
-        for _ in range(3):
-            P.mttkrp(Xd, A, n, out=outs[n], ws=ws)
-        mt[n] = event_time(lambda: P.mttkrp(Xd, A, n, out=outs[n], ws=ws), args.mttkrp_reps, stream)
+    if args.profile_kernels:
+        ws = P.Workspace()
+        for n in range(3):
+            M = torch.empty((s, R), dtype=torch.float32, device="cuda")
+            for _ in range(3):
+                P.mttkrp(Xd, A, n, out=M, ws=ws)
+        Xc = Xd.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": f"3 x cp_mttkrp per mode, {s}^3 R={R} FP32; one copy of "
+                                             f"{Xd.numel() * 4} bytes"}), flush=True)
+        del Xc
+        return
+
+    # ---- dominant kernel: single-mode MTTKRP (2 s^3 R flops per call), HIP events
     flops = 2.0 * s ** 3 * R
+    mt32 = mttkrp_times(P, Xd, A, args.mttkrp_reps, stream)
+    mt = {n: v[0] for n, v in mt32.items()}
     mt_tf = {n: flops / t / 1e12 for n, t in mt.items()}
-    mean_t = sum(mt.values()) / 3
-    log(f"[bench] MTTKRP per-mode ms {[round(t * 1e3, 4) for t in mt.values()]}, "
+    mean_t = sum(v[1] for v in mt32.values()) / 3
+    log(f"[bench] MTTKRP FP32 per-mode median ms {[round(t * 1e3, 4) for t in mt.values()]}, "
         f"TFLOP/s {[round(v, 1) for v in mt_tf.values()]}")
+    X64d = torch.from_numpy(X64).cuda()
+    A64m = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
+    mt64 = mttkrp_times(P, X64d, A64m, args.mttkrp_reps, stream)
+    del X64d, A64m
+    log(f"[bench] MTTKRP FP64 per-mode median ms {[round(v[0] * 1e3, 4) for v in mt64.values()]}")
+
+    # launch floor: an event-timed one-element fill kernel
+    one = torch.zeros(1, device="cuda")
+    floor = event_time(lambda: one.fill_(1.0), 200, stream)
 
     # ---- ALS sweep (comparison method)
     Aals = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
@@ -122,28 +186,43 @@ def main():
     iters = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = gn.step()
+        gn.step()
         P.residual(Xd, gn.A, out=resid, ws=gn.ws)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    iters.append(gn.stats()["cg_iters"])
     r_now = float(resid[0] / resid[1])
     ms_step = elapsed / args.steps * 1e3
-    log(f"[bench] GN step + residual: {ms_step:.3f} ms; last cg_iters {iters[-1]}; residual {r_now:.3e}")
+    log(f"[bench] GN step + residual: {ms_step:.3f} ms; residual {r_now:.3e}")
 
-    # ---- GN step with exactly 20 CG iterations (eps_cg = 0)
+    # CG iterations of the timed steps: the kernels are deterministic, so an untimed replay from
+    # the same start reads them step by step.
+    Ar = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+    gr = P.GaussNewton(Xd, Ar, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    for k in range(args.warmup + args.steps):
+        gr.step()
+        if k >= args.warmup:
+            iters.append(gr.stats()["cg_iters"])
+    del Ar, gr
+
+    # ---- GN step with exactly 20 CG iterations (eps_cg = 0), FP32 and FP64
     A20 = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
     ws20 = P.Workspace()
     sb = P.stats_buffer(Xd.device)
     for _ in range(2):
         P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20)
     t20 = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 5, stream)
+    t0cg = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 0, stats=sb, ws=ws20), 5, stream)
     res_t = event_time(lambda: P.residual(Xd, gn.A, out=resid, ws=gn.ws), 10, stream)
 
     # ---- time to relative residual 1e-8, FP64 storage (the FP32 rounding floor is ~3e-8)
     ttt = None
     if not args.no_time_to_target:
         X64d = torch.from_numpy(X64).cuda()
+        A20 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
+        for _ in range(2):
+            P.gn_step(X64d, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20)
+        t20_64 = event_time(lambda: P.gn_step(X64d, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 3, stream)
+        del A20
         A64 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
         g64 = P.GaussNewton(X64d, A64, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
         torch.cuda.synchronize()
@@ -157,7 +236,7 @@ def main():
             if r64 <= 1e-8:
                 break
         ttt = dict(fp64_seconds=time.perf_counter() - t0, fp64_steps=steps64, fp64_residual=r64,
-                   mixed_seconds=None)
+                   mixed_seconds=None, fp64_gn_step_20cg_ms=t20_64 * 1e3)
         log(f"[bench] FP64 time to 1e-8: {ttt['fp64_seconds']:.3f} s in {steps64} steps (r={r64:.2e})")
         del X64d, A64, g64
 
@@ -185,6 +264,9 @@ def main():
                           f"workload in FP64 on the FP32-rounded inputs, {cpu_el:.1f} s")
         log(f"[bench] CPU oracle: {cpu['value']:.3f} GN steps/s on {cores} threads")
 
+    traffic = None
+    if MTTKRP_TRAFFIC is not None and MTTKRP_TRAFFIC["source_sha256"] == kernel_source_hash():
+        traffic = MTTKRP_TRAFFIC["bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": 1e3 / ms_step,
@@ -204,14 +286,23 @@ def main():
                    "dims": [s, s, s], "rank": R, "device": dev_name},
         "roofline": {"bound": "mfma", "achieved": flops / mean_t / 1e12,
                      "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": flops / mean_t / 1e12 / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "cp_mttkrp (single mode, mean over modes)"},
-        "mttkrp_tflops": {f"mode{n}": v for n, v in mt_tf.items()},
-        "mttkrp_ms": {f"mode{n}": t * 1e3 for n, t in mt.items()},
+                     "frac": flops / mean_t / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": traffic,
+                     "kernel": "cp_mttkrp FP32 single mode (mean over modes and calls)"},
+        "mttkrp_fp32": {f"mode{n}": {"median_ms": v[0] * 1e3, "mean_ms": v[1] * 1e3,
+                                     "tflops_median": flops / v[0] / 1e12} for n, v in mt32.items()},
+        "mttkrp_fp64": {f"mode{n}": {"median_ms": v[0] * 1e3, "mean_ms": v[1] * 1e3,
+                                     "tflops_median": flops / v[0] / 1e12,
+                                     "frac_fp64_peak": flops / v[0] / 1e12 / PEAK_FP64_MFMA_TFLOPS}
+                        for n, v in mt64.items()},
         "gn_step_20cg_ms": t20 * 1e3,
+        "gn_steps_per_s_20cg": 1.0 / t20,
+        "cg_iteration_ms": (t20 - t0cg) / 20 * 1e3,
+        "launch_floor_ms": floor * 1e3,
         "residual_ms": res_t * 1e3,
         "als_sweep_ms": als_t * 1e3,
-        "last_cg_iters": iters[-1],
+        "cg_iters_mean": float(np.mean(iters)),
+        "cg_iters": iters,
         "residual_after": r_now,
         "time_to_1e-8": ttt,
         "cpu_baseline": cpu,
