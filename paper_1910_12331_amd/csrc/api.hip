@@ -37,10 +37,9 @@ void launch_fin_residual_expansion(const Dims&, int, const double*, const double
                                    const double*, double*, hipStream_t);
 int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipStream_t, bool);
 size_t cg_slot_bytes(const Plan&);
-int cg_supported(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
-              double*, double*, double*, double*, double*, double*, void*, CgState*, double, int,
-              hipStream_t);
+              double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
+              double, int, hipStream_t);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 
@@ -116,6 +115,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_red = take((size_t)2 * p->N * kRedSlots * 8);
   p->off_state = take(sizeof(CgState));
   p->off_w1 = take(vec);
+  p->off_r1 = take(vec);
   p->off_slots = take(cg_slot_bytes(*p));
   p->bytes = off;
   return CP_OK;
@@ -346,7 +346,6 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   const Dims d = make_dims(p);
   const Ws w = carve(p, ws);
   const int64_t RR = (int64_t)p.R * p.R;
-  const int64_t cnt = p.sum_s * p.R;
   const int nb = rowmm_blocks(d);
 
   launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
@@ -354,50 +353,10 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
   // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
   launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st);
-  if (cg_supported(p)) {
-    // CG: three fused launches per iteration (cp. pcg.hip)
-    launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, w.z, w.w, (double*)(w.base + p.off_w1), w.q,
-              w.bp, w.base + p.off_slots, w.st, prm->lambda, prm->cg_maxiter, st);
-    PerMode<void*> aout{};
-    for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
-    launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
-    launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
-    return hip_status();
-  }
-  // Ranks whose R x R tiles do not fit the fused kernels' LDS: one launch per vector operation.
-  // CG initialisation: V = 0, R = -G (written by the gradient), Z = R P_inv, W = Z.
-  launch_fill(cnt, w.v, 0.0, st);
-  {
-    RowMM a{};
-    a.l1 = w.r;
-    a.t1 = w.pinv;
-    a.t1_stride = RR;
-    a.out = w.z;
-    a.out2 = w.w;
-    a.out2_scale = 1.0;
-    a.dotw = w.r;
-    a.red_dot = w.red_dot;
-    a.mode_only = -1;
-    launch_rowmm(d, a, w.st, st);
-  }
-  launch_fin_cginit(d, nb, w.red_dot, w.st, st);
-  PerMode<void*> none2{};
-  for (int it = 0; it < prm->cg_maxiter; ++it) {
-    matvec_core(p, d, w, w.w, prm->lambda, w.q, none2, true, st);
-    launch_fin_alpha(d, nb, w.red_dot, w.st, st);
-    launch_cg_axpy(d, w.v, w.r, w.w, w.q, w.red_nrm, w.st, st);
-    RowMM a{};
-    a.l1 = w.r;
-    a.t1 = w.pinv;
-    a.t1_stride = RR;
-    a.out = w.z;
-    a.dotw = w.r;
-    a.red_dot = w.red_dot;
-    a.mode_only = -1;
-    launch_rowmm(d, a, w.st, st);
-    launch_fin_beta(d, nb, w.red_dot, w.red_nrm, w.st, st);
-    launch_cg_wupdate(cnt, w.w, w.z, w.st, st);
-  }
+  // CG: three launches per iteration, scalars kept on the device.
+  launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
+            (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, prm->lambda,
+            prm->cg_maxiter, st);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
   launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);

@@ -58,7 +58,8 @@ struct Plan {
   size_t off_apad = 0, off_fpk_last = 0, off_fpk_prev = 0, off_part = 0, off_p1 = 0;
   size_t off_m64 = 0, off_a64 = 0, off_s = 0, off_gam = 0, off_pinv = 0;
   size_t off_g = 0, off_v = 0, off_r = 0, off_z = 0, off_w = 0, off_q = 0;
-  size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0, off_w1 = 0, off_slots = 0;
+  size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0, off_w1 = 0, off_r1 = 0;
+  size_t off_slots = 0;
   size_t bytes = 0;
 };
 
@@ -74,6 +75,7 @@ struct CgState {
   int32_t status;    // CP_OK or a device status code
   int32_t iters;
   int32_t pad;
+  double rho[2];     // sum <R,Z> of the last two CG iterations (by iteration parity)
 };
 
 // Per-mode pointer bundles passed by value to kernels.

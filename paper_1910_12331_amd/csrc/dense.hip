@@ -460,10 +460,6 @@ __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restric
 // last factor is streamed in a packed B-operand layout, and each reconstructed 16x16 tile is
 // compared with X in FP64.
 // ------------------------------------------------------------------------------------------
-template <typename T> struct ResCfg;
-template <> struct ResCfg<float> { static constexpr int MB = 4; };
-template <> struct ResCfg<double> { static constexpr int MB = 2; };
-
 struct ResArgs {
   const void* X;
   const void* apad[kMaxOrder];  // [s_m][Rp] compute precision
@@ -474,57 +470,122 @@ struct ResArgs {
   double* red;                  // [2][kRedSlots]
 };
 
+// Direct residual (Section 5): ||X - [[A]]||^2 and ||X||^2 in one pass over X. X is viewed as
+// [O][K] with K = s_N; the reconstruction is the product of the Khatri-Rao rows of the first N-1
+// factors (O x R, built in registers) with A(N)^T, on the matrix cores. Work items are
+// (16 MB-row tile, 16-column block) pairs in tile-major order; wavefront w owns the contiguous
+// item range [w I / W, (w+1) I / W), so the load is balanced to one item. The next item's
+// B fragment and X values are requested before the current item's products (ping-pong
+// buffers); the Khatri-Rao rows are rebuilt only when the tile changes.
+template <typename T> struct ResCfg;
+template <> struct ResCfg<float> { static constexpr int MB = 4, OCC = 2; };
+template <> struct ResCfg<double> { static constexpr int MB = 2, OCC = 1; };
+
+template <typename T, int MB, int RS>
+struct ResBuf {
+  T b[RS];
+  T x[MB][4];
+};
+
 template <typename T, int NBR>
-__global__ __launch_bounds__(256, 2) void k_residual(ResArgs a) {
+__global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   constexpr int MB = ResCfg<T>::MB;
   constexpr int RS = 4 * NBR;
   typedef typename Mfma<T>::v4 v4;
   const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   const T* X = (const T*)a.X;
   const T* B = (const T*)a.bpk;
+  const int64_t ntiles = (a.O + 16 * MB - 1) / (16 * MB);
+  const int64_t nitems = ntiles * a.KB;
+  const int64_t i0 = wave * nitems / nwaves, i1 = (wave + 1) * nitems / nwaves;
   double d2 = 0.0, x2 = 0.0;
-  for (int64_t tile = wave; tile * 16 * MB < a.O; tile += nwaves) {
-    const int64_t o0 = tile * 16 * MB;
+  if (i0 < i1) {
+    int64_t t = i0 / a.KB, kb = i0 - t * a.KB;   // position of item i
+    int64_t tn = t, kbn = kb;                      // position of the item being prefetched
+    int64_t tile_built = -1;
     T ar[MB][RS];
+    ResBuf<T, MB, RS> bufA, bufB;
+
+    auto load = [&](ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int64_t o = o0 + 16 * mb + m;
+      for (int s = 0; s < RS; ++s) bf.b[s] = B[(kk * RS + s) * kWave + lane];
+      const int64_t col = kk * 16 + m;
 #pragma unroll
-      for (int s = 0; s < RS; ++s) ar[mb][s] = (o < a.O) ? T(1) : T(0);
-      if (o < a.O) {
-        int64_t rem = o;
-        for (int q = a.N - 2; q >= 0; --q) {
-          const int64_t idx = rem % a.s[q];
-          rem /= a.s[q];
-          const T* row = (const T*)a.apad[q] + idx * a.Rp + g;
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int s = 0; s < RS; ++s) ar[mb][s] *= row[4 * s];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
+          bf.x[mb][v] = (o < a.O && col < a.K) ? X[o * a.K + col] : T(0);
+        }
+    };
+    auto advance = [&](int64_t& tt, int64_t& kk) {
+      if (++kk == a.KB) {
+        kk = 0;
+        ++tt;
+      }
+    };
+    auto build = [&](int64_t tt) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int64_t o = tt * 16 * MB + 16 * mb + m;
+#pragma unroll
+        for (int s = 0; s < RS; ++s) ar[mb][s] = (o < a.O) ? T(1) : T(0);
+        if (o < a.O) {
+          int64_t rem = o;
+          for (int q = a.N - 2; q >= 0; --q) {
+            const int64_t idx = rem % a.s[q];
+            rem /= a.s[q];
+            const T* row = (const T*)a.apad[q] + idx * a.Rp + g;
+#pragma unroll
+            for (int s = 0; s < RS; ++s) ar[mb][s] *= row[4 * s];
+          }
         }
       }
-    }
-    for (int64_t kb = 0; kb < a.KB; ++kb) {
-      T br[RS];
-#pragma unroll
-      for (int s = 0; s < RS; ++s) br[s] = B[(kb * RS + s) * kWave + lane];
-      const int64_t k = kb * 16 + m;
+    };
+    auto consume = [&](const ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
+      const int64_t col = kk * 16 + m;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         v4 acc = v4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < RS; ++s) acc = Mfma<T>::mac(ar[mb][s], br[s], acc);
+        for (int s = 0; s < RS; ++s) acc = Mfma<T>::mac(ar[mb][s], bf.b[s], acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t o = o0 + 16 * mb + Mfma<T>::out_row(lane, v);
-          if (o < a.O && k < a.K) {
-            const double x = (double)X[o * a.K + k];
+          const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
+          if (o < a.O && col < a.K) {
+            const double x = (double)bf.x[mb][v];
             const double df = x - (double)acc[v];
             d2 += df * df;
             x2 += x * x;
           }
         }
       }
+    };
+
+    load(bufA, tn, kbn);
+    advance(tn, kbn);
+    int64_t i = i0;
+    while (true) {
+      if (i + 1 < i1) load(bufB, tn, kbn);
+      advance(tn, kbn);
+      if (t != tile_built) {
+        build(t);
+        tile_built = t;
+      }
+      consume(bufA, t, kb);
+      advance(t, kb);
+      if (++i >= i1) break;
+      if (i + 1 < i1) load(bufA, tn, kbn);
+      advance(tn, kbn);
+      if (t != tile_built) {
+        build(t);
+        tile_built = t;
+      }
+      consume(bufB, t, kb);
+      advance(t, kb);
+      if (++i >= i1) break;
     }
   }
   block_sum2(d2, x2);
@@ -766,9 +827,9 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     a.bpk = ws + p.off_part;
     hipLaunchKernelGGL(k_pack_last<T>, dim3(grid1(a.KB * p.Rp / 4 * kWave, 1024)), dim3(256), 0,
                        s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part));
-    const int64_t tiles = (a.O + 16 * MB - 1) / (16 * MB);
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2 * kNumCU) blocks = 2 * kNumCU;   // one resident round of workgroups
+    const int64_t items = (a.O + 16 * MB - 1) / (16 * MB) * a.KB;
+    int64_t blocks = (items + 3) / 4;
+    if (blocks > ResCfg<T>::OCC * kNumCU) blocks = ResCfg<T>::OCC * kNumCU;   // one resident round
     switch (p.NBt) {
 #define CPGN_RES(k) \
   case k: hipLaunchKernelGGL((k_residual<T, k>), dim3(blocks), dim3(256), 0, s, a); break;

@@ -1,417 +1,519 @@
-// Algorithm 2 (CP-CG) of Singh, Ma, Yang, Solomonik (arXiv:1910.12331) as three fused kernels
-// per iteration (all vectors FP64, packed [sum_n s_n, R]):
-//   k_cg_proj    W = Z + beta W_old (into the other W buffer) and B(p) = A(p)^T W(p) in 16x16
-//                tiles of the R x R result; a tile sums over all rows of its mode (no partials).
-//   k_cg_matvec  Y(n) = sum_{p != n} Gamma(n,p) * B(p) staged in LDS, then
-//                Q(n) = lambda W(n) + W(n) Gamma(n,n) + A(n) Y(n)^T (eq. (7)) for a block of rows,
-//                <W,Q> per block; the last block to finish forms alpha = rho / sum <W,Q>.
-//   k_cg_update  V += alpha W, R -= alpha Q, Z = R P_inv(n), <R,Z> and ||R(n)||^2 per block; the
-//                last block forms beta = rho_new / rho and the stop test
-//                sum_n ||R(n)||_F <= eps_cg sum_n ||G(n)||_F.
-// The CG scalars stay in device memory; a kernel that finds the state done returns at once, so
-// the host enqueues cg_maxiter iterations without synchronising. "Last block" reductions add the
-// per-block partials in block order, so results do not depend on scheduling.
+// Algorithm 2 (CP-CG) of Singh, Ma, Yang, Solomonik (arXiv:1910.12331): preconditioned CG on
+// (J^T J + lambda I) V = -G with the block preconditioner (Gamma(n,n) + lambda I)^-1 of
+// Section 3.3, as three launches per iteration. All vectors are FP64, packed [sum_n s_n, R] by
+// mode.
+//
+//   k_cg_proj    rho = sum <R,Z> and the stop test sum_n ||R(n)||_F <= eps sum_n ||G(n)||_F from
+//                the previous launch's per-block partials; beta = rho / rho_old;
+//                W = Z + beta W_old; B(p) = A(p)^T W(p), one 16 x 16 tile of B(p) per workgroup
+//                (the sum over all s_p rows stays inside the workgroup).
+//   k_cg_matvec  Q(n) = lambda W(n) + W(n) Gamma(n,n) + A(n) Y(n)^T with
+//                Y(n) = sum_{p != n} Gamma(n,p) * B(p) (eq. (7) contracted in factored form),
+//                for a 64-row x 16-column block; per-block <W,Q>.
+//   k_cg_update  alpha = rho / sum <W,Q> from the matvec partials; V += alpha W;
+//                R_new = R - alpha Q; Z = R_new P_inv(n) for the block; per-block <R_new,Z> and
+//                ||R_new||^2 (per mode).
+//
+// Every workgroup of a launch reduces the previous launch's partials itself, in one fixed order,
+// so all of them obtain bitwise the same alpha, beta and stop decision without atomics or a
+// second pass; the result does not depend on scheduling. A launch that finds the state done
+// returns at once, so the host enqueues cg_maxiter iterations without synchronising. Vectors
+// that a launch reads in full rows while other workgroups of the same launch write them (R, W)
+// are double-buffered by iteration parity.
+//
+// The row x (R x R) products run on the 16x16x4 FP64 matrix instruction. Lane l = 16 g + m of a
+// wavefront owns row m of a 16-row tile and the contiguous k-range [g K/4, (g+1) K/4) of the
+// contraction (K = R padded to 16 KB): its operands are loaded straight from memory into
+// registers, all in one batch, while the shared 16-column slice of the R x R operand goes
+// through LDS.
 #include "cpgn_internal.h"
 
 namespace cpgn {
 
-constexpr int kRowBlk = 16;       // rows per block in the row kernels
-constexpr int kTile = 16;         // B(p) tile edge
-constexpr int kChunk = 64;        // rows staged per LDS chunk in k_cg_proj
-constexpr int kMaxR = 128;
+constexpr int kCgRows = 64;     // rows per workgroup in init / matvec / update (4 wavefronts)
+constexpr int kProjWaves = 8;   // wavefronts per B(p) tile in k_cg_proj
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
 struct CgArgs {
   Dims d;
   const double* A64;
-  const double* gam;      // Gamma[n][p]
+  const double* gam;      // Gamma[n][p], R x R each
   const double* pinv;     // P_inv[n]
   double* V;
-  double* Rv;             // -G on entry
+  double* Rv[2];          // residual, double-buffered; Rv[0] = -G on entry
   double* Z;
-  double* W[2];           // ping-pong W buffers
+  double* W[2];           // search direction, double-buffered
   double* Q;
-  double* B;
-  double* slot_dot;       // [nrowblk]
-  double* slot_nrm;       // [nrowblk]
-  unsigned* counter;      // last-block counters [2]
+  double* B;              // B(p) = A(p)^T W(p), [N][R][R]
+  double* slot_wq;        // per-block partials [nslot]
+  double* slot_rz;
+  double* slot_nrm;
   CgState* st;
   double lambda;
-  int nrowblk;
+  int TB;                 // 16-column tiles of R
+  int nslot;              // row blocks x TB
   int rb_off[kMaxOrder + 1];
 };
 
-__device__ __forceinline__ void bsum2(double& a, double& b) {
-  __shared__ double sa[256], sb[256];
-  const int t = threadIdx.x;
-  sa[t] = a;
-  sb[t] = b;
+// Sum of v[0..NV) over the workgroup; every thread receives the same bits. Lanes combine by an
+// xor butterfly (each pairwise sum is formed identically in both partners), then wavefront
+// partials are added in wavefront order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double red[16][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wv][i] = v[i];
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      sa[t] += sa[t + w];
-      sb[t] += sb[t + w];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w][i];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+// Per-thread share of the previous init / update launch's partials (slot order is mode-major):
+// v[0] gathers <R,Z>, v[1 + n] gathers ||R(n)||^2. The loads of all slots go out together.
+struct RzShare {
+  double v[1 + kMaxOrder];
+};
+
+__device__ __forceinline__ void load_rz(const CgArgs& a, RzShare& sh) {
+#pragma unroll
+  for (int i = 0; i < 1 + kMaxOrder; ++i) sh.v[i] = 0.0;
+  for (int i = threadIdx.x; i < a.nslot; i += blockDim.x) {
+    const double rz = a.slot_rz[i], nr = a.slot_nrm[i];
+    const int rb = i / a.TB;
+    sh.v[0] += rz;
+#pragma unroll
+    for (int n = 0; n < kMaxOrder; ++n)
+      sh.v[1 + n] += (rb >= a.rb_off[n] && rb < a.rb_off[n + 1] && n < a.d.N) ? nr : 0.0;
+  }
+}
+
+// rho = sum <R,Z> and rsum = sum_n sqrt(sum ||R(n)||^2), identical in every thread.
+__device__ __forceinline__ void reduce_rz(const CgArgs& a, RzShare& sh, double& rho, double& rsum) {
+  block_sum(sh.v);
+  rho = sh.v[0];
+  rsum = 0.0;
+  for (int n = 0; n < a.d.N; ++n) rsum += sqrt(sh.v[1 + n]);
+}
+
+// Records the CG state before iteration `it` (it iterations done) and decides whether to stop.
+// Called by every workgroup with identical inputs; workgroup 0 writes.
+__device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, double rho_old,
+                                         double rsum, double gsum, double eps, double& beta) {
+  beta = it == 0 ? 0.0 : rho / rho_old;
+  bool stop = false;
+  int status = CP_OK;
+  if (!isfinite(rho) || !isfinite(rsum)) {
+    status = CP_ENONFINITE;
+    stop = true;
+  } else if (!(rsum > eps * gsum)) {
+    stop = true;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CgState* st = a.st;
+    st->rho[it & 1] = rho;
+    st->rz = rho;
+    st->rsum = rsum;
+    st->iters = it;
+    if (it > 0) st->beta = beta;
+    if (stop) {
+      st->status = status;
+      st->done = 1;
     }
+  }
+  return stop;
+}
+
+// Contraction index of MFMA step j for lane group g: steps come in pairs that read two
+// adjacent k (one 16-byte load per lane), k = 8 (j / 2) + 2 g + (j % 2).
+__device__ __forceinline__ int kstep(int j, int g) { return 8 * (j >> 1) + 2 * g + (j & 1); }
+
+// LDS index of element (k, c) of a K x 16 operand slice: rows in pairs, each pair followed by a
+// padding row, so that the four lane groups (k = 8j + 2g + e) read alternate bank halves.
+__device__ __forceinline__ int sidx(int k, int c) { return (k + (k >> 1)) * 16 + c; }
+constexpr int slice_elems(int KP) { return (KP + KP / 2) * 16; }
+
+// Operand row r[0..KQ) of lane group g: elements kstep(j, g) of `row` (zero past R or when the
+// row is outside the mode). EVEN: R is even, so each pair is one aligned 16-byte load.
+template <int KQ, bool EVEN>
+__device__ __forceinline__ void load_oprow(double (&r)[KQ], const double* row, bool rowok, int R,
+                                           int g) {
+#pragma unroll
+  for (int j = 0; j < KQ; j += 2) {
+    const int k = kstep(j, g);
+    if (EVEN) {
+      double2 v = make_double2(0.0, 0.0);
+      if (rowok && k < R) v = *reinterpret_cast<const double2*>(row + k);
+      r[j] = v.x;
+      r[j + 1] = v.y;
+    } else {
+      r[j] = rowok && k < R ? row[k] : 0.0;
+      r[j + 1] = rowok && k + 1 < R ? row[k + 1] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_cg_update<KB, INIT>: one 64 x 16 block of Z = R_new P_inv(n), plus V and R for that block.
+// INIT: CG initialisation (alpha = 0, V = 0, R = -G unchanged, so R_new = R and Rv is not
+// rewritten). Otherwise alpha = rho / sum <W,Q> from k_cg_matvec's partials.
+// grid: nslot workgroups of 256 threads; block b covers row block b / TB, columns 16 (b % TB).
+// ---------------------------------------------------------------------------------------------
+template <int KB, bool INIT, bool EVEN>
+__global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
+  constexpr int KQ = 4 * KB;    // MFMA steps (k values per lane)
+  constexpr int KP = 16 * KB;   // padded contraction length
+  __shared__ double Ps[slice_elems(KP)];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
+  const int R = a.d.R;
+  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows + wv * 16;   // first row of the tile
+  const int64_t rbase = a.d.off[n];
+  const double* Rin = a.Rv[it & 1];
+  double* Rout = a.Rv[(it + 1) & 1];
+  const double* W = a.W[(it + 1) & 1];
+  __shared__ int sdone;
+  if (t == 0) sdone = a.st->done;   // read once per workgroup: workgroup 0 may set it meanwhile
+  const double rho = INIT ? 0.0 : a.st->rho[it & 1];
+
+  // Operand rows: row k0 + m, k = kstep(j, g).
+  const bool rowok = k0 + m < s;
+  double ro[KQ], qo[KQ];
+  load_oprow<KQ, EVEN>(ro, Rin + (rbase + k0 + m) * R, rowok, R, g);
+  if (!INIT) load_oprow<KQ, EVEN>(qo, a.Q + (rbase + k0 + m) * R, rowok, R, g);
+  // P_inv(n)[:, c0:c0+16] into LDS (k-major, 16 contiguous columns per k).
+  const double* P = a.pinv + (int64_t)n * R * R;
+  double ps[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int e = t + 256 * i, k = e >> 4, c = e & 15;
+    ps[i] = (k < R && c0 + c < R) ? P[(int64_t)k * R + c0 + c] : 0.0;
+  }
+  // This lane's outputs: rows k0 + g + 4v, column c0 + m.
+  const bool colok = c0 + m < R;
+  double rd[4], qd[4], vd[4], wd[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = k0 + g + 4 * v;
+    const bool ok = colok && row < s;
+    const int64_t e = (rbase + row) * R + c0 + m;
+    rd[v] = ok ? Rin[e] : 0.0;
+    qd[v] = !INIT && ok ? a.Q[e] : 0.0;
+    vd[v] = !INIT && ok ? a.V[e] : 0.0;
+    wd[v] = !INIT && ok ? W[e] : 0.0;
+  }
+  double wq = 0.0;
+  if (!INIT) {
+    double v1[1] = {0.0};
+    for (int i = t; i < a.nslot; i += 256) v1[0] += a.slot_wq[i];
+    block_sum(v1);
+    wq = v1[0];
+  } else {
     __syncthreads();
   }
-  a = sa[0];
-  b = sb[0];
-  __syncthreads();
-}
-
-__device__ __forceinline__ void rowblk(const CgArgs& a, int task, int& n, int64_t& k0) {
-  n = 0;
-  while (task >= a.rb_off[n + 1]) ++n;
-  k0 = (int64_t)(task - a.rb_off[n]) * kRowBlk;
-}
-
-// True in every thread of the block that finished last (its partial is already written).
-__device__ __forceinline__ bool last_block(unsigned* counter) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = prev == gridDim.x * gridDim.y - 1;
-    if (is_last) *counter = 0u;   // ready for the next use
+  if (sdone) return;
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int e = t + 256 * i;
+    Ps[sidx(e >> 4, e & 15)] = ps[i];
+  }
+  double alpha = 0.0;
+  if (!INIT) {
+    int status = CP_OK;
+    if (!isfinite(wq)) status = CP_ENONFINITE;
+    else if (!(wq > 0.0)) status = CP_EBREAKDOWN;
+    if (status != CP_OK) {
+      if (blockIdx.x == 0 && t == 0) {
+        a.st->status = status;
+        a.st->done = 1;
+      }
+      return;
+    }
+    alpha = rho / wq;
+    if (blockIdx.x == 0 && t == 0) a.st->alpha = alpha;
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) ro[j] = __fma_rn(-alpha, qo[j], ro[j]);
   }
   __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-__device__ __forceinline__ double sum_slots(const double* s, int n) {
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) a += s[i];
-  bsum2(a, b);
-  return a;
-}
-
-// acc[kk] += sum_z L[kk][z] T[z][r] for the kRowBlk rows staged in LDS (L: [kRowBlk][R]) and the
-// R x R matrix T staged in LDS with row stride R + 1. Thread t owns column r = t % 128 and rows
-// h*8 .. h*8+7, h = t / 128.
-__device__ __forceinline__ void rowblock_times(const double* L, const double* T, int R,
-                                               double acc[8]) {
-  const int r = threadIdx.x & 127, h = threadIdx.x >> 7;
-  if (r >= R) return;
-  const double* Lh = L + h * 8 * R;
-#pragma unroll 4
-  for (int z = 0; z < R; ++z) {
-    const double tv = T[z * (R + 1) + r];
+  dv4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) acc[kk] += Lh[kk * R + z] * tv;
-  }
-}
-
-
-// Stage an R x R matrix into LDS with row stride R + 1 (optionally transposed), eight loads
-// in flight per thread so that the copy costs about one memory latency.
-__device__ __forceinline__ void stage_rr(double* T, const double* src, int R, bool transpose) {
-  const int RR = R * R;
-  for (int e0 = threadIdx.x; e0 < RR; e0 += 256 * 8) {
-    double v[8];
+  for (int j = 0; j < KQ; ++j)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ro[j], Ps[sidx(kstep(j, g), m)], acc, 0, 0, 0);
+  double dot = 0.0, nrm = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * 256;
-      v[u] = e < RR ? src[e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * 256;
-      if (e < RR) {
-        const int i = e / R, j = e - i * R;
-        if (transpose) T[j * (R + 1) + i] = v[u];
-        else T[i * (R + 1) + j] = v[u];
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = k0 + g + 4 * v;
+    if (colok && row < s) {
+      const int64_t e = (rbase + row) * R + c0 + m;
+      const double rn = INIT ? rd[v] : __fma_rn(-alpha, qd[v], rd[v]);
+      if (INIT) {
+        a.V[e] = 0.0;
+      } else {
+        a.V[e] = __fma_rn(alpha, wd[v], vd[v]);
+        Rout[e] = rn;
       }
+      a.Z[e] = acc[v];
+      dot += acc[v] * rn;
+      nrm += rn * rn;
     }
   }
-}
-
-// T[z][r] = Y(n)[r][z] = sum_{p != n} Gamma(n,p)[r][z] B(p)[r][z], batched like stage_rr.
-__device__ __forceinline__ void stage_y(double* T, const double* gam, const double* B, int n,
-                                        int N, int R) {
-  const int RR = R * R;
-  for (int e0 = threadIdx.x; e0 < RR; e0 += 256 * 4) {
-    double y[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int p = 0; p < N; ++p) {
-      if (p == n) continue;
-      double g[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + u * 256;
-        g[u] = e < RR ? gam[((int64_t)n * N + p) * RR + e] : 0.0;
-        b[u] = e < RR ? B[(int64_t)p * RR + e] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] += g[u] * b[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * 256;
-      if (e < RR) {
-        const int r = e / R, z = e - r * R;
-        T[z * (R + 1) + r] = y[u];
-      }
-    }
+  double v2[2] = {dot, nrm};
+  block_sum(v2);
+  if (t == 0) {
+    a.slot_rz[blockIdx.x] = v2[0];
+    a.slot_nrm[blockIdx.x] = v2[1];
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Initialisation: V = 0, W_0 = 0, Z = R P_inv (R = -G), rho = sum <R,Z>, stop test.
+// k_cg_proj: stop test and beta, W = Z + beta W_old (stored by the row-tile-0 workgroups), and
+// one 16 x 16 tile of B(p) = A(p)^T W(p). grid: N * TB * TB workgroups of 512 threads; the
+// eight wavefronts split the rows of mode p and their partial tiles are added in order.
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cg_init(CgArgs a) {
-  if (a.st->done) return;
-  extern __shared__ double sm[];
-  const int R = a.d.R, t = threadIdx.x;
-  double* L = sm;                       // [kRowBlk][R]
-  double* T = sm + kRowBlk * R;         // [R][R + 1]
-  int n;
-  int64_t k0;
-  rowblk(a, blockIdx.x, n, k0);
-  const int64_t rows = a.d.s[n] - k0 < kRowBlk ? a.d.s[n] - k0 : kRowBlk;
-  const int64_t base = (a.d.off[n] + k0) * R;
-  stage_rr(T, a.pinv + (int64_t)n * R * R, R, false);
-  for (int e = t; e < kRowBlk * R; e += 256) {
-    const bool in = e / R < rows;
-    L[e] = in ? a.Rv[base + e] : 0.0;
-    if (in) {
-      a.V[base + e] = 0.0;
-      a.W[0][base + e] = 0.0;
-    }
-  }
-  __syncthreads();
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  rowblock_times(L, T, R, acc);
-  const int r = t & 127, h = t >> 7;
-  double dot = 0.0, dummy = 0.0;
-  if (r < R) {
-    for (int kk = 0; kk < 8; ++kk) {
-      const int row = h * 8 + kk;
-      if (row < rows) {
-        a.Z[base + row * R + r] = acc[kk];
-        dot += acc[kk] * L[row * R + r];
-      }
-    }
-  }
-  bsum2(dot, dummy);
-  if (t == 0) a.slot_dot[blockIdx.x] = dot;
-  if (last_block(&a.counter[0])) {
-    const double rho = sum_slots(a.slot_dot, a.nrowblk);
-    if (t == 0) {
-      CgState* st = a.st;
-      st->rz = rho;
-      st->beta = 0.0;
-      if (!isfinite(rho)) {
-        st->status = CP_ENONFINITE;
-        st->done = 1;
-      } else if (!(st->rsum > st->eps * st->gsum)) {
-        st->done = 1;
-      }
-    }
+constexpr int kProjSteps = 16;   // 4-row MFMA steps loaded per batch and wavefront
+
+struct ProjBatch {
+  double av[kProjSteps], zv[kProjSteps], wo[kProjSteps];
+};
+
+__device__ __forceinline__ void proj_load(ProjBatch& b, const CgArgs& a, const double* Wold, int it,
+                                          int64_t qb, int64_t q1, int64_t s, int64_t base, int R,
+                                          int r0, int z0, int m, int g, bool rok, bool zok) {
+#pragma unroll
+  for (int j = 0; j < kProjSteps; ++j) {
+    const int64_t k = (qb + j) * 4 + g;
+    const bool ok = qb + j < q1 && k < s;
+    const int64_t row = (base + k) * R;
+    b.av[j] = ok && rok ? a.A64[row + r0 + m] : 0.0;
+    b.zv[j] = ok && zok ? a.Z[row + z0 + m] : 0.0;
+    b.wo[j] = ok && zok && it > 0 ? Wold[row + z0 + m] : 0.0;
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// W = Z + beta W_old (stored by the tiles with row-tile 0) and B(p) = A(p)^T W(p).
-// grid: N * TB * TB blocks.
-// ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cg_proj(CgArgs a, int it) {
-  if (a.st->done) return;
-  __shared__ double as[kChunk][kTile + 1], wsm[kChunk][kTile + 1];
-  const int R = a.d.R, t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  const int TB = (R + kTile - 1) / kTile;
+__global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
+  __shared__ double part[kProjWaves][64][4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
+  const int R = a.d.R, TB = a.TB;
   const int p = blockIdx.x / (TB * TB), rt = (blockIdx.x / TB) % TB, zt = blockIdx.x % TB;
-  const int r0 = rt * kTile, z0 = zt * kTile;
-  const int64_t s = a.d.s[p], base = a.d.off[p] * R;
-  const double beta = a.st->beta;
+  const int r0 = rt * 16, z0 = zt * 16;
+  const int64_t s = a.d.s[p], base = a.d.off[p];
   const double* Wold = a.W[it & 1];
   double* Wnew = a.W[(it + 1) & 1];
-  double acc = 0.0;
-  for (int64_t c0 = 0; c0 < s; c0 += kChunk) {
-    double av[4], zv[4], wv[4];
+  // Wavefront wv takes the 4-row steps [q0, q1) of this mode's rows.
+  const int64_t nsteps = (s + 3) / 4;
+  const int64_t per = (nsteps + kProjWaves - 1) / kProjWaves;
+  const int64_t q0 = wv * per, q1 = q0 + per < nsteps ? q0 + per : nsteps;
+  const bool rok = r0 + m < R, zok = z0 + m < R;
+  const bool store_w = rt == 0 && zok;
+  // The first batch of rows is requested before the scalars it waits for.
+  ProjBatch b;
+  proj_load(b, a, Wold, it, q0, q1, s, base, R, r0, z0, m, g, rok, zok);
+
+  __shared__ int sdone;
+  if (t == 0) sdone = a.st->done;   // read once per workgroup: workgroup 0 may set it meanwhile
+  const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(it + 1) & 1];
+  RzShare sh;
+  load_rz(a, sh);
+  double rho, rsum, beta;
+  reduce_rz(a, sh, rho, rsum);      // its barriers publish sdone
+  if (sdone) return;
+  if (cg_check(a, it, rho, rho_old, rsum, gsum, eps, beta)) return;
+
+  dv4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t qb = q0; qb < q1; qb += kProjSteps) {
+    if (qb != q0) proj_load(b, a, Wold, it, qb, q1, s, base, R, r0, z0, m, g, rok, zok);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = t + u * 256, kk = e >> 4, cc = e & 15;
-      const int64_t k = c0 + kk;
-      const int rc = r0 + cc, zc = z0 + cc;
-      const bool ina = k < s && rc < R, inw = k < s && zc < R;
-      av[u] = ina ? a.A64[base + k * R + rc] : 0.0;
-      zv[u] = inw ? a.Z[base + k * R + zc] : 0.0;
-      wv[u] = inw ? Wold[base + k * R + zc] : 0.0;
+    for (int j = 0; j < kProjSteps; ++j) {
+      const double w = it > 0 ? __fma_rn(beta, b.wo[j], b.zv[j]) : b.zv[j];
+      const int64_t k = (qb + j) * 4 + g;
+      if (store_w && qb + j < q1 && k < s) Wnew[(base + k) * R + z0 + m] = w;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b.av[j], w, acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = t + u * 256, kk = e >> 4, cc = e & 15;
-      const int64_t k = c0 + kk;
-      const int zc = z0 + cc;
-      const double w = zv[u] + beta * wv[u];
-      if (rt == 0 && k < s && zc < R) Wnew[base + k * R + zc] = w;
-      as[kk][cc] = av[u];
-      wsm[kk][cc] = w;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kChunk; ++kk) acc += as[kk][ty] * wsm[kk][tx];
-    __syncthreads();
   }
-  if (r0 + ty < R && z0 + tx < R) a.B[(int64_t)p * R * R + (int64_t)(r0 + ty) * R + z0 + tx] = acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wv][lane][v] = acc[v];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double bsum = 0.0;
+      for (int w = 0; w < kProjWaves; ++w) bsum += part[w][lane][v];
+      const int r = r0 + g + 4 * v, z = z0 + m;
+      if (r < R && z < R) a.B[(int64_t)p * R * R + (int64_t)r * R + z] = bsum;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Q = lambda W + W Gamma(n,n) + A Y(n)^T for a block of rows; alpha in the last block.
+// k_cg_matvec<KB>: one 64 x 16 block of Q(n) = lambda W + W Gamma(n,n) + A Y(n)^T and its
+// partial <W,Q>. grid: nslot workgroups of 256 threads.
 // ---------------------------------------------------------------------------------------------
+template <int KB, bool EVEN>
 __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
-  if (a.st->done) return;
-  extern __shared__ double sm[];
-  const int R = a.d.R, N = a.d.N, t = threadIdx.x;
+  constexpr int KQ = 4 * KB;
+  constexpr int KP = 16 * KB;
+  __shared__ double Gs[slice_elems(KP)];   // Gamma(n,n)[k][c0 + c]
+  __shared__ double Ys[slice_elems(KP)];   // Y(n)[c0 + c][k]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
+  const int R = a.d.R, N = a.d.N;
   const int64_t RR = (int64_t)R * R;
-  double* Lw = sm;                      // [kRowBlk][R]
-  double* La = sm + kRowBlk * R;        // [kRowBlk][R]
-  double* T = sm + 2 * kRowBlk * R;     // [R][R + 1]
-  int n;
-  int64_t k0;
-  rowblk(a, blockIdx.x, n, k0);
-  const int64_t rows = a.d.s[n] - k0 < kRowBlk ? a.d.s[n] - k0 : kRowBlk;
-  const int64_t base = (a.d.off[n] + k0) * R;
+  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows + wv * 16;
+  const int64_t rbase = a.d.off[n];
   const double* W = a.W[(it + 1) & 1];
-  for (int e = t; e < kRowBlk * R; e += 256) {
-    const bool in = e / R < rows;
-    Lw[e] = in ? W[base + e] : 0.0;
-    La[e] = in ? a.A64[base + e] : 0.0;
-  }
-  stage_rr(T, a.gam + (int64_t)n * (N + 1) * RR, R, false);   // Gamma(n,n)
-  __syncthreads();
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  rowblock_times(Lw, T, R, acc);
-  __syncthreads();
-  stage_y(T, a.gam, a.B, n, N, R);   // T[z][r] = Y(n)[r][z]
-  __syncthreads();
-  rowblock_times(La, T, R, acc);
-  const int r = t & 127, h = t >> 7;
-  double dot = 0.0, dummy = 0.0;
-  if (r < R) {
-    for (int kk = 0; kk < 8; ++kk) {
-      const int row = h * 8 + kk;
-      if (row < rows) {
-        const double w = Lw[row * R + r];
-        const double q = acc[kk] + a.lambda * w;
-        a.Q[base + row * R + r] = q;
-        dot += w * q;
-      }
-    }
-  }
-  bsum2(dot, dummy);
-  if (t == 0) a.slot_dot[blockIdx.x] = dot;
-  if (last_block(&a.counter[0])) {
-    const double wq = sum_slots(a.slot_dot, a.nrowblk);
-    if (t == 0) {
-      CgState* st = a.st;
-      if (!isfinite(wq)) {
-        st->status = CP_ENONFINITE;
-        st->done = 1;
-      } else if (!(wq > 0.0)) {
-        st->status = CP_EBREAKDOWN;
-        st->done = 1;
-      } else {
-        st->alpha = st->rz / wq;
-      }
-    }
-  }
-}
+  __shared__ int sdone;
+  if (t == 0) sdone = a.st->done;   // no workgroup writes it during this launch
 
-// ---------------------------------------------------------------------------------------------
-// V += alpha W, R -= alpha Q, Z = R P_inv; beta and the stop test in the last block.
-// ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
-  if (a.st->done) return;
-  extern __shared__ double sm[];
-  const int R = a.d.R, N = a.d.N, t = threadIdx.x;
-  double* L = sm;                       // [kRowBlk][R]
-  double* T = sm + kRowBlk * R;         // [R][R + 1]
-  int n;
-  int64_t k0;
-  rowblk(a, blockIdx.x, n, k0);
-  const int64_t rows = a.d.s[n] - k0 < kRowBlk ? a.d.s[n] - k0 : kRowBlk;
-  const int64_t base = (a.d.off[n] + k0) * R;
-  const double alpha = a.st->alpha;
-  const double* W = a.W[(it + 1) & 1];
-  stage_rr(T, a.pinv + (int64_t)n * R * R, R, false);
-  double nrm = 0.0;
-  for (int e = t; e < kRowBlk * R; e += 256) {
-    double rv = 0.0;
-    if (e / R < rows) {
-      a.V[base + e] += alpha * W[base + e];
-      rv = a.Rv[base + e] - alpha * a.Q[base + e];
-      a.Rv[base + e] = rv;
-      nrm += rv * rv;
+  const bool rowok = k0 + m < s;
+  double wo[KQ], ao[KQ];
+  load_oprow<KQ, EVEN>(wo, W + (rbase + k0 + m) * R, rowok, R, g);
+  load_oprow<KQ, EVEN>(ao, a.A64 + (rbase + k0 + m) * R, rowok, R, g);
+  // Shared slices, element e -> (c = e / KP, k = e % KP): contiguous in k in memory.
+  const double* Gnn = a.gam + (int64_t)n * (N + 1) * RR;
+  double gs[KB], ys[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int e = t + 256 * i, c = e / KP, k = e - c * KP;
+    const bool ok = k < R && c0 + c < R;
+    gs[i] = ok ? Gnn[(int64_t)(c0 + c) * R + k] : 0.0;   // Gamma(n,n) is symmetric
+    ys[i] = 0.0;
+  }
+  // Y(n) slice: the other modes q != n in ascending order, two per batch of loads.
+  for (int qi = 0; qi < N - 1; qi += 2) {
+    const int q1 = qi < n ? qi : qi + 1;
+    const bool two = qi + 1 < N - 1;
+    const int q2 = two ? (qi + 1 < n ? qi + 1 : qi + 2) : q1;
+    const double* g1 = a.gam + ((int64_t)n * N + q1) * RR;
+    const double* b1 = a.B + (int64_t)q1 * RR;
+    const double* g2 = a.gam + ((int64_t)n * N + q2) * RR;
+    const double* b2 = a.B + (int64_t)q2 * RR;
+    double gv1[KB], bv1[KB], gv2[KB], bv2[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      const int e = t + 256 * i, c = e / KP, k = e - c * KP;
+      const bool ok = k < R && c0 + c < R;
+      const int64_t off = (int64_t)(c0 + c) * R + k;
+      gv1[i] = ok ? g1[off] : 0.0;
+      bv1[i] = ok ? b1[off] : 0.0;
+      gv2[i] = ok && two ? g2[off] : 0.0;
+      bv2[i] = ok && two ? b2[off] : 0.0;
     }
-    L[e] = rv;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      ys[i] = __fma_rn(gv1[i], bv1[i], ys[i]);
+      if (two) ys[i] = __fma_rn(gv2[i], bv2[i], ys[i]);
+    }
+  }
+  const bool colok = c0 + m < R;
+  double wd[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = k0 + g + 4 * v;
+    wd[v] = colok && row < s ? W[(rbase + row) * R + c0 + m] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int e = t + 256 * i, c = e / KP, k = e - c * KP;
+    Gs[sidx(k, c)] = gs[i];
+    Ys[sidx(k, c)] = ys[i];
   }
   __syncthreads();
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  rowblock_times(L, T, R, acc);
-  const int r = t & 127, h = t >> 7;
+  if (sdone) return;
+  dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < KQ; ++j)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wo[j], Gs[sidx(kstep(j, g), m)], acc, 0, 0, 0);
+#pragma unroll
+  for (int j = 0; j < KQ; ++j)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[j], Ys[sidx(kstep(j, g), m)], acc, 0, 0, 0);
   double dot = 0.0;
-  if (r < R) {
-    for (int kk = 0; kk < 8; ++kk) {
-      const int row = h * 8 + kk;
-      if (row < rows) {
-        a.Z[base + row * R + r] = acc[kk];
-        dot += acc[kk] * L[row * R + r];
-      }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = k0 + g + 4 * v;
+    if (colok && row < s) {
+      const double q = __fma_rn(a.lambda, wd[v], acc[v]);
+      a.Q[(rbase + row) * R + c0 + m] = q;
+      dot += wd[v] * q;
     }
   }
-  bsum2(dot, nrm);
-  if (t == 0) {
-    a.slot_dot[blockIdx.x] = dot;
-    a.slot_nrm[blockIdx.x] = nrm;
-  }
-  if (last_block(&a.counter[1])) {
-    const double rz = sum_slots(a.slot_dot, a.nrowblk);
-    double rs = 0.0;
-    for (int m = 0; m < N; ++m) rs += sqrt(sum_slots(a.slot_nrm + a.rb_off[m], a.rb_off[m + 1] - a.rb_off[m]));
-    if (t == 0) {
-      CgState* st = a.st;
-      st->beta = rz / st->rz;
-      st->rz = rz;
-      st->rsum = rs;
-      st->iters += 1;
-      if (!isfinite(rz) || !isfinite(rs)) {
-        st->status = CP_ENONFINITE;
-        st->done = 1;
-      } else if (!(rs > st->eps * st->gsum)) {
-        st->done = 1;
-      }
-    }
-  }
+  double v1[1] = {dot};
+  block_sum(v1);
+  if (t == 0) a.slot_wq[blockIdx.x] = v1[0];
 }
 
-__global__ void k_counter_reset(unsigned* c) {
-  if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+// After the last enqueued iteration: the state for cg_maxiter completed iterations.
+__global__ __launch_bounds__(512) void k_cg_final(CgArgs a, int maxiter) {
+  __shared__ int sdone;
+  if (threadIdx.x == 0) sdone = a.st->done;
+  const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(maxiter + 1) & 1];
+  RzShare sh;
+  load_rz(a, sh);
+  double rho, rsum, beta;
+  reduce_rz(a, sh, rho, rsum);
+  if (sdone) return;
+  cg_check(a, maxiter, rho, rho_old, rsum, gsum, eps, beta);
+  if (threadIdx.x == 0) a.st->done = 1;
+}
+
+int cg_tiles(const Plan& p) { return (p.R + 15) / 16; }
+
+int cg_row_blocks(const Plan& p) {
+  int nb = 0;
+  for (int n = 0; n < p.N; ++n) nb += (int)((p.s[n] + kCgRows - 1) / kCgRows);
+  return nb;
 }
 
 size_t cg_slot_bytes(const Plan& p) {
-  int64_t nb = 0;
-  for (int n = 0; n < p.N; ++n) nb += (p.s[n] + kRowBlk - 1) / kRowBlk;
-  return (size_t)(2 * nb) * sizeof(double) + 256;
+  return (size_t)3 * cg_row_blocks(p) * cg_tiles(p) * sizeof(double);
 }
 
-int cg_supported(const Plan& p) {
-  const size_t lds = (size_t)(2 * kRowBlk * p.R + (size_t)p.R * (p.R + 1)) * sizeof(double);
-  return p.R <= kMaxR && lds <= 150 * 1024;
+template <int KB, bool EVEN>
+static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<KB, true, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, 0);
+  for (int it = 0; it < maxiter; ++it) {
+    hipLaunchKernelGGL(k_cg_proj, dim3(N * a.TB * a.TB), dim3(512), 0, s, a, it);
+    hipLaunchKernelGGL((k_cg_matvec<KB, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, it);
+    hipLaunchKernelGGL((k_cg_update<KB, false, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, it);
+  }
+  hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(512), 0, s, a, maxiter);
 }
 
-// Enqueues the initialisation and cg_maxiter iterations.
+template <int KB>
+static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
+  if (a.d.R % 2 == 0) launch_kb<KB, true>(a, N, maxiter, s);
+  else launch_kb<KB, false>(a, N, maxiter, s);
+}
+
+// Enqueues CG initialisation, cg_maxiter iterations and the final state. R = -G must be in R0.
 int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
-              const double* pinv, double* V, double* Rv, double* Z, double* W0, double* W1,
-              double* Q, double* B, void* slots, CgState* st, double lambda, int maxiter,
-              hipStream_t s) {
+              const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
+              double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
+              int maxiter, hipStream_t s) {
   CgArgs a{};
   a.d = d;
   a.A64 = A64;
   a.gam = gam;
   a.pinv = pinv;
   a.V = V;
-  a.Rv = Rv;
+  a.Rv[0] = R0;
+  a.Rv[1] = R1;
   a.Z = Z;
   a.W[0] = W0;
   a.W[1] = W1;
@@ -419,29 +521,24 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
   a.B = B;
   a.st = st;
   a.lambda = lambda;
+  a.TB = cg_tiles(p);
   a.rb_off[0] = 0;
   for (int n = 0; n < p.N; ++n)
-    a.rb_off[n + 1] = a.rb_off[n] + (int)((p.s[n] + kRowBlk - 1) / kRowBlk);
-  a.nrowblk = a.rb_off[p.N];
-  a.slot_dot = (double*)slots;
-  a.slot_nrm = a.slot_dot + a.nrowblk;
-  a.counter = (unsigned*)((char*)slots + cg_slot_bytes(p) - 256);
-  const int R = p.R, TB = (R + kTile - 1) / kTile;
-  const size_t lds1 = (size_t)(kRowBlk * R + R * (R + 1)) * sizeof(double);
-  const size_t lds2 = (size_t)(2 * kRowBlk * R + R * (R + 1)) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_cg_init, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_cg_matvec, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_cg_update, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, s, a.counter);
-  hipLaunchKernelGGL(k_cg_init, dim3(a.nrowblk), dim3(256), lds1, s, a);
-  for (int it = 0; it < maxiter; ++it) {
-    hipLaunchKernelGGL(k_cg_proj, dim3(p.N * TB * TB), dim3(256), 0, s, a, it);
-    hipLaunchKernelGGL(k_cg_matvec, dim3(a.nrowblk), dim3(256), lds2, s, a, it);
-    hipLaunchKernelGGL(k_cg_update, dim3(a.nrowblk), dim3(256), lds1, s, a, it);
+    a.rb_off[n + 1] = a.rb_off[n] + (int)((p.s[n] + kCgRows - 1) / kCgRows);
+  a.nslot = a.rb_off[p.N] * a.TB;
+  a.slot_wq = (double*)slots;
+  a.slot_rz = a.slot_wq + a.nslot;
+  a.slot_nrm = a.slot_rz + a.nslot;
+  switch (a.TB) {
+    case 1: launch_kb<1>(a, p.N, maxiter, s); break;
+    case 2: launch_kb<2>(a, p.N, maxiter, s); break;
+    case 3: launch_kb<3>(a, p.N, maxiter, s); break;
+    case 4: launch_kb<4>(a, p.N, maxiter, s); break;
+    case 5: launch_kb<5>(a, p.N, maxiter, s); break;
+    case 6: launch_kb<6>(a, p.N, maxiter, s); break;
+    case 7: launch_kb<7>(a, p.N, maxiter, s); break;
+    case 8: launch_kb<8>(a, p.N, maxiter, s); break;
+    default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
 }
