@@ -224,20 +224,27 @@ def main():
         t20_64 = event_time(lambda: P.gn_step(X64d, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 3, stream)
         del A20
         A64 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
-        g64 = P.GaussNewton(X64d, A64, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        steps64, r64 = 0, 1.0
-        while steps64 < 300:
-            g64.step()
-            steps64 += 1
-            rr = P.residual(X64d, g64.A, out=resid, ws=g64.ws).cpu()
-            r64 = float(rr[0] / rr[1])
-            if r64 <= 1e-8:
-                break
-        ttt = dict(fp64_seconds=time.perf_counter() - t0, fp64_steps=steps64, fp64_residual=r64,
-                   mixed_seconds=None, fp64_gn_step_20cg_ms=t20_64 * 1e3)
-        log(f"[bench] FP64 time to 1e-8: {ttt['fp64_seconds']:.3f} s in {steps64} steps (r={r64:.2e})")
+        g64, h64 = P.gn_to_target(X64d, A64, 1e-8, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+        fp64_s = time.perf_counter() - t0
+        # mixed: FP32 storage until its residual is <= 1e-6 (or stalls near the FP32 rounding
+        # floor), then FP64 from the same factors and damping schedule
+        X32d = X64d.float()
+        A32 = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hmx = P.gn_mixed_to_target(X32d, X64d, A32, 1e-8, 1e-6,
+                                      P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+        mixed_s = time.perf_counter() - t0
+        n32 = sum(1 for p_, _ in hmx if p_ == "torch.float32")
+        ttt = dict(fp64_seconds=fp64_s, fp64_steps=len(h64), fp64_residual=h64[-1],
+                   mixed_seconds=mixed_s, mixed_steps_fp32=n32, mixed_steps_fp64=len(hmx) - n32,
+                   mixed_residual=hmx[-1][1], speedup=fp64_s / mixed_s,
+                   fp64_gn_step_20cg_ms=t20_64 * 1e3)
+        log(f"[bench] time to 1e-8: FP64 {fp64_s:.3f} s in {len(h64)} steps (r={h64[-1]:.2e}); "
+            f"mixed {mixed_s:.3f} s in {n32} FP32 + {len(hmx) - n32} FP64 steps (r={hmx[-1][1]:.2e})")
+        del X32d, A32
         del X64d, A64, g64
 
     # ---- CPU baseline: the oracle on host cores, bounded sample of the same workload

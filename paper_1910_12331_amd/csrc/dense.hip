@@ -508,16 +508,23 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
     T ar[MB][RS];
     ResBuf<T, MB, RS> bufA, bufB;
 
+    // Every load is issued unconditionally; X offsets are additive (a per-lane part, a
+    // per-(mb,v) wave-uniform part and the item's column) and clamped to the last element, and
+    // out-of-range values are skipped where they are consumed. A skipped or exec-masked load
+    // here would make the compiler wait for the whole outstanding prefetch.
+    const int64_t last = a.O * a.K - 1;
+    const int64_t lane_row = (int64_t)Mfma<T>::out_row(lane, 0) * a.K + m;
+    const int dv = Mfma<T>::out_row(0, 1);   // row step between accumulator elements
     auto load = [&](ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
 #pragma unroll
       for (int s = 0; s < RS; ++s) bf.b[s] = B[(kk * RS + s) * kWave + lane];
-      const int64_t col = kk * 16 + m;
+      const int64_t off0 = tt * 16 * MB * a.K + kk * 16 + lane_row;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
-          bf.x[mb][v] = (o < a.O && col < a.K) ? X[o * a.K + col] : T(0);
+          const int64_t off = off0 + (int64_t)(16 * mb + dv * v) * a.K;
+          bf.x[mb][v] = X[off < last ? off : last];
         }
     };
     auto advance = [&](int64_t& tt, int64_t& kk) {
@@ -545,22 +552,43 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
       }
     };
     auto consume = [&](const ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
-      const int64_t col = kk * 16 + m;
+      // The MB accumulation chains are interleaved so that consecutive matrix instructions
+      // are independent.
+      v4 acc[MB];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        v4 acc = v4{0, 0, 0, 0};
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = v4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < RS; ++s) acc = Mfma<T>::mac(ar[mb][s], bf.b[s], acc);
+      for (int s = 0; s < RS; ++s)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
-          if (o < a.O && col < a.K) {
-            const double x = (double)bf.x[mb][v];
-            const double df = x - (double)acc[v];
-            d2 += df * df;
-            x2 += x * x;
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = Mfma<T>::mac(ar[mb][s], bf.b[s], acc[mb]);
+      if ((tt + 1) * 16 * MB <= a.O && (kk + 1) * 16 <= a.K) {
+        // Full tile: the 16 squares of this lane are summed in the tensor precision (exact
+        // differences near a fit), then added to the FP64 totals.
+        T dsq = T(0), xsq = T(0);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T x = bf.x[mb][v];
+            const T df = x - acc[mb][v];
+            dsq = fma(df, df, dsq);
+            xsq = fma(x, x, xsq);
           }
-        }
+        d2 += (double)dsq;
+        x2 += (double)xsq;
+      } else {
+        const int64_t col = kk * 16 + m;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
+            const bool ok = o < a.O && col < a.K;
+            const double x = ok ? (double)bf.x[mb][v] : 0.0;
+            const double df = x - (ok ? (double)acc[mb][v] : 0.0);
+            d2 = fma(df, df, d2);
+            x2 = fma(x, x, x2);
+          }
       }
     };
 
@@ -568,7 +596,8 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
     advance(tn, kbn);
     int64_t i = i0;
     while (true) {
-      if (i + 1 < i1) load(bufB, tn, kbn);
+      bool more = i + 1 < i1;   // past the range, the current item is loaded again (unused)
+      load(bufB, more ? tn : t, more ? kbn : kb);
       advance(tn, kbn);
       if (t != tile_built) {
         build(t);
@@ -577,7 +606,8 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
       consume(bufA, t, kb);
       advance(t, kb);
       if (++i >= i1) break;
-      if (i + 1 < i1) load(bufA, tn, kbn);
+      more = i + 1 < i1;
+      load(bufA, more ? tn : t, more ? kbn : kb);
       advance(tn, kbn);
       if (t != tile_built) {
         build(t);

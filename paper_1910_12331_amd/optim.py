@@ -91,3 +91,52 @@ class ALS:
     def residual(self) -> float:
         r = api.residual(self.X, self.A, ws=self.ws).cpu()
         return float(r[0] / r[1])
+
+
+def gn_to_target(X, A, target, config: GNConfig | None = None, max_steps: int = 300):
+    """Gauss-Newton steps on (X, A) until the direct relative residual is <= target or
+    max_steps steps were taken. The residual is read after every step (one host
+    synchronisation per step). Returns (optimizer, list of per-step residuals)."""
+    opt = GaussNewton(X, A, config)
+    hist = []
+    while opt.steps < max_steps:
+        opt.step()
+        hist.append(opt.residual())
+        if hist[-1] <= target:
+            break
+    return opt, hist
+
+
+def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
+                       config: GNConfig | None = None, max_steps: int = 300):
+    """Mixed-precision Gauss-Newton run to a residual target below the low precision's floor.
+
+    Steps run on X_low (e.g. FP32 storage, half the bytes and twice the matrix-core rate of
+    FP64) until its relative residual is <= switch_residual, or stops halving once below 1e-4
+    (the storage rounding floor is near); the factors are then cast to X_high's precision and
+    the same damping schedule continues on X_high until the residual is <= target. X_low and
+    X_high hold the same tensor. Returns (factors, history of (precision, residual))."""
+    cfg = config or GNConfig()
+    sched = cfg.schedule or DampingSchedule()
+    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched)
+    opt = GaussNewton(X_low, A, low_cfg)
+    hist = []
+    prev = float("inf")
+    while opt.steps < max_steps:
+        opt.step()
+        r = opt.residual()
+        hist.append((str(X_low.dtype), r))
+        if r <= target or r <= switch_residual or (r < 1e-4 and r > 0.5 * prev):
+            break
+        prev = r
+    if hist and hist[-1][1] <= target:
+        return opt.A, hist
+    A_high = [a.to(X_high.dtype) for a in opt.A]
+    high = GaussNewton(X_high, A_high, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched))
+    while opt.steps + high.steps < max_steps:
+        high.step()
+        r = high.residual()
+        hist.append((str(X_high.dtype), r))
+        if r <= target:
+            break
+    return high.A, hist
