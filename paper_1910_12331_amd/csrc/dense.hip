@@ -38,37 +38,6 @@ __device__ __forceinline__ bool state_done(const CgState* st) {
   return *(volatile const int32_t*)&st->done != 0;
 }
 
-// ------------------------------------------------------------------------------------------
-// C(n) = X(n)^T Y(n) for every mode (R x R, FP64). 16x16 output tile per workgroup, rows of
-// X and Y staged through LDS 16 at a time. Used for the Grams (Y = X) and for the CG
-// projections B(p) = A(p)^T W(p).
-// ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram2(Dims d, const double* __restrict__ Xp,
-                                               const double* __restrict__ Yp, double* __restrict__ C,
-                                               int mode_only, const CgState* st) {
-  if (st && state_done(st)) return;
-  const int n = mode_only >= 0 ? mode_only : blockIdx.z;
-  const int R = d.R;
-  const int tiles = (R + 15) / 16;
-  const int r0 = 16 * (blockIdx.x % tiles), z0 = 16 * (blockIdx.x / tiles);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __shared__ double xs[16][17], ys[16][17];
-  const double* X = Xp + d.off[n] * R;
-  const double* Y = Yp + d.off[n] * R;
-  const int64_t s = d.s[n];
-  double acc = 0.0;
-  for (int64_t k0 = 0; k0 < s; k0 += 16) {
-    const int64_t k = k0 + ty;
-    xs[ty][tx] = (k < s && r0 + tx < R) ? X[k * R + r0 + tx] : 0.0;
-    ys[ty][tx] = (k < s && z0 + tx < R) ? Y[k * R + z0 + tx] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc += xs[kk][ty] * ys[kk][tx];
-    __syncthreads();
-  }
-  if (r0 + ty < R && z0 + tx < R) C[((int64_t)n * R + r0 + ty) * R + z0 + tx] = acc;
-}
-
 // Gam[n][p] = Hadamard product of S(m) over m not in {n, p} (all-ones when empty), eq. (6).
 __global__ void k_gamma(Dims d, const double* __restrict__ S, double* __restrict__ Gam) {
   const int R = d.R, N = d.N;
@@ -344,14 +313,6 @@ __global__ void k_status_out(const CgState* st, int32_t* out) {
   if (threadIdx.x == 0) *out = st->status;
 }
 
-// ------------------------------------------------------------------------------------------
-// P = (G + lambda I)^-1 for an R x R SPD matrix, one workgroup per matrix, in LDS:
-// right-looking Cholesky G + lambda I = L L^T in place (pivots must be positive), then L^-1
-// by forward elimination overwriting L, then P = L^-T L^-1. Both sweeps take one barrier per
-// column: the scaling of column (row) j is deferred to step j+1, where nothing reads it, and
-// the column the elimination needs next is copied one step ahead. The 256 threads sweep the
-// trailing triangle as a 16 x 16 grid.
-// A non-positive pivot records CP_ENOTSPD and marks the state done.
 // ------------------------------------------------------------------------------------------
 // P = (G + lambda I)^-1 for an R x R SPD matrix (R <= 128), one workgroup per matrix, FP64.
 // In-place Gauss-Jordan inversion without pivoting: for an SPD matrix its pivots are the
@@ -727,11 +688,14 @@ int grid1(int64_t n, int cap) {
   return (int)g;
 }
 
+void launch_gram_mfma(const Dims&, const double*, const double*, double*, int, const CgState*,
+                      hipStream_t);
+void launch_rowmm_mfma(const Dims&, const RowMM&, const CgState*, hipStream_t);
+int rowmm_mfma_blocks(const Dims&);
+
 void launch_gram2(const Dims& d, const double* X, const double* Y, double* C, int mode_only,
                   const CgState* st, hipStream_t s) {
-  const int tiles = (d.R + 15) / 16;
-  dim3 grid(tiles * tiles, 1, mode_only >= 0 ? 1 : d.N);
-  hipLaunchKernelGGL(k_gram2, grid, dim3(256), 0, s, d, X, Y, C, mode_only, st);
+  launch_gram_mfma(d, X, Y, C, mode_only, st, s);
 }
 
 void launch_gamma(const Dims& d, const double* S, double* Gam, hipStream_t s) {
@@ -746,12 +710,17 @@ void launch_ycore(const Dims& d, const double* Gam, const double* B, double* Y, 
 }
 
 int rowmm_blocks(const Dims& d) {
+  if (d.R <= 128) return rowmm_mfma_blocks(d);
   int64_t mx = 0;
   for (int n = 0; n < d.N; ++n) mx = d.s[n] > mx ? d.s[n] : mx;
   return grid1(mx * d.R, 256);
 }
 
 void launch_rowmm(const Dims& d, const RowMM& a, const CgState* st, hipStream_t s) {
+  if (d.R <= 128) {
+    launch_rowmm_mfma(d, a, st, s);
+    return;
+  }
   dim3 grid(rowmm_blocks(d), a.mode_only >= 0 ? 1 : d.N);
   hipLaunchKernelGGL(k_rowmm, grid, dim3(256), 0, s, d, a, st);
 }

@@ -26,14 +26,12 @@
 // contraction (K = R padded to 16 KB): its operands are loaded straight from memory into
 // registers, all in one batch, while the shared 16-column slice of the R x R operand goes
 // through LDS.
-#include "cpgn_internal.h"
+#include "mfma64.h"
 
 namespace cpgn {
 
 constexpr int kCgRows = 64;     // rows per workgroup in init / matvec / update (4 wavefronts)
 constexpr int kProjWaves = 8;   // wavefronts per B(p) tile in k_cg_proj
-
-typedef double dv4 __attribute__((ext_vector_type(4)));
 
 struct CgArgs {
   Dims d;
@@ -55,30 +53,6 @@ struct CgArgs {
   int nslot;              // row blocks x TB
   int rb_off[kMaxOrder + 1];
 };
-
-// Sum of v[0..NV) over the workgroup; every thread receives the same bits. Lanes combine by an
-// xor butterfly (each pairwise sum is formed identically in both partners), then wavefront
-// partials are added in wavefront order.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-  __shared__ double red[16][NV];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-    for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[wv][i] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w][i];
-    v[i] = s;
-  }
-  __syncthreads();
-}
 
 // Per-thread share of the previous init / update launch's partials (slot order is mode-major):
 // v[0] gathers <R,Z>, v[1 + n] gathers ||R(n)||^2. The loads of all slots go out together.
@@ -133,35 +107,6 @@ __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, do
     }
   }
   return stop;
-}
-
-// Contraction index of MFMA step j for lane group g: steps come in pairs that read two
-// adjacent k (one 16-byte load per lane), k = 8 (j / 2) + 2 g + (j % 2).
-__device__ __forceinline__ int kstep(int j, int g) { return 8 * (j >> 1) + 2 * g + (j & 1); }
-
-// LDS index of element (k, c) of a K x 16 operand slice: rows in pairs, each pair followed by a
-// padding row, so that the four lane groups (k = 8j + 2g + e) read alternate bank halves.
-__device__ __forceinline__ int sidx(int k, int c) { return (k + (k >> 1)) * 16 + c; }
-constexpr int slice_elems(int KP) { return (KP + KP / 2) * 16; }
-
-// Operand row r[0..KQ) of lane group g: elements kstep(j, g) of `row` (zero past R or when the
-// row is outside the mode). EVEN: R is even, so each pair is one aligned 16-byte load.
-template <int KQ, bool EVEN>
-__device__ __forceinline__ void load_oprow(double (&r)[KQ], const double* row, bool rowok, int R,
-                                           int g) {
-#pragma unroll
-  for (int j = 0; j < KQ; j += 2) {
-    const int k = kstep(j, g);
-    if (EVEN) {
-      double2 v = make_double2(0.0, 0.0);
-      if (rowok && k < R) v = *reinterpret_cast<const double2*>(row + k);
-      r[j] = v.x;
-      r[j + 1] = v.y;
-    } else {
-      r[j] = rowok && k < R ? row[k] : 0.0;
-      r[j + 1] = rowok && k + 1 < R ? row[k + 1] : 0.0;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------------------------
