@@ -81,6 +81,16 @@ __device__ __forceinline__ void reduce_rz(const CgArgs& a, RzShare& sh, double& 
   for (int n = 0; n < a.d.N; ++n) rsum += sqrt(sh.v[1 + n]);
 }
 
+// True in every thread of the workgroup when CG has stopped. One thread reads the flag (another
+// workgroup of the same launch may be setting it) and the barrier hands its value to all, so
+// the early return is uniform; a stopped launch returns before loading anything else.
+__device__ __forceinline__ bool cg_stopped(const CgState* st) {
+  __shared__ int sdone;
+  if (threadIdx.x == 0) sdone = __builtin_nontemporal_load(&st->done);
+  __syncthreads();
+  return sdone != 0;
+}
+
 // Records the CG state before iteration `it` (it iterations done) and decides whether to stop.
 // Called by every workgroup with identical inputs; workgroup 0 writes.
 __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, double rho_old,
@@ -131,8 +141,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   const double* Rin = a.Rv[it & 1];
   double* Rout = a.Rv[(it + 1) & 1];
   const double* W = a.W[(it + 1) & 1];
-  __shared__ int sdone;
-  if (t == 0) sdone = a.st->done;   // read once per workgroup: workgroup 0 may set it meanwhile
+  if (cg_stopped(a.st)) return;
   const double rho = INIT ? 0.0 : a.st->rho[it & 1];
 
   // Operand rows: row k0 + m, k = kstep(j, g).
@@ -167,10 +176,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
     for (int i = t; i < a.nslot; i += 256) v1[0] += a.slot_wq[i];
     block_sum(v1);
     wq = v1[0];
-  } else {
-    __syncthreads();
   }
-  if (sdone) return;
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     const int e = t + 256 * i;
@@ -264,18 +270,15 @@ __global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
   const int64_t q0 = wv * per, q1 = q0 + per < nsteps ? q0 + per : nsteps;
   const bool rok = r0 + m < R, zok = z0 + m < R;
   const bool store_w = rt == 0 && zok;
+  if (cg_stopped(a.st)) return;
   // The first batch of rows is requested before the scalars it waits for.
   ProjBatch b;
   proj_load(b, a, Wold, it, q0, q1, s, base, R, r0, z0, m, g, rok, zok);
-
-  __shared__ int sdone;
-  if (t == 0) sdone = a.st->done;   // read once per workgroup: workgroup 0 may set it meanwhile
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(it + 1) & 1];
   RzShare sh;
   load_rz(a, sh);
   double rho, rsum, beta;
-  reduce_rz(a, sh, rho, rsum);      // its barriers publish sdone
-  if (sdone) return;
+  reduce_rz(a, sh, rho, rsum);
   if (cg_check(a, it, rho, rho_old, rsum, gsum, eps, beta)) return;
 
   dv4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -323,8 +326,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows + wv * 16;
   const int64_t rbase = a.d.off[n];
   const double* W = a.W[(it + 1) & 1];
-  __shared__ int sdone;
-  if (t == 0) sdone = a.st->done;   // no workgroup writes it during this launch
+  if (cg_stopped(a.st)) return;
 
   const bool rowok = k0 + m < s;
   double wo[KQ], ao[KQ];
@@ -380,7 +382,6 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
     Ys[sidx(k, c)] = ys[i];
   }
   __syncthreads();
-  if (sdone) return;
   dv4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < KQ; ++j)
@@ -405,14 +406,12 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
 
 // After the last enqueued iteration: the state for cg_maxiter completed iterations.
 __global__ __launch_bounds__(512) void k_cg_final(CgArgs a, int maxiter) {
-  __shared__ int sdone;
-  if (threadIdx.x == 0) sdone = a.st->done;
+  if (cg_stopped(a.st)) return;
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(maxiter + 1) & 1];
   RzShare sh;
   load_rz(a, sh);
   double rho, rsum, beta;
   reduce_rz(a, sh, rho, rsum);
-  if (sdone) return;
   cg_check(a, maxiter, rho, rho_old, rsum, gsum, eps, beta);
   if (threadIdx.x == 0) a.st->done = 1;
 }
