@@ -424,7 +424,7 @@ __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restric
 struct ResArgs {
   const void* X;
   const void* apad[kMaxOrder];  // [s_m][Rp] compute precision
-  const void* bpk;              // [K/16][RS][64]: A(N)[16kb + lane%16][4s + lane/16]
+  const void* bpk;              // [K/16][RS][64]: A(N)[16kb + lane%16][(lane/16) RS + s]
   int64_t O, K, KB;
   int64_t s[kMaxOrder];
   int N, Rp;
@@ -433,96 +433,166 @@ struct ResArgs {
 
 // Direct residual (Section 5): ||X - [[A]]||^2 and ||X||^2 in one pass over X. X is viewed as
 // [O][K] with K = s_N; the reconstruction is the product of the Khatri-Rao rows of the first N-1
-// factors (O x R, built in registers) with A(N)^T, on the matrix cores. Work items are
-// (16 MB-row tile, 16-column block) pairs in tile-major order; wavefront w owns the contiguous
-// item range [w I / W, (w+1) I / W), so the load is balanced to one item. The next item's
-// B fragment and X values are requested before the current item's products (ping-pong
-// buffers); the Khatri-Rao rows are rebuilt only when the tile changes.
+// factors (O x R, built in registers) with A(N)^T, on the matrix cores.
+// A workgroup owns a group of four 16 MB-row tiles (one per wavefront) and walks the 16-column
+// blocks kb of its item range [b I / B, (b+1) I / B) over (group, kb) items in group-major
+// order, so that the load is balanced to one item. The B fragment of column block kb (the
+// packed last factor) is shared by the four wavefronts through LDS: each thread loads one
+// 1/256 share for the next item while the current one is multiplied, and a barrier per item
+// publishes it. X values of the next item are requested before the current item's products
+// (ping-pong registers); the Khatri-Rao rows are rebuilt only when the group changes.
 template <typename T> struct ResCfg;
 template <> struct ResCfg<float> { static constexpr int MB = 4, OCC = 2; };
 template <> struct ResCfg<double> { static constexpr int MB = 2, OCC = 1; };
 
-template <typename T, int MB, int RS>
-struct ResBuf {
-  T b[RS];
+template <typename T, int MB>
+struct ResX {
   T x[MB][4];
 };
 
-template <typename T, int NBR>
+// FP32 multiplies with the operands swapped (the B fragment as A operand, the Khatri-Rao rows
+// as B operand), which leaves lane 16 g + m with reconstructed entries (row m, columns 4 g + v):
+// four consecutive columns of one X row, read with one 16-byte load when K is a multiple of 4
+// (VX). FP64 keeps the direct form (its accumulator layout strides rows by 4).
+template <typename T, int NBR, bool VX>
 __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   constexpr int MB = ResCfg<T>::MB;
-  constexpr int RS = 4 * NBR;
+  constexpr bool SWAP = sizeof(T) == 4;
+  constexpr int RS = 4 * NBR;          // MFMA steps (R padded to 16 NBR, 4 per step)
+  constexpr int BSH = RS * kWave / 256;   // B elements per thread per item (= NBR)
   typedef typename Mfma<T>::v4 v4;
-  const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  __shared__ T bs[2][RS * kWave];
+  struct ResB {
+    T v[BSH];
+  };
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, m = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const T* X = (const T*)a.X;
   const T* B = (const T*)a.bpk;
   const int64_t ntiles = (a.O + 16 * MB - 1) / (16 * MB);
-  const int64_t nitems = ntiles * a.KB;
-  const int64_t i0 = wave * nitems / nwaves, i1 = (wave + 1) * nitems / nwaves;
+  const int64_t ngroups = (ntiles + 3) / 4;
+  const int64_t nitems = ngroups * a.KB;
+  const int64_t i0 = blockIdx.x * nitems / gridDim.x, i1 = (blockIdx.x + 1) * nitems / gridDim.x;
   double d2 = 0.0, x2 = 0.0;
   if (i0 < i1) {
-    int64_t t = i0 / a.KB, kb = i0 - t * a.KB;   // position of item i
-    int64_t tn = t, kbn = kb;                      // position of the item being prefetched
-    int64_t tile_built = -1;
-    T ar[MB][RS];
-    ResBuf<T, MB, RS> bufA, bufB;
-
-    // Every load is issued unconditionally; X offsets are additive (a per-lane part, a
-    // per-(mb,v) wave-uniform part and the item's column) and clamped to the last element, and
-    // out-of-range values are skipped where they are consumed. A skipped or exec-masked load
-    // here would make the compiler wait for the whole outstanding prefetch.
     const int64_t last = a.O * a.K - 1;
     const int64_t lane_row = (int64_t)Mfma<T>::out_row(lane, 0) * a.K + m;
     const int dv = Mfma<T>::out_row(0, 1);   // row step between accumulator elements
-    auto load = [&](ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
+    T ar[MB][RS];
+    ResB bn;
+    ResX<T, MB> xa, xb;
+    int64_t grp = i0 / a.KB, kb = i0 - grp * a.KB;   // item being multiplied
+    int64_t gn = grp, kbn = kb;                      // item being prefetched
+    int64_t built = -1;
+
+    auto load_b = [&](ResB& bn, int64_t kk) {
 #pragma unroll
-      for (int s = 0; s < RS; ++s) bf.b[s] = B[(kk * RS + s) * kWave + lane];
-      const int64_t off0 = tt * 16 * MB * a.K + kk * 16 + lane_row;
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t off = off0 + (int64_t)(16 * mb + dv * v) * a.K;
-          bf.x[mb][v] = X[off < last ? off : last];
-        }
+      for (int j = 0; j < BSH; ++j) bn.v[j] = B[kk * RS * kWave + t + 256 * j];
     };
-    auto advance = [&](int64_t& tt, int64_t& kk) {
-      if (++kk == a.KB) {
-        kk = 0;
-        ++tt;
+    auto store_b = [&](const ResB& bn, int buf) {
+#pragma unroll
+      for (int j = 0; j < BSH; ++j) bs[buf][t + 256 * j] = bn.v[j];
+    };
+    // X of item (gg, kk) for this wavefront's tile; every load is issued from a clamped offset
+    // (out-of-range values are skipped where consumed).
+    auto load_x = [&](ResX<T, MB>& xr, int64_t gg, int64_t kk) {
+      const int64_t tile = gg * 4 + wv;
+      if constexpr (SWAP) {
+        // entries (row 16 mb + m, columns 4 g + v) of the tile
+        const int64_t off0 = (tile * 16 * MB + m) * a.K + kk * 16 + 4 * g;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int64_t off = off0 + (int64_t)(16 * mb) * a.K;
+          if constexpr (VX) {
+            typedef T tv4 __attribute__((ext_vector_type(4)));
+            const tv4 w = *(const tv4*)(X + (off < last - 3 ? off : last - 3));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xr.x[mb][v] = w[v];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xr.x[mb][v] = X[off + v < last ? off + v : last];
+          }
+        }
+      } else {
+        const int64_t off0 = tile * 16 * MB * a.K + kk * 16 + lane_row;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t off = off0 + (int64_t)(16 * mb + dv * v) * a.K;
+            xr.x[mb][v] = X[off < last ? off : last];
+          }
       }
     };
-    auto build = [&](int64_t tt) {
+    auto advance = [&](int64_t& gg, int64_t& kk) {
+      if (++kk == a.KB) {
+        kk = 0;
+        ++gg;
+      }
+    };
+    // Khatri-Rao rows of this wavefront's tile: lane (g, m) holds, for row 16 mb + m, the
+    // contiguous k-range [g RS, (g+1) RS) of the padded factor rows (16-byte loads). The first
+    // factor's rows for all sub-tiles are requested together; each further factor multiplies in.
+    auto build = [&](int64_t gg) {
+      constexpr int VW = 16 / (int)sizeof(T);
+      typedef T tvw __attribute__((ext_vector_type(VW)));
+      const int64_t tile = gg * 4 + wv;
+      // Mixed-radix digits of row tile*16MB + r: the tile's first row is split once (wave-
+      // uniform), each lane then adds its offset r = 16 mb + m < 64 digit by digit with small
+      // 32-bit carries. Rows past O read factor row 0; the epilogue skips them.
+      int64_t brem = tile * 16 * MB;
+      uint32_t carry[MB];
+      bool in[MB];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const int64_t o = tt * 16 * MB + 16 * mb + m;
+        carry[mb] = 16 * mb + m;
+        in[mb] = brem + 16 * mb + m < a.O;
+      }
+      for (int q = a.N - 2; q >= 0; --q) {
+        const int64_t sq = a.s[q];
+        const uint32_t bd = (uint32_t)(brem % sq);
+        brem /= sq;
+        const uint32_t s32 = (uint32_t)sq;
+        const bool first = q == a.N - 2;
 #pragma unroll
-        for (int s = 0; s < RS; ++s) ar[mb][s] = (o < a.O) ? T(1) : T(0);
-        if (o < a.O) {
-          int64_t rem = o;
-          for (int q = a.N - 2; q >= 0; --q) {
-            const int64_t idx = rem % a.s[q];
-            rem /= a.s[q];
-            const T* row = (const T*)a.apad[q] + idx * a.Rp + g;
+        for (int mb = 0; mb < MB; ++mb) {
+          const uint32_t tq = bd + carry[mb];
+          const uint32_t idx = in[mb] ? tq % s32 : 0u;
+          carry[mb] = tq / s32;
+          const T* row = (const T*)a.apad[q] + (int64_t)idx * a.Rp + g * RS;
+          if (first) {   // loaded straight into the operand registers
 #pragma unroll
-            for (int s = 0; s < RS; ++s) ar[mb][s] *= row[4 * s];
+            for (int s = 0; s < RS; s += VW) {
+              const tvw w = *(const tvw*)(row + s);
+#pragma unroll
+              for (int u = 0; u < VW; ++u) ar[mb][s + u] = w[u];
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < RS; s += VW) {
+              const tvw w = *(const tvw*)(row + s);
+#pragma unroll
+              for (int u = 0; u < VW; ++u) ar[mb][s + u] *= w[u];
+            }
+            // one sub-tile's factor row in flight at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
     };
-    auto consume = [&](const ResBuf<T, MB, RS>& bf, int64_t tt, int64_t kk) {
-      // The MB accumulation chains are interleaved so that consecutive matrix instructions
-      // are independent.
+    auto consume = [&](const ResX<T, MB>& xr, int buf, int64_t gg, int64_t kk) {
+      const int64_t tile = gg * 4 + wv;
       v4 acc[MB];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[mb] = v4{0, 0, 0, 0};
 #pragma unroll
-      for (int s = 0; s < RS; ++s)
+      for (int s = 0; s < RS; ++s) {
+        const T b = bs[buf][s * kWave + lane];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = Mfma<T>::mac(ar[mb][s], bf.b[s], acc[mb]);
-      if ((tt + 1) * 16 * MB <= a.O && (kk + 1) * 16 <= a.K) {
+        for (int mb = 0; mb < MB; ++mb)
+          acc[mb] = SWAP ? Mfma<T>::mac(b, ar[mb][s], acc[mb]) : Mfma<T>::mac(ar[mb][s], b, acc[mb]);
+      }
+      if ((tile + 1) * 16 * MB <= a.O && (kk + 1) * 16 <= a.K) {
         // Full tile: the 16 squares of this lane are summed in the tensor precision (exact
         // differences near a fit), then added to the FP64 totals.
         T dsq = T(0), xsq = T(0);
@@ -530,7 +600,7 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const T x = bf.x[mb][v];
+            const T x = xr.x[mb][v];
             const T df = x - acc[mb][v];
             dsq = fma(df, df, dsq);
             xsq = fma(x, x, xsq);
@@ -538,44 +608,48 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
         d2 += (double)dsq;
         x2 += (double)xsq;
       } else {
-        const int64_t col = kk * 16 + m;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int64_t o = tt * 16 * MB + 16 * mb + Mfma<T>::out_row(lane, v);
+            const int64_t o = tile * 16 * MB + 16 * mb + (SWAP ? m : Mfma<T>::out_row(lane, v));
+            const int64_t col = kk * 16 + (SWAP ? 4 * g + v : m);
             const bool ok = o < a.O && col < a.K;
-            const double x = ok ? (double)bf.x[mb][v] : 0.0;
+            const double x = ok ? (double)xr.x[mb][v] : 0.0;
             const double df = x - (ok ? (double)acc[mb][v] : 0.0);
             d2 = fma(df, df, d2);
             x2 = fma(x, x, x2);
           }
       }
     };
+    // One item: request the next one (its B share and X values; past the range the current item
+    // again, unused), multiply the current one with the B fragment in LDS slot buf, publish the
+    // next B fragment in the other slot.
+    auto step = [&](ResX<T, MB>& cur, ResX<T, MB>& nxt, int buf, int64_t i) {
+      const bool more = i + 1 < i1;
+      load_b(bn, more ? kbn : kb);
+      load_x(nxt, more ? gn : grp, more ? kbn : kb);
+      advance(gn, kbn);
+      if (grp != built) {
+        build(grp);
+        built = grp;
+      }
+      consume(cur, buf, grp, kb);
+      advance(grp, kb);
+      store_b(bn, buf ^ 1);
+      __syncthreads();
+    };
 
-    load(bufA, tn, kbn);
-    advance(tn, kbn);
+    load_b(bn, kbn);
+    load_x(xa, gn, kbn);
+    advance(gn, kbn);
+    store_b(bn, 0);
+    __syncthreads();
     int64_t i = i0;
     while (true) {
-      bool more = i + 1 < i1;   // past the range, the current item is loaded again (unused)
-      load(bufB, more ? tn : t, more ? kbn : kb);
-      advance(tn, kbn);
-      if (t != tile_built) {
-        build(t);
-        tile_built = t;
-      }
-      consume(bufA, t, kb);
-      advance(t, kb);
+      step(xa, xb, 0, i);
       if (++i >= i1) break;
-      more = i + 1 < i1;
-      load(bufA, more ? tn : t, more ? kbn : kb);
-      advance(tn, kbn);
-      if (t != tile_built) {
-        build(t);
-        tile_built = t;
-      }
-      consume(bufB, t, kb);
-      advance(t, kb);
+      step(xb, xa, 1, i);
       if (++i >= i1) break;
     }
   }
@@ -586,7 +660,8 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   }
 }
 
-// Pack the last factor for the residual B operand: bpk[kb][s][lane] = A[16kb + m][4s + g].
+// Pack the last factor for the residual's B fragments: bpk[kb][s][lane] = A[16kb + m][g RS + s]
+// (lane group g owns the contiguous k-range [g RS, (g+1) RS) of the contraction).
 template <typename T>
 __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, int64_t KB,
                             T* __restrict__ bpk) {
@@ -599,7 +674,7 @@ __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, 
     const int s = (int)(rest % RS);
     const int64_t kb = rest / RS;
     const int64_t k = 16 * kb + (lane & 15);
-    bpk[e] = k < K ? apad_last[k * Rp + 4 * s + (lane >> 4)] : T(0);
+    bpk[e] = k < K ? apad_last[k * Rp + (lane >> 4) * RS + s] : T(0);
   }
 }
 
@@ -826,12 +901,16 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     a.bpk = ws + p.off_part;
     hipLaunchKernelGGL(k_pack_last<T>, dim3(grid1(a.KB * p.Rp / 4 * kWave, 1024)), dim3(256), 0,
                        s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part));
-    const int64_t items = (a.O + 16 * MB - 1) / (16 * MB) * a.KB;
-    int64_t blocks = (items + 3) / 4;
+    const int64_t items = ((a.O + 16 * MB - 1) / (16 * MB) + 3) / 4 * a.KB;
+    int64_t blocks = items;
     if (blocks > ResCfg<T>::OCC * kNumCU) blocks = ResCfg<T>::OCC * kNumCU;   // one resident round
+    const bool vx = a.K % 4 == 0 && ((uintptr_t)X % 16) == 0;
     switch (p.NBt) {
-#define CPGN_RES(k) \
-  case k: hipLaunchKernelGGL((k_residual<T, k>), dim3(blocks), dim3(256), 0, s, a); break;
+#define CPGN_RES(k)                                                                         \
+  case k:                                                                                   \
+    if (vx) hipLaunchKernelGGL((k_residual<T, k, true>), dim3(blocks), dim3(256), 0, s, a);  \
+    else hipLaunchKernelGGL((k_residual<T, k, false>), dim3(blocks), dim3(256), 0, s, a);    \
+    break;
       CPGN_RES(1) CPGN_RES(2) CPGN_RES(3) CPGN_RES(4) CPGN_RES(5) CPGN_RES(6) CPGN_RES(7)
       CPGN_RES(8)
 #undef CPGN_RES
