@@ -442,7 +442,7 @@ struct ResArgs {
 // publishes it. X values of the next item are requested before the current item's products
 // (ping-pong registers); the Khatri-Rao rows are rebuilt only when the group changes.
 template <typename T> struct ResCfg;
-template <> struct ResCfg<float> { static constexpr int MB = 4, OCC = 2; };
+template <> struct ResCfg<float> { static constexpr int MB = 3, OCC = 2; };
 template <> struct ResCfg<double> { static constexpr int MB = 2, OCC = 1; };
 
 template <typename T, int MB>
