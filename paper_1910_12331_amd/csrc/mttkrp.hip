@@ -195,11 +195,16 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
   };
   auto consume = [&](Buf& b, int64_t chunk) {
     if constexpr (!PF) load_f<T, NB>(F, a, chunk, lane, b.f);
+    // B operands of all four substeps are formed before the first product, so no multiply
+    // waits on (or stalls) the matrix instructions reading the previous substep's operands.
+    T bt4[4][NB];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) bt4[t][nb] = DT ? b.f[nb][t] : b.f[nb][t] * kro[nb];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      T bt[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) bt[nb] = DT ? b.f[nb][t] : b.f[nb][t] * kro[nb];
+      const T* bt = bt4[t];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
