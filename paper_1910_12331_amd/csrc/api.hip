@@ -14,16 +14,9 @@ void launch_gram2(const Dims&, const double*, const double*, double*, int, const
 void launch_gamma(const Dims&, const double*, double*, hipStream_t);
 void launch_ycore(const Dims&, const double*, const double*, double*, const CgState*, hipStream_t);
 int rowmm_blocks(const Dims&);
-void launch_cg_axpy(const Dims&, double*, double*, const double*, const double*, double*,
-                    const CgState*, hipStream_t);
-void launch_cg_wupdate(int64_t, double*, const double*, const CgState*, hipStream_t);
-void launch_fill(int64_t, double*, double, hipStream_t);
 void launch_to64(const Dims&, const PerMode<const void*>&, int, double*, hipStream_t);
 void launch_fin_grad(const Dims&, int, const double*, CgState*, double, double*, hipStream_t);
 void launch_state_reset(CgState*, hipStream_t);
-void launch_fin_cginit(const Dims&, int, const double*, CgState*, hipStream_t);
-void launch_fin_alpha(const Dims&, int, const double*, CgState*, hipStream_t);
-void launch_fin_beta(const Dims&, int, const double*, const double*, CgState*, hipStream_t);
 void launch_gn_apply(const Dims&, double*, const double*, const PerMode<void*>&, int, double*,
                      const CgState*, hipStream_t);
 void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stats*, hipStream_t);

@@ -126,43 +126,6 @@ __global__ __launch_bounds__(256) void k_rowmm(Dims d, RowMM a, const CgState* s
   }
 }
 
-// V += alpha W; R -= alpha Q; partial ||R(n)||^2 per workgroup (grid.y = mode).
-__global__ __launch_bounds__(256) void k_cg_axpy(Dims d, double* __restrict__ V, double* __restrict__ Rv,
-                                                 const double* __restrict__ W,
-                                                 const double* __restrict__ Q, double* red_nrm,
-                                                 const CgState* st) {
-  if (state_done(st)) return;
-  const int n = blockIdx.y;
-  const double alpha = st->alpha;
-  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
-  double nrm = 0.0, dummy = 0.0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    V[base + e] += alpha * W[base + e];
-    const double r = Rv[base + e] - alpha * Q[base + e];
-    Rv[base + e] = r;
-    nrm += r * r;
-  }
-  block_sum2(nrm, dummy);
-  if (threadIdx.x == 0) red_nrm[n * kRedSlots + blockIdx.x] = nrm;
-}
-
-// W = Z + beta W (all modes, flat).
-__global__ void k_cg_wupdate(int64_t cnt, double* __restrict__ W, const double* __restrict__ Z,
-                             const CgState* st) {
-  if (state_done(st)) return;
-  const double beta = st->beta;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
-       e += (int64_t)gridDim.x * blockDim.x)
-    W[e] = Z[e] + beta * W[e];
-}
-
-__global__ void k_fill(int64_t cnt, double* __restrict__ p, double v) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
-       e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = v;
-}
-
 // Per-mode conversion of caller buffers to packed FP64.
 __global__ void k_to64(Dims d, PerMode<const void*> src, int dtype, double* __restrict__ dst) {
   const int n = blockIdx.y;
@@ -210,63 +173,6 @@ __global__ void k_state_reset(CgState* st) {
     st->iters = 0;
     st->status = CP_OK;
     st->done = 0;
-  }
-}
-
-// After Z = R P_inv with R = -G: rho = sum <R,Z>; CG runs while rsum > eps * gsum.
-__global__ void k_fin_cginit(int N, int nblocks, const double* red_dot, CgState* st) {
-  if (state_done(st)) return;
-  double rz = 0.0;
-  for (int n = 0; n < N; ++n) rz += sum_slots(red_dot + n * kRedSlots, nblocks);
-  if (threadIdx.x == 0) {
-    st->rz = rz;
-    if (!isfinite(rz)) {
-      st->status = CP_ENONFINITE;
-      st->done = 1;
-    } else if (!(st->rsum > st->eps * st->gsum)) {
-      st->done = 1;
-    }
-  }
-}
-
-// alpha = sum <R,Z> / sum <W,Q>; breakdown when sum <W,Q> <= 0.
-__global__ void k_fin_alpha(int N, int nblocks, const double* red_dot, CgState* st) {
-  if (state_done(st)) return;
-  double wq = 0.0;
-  for (int n = 0; n < N; ++n) wq += sum_slots(red_dot + n * kRedSlots, nblocks);
-  if (threadIdx.x == 0) {
-    if (!isfinite(wq)) {
-      st->status = CP_ENONFINITE;
-      st->done = 1;
-    } else if (!(wq > 0.0)) {
-      st->status = CP_EBREAKDOWN;
-      st->done = 1;
-    } else {
-      st->alpha = st->rz / wq;
-    }
-  }
-}
-
-// beta = sum <R,Z>_new / sum <R,Z>_old; stop test on sum_n ||R(n)||_F.
-__global__ void k_fin_beta(int N, int nblocks, const double* red_dot, const double* red_nrm,
-                           CgState* st) {
-  if (state_done(st)) return;
-  double rz = 0.0, rs = 0.0;
-  for (int n = 0; n < N; ++n) {
-    rz += sum_slots(red_dot + n * kRedSlots, nblocks);
-    rs += sqrt(sum_slots(red_nrm + n * kRedSlots, nblocks));
-  }
-  if (threadIdx.x == 0) {
-    st->beta = rz / st->rz;
-    st->rz = rz;
-    st->rsum = rs;
-    st->iters += 1;
-    if (!isfinite(rz) || !isfinite(rs)) {
-      st->status = CP_ENONFINITE;
-      st->done = 1;
-    } else if (!(rs > st->eps * st->gsum)) {
-      st->done = 1;
-    }
   }
 }
 
@@ -800,20 +706,6 @@ void launch_rowmm(const Dims& d, const RowMM& a, const CgState* st, hipStream_t 
   hipLaunchKernelGGL(k_rowmm, grid, dim3(256), 0, s, d, a, st);
 }
 
-void launch_cg_axpy(const Dims& d, double* V, double* Rv, const double* W, const double* Q,
-                    double* red_nrm, const CgState* st, hipStream_t s) {
-  dim3 grid(rowmm_blocks(d), d.N);
-  hipLaunchKernelGGL(k_cg_axpy, grid, dim3(256), 0, s, d, V, Rv, W, Q, red_nrm, st);
-}
-
-void launch_cg_wupdate(int64_t cnt, double* W, const double* Z, const CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_wupdate, dim3(grid1(cnt, 1024)), dim3(256), 0, s, cnt, W, Z, st);
-}
-
-void launch_fill(int64_t cnt, double* p, double v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(grid1(cnt, 1024)), dim3(256), 0, s, cnt, p, v);
-}
-
 void launch_to64(const Dims& d, const PerMode<const void*>& src, int dtype, double* dst,
                  hipStream_t s) {
   dim3 grid(rowmm_blocks(d), d.N);
@@ -828,21 +720,6 @@ void launch_fin_grad(const Dims& d, int nblocks, const double* red_nrm, CgState*
 
 void launch_state_reset(CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st);
-}
-
-void launch_fin_cginit(const Dims& d, int nblocks, const double* red_dot, CgState* st,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_cginit, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, st);
-}
-
-void launch_fin_alpha(const Dims& d, int nblocks, const double* red_dot, CgState* st,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, st);
-}
-
-void launch_fin_beta(const Dims& d, int nblocks, const double* red_dot, const double* red_nrm,
-                     CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, d.N, nblocks, red_dot, red_nrm, st);
 }
 
 void launch_gn_apply(const Dims& d, double* A64, const double* V, const PerMode<void*>& Aout,
