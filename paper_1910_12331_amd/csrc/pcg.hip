@@ -54,31 +54,70 @@ struct CgArgs {
   int rb_off[kMaxOrder + 1];
 };
 
-// Per-thread share of the previous init / update launch's partials (slot order is mode-major):
-// v[0] gathers <R,Z>, v[1 + n] gathers ||R(n)||^2. The loads of all slots go out together.
-struct RzShare {
-  double v[1 + kMaxOrder];
-};
-
-__device__ __forceinline__ void load_rz(const CgArgs& a, RzShare& sh) {
-#pragma unroll
-  for (int i = 0; i < 1 + kMaxOrder; ++i) sh.v[i] = 0.0;
-  for (int i = threadIdx.x; i < a.nslot; i += blockDim.x) {
-    const double rz = a.slot_rz[i], nr = a.slot_nrm[i];
-    const int rb = i / a.TB;
-    sh.v[0] += rz;
-#pragma unroll
-    for (int n = 0; n < kMaxOrder; ++n)
-      sh.v[1 + n] += (rb >= a.rb_off[n] && rb < a.rb_off[n + 1] && n < a.d.N) ? nr : 0.0;
+// Sums of per-block partials, identical in every thread of the workgroup. The slots are staged
+// in LDS (1024 at a time); each sum is split into 8 contiguous pieces added sequentially by 8
+// threads, and the 8 piece sums are added in order by one thread. This has a shorter critical
+// path than a cross-lane butterfly (each xor step is a dependent LDS round trip) and a fixed
+// order, so every workgroup gets the same bits; one barrier hands the results to all threads.
+//   slot_sums<1>: sum of s0[0..nslot) (unused: a butterfly serves one value as well).
+//   slot_sums<2>: sum of s0, and the sums of s1 over each mode's slot range [rb_off[n] TB,
+//                 rb_off[n+1] TB) (slot order is mode-major).
+template <int K>
+__device__ __forceinline__ void slot_sums(const CgArgs& a, const double* s0, const double* s1,
+                                          double (&out)[1 + kMaxOrder]) {
+  constexpr int kChunkSlots = 1024, kPieces = 8;
+  __shared__ double l0[kChunkSlots], l1[K == 2 ? kChunkSlots : 1];
+  __shared__ double piece[1 + kMaxOrder][kPieces];
+  __shared__ double res[1 + kMaxOrder];
+  const int t = threadIdx.x;
+  const int nsum = K == 2 ? 1 + a.d.N : 1;
+  const int q = t / kPieces, pc = t - q * kPieces;   // sum q, piece pc
+  int lo_n = 0, hi_n = a.nslot;
+  if (K == 2 && q >= 1 && q < nsum) {
+    lo_n = a.rb_off[q - 1] * a.TB;
+    hi_n = a.rb_off[q] * a.TB;
   }
+  double acc = 0.0;
+  for (int c0 = 0; c0 < a.nslot; c0 += kChunkSlots) {
+    const int cn = a.nslot - c0 < kChunkSlots ? a.nslot - c0 : kChunkSlots;
+    for (int i = t; i < cn; i += blockDim.x) {
+      l0[i] = s0[c0 + i];
+      if (K == 2) l1[i] = s1[c0 + i];
+    }
+    __syncthreads();
+    if (q < nsum) {
+      const int lo = lo_n - c0 > 0 ? lo_n - c0 : 0, hi = hi_n - c0 < cn ? hi_n - c0 : cn;
+      if (lo < hi) {
+        const int len = hi - lo, per = (len + kPieces - 1) / kPieces;
+        const int b0 = lo + pc * per, b1 = b0 + per < hi ? b0 + per : hi;
+        const double* src = q == 0 ? l0 : l1;
+        for (int i = b0; i < b1; ++i) acc += src[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (q < nsum) piece[q][pc] = acc;
+  __syncthreads();
+  if (t < nsum) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPieces; ++i) r += piece[t][i];
+    res[t] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 1 + kMaxOrder; ++i) out[i] = i < nsum ? res[i] : 0.0;
 }
 
-// rho = sum <R,Z> and rsum = sum_n sqrt(sum ||R(n)||^2), identical in every thread.
-__device__ __forceinline__ void reduce_rz(const CgArgs& a, RzShare& sh, double& rho, double& rsum) {
-  block_sum(sh.v);
-  rho = sh.v[0];
+// rho = sum <R,Z> and rsum = sum_n sqrt(sum ||R(n)||^2) from the previous init / update launch.
+__device__ __forceinline__ void reduce_rz(const CgArgs& a, double& rho, double& rsum) {
+  double v[1 + kMaxOrder];
+  slot_sums<2>(a, a.slot_rz, a.slot_nrm, v);
+  rho = v[0];
   rsum = 0.0;
-  for (int n = 0; n < a.d.N; ++n) rsum += sqrt(sh.v[1 + n]);
+#pragma unroll
+  for (int n = 0; n < kMaxOrder; ++n)
+    if (n < a.d.N) rsum += sqrt(v[1 + n]);
 }
 
 // True in every thread of the workgroup when CG has stopped. One thread reads the flag (another
@@ -171,7 +210,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
     wd[v] = !INIT && ok ? W[e] : 0.0;
   }
   double wq = 0.0;
-  if (!INIT) {
+  if (!INIT) {   // one value: a butterfly is as short as the sequential pieces
     double v1[1] = {0.0};
     for (int i = t; i < a.nslot; i += 256) v1[0] += a.slot_wq[i];
     block_sum(v1);
@@ -275,10 +314,8 @@ __global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
   ProjBatch b;
   proj_load(b, a, Wold, it, q0, q1, s, base, R, r0, z0, m, g, rok, zok);
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(it + 1) & 1];
-  RzShare sh;
-  load_rz(a, sh);
   double rho, rsum, beta;
-  reduce_rz(a, sh, rho, rsum);
+  reduce_rz(a, rho, rsum);
   if (cg_check(a, it, rho, rho_old, rsum, gsum, eps, beta)) return;
 
   dv4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -408,10 +445,8 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
 __global__ __launch_bounds__(512) void k_cg_final(CgArgs a, int maxiter) {
   if (cg_stopped(a.st)) return;
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(maxiter + 1) & 1];
-  RzShare sh;
-  load_rz(a, sh);
   double rho, rsum, beta;
-  reduce_rz(a, sh, rho, rsum);
+  reduce_rz(a, rho, rsum);
   cg_check(a, maxiter, rho, rho_old, rsum, gsum, eps, beta);
   if (threadIdx.x == 0) a.st->done = 1;
 }
