@@ -236,11 +236,14 @@ __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restric
                                                  int first_mode, CgState* st) {
   constexpr int RP = 32 * NBK;
   __shared__ double colbuf[2][RP], rowbuf[2][RP];
+  __shared__ int sbad;
   const int n = first_mode + blockIdx.x;
   const double* G = Gin + n * g_stride;
   double* P = Pout + n * p_stride;
   const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
-  if (st->status != CP_OK) return;
+  if (t == 0) sbad = st->status != CP_OK;   // one read: another workgroup may set it meanwhile
+  __syncthreads();
+  if (sbad) return;
   double a[NBK][NBK];
 #pragma unroll
   for (int ai = 0; ai < NBK; ++ai)
