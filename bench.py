@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-streams", type=int, default=8)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run each single-mode MTTKRP and one device copy of X of known size "
                          "(the workload the rocprofv3 counter runs are taken on), then exit")
@@ -247,6 +249,39 @@ def main():
         del X32d, A32
         del X64d, A64, g64
 
+    # ---- workload 5: 64 independent FP32 problems (modes U{60..200}, rank U{8,16,32,64}),
+    # one GN step each per batched step, spread over HIP streams
+    batched = None
+    if not args.no_batched:
+        from workloads import batched_problems
+        probs = batched_problems(64)
+        devs = [(torch.tensor(p_.x, dtype=torch.float32, device="cuda"),
+                 [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p_.init]) for p_ in probs]
+        res = {}
+        for ns in (1, args.batched_streams):
+            cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
+            torch.cuda.synchronize()
+            bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns)
+            for _ in range(2):
+                bgn.step()
+            bgn.synchronize()
+            per = []
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ev = bgn.step(timed=True)
+                bgn.synchronize()
+                per += [e0.elapsed_time(e1) for e0, e1 in ev]
+            el = time.perf_counter() - t0
+            res[ns] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
+                           step_ms_p99=float(np.percentile(per, 99)))
+            del bgn, cur
+        batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
+                       streams_1=res[1], **{f"streams_{args.batched_streams}": res[args.batched_streams]})
+        log(f"[bench] batched workload: {res[args.batched_streams]['problem_steps_per_s']:.0f} problem-steps/s on "
+            f"{args.batched_streams} streams ({res[1]['problem_steps_per_s']:.0f} on one); per-problem step "
+            f"p50 {res[args.batched_streams]['step_ms_p50']:.3f} ms, p99 {res[args.batched_streams]['step_ms_p99']:.3f} ms")
+        del devs
+
     # ---- CPU baseline: the oracle on host cores, bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -312,6 +347,7 @@ def main():
         "cg_iters": iters,
         "residual_after": r_now,
         "time_to_1e-8": ttt,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

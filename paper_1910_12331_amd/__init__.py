@@ -7,8 +7,9 @@ from . import _lib
 from .api import (CpError, Workspace, als_sweep, gn_gradient, gn_step, jtj_matvec, mttkrp,
                   read_stats, residual, stats_buffer)
 from .autograd import CPObjective, cp_objective
-from .optim import ALS, DampingSchedule, GaussNewton, GNConfig, gn_mixed_to_target, gn_to_target
+from .optim import (ALS, BatchedGaussNewton, DampingSchedule, GaussNewton, GNConfig,
+                    gn_mixed_to_target, gn_to_target)
 
 __all__ = ["CpError", "Workspace", "als_sweep", "gn_gradient", "gn_step", "jtj_matvec", "mttkrp",
            "read_stats", "residual", "stats_buffer", "ALS", "DampingSchedule", "GaussNewton",
-           "GNConfig", "gn_to_target", "gn_mixed_to_target", "CPObjective", "cp_objective"]
+           "GNConfig", "BatchedGaussNewton", "gn_to_target", "gn_mixed_to_target", "CPObjective", "cp_objective"]

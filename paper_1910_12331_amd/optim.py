@@ -140,3 +140,47 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
         if r <= target:
             break
     return high.A, hist
+
+
+class BatchedGaussNewton:
+    """Independent Gauss-Newton decompositions advanced together (many random restarts or
+    many small tensors). Problem i runs on HIP stream i % n_streams with its own workspace and
+    damping schedule, so small problems overlap on the GPU; each problem's iterates are the ones
+    a single-stream run produces (the kernels are deterministic). All streams have the default
+    priority."""
+
+    def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8):
+        cfg = config or GNConfig()
+        torch.cuda.current_stream().synchronize()   # inputs were written on the current stream
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
+        self.opts = []
+        for i, (X, A) in enumerate(problems):
+            with torch.cuda.stream(self.streams[i % len(self.streams)]):
+                self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter)))
+
+    def step(self, timed: bool = False):
+        """One Gauss-Newton step of every problem. With timed=True returns one (start, end) pair
+        of HIP events per problem, recorded on its stream around its step."""
+        events = []
+        for i, opt in enumerate(self.opts):
+            s = self.streams[i % len(self.streams)]
+            with torch.cuda.stream(s):
+                if timed:
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(s)
+                opt.step()
+                if timed:
+                    e1.record(s)
+                    events.append((e0, e1))
+        return events
+
+    def synchronize(self):
+        for s in self.streams:
+            s.synchronize()
+
+    def residuals(self):
+        out = []
+        for i, opt in enumerate(self.opts):
+            with torch.cuda.stream(self.streams[i % len(self.streams)]):
+                out.append(opt.residual())
+        return out

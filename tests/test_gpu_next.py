@@ -100,3 +100,38 @@ def test_gn_to_target_matches_oracle_step_count():
     _, ohist, _ = O.gn(p.x, p.init, O.LambdaSchedule(1e-4, 1e-10, 1e-4, 2.0), 1e-3, 20, 1e-10, 200)
     assert hist[-1] <= 1e-10
     assert abs(len(hist) - len(ohist)) <= 3
+
+
+# ------------------------------------------------------------------ batched problems (workload 5)
+def test_batched_streams_match_single_stream_runs():
+    """Problems advanced on three streams end bitwise where sequential single-stream runs end,
+    and each first step matches the oracle."""
+    from workloads import batched_problems
+    probs = batched_problems(5)
+    devs = [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+             [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    seq = []
+    for X, A in devs:
+        A2 = [a.clone() for a in A]
+        g = P.GaussNewton(X, A2)
+        for _ in range(2):
+            g.step()
+        seq.append(A2)
+    torch.cuda.synchronize()
+    b = P.BatchedGaussNewton(devs, n_streams=3)
+    b.step()
+    b.synchronize()
+    # first step against the oracle on the FP32-rounded inputs
+    for p, opt in zip(probs[:2], b.opts[:2]):
+        xs = p.x.astype(np.float32).astype(np.float64)
+        As = [a.astype(np.float32).astype(np.float64) for a in p.init]
+        its = opt.stats()["cg_iters"]   # same iteration count, so no tie at the stop threshold
+        ref, _ = O.gn_step(xs, As, 1e-4, 0.0, its)
+        for a, r in zip(opt.A, ref):
+            assert rel(a.double().cpu().numpy(), r) < 1e-4
+    ev = b.step(timed=True)
+    b.synchronize()
+    assert len(ev) == len(probs) and all(e0.elapsed_time(e1) > 0 for e0, e1 in ev)
+    for opt, A2 in zip(b.opts, seq):
+        for a, a2 in zip(opt.A, A2):
+            assert torch.equal(a, a2)

@@ -27,6 +27,7 @@ __all__ = [
     "Problem",
     "make_problem",
     "WORKLOADS",
+    "batched_problems",
 ]
 
 
@@ -134,10 +135,26 @@ def make_problem(dims, rank, workload=0, problem=0, kind="gaussian", noise=0.0, 
                    meta=dict(kind=kind, noise=noise, workload=workload, problem=problem))
 
 
+def batched_problems(count=64, workload=5, lo=60, hi=200, ranks=(8, 16, 32, 64), noise=1e-4):
+    """Workload 5: `count` independent problems of order 3 with mode sizes drawn uniformly from
+    [lo, hi] per mode and the rank drawn from `ranks`, N(0,1) planted factors, relative noise
+    `noise`. The shape of problem i comes from seed seed_for(workload, i, init=True) + 1, its data
+    from make_problem(..., workload, i)."""
+    out = []
+    for i in range(count):
+        srng = np.random.default_rng(seed_for(workload, i, init=True) + 1)
+        dims = tuple(int(v) for v in srng.integers(lo, hi + 1, size=3))
+        rank = int(srng.choice(ranks))
+        out.append(make_problem(dims, rank, workload=workload, problem=i, noise=noise))
+    return out
+
+
 # The five workloads: (dims, rank, kind, noise, storage dtype).
 WORKLOADS = {
     1: dict(dims=(40, 40, 40), rank=5, kind="gaussian", noise=0.0, dtype="f64"),
     2: dict(dims=(300, 300, 300), rank=50, kind="congruent", noise=1e-6, dtype="f64"),
     3: dict(dims=(400, 400, 400), rank=100, kind="gaussian", noise=0.0, dtype="f32"),
     4: dict(dims=(80, 80, 80, 80), rank=64, kind="lognorm", noise=1e-3, dtype="bf16"),
+    5: dict(dims="64 problems, each mode U{60..200}", rank="U{8,16,32,64}", kind="gaussian",
+            noise=1e-4, dtype="f32"),
 }
