@@ -36,6 +36,7 @@ __all__ = [
     "objective", "gradient", "jtj_matvec", "preconditioner", "pcg", "PCGResult", "gn_step",
     "GNStepStats", "LambdaSchedule", "als_sweep", "residual", "residual_expansion", "gn", "als",
     "jacobian", "jtj_dense", "flatten_factors", "unflatten_factors", "OracleError",
+    "damping_matrix",
 ]
 
 
@@ -148,8 +149,21 @@ def gradient(X, A):
     return [A[n] @ gamma(S, n, n) - mttkrp(X, A, n) for n in range(N)]
 
 
-def jtj_matvec(A, W, lam=0.0, Gam=None):
-    """Q(n) = lam W(n) + sum_p MatVec(A(n), A(p), Gamma(n,p), W(p))  (Algorithm 2, eq. (7)).
+def damping_matrix(Gam, n, damping="identity"):
+    """The damping matrix D of mode n's block in (J^T J + lam D) (Section 3.2): the identity, or
+    for damping == "diagonal" the diagonal of J^T J, whose block (n, n) is Gamma(n,n) (x) I by
+    eq. (5), so every row of mode n is scaled by diag(Gamma(n,n))."""
+    R = Gam[n][n].shape[0]
+    if damping == "identity":
+        return np.eye(R)
+    if damping == "diagonal":
+        return np.diag(np.diag(Gam[n][n]))
+    raise ValueError(damping)
+
+
+def jtj_matvec(A, W, lam=0.0, Gam=None, damping="identity"):
+    """Q(n) = lam W(n) D(n) + sum_p MatVec(A(n), A(p), Gamma(n,p), W(p))  (Algorithm 2,
+    eq. (7)), with D(n) the damping matrix (identity, or the diagonal of J^T J).
 
     Each (n, p) term is the Listing 1 contraction written out literally:
       n == p:  U[k,r] = sum_z Gamma(n,n)[r,z] W(n)[k,z]
@@ -160,7 +174,7 @@ def jtj_matvec(A, W, lam=0.0, Gam=None):
         Gam = gamma_set(grams(A))
     Q = []
     for n in range(N):
-        U = lam * W[n]
+        U = lam * (W[n] @ damping_matrix(Gam, n, damping))
         for p in range(N):
             if n == p:
                 U = U + np.einsum("rz,kz->kr", Gam[n][p], W[p])
@@ -170,12 +184,12 @@ def jtj_matvec(A, W, lam=0.0, Gam=None):
     return Q
 
 
-def preconditioner(Gam, lam):
-    """P_inv(n) = (Gamma(n,n) + lam I)^-1 for every mode, built from a Cholesky factor
+def preconditioner(Gam, lam, damping="identity"):
+    """P_inv(n) = (Gamma(n,n) + lam D(n))^-1 for every mode, built from a Cholesky factor
     (Algorithm 2, Section 3.3). Raises OracleError when the shifted matrix is not SPD."""
     out = []
     for n in range(len(Gam)):
-        g = Gam[n][n] + lam * np.eye(Gam[n][n].shape[0])
+        g = Gam[n][n] + lam * damping_matrix(Gam, n, damping)
         try:
             c = scipy.linalg.cho_factor(g, lower=True)
         except np.linalg.LinAlgError as e:
@@ -203,8 +217,9 @@ class PCGResult:
     history: list = field(default_factory=list)
 
 
-def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None):
-    """Algorithm 2 (CP-CG): preconditioned implicit CG for (J^T J + lam I) V = -G.
+def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity"):
+    """Algorithm 2 (CP-CG): preconditioned implicit CG for (J^T J + lam D) V = -G, with D the
+    identity or (damping == "diagonal") the diagonal of J^T J.
 
     Steps, in the paper's order: P_inv(n) = (Gamma(n,n) + lam I)^-1; V = 0; R = -G;
     Z = R P_inv; W = Z. While sum ||R(n)|| > eps_cg sum ||G(n)|| (and fewer than ``maxiter``
@@ -217,7 +232,7 @@ def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None):
     N = len(A)
     if Gam is None:
         Gam = gamma_set(grams(A))
-    P = preconditioner(Gam, lam)
+    P = preconditioner(Gam, lam, damping)
     V = [np.zeros_like(g) for g in G]
     R = [-g for g in G]
     Z = [R[n] @ P[n] for n in range(N)]
@@ -229,7 +244,7 @@ def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None):
     alpha = beta = 0.0
     hist = []
     while rsum > eps_cg * gsum and it < maxiter:
-        Q = jtj_matvec(A, W, lam, Gam)
+        Q = jtj_matvec(A, W, lam, Gam, damping)
         wq = sum(_inner(W[n], Q[n]) for n in range(N))
         if not wq > 0.0:
             raise OracleError("CG breakdown: sum <W,Q> <= 0")
@@ -261,7 +276,7 @@ class GNStepStats:
     update_norm: float
 
 
-def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20):
+def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity"):
     """One loop body of Algorithm 1 (CP-GN): all M(n) at the current point, Gamma(n,p),
     G(n) = A(n) Gamma(n,n) - M(n), V = CP-CG(G, A, Gamma, eps_cg, lam), A(n) += V(n).
 
@@ -272,7 +287,7 @@ def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20):
     Gam = gamma_set(S)
     M = [mttkrp(X, A, n) for n in range(N)]
     G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
-    res = pcg(G, A, lam, eps_cg, maxiter, Gam)
+    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping)
     newA = [A[n] + res.V[n] for n in range(N)]
     upd = math.sqrt(sum(float(np.sum(v * v)) for v in res.V))
     return newA, GNStepStats(cg_iters=res.iters, grad_norm_sum=res.grad_norm_sum,
@@ -359,7 +374,8 @@ def residual_expansion(X, A):
 # Drivers (Algorithm 1 outer loop; ALS loop)
 # --------------------------------------------------------------------------------------------
 
-def gn(X, A0, schedule=None, eps_cg=1e-3, maxiter=20, target=1e-10, maxsteps=200, log=None):
+def gn(X, A0, schedule=None, eps_cg=1e-3, maxiter=20, target=1e-10, maxsteps=200, log=None,
+       damping="identity"):
     """Algorithm 1 driver: GN steps until the direct relative residual <= target or maxsteps.
     lambda for step k is the schedule's value at step k (advanced after every step)."""
     sched = schedule or LambdaSchedule()
@@ -369,7 +385,7 @@ def gn(X, A0, schedule=None, eps_cg=1e-3, maxiter=20, target=1e-10, maxsteps=200
         num, den = residual(X, A)
         if num / den <= target:
             break
-        A, st = gn_step(X, A, sched.value, eps_cg, maxiter)
+        A, st = gn_step(X, A, sched.value, eps_cg, maxiter, damping)
         sched.advance()
         rec = dict(step=step, lam=st.lam, cg_iters=st.cg_iters, grad_norm_sum=st.grad_norm_sum)
         hist.append(rec)

@@ -416,3 +416,48 @@ def test_als_sweep_is_gauss_seidel_least_squares():
     new = O.als_sweep(X, A)
     for a, b in zip(new, ref):
         assert rel(a, b) < 1e-12
+
+
+# ------------------------------------------------------------------ diagonal damping (Section 3.2)
+def test_diagonal_damping_is_diag_of_explicit_jtj():
+    """D = diag(J^T J) taken from the explicit Jacobian equals the damping matrix built from
+    Gamma(n,n); the damped product equals (H + lam diag(H)) w."""
+    dims, rank, lam = (4, 3, 5), 3, 0.3
+    A = factors(dims, rank, 41)
+    W = factors(dims, rank, 42)
+    H = O.jtj_dense(A)
+    Gam = O.gamma_set(O.grams(A))
+    dflat = np.concatenate([np.tile(np.diag(O.damping_matrix(Gam, n, "diagonal")), dims[n])
+                            for n in range(3)])
+    assert rel(dflat, np.diag(H)) < 1e-14
+    q = O.flatten_factors(O.jtj_matvec(A, W, lam, damping="diagonal"))
+    w = O.flatten_factors(W)
+    assert rel(q, H @ w + lam * np.diag(H) * w) < 1e-13
+
+
+def test_diagonal_damping_pcg_converges_to_dense_solve():
+    dims, rank, lam = (3, 4, 2), 2, 0.05
+    A = factors(dims, rank, 43)
+    X = rnd(dims, 44)
+    G = O.gradient(X, A)
+    n = sum(dims) * rank
+    res = O.pcg(G, A, lam, eps_cg=1e-14, maxiter=10 * n, damping="diagonal")
+    H = O.jtj_dense(A)
+    ref = np.linalg.solve(H + lam * np.diag(np.diag(H)), -O.flatten_factors(G))
+    assert rel(O.flatten_factors(res.V), ref) < 1e-10
+    # the preconditioner is the inverse of the damped diagonal block
+    Gam = O.gamma_set(O.grams(A))
+    P = O.preconditioner(Gam, lam, "diagonal")
+    blk = Gam[1][1] + lam * np.diag(np.diag(Gam[1][1]))
+    assert rel(P[1] @ blk, np.eye(rank)) < 1e-12
+
+
+def test_diagonal_damping_scale_invariance_of_the_damping_term():
+    """Scaling column r of A(m), m != n, by c scales Gamma(n,n)[r,r] and the damping entry of
+    mode n alike (unlike lam I): the diagonal term follows the problem's own scaling."""
+    A = factors((4, 3, 5), 2, 45)
+    B = [a.copy() for a in A]
+    B[1][:, 0] *= 3.0
+    G1, G2 = O.gamma_set(O.grams(A)), O.gamma_set(O.grams(B))
+    d1, d2 = O.damping_matrix(G1, 0, "diagonal"), O.damping_matrix(G2, 0, "diagonal")
+    assert abs(d2[0, 0] - 9.0 * d1[0, 0]) <= 1e-12 * d2[0, 0] and abs(d2[1, 1] - d1[1, 1]) < 1e-14
