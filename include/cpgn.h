@@ -80,6 +80,12 @@ enum {
 /* Residual methods for cp_residual. */
 enum { CP_RESIDUAL_DIRECT = 0, CP_RESIDUAL_EXPANSION = 1 };
 
+/* cp_gn_params.flags bits. CP_GN_DIAG_DAMPING: damp with lambda diag(J^T J) instead of lambda I
+   (Section 3.2). The diagonal of J^T J in mode n's block is diag(Gamma^(n,n)) for every row
+   (eq. (5)), so the CG system becomes (J^T J + lambda D) V = -G with D^(n) = diag(Gamma^(n,n)),
+   and the preconditioner (Gamma^(n,n) + lambda diag(Gamma^(n,n)))^-1. */
+#define CP_GN_DIAG_DAMPING 1u
+
 typedef struct {
   int32_t order;                 /* N, 2 <= N <= CP_MAX_ORDER                               */
   int32_t rank;                  /* R >= 1                                                  */
@@ -92,7 +98,7 @@ typedef struct {
   double lambda;                 /* Tikhonov damping of J^T J + lambda I (>= 0), Section 3.2 */
   double cg_tol;                 /* eps_cg: CG runs while sum||R(n)|| > eps_cg sum||G(n)||   */
   int32_t cg_maxiter;            /* cap on CG iterations (>= 0)                              */
-  uint32_t flags;                /* reserved, must be 0                                      */
+  uint32_t flags;                /* 0 or CP_GN_DIAG_DAMPING; other bits must be 0            */
 } cp_gn_params;
 
 /* Written to DEVICE memory by cp_gn_step. */
@@ -139,7 +145,8 @@ int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* c
 /*
  * One loop body of Algorithm 1 (CP-GN): all MTTKRPs at the current point, Grams and Gamma
  * matrices, G^(n), then Algorithm 2 (CP-CG) on (J^T J + lambda I) V = -G with the block
- * preconditioner (Gamma^(n,n) + lambda I)^-1 (Section 3.3), then A^(n) += V^(n).
+ * preconditioner (Gamma^(n,n) + lambda I)^-1 (Section 3.3), then A^(n) += V^(n). With
+ * CP_GN_DIAG_DAMPING in params->flags, lambda I is replaced by lambda diag(J^T J) in both.
  * CG uses beta = sum<R,Z>_new / sum<R,Z>_old (standard preconditioned CG).
  *   A: N device pointers, read and overwritten in place (f_dtype).
  *   params: HOST pointer. stats: DEVICE pointer to one cp_gn_stats.

@@ -166,13 +166,17 @@ def read_stats(buf: torch.Tensor) -> dict:
 
 
 def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
-            cg_maxiter: int = 20, stats=None, ws=None):
-    """One Algorithm 1 step in place on A; returns the device stats buffer (cp_gn_stats)."""
+            cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity"):
+    """One Algorithm 1 step in place on A; returns the device stats buffer (cp_gn_stats).
+    damping: "identity" (lam I) or "diagonal" (lam diag(J^T J), Section 3.2)."""
+    if damping not in ("identity", "diagonal"):
+        raise ValueError("damping must be 'identity' or 'diagonal'")
     _dev(X, "X")
     R = int(A[0].shape[1])
     _factors(A, X.shape, X.dtype, R)
     prob = _problem(X, R)
-    prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter), 0)
+    prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
+                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
     if stats is None:
         stats = stats_buffer(X.device)
     w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)

@@ -23,7 +23,7 @@ void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stat
 void launch_status_out(const CgState*, int32_t*, hipStream_t);
 int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
-                   hipStream_t);
+                   hipStream_t, bool diag_damping = false);
 int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t);
 int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
 void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
@@ -32,7 +32,7 @@ int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipS
 size_t cg_slot_bytes(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
               double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
-              double, int, hipStream_t);
+              double, int, bool, hipStream_t);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 
@@ -331,7 +331,7 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   if (rc) return rc;
   if (!X || !prm || !stats) return CP_EINVAL;
   if (!(prm->lambda >= 0.0) || !isfinite(prm->lambda) || !(prm->cg_tol >= 0.0) ||
-      !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 || prm->flags != 0)
+      !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 || (prm->flags & ~CP_GN_DIAG_DAMPING) != 0)
     return CP_EINVAL;
   if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
@@ -345,11 +345,13 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   PerMode<void*> none{};
   gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
   // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
-  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st);
+  const bool diag = (prm->flags & CP_GN_DIAG_DAMPING) != 0;
+  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st,
+                 diag);
   // CG: three launches per iteration, scalars kept on the device.
   launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
             (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, prm->lambda,
-            prm->cg_maxiter, st);
+            prm->cg_maxiter, diag, st);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
   launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);

@@ -233,7 +233,7 @@ template <int NBK>
 __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restrict__ Gin,
                                                  int64_t g_stride, double lambda,
                                                  double* __restrict__ Pout, int64_t p_stride,
-                                                 int first_mode, CgState* st) {
+                                                 int first_mode, CgState* st, int diag_damping) {
   constexpr int RP = 32 * NBK;
   __shared__ double colbuf[2][RP], rowbuf[2][RP];
   __shared__ int sbad;
@@ -250,7 +250,10 @@ __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restric
 #pragma unroll
     for (int bk = 0; bk < NBK; ++bk) {
       const int i = ty + 32 * ai, k = tx + 32 * bk;
-      a[ai][bk] = (i < R && k < R) ? G[i * R + k] + (i == k ? lambda : 0.0) : (i == k ? 1.0 : 0.0);
+      // lambda I, or lambda diag(G); G is read only inside the R x R block
+      a[ai][bk] = (i < R && k < R)
+                      ? G[i * R + k] + (i == k ? (diag_damping ? lambda * G[i * R + i] : lambda) : 0.0)
+                      : (i == k ? 1.0 : 0.0);
     }
   for (int j = 0; j < R; ++j) {
     const int b = j & 1, jb = j >> 5, jt = j & 31;
@@ -744,13 +747,14 @@ void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
 int spd_inv_supported(int R) { return R >= 1 && R <= 128; }
 
 int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
-                   int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s) {
+                   int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                   bool diag_damping) {
   const int nbk = (R + 31) / 32;
   switch (nbk) {
 #define CPGN_SPD(k)                                                                          \
   case k:                                                                                    \
     hipLaunchKernelGGL((k_spd_inv<k>), dim3(count), dim3(1024), 0, s, R, G, g_stride, lambda, \
-                       P, p_stride, first_mode, st);                                         \
+                       P, p_stride, first_mode, st, diag_damping ? 1 : 0);                   \
     break;
     CPGN_SPD(1) CPGN_SPD(2) CPGN_SPD(3) CPGN_SPD(4)
 #undef CPGN_SPD

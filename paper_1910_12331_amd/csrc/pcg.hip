@@ -7,7 +7,8 @@
 //                the previous launch's per-block partials; beta = rho / rho_old;
 //                W = Z + beta W_old; B(p) = A(p)^T W(p), one 16 x 16 tile of B(p) per workgroup
 //                (the sum over all s_p rows stays inside the workgroup).
-//   k_cg_matvec  Q(n) = lambda W(n) + W(n) Gamma(n,n) + A(n) Y(n)^T with
+//   k_cg_matvec  Q(n) = lambda W(n) D(n) + W(n) Gamma(n,n) + A(n) Y(n)^T (D = I, or the diagonal
+//                of J^T J, diag(Gamma(n,n)), for diagonal damping) with
 //                Y(n) = sum_{p != n} Gamma(n,p) * B(p) (eq. (7) contracted in factored form),
 //                for a 64-row x 16-column block; per-block <W,Q>.
 //   k_cg_update  alpha = rho / sum <W,Q> from the matvec partials; V += alpha W;
@@ -49,6 +50,7 @@ struct CgArgs {
   double* slot_nrm;
   CgState* st;
   double lambda;
+  int diag_damping;       // damping lambda diag(Gamma(n,n)) instead of lambda I
   int TB;                 // 16-column tiles of R
   int nslot;              // row blocks x TB
   int rb_off[kMaxOrder + 1];
@@ -412,6 +414,9 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
     const int64_t row = k0 + g + 4 * v;
     wd[v] = colok && row < s ? W[(rbase + row) * R + c0 + m] : 0.0;
   }
+  // damping of this lane's column: lambda, or lambda Gamma(n,n)[c][c] (diagonal of J^T J)
+  const double lam_c = a.diag_damping && colok ? a.lambda * Gnn[(int64_t)(c0 + m) * (R + 1)]
+                                               : a.lambda;
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     const int e = t + 256 * i, c = e / KP, k = e - c * KP;
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   for (int v = 0; v < 4; ++v) {
     const int64_t row = k0 + g + 4 * v;
     if (colok && row < s) {
-      const double q = __fma_rn(a.lambda, wd[v], acc[v]);
+      const double q = __fma_rn(lam_c, wd[v], acc[v]);
       a.Q[(rbase + row) * R + c0 + m] = q;
       dot += wd[v] * q;
     }
@@ -484,7 +489,7 @@ static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
 int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
               const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
               double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
-              int maxiter, hipStream_t s) {
+              int maxiter, bool diag_damping, hipStream_t s) {
   CgArgs a{};
   a.d = d;
   a.A64 = A64;
@@ -500,6 +505,7 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
   a.B = B;
   a.st = st;
   a.lambda = lambda;
+  a.diag_damping = diag_damping ? 1 : 0;
   a.TB = cg_tiles(p);
   a.rb_off[0] = 0;
   for (int n = 0; n < p.N; ++n)

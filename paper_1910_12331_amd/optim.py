@@ -46,6 +46,7 @@ class GNConfig:
     cg_tol: float = 1e-3
     cg_maxiter: int = 20
     schedule: DampingSchedule | None = None
+    damping: str = "identity"       # or "diagonal": lam diag(J^T J) (Section 3.2)
 
 
 class GaussNewton:
@@ -61,7 +62,7 @@ class GaussNewton:
 
     def step(self) -> torch.Tensor:
         api.gn_step(self.X, self.A, self.schedule.value, self.cfg.cg_tol, self.cfg.cg_maxiter,
-                    stats=self.stats_buf, ws=self.ws)
+                    stats=self.stats_buf, ws=self.ws, damping=self.cfg.damping)
         self.schedule.advance()
         self.steps += 1
         return self.stats_buf
@@ -118,7 +119,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     X_high hold the same tensor. Returns (factors, history of (precision, residual))."""
     cfg = config or GNConfig()
     sched = cfg.schedule or DampingSchedule()
-    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched)
+    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping)
     opt = GaussNewton(X_low, A, low_cfg)
     hist = []
     prev = float("inf")
@@ -132,7 +133,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     if hist and hist[-1][1] <= target:
         return opt.A, hist
     A_high = [a.to(X_high.dtype) for a in opt.A]
-    high = GaussNewton(X_high, A_high, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched))
+    high = GaussNewton(X_high, A_high, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping))
     while opt.steps + high.steps < max_steps:
         high.step()
         r = high.residual()
@@ -156,7 +157,8 @@ class BatchedGaussNewton:
         self.opts = []
         for i, (X, A) in enumerate(problems):
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
-                self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter)))
+                self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter,
+                                                             damping=cfg.damping)))
 
     def step(self, timed: bool = False):
         """One Gauss-Newton step of every problem. With timed=True returns one (start, end) pair

@@ -124,7 +124,7 @@ def test_call_validation_without_launch(lib):
     # Gauss-Newton parameters
     st = C.c_void_p(0x50000)
     for prm in [L.CpGnParams(-1.0, 1e-3, 20, 0), L.CpGnParams(1e-3, -1.0, 20, 0),
-                L.CpGnParams(1e-3, 1e-3, -1, 0), L.CpGnParams(1e-3, 1e-3, 20, 1),
+                L.CpGnParams(1e-3, 1e-3, -1, 0), L.CpGnParams(1e-3, 1e-3, 20, 2),
                 L.CpGnParams(float("nan"), 1e-3, 20, 0)]:
         assert lib.cp_gn_step(C.byref(p), X, A, C.byref(prm), st, ws, need, None) == L.CP_EINVAL
     good = L.CpGnParams(1e-3, 1e-3, 20, 0)
@@ -157,3 +157,9 @@ def test_damping_schedule_matches_oracle_definition():
     s = DampingSchedule(1.0, 0.25, 1.0, 2.0)
     seq = [s.value] + [s.advance() for _ in range(6)]
     assert seq == [1.0, 0.5, 0.25, 0.5, 1.0, 0.5, 0.25]
+
+
+def test_gn_flag_constant_matches_header():
+    text = open(os.path.join(ROOT, "include", "cpgn.h")).read()
+    m = re.search(r"#define\s+CP_GN_DIAG_DAMPING\s+(\d+)u", text)
+    assert m and int(m.group(1)) == L.GN_DIAG_DAMPING

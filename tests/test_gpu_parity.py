@@ -162,24 +162,24 @@ def test_jtj_matvec_matches_oracle(dims, rank, lam, dt):
 
 
 # ------------------------------------------------------------------------------------ GN step
-def oracle_sensitivity(Xh, Ah, lam, eps, maxiter, seed=1):
+def oracle_sensitivity(Xh, Ah, lam, eps, maxiter, seed=1, damping="identity"):
     """Change of the oracle's GN update when its input factors move by 1e-15 relative: the
     rounding-level spread that any implementation with another summation order inherits
     (large once CG iterates past its rounding floor and loses orthogonality)."""
     rng = np.random.default_rng(seed)
     A2 = [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in Ah]
-    v1 = O.flatten_factors([b - a for a, b in zip(Ah, O.gn_step(Xh, Ah, lam, eps, maxiter)[0])])
-    v2 = O.flatten_factors([b - a for a, b in zip(A2, O.gn_step(Xh, A2, lam, eps, maxiter)[0])])
+    v1 = O.flatten_factors([b - a for a, b in zip(Ah, O.gn_step(Xh, Ah, lam, eps, maxiter, damping)[0])])
+    v2 = O.flatten_factors([b - a for a, b in zip(A2, O.gn_step(Xh, A2, lam, eps, maxiter, damping)[0])])
     return float(np.linalg.norm(v1 - v2) / max(np.linalg.norm(v1), 1e-300))
 
 
-def gn_compare(p, dt, lam, eps, maxiter, tol_v):
+def gn_compare(p, dt, lam, eps, maxiter, tol_v, damping="identity"):
     Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
     if tol_v == "sensitivity":
-        tol_v = max(1e-12, 10 * oracle_sensitivity(Xh, Ah, lam, eps, maxiter))
+        tol_v = max(1e-12, 10 * oracle_sensitivity(Xh, Ah, lam, eps, maxiter, damping=damping))
     Ad = to_dev(p.init, dt)
-    st = P.read_stats(P.gn_step(to_dev([p.x], dt)[0], Ad, lam, eps, maxiter))
-    newA, ref = O.gn_step(Xh, Ah, lam, eps, maxiter)
+    st = P.read_stats(P.gn_step(to_dev([p.x], dt)[0], Ad, lam, eps, maxiter, damping=damping))
+    newA, ref = O.gn_step(Xh, Ah, lam, eps, maxiter, damping)
     assert st["status"] == 0
     assert st["cg_iters"] == ref.cg_iters
     V = [a - b for a, b in zip(host(Ad), Ah)]
@@ -194,6 +194,21 @@ def gn_compare(p, dt, lam, eps, maxiter, tol_v):
 def test_gn_step_fixed_iterations_fp64(maxiter):
     p = make_problem((40, 40, 40), 5, workload=1)
     gn_compare(p, torch.float64, 1e-4, 0.0, maxiter, 1e-12)
+
+
+@pytest.mark.parametrize("maxiter", [0, 1, 5, 10])
+def test_gn_step_diagonal_damping_fixed_iterations_fp64(maxiter):
+    """lam diag(J^T J) damping (Section 3.2) in the CG product and the preconditioner."""
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float64, 1e-2, 0.0, maxiter, 1e-12, damping="diagonal")
+
+
+@pytest.mark.parametrize("damping", ["identity", "diagonal"])
+def test_gn_step_high_rank_rank_exceeds_mode_size(damping):
+    """The high-rank regime of Section 5 (s = 80, R = 120 > s): each Gram has rank 80 < R, the
+    damped systems stay SPD. CG with the tolerance test, both damping forms, FP64."""
+    p = make_problem((80, 80, 80), 120, workload=0, problem=120, noise=1e-2)
+    gn_compare(p, torch.float64, 1e-2, 1e-3, 20, "sensitivity", damping=damping)
 
 
 def test_gn_step_past_cg_rounding_floor_fp64():
