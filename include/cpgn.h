@@ -35,10 +35,15 @@
  *     workgroup's registers) and return CP_EUNSUPPORTED otherwise; the other calls take any rank.
  *
  * Precision
- *   - x_dtype must equal f_dtype and be CP_F64 or CP_F32. The tensor contraction (MTTKRP,
+ *   - x_dtype equals f_dtype, CP_F64 or CP_F32; or f_dtype = CP_F32 and x_dtype = CP_BF16 or
+ *     CP_BF16X3 (a bfloat16 tensor). With x_dtype = f_dtype the tensor contraction (MTTKRP,
  *     reconstruction) runs on the matrix cores in that precision with accumulation in the same
- *     precision; Grams, Gamma matrices, the CG vectors and scalars, Cholesky factors and all
- *     norms and inner products are kept in FP64 on the device.
+ *     precision. With a bfloat16 tensor the MTTKRP multiplies X by the inner factor rounded
+ *     to bfloat16 (split into two bfloat16 parts for CP_BF16X3) on the bf16 matrix cores,
+ *     accumulates in FP32 and applies the remaining Khatri-Rao factors in FP32; the residual
+ *     reads X in bfloat16 and reconstructs in FP32. In every case the Grams, Gamma matrices,
+ *     the CG vectors and scalars, Cholesky factors and all norms and inner products are kept in
+ *     FP64 on the device.
  */
 #ifndef CPGN_H
 #define CPGN_H
@@ -53,7 +58,13 @@ extern "C" {
 #define CP_MAX_ORDER 8
 #define CP_ABI_VERSION 1
 
-typedef enum { CP_F64 = 0, CP_F32 = 1 } cp_dtype;
+/* Element types. CP_BF16 and CP_BF16X3 describe the tensor X only (x_dtype), with f_dtype =
+   CP_F32:
+     CP_BF16    X holds prod(dims) bfloat16 values.
+     CP_BF16X3  X holds two planes of prod(dims) bfloat16 values each, hi then lo; the tensor is
+                hi + lo (see cp_tensor_to_bf16). The contraction takes three bf16 products per
+                term, hi*hi + hi*lo + lo*hi, of X's planes and a like split of the factor. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X3 = 3 } cp_dtype;
 
 /* Return / device status codes. */
 enum {
@@ -172,6 +183,16 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
  */
 int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int method,
                 double* out_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Storage conversion for the bfloat16 tensor forms (x_dtype CP_BF16 / CP_BF16X3); not a step of
+ * the method. Rounds the n FP32 values of X to nearest bfloat16 (ties to even) into out[0..n).
+ * With split != 0 it also writes the rounded remainder lo = bf16(x - hi) into out[n..2n), so
+ * that hi + lo carries about 16 significant bits of x.
+ *   X: device, n floats (finite). out: device, n (or 2n with split) 16-bit values, written.
+ *   Returns CP_EINVAL for n < 0 or a NULL pointer with n > 0.
+ */
+int cp_tensor_to_bf16(const float* X, int64_t n, int split, void* out, void* stream);
 
 /* Static description of a status code. */
 const char* cp_status_string(int status);

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpgn.so")
 
 MAX_ORDER = 8
-CP_F64, CP_F32 = 0, 1
+CP_F64, CP_F32, CP_BF16, CP_BF16X3 = 0, 1, 2, 3
 CP_OK, CP_EINVAL, CP_EUNSUPPORTED, CP_EWORKSPACE, CP_EHIP = 0, -1, -2, -3, -4
 CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
 OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL = range(6)
@@ -16,7 +16,7 @@ GN_DIAG_DAMPING = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_als_sweep", "cp_residual", "cp_status_string", "cp_abi_version"]
+           "cp_als_sweep", "cp_residual", "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
 class CpProblem(C.Structure):
@@ -67,6 +67,8 @@ def load(path: str = LIB_PATH):
     lib.cp_als_sweep.argtypes = [P(CpProblem), vp, PTRS, C.c_double, vp, vp, sz, vp]
     lib.cp_residual.restype = i32
     lib.cp_residual.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
+    lib.cp_tensor_to_bf16.restype = i32
+    lib.cp_tensor_to_bf16.argtypes = [vp, C.c_int64, i32, vp, vp]
     if lib.cp_abi_version() != 1:
         raise RuntimeError("libcpgn.so ABI version mismatch")
     _lib = lib

@@ -17,6 +17,55 @@ from . import _lib as L
 _DT = {torch.float64: L.CP_F64, torch.float32: L.CP_F32}
 
 
+class SplitBF16Tensor:
+    """A tensor stored as two bfloat16 planes whose sum is the tensor (x_dtype CP_BF16X3):
+    `planes` has shape (2, *dims), hi plane first. Its MTTKRP takes three bf16 products per term
+    (hi*hi + hi*lo + lo*hi) and is accurate to about 2^-16 relative. Build one from FP32 with
+    to_bf16(X, split=True)."""
+
+    dtype = "bf16x3"
+
+    def __init__(self, planes: torch.Tensor):
+        if planes.dtype != torch.bfloat16 or planes.dim() < 2 or planes.shape[0] != 2:
+            raise ValueError("planes must be a (2, *dims) bfloat16 tensor")
+        self.planes = planes
+        self.shape = tuple(planes.shape[1:])
+        self.device = planes.device
+        self.is_cuda = planes.is_cuda
+
+    def is_contiguous(self) -> bool:
+        return self.planes.is_contiguous()
+
+    def data_ptr(self) -> int:
+        return self.planes.data_ptr()
+
+    def dim(self) -> int:
+        return len(self.shape)
+
+    def to_float(self) -> torch.Tensor:
+        """hi + lo in FP32 (exact for planes made from FP32 values)."""
+        return self.planes[0].float() + self.planes[1].float()
+
+
+def factor_dtype(X) -> torch.dtype:
+    """dtype of the factor matrices that go with tensor X: FP32 for the bfloat16 forms."""
+    if isinstance(X, SplitBF16Tensor) or X.dtype == torch.bfloat16:
+        return torch.float32
+    return X.dtype
+
+
+def to_bf16(X: torch.Tensor, split: bool = False):
+    """Round an FP32 GPU tensor to bfloat16 (nearest even) with the library's conversion kernel.
+    split=True also keeps the rounding remainder as a second bfloat16 plane and returns a
+    SplitBF16Tensor; otherwise a bfloat16 tensor of X's shape."""
+    _dev(X, "X", torch.float32)
+    n = X.numel()
+    out = torch.empty(((2,) if split else ()) + tuple(X.shape), dtype=torch.bfloat16, device=X.device)
+    _check(L.load().cp_tensor_to_bf16(X.data_ptr(), n, 1 if split else 0, out.data_ptr(), _stream()),
+           "cp_tensor_to_bf16")
+    return SplitBF16Tensor(out) if split else out
+
+
 class CpError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {L.status_string(code)} (code {code})")
@@ -28,8 +77,14 @@ def _check(rc: int, where: str):
         raise CpError(rc, where)
 
 
-def _problem(X: torch.Tensor, rank: int) -> L.CpProblem:
-    if X.dtype not in _DT:
+def _problem(X, rank: int) -> L.CpProblem:
+    if isinstance(X, SplitBF16Tensor):
+        xd, fd = L.CP_BF16X3, L.CP_F32
+    elif X.dtype == torch.bfloat16:
+        xd, fd = L.CP_BF16, L.CP_F32
+    elif X.dtype in _DT:
+        xd = fd = _DT[X.dtype]
+    else:
         raise TypeError(f"unsupported tensor dtype {X.dtype}")
     if X.dim() < 2 or X.dim() > L.MAX_ORDER:
         raise ValueError("tensor order must be between 2 and 8")
@@ -38,7 +93,7 @@ def _problem(X: torch.Tensor, rank: int) -> L.CpProblem:
     p.rank = int(rank)
     for i, s in enumerate(X.shape):
         p.dims[i] = int(s)
-    p.x_dtype = p.f_dtype = _DT[X.dtype]
+    p.x_dtype, p.f_dtype = xd, fd
     return p
 
 
@@ -112,11 +167,11 @@ def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=N
     """M = X_(mode) P^(mode) (Section 2.2, eq. (1)); returns a dims[mode] x R tensor."""
     _dev(X, "X")
     R = int(A[0].shape[1])
-    _factors(A, X.shape, X.dtype, R)
+    _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     if out is None:
-        out = torch.empty((X.shape[mode], R), dtype=X.dtype, device=X.device)
-    _dev(out, "out", X.dtype, (X.shape[mode], R))
+        out = torch.empty((X.shape[mode], R), dtype=factor_dtype(X), device=X.device)
+    _dev(out, "out", factor_dtype(X), (X.shape[mode], R))
     w, nb = _ws(prob, L.OP_MTTKRP, X.device, ws)
     _check(L.load().cp_mttkrp(C.byref(prob), X.data_ptr(), _ptrs(A), int(mode), out.data_ptr(), w, nb,
                               _stream()), "cp_mttkrp")
@@ -127,7 +182,7 @@ def gn_gradient(X: torch.Tensor, A: Sequence[torch.Tensor], ws=None):
     """G(n) = A(n) Gamma(n,n) - M(n) for every mode (Algorithm 1). Returns (G list, sum ||G||)."""
     _dev(X, "X")
     R = int(A[0].shape[1])
-    _factors(A, X.shape, X.dtype, R)
+    _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     G = [torch.empty_like(a) for a in A]
     gsum = torch.empty(1, dtype=torch.float64, device=X.device)
@@ -173,7 +228,7 @@ def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: floa
         raise ValueError("damping must be 'identity' or 'diagonal'")
     _dev(X, "X")
     R = int(A[0].shape[1])
-    _factors(A, X.shape, X.dtype, R)
+    _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
                        L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
@@ -189,7 +244,7 @@ def als_sweep(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float = 0.0, stat
     """One ALS sweep in place on A (Section 2.2); returns the device int32 status."""
     _dev(X, "X")
     R = int(A[0].shape[1])
-    _factors(A, X.shape, X.dtype, R)
+    _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=X.device)
@@ -204,7 +259,7 @@ def residual(X: torch.Tensor, A: Sequence[torch.Tensor], method: int = L.RESIDUA
     """Device tensor [||X - [[A]]||_F, ||X||_F] (Section 5)."""
     _dev(X, "X")
     R = int(A[0].shape[1])
-    _factors(A, X.shape, X.dtype, R)
+    _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=X.device)

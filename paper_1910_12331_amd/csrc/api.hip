@@ -41,15 +41,19 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int make_plan(const cp_problem* prob, Plan* p) {
   if (!prob || !p) return CP_EINVAL;
   if (prob->order < 2 || prob->order > kMaxOrder || prob->rank < 1) return CP_EINVAL;
-  if (prob->x_dtype != prob->f_dtype) return CP_EUNSUPPORTED;
-  if (prob->x_dtype != CP_F64 && prob->x_dtype != CP_F32) return CP_EUNSUPPORTED;
+  const bool native = prob->x_dtype == prob->f_dtype &&
+                      (prob->x_dtype == CP_F64 || prob->x_dtype == CP_F32);
+  const bool bf16 = prob->f_dtype == CP_F32 &&
+                    (prob->x_dtype == CP_BF16 || prob->x_dtype == CP_BF16X3);
+  if (!native && !bf16) return CP_EUNSUPPORTED;
   *p = Plan{};
   p->N = prob->order;
   p->R = prob->rank;
   if (p->R > (1 << 20)) return CP_EINVAL;
   p->Rp = (p->R + 15) / 16 * 16;
   p->NBt = p->Rp / 16;
-  p->dtype = prob->x_dtype;
+  p->dtype = prob->f_dtype;
+  p->xk = prob->x_dtype == CP_BF16 ? 1 : prob->x_dtype == CP_BF16X3 ? 2 : 0;
   p->esz = p->dtype == CP_F64 ? 8 : 4;
   p->total = 1;
   for (int n = 0; n < p->N; ++n) {
@@ -65,7 +69,14 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->qc_prev = (p->s[p->N - 2] + 15) / 16;
   int64_t part = p->qc_last * 16 * p->Rp;   // residual's packed last factor reuses this region
   int64_t p1 = 0;
-  for (int n = 0; n < p->N; ++n) {
+  int64_t krp = 0;
+  for (int n = 0; n < p->N && p->xk != 0; ++n) {
+    const MttkrpGeom g = mttkrp_geom_bf16(*p, n);
+    const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
+    part = e > part ? e : part;
+    krp += g.O * p->Rp;
+  }
+  for (int n = 0; n < p->N && p->xk == 0; ++n) {
     for (int v = 0; v < 4; ++v) {   // geometry of every launch form (vector loads, tree)
       const bool dt = v >= 2;
       if (dt && !(n == 0 && p->N == 3)) continue;
@@ -88,8 +99,15 @@ int make_plan(const cp_problem* prob, Plan* p) {
     return at;
   };
   p->off_apad = take((size_t)p->sum_s * p->Rp * p->esz);
-  p->off_fpk_last = take((size_t)p->qc_last * p->NBt * 256 * p->esz);
-  p->off_fpk_prev = take((size_t)p->qc_prev * p->NBt * 256 * p->esz);
+  // packed inner factors: 16-row chunks in the compute precision, or 32-row chunks of
+  // bfloat16 (two planes for the split form)
+  const size_t np = p->xk == 2 ? 2 : 1;
+  const size_t fl = p->xk ? (size_t)(p->s[p->N - 1] + 31) / 32 * p->NBt * 1024 * np
+                          : (size_t)p->qc_last * p->NBt * 256 * p->esz;
+  const size_t fp = p->xk ? (size_t)(p->s[p->N - 2] + 31) / 32 * p->NBt * 1024 * np
+                          : (size_t)p->qc_prev * p->NBt * 256 * p->esz;
+  p->off_fpk_last = take(fl);
+  p->off_fpk_prev = take(fp);
   p->off_part = take((size_t)part * p->esz);
   p->off_p1 = take((size_t)p1 * p->esz);
   p->off_m64 = take(vec);
@@ -110,6 +128,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_w1 = take(vec);
   p->off_r1 = take(vec);
   p->off_slots = take(cg_slot_bytes(*p));
+  p->off_krp = take((size_t)krp * 4);
   p->bytes = off;
   return CP_OK;
 }

@@ -47,6 +47,7 @@ template <> struct Mfma<double> {
 struct Plan {
   int N = 0, R = 0, Rp = 0, NBt = 0;   // order, rank, rank padded to 16, column blocks of 16
   int dtype = 0;                       // CP_F64 or CP_F32 (compute precision of X and factors)
+  int xk = 0;                          // X storage: 0 = dtype, 1 = bfloat16, 2 = split bfloat16
   size_t esz = 0;                      // bytes per element of the compute precision
   int64_t s[kMaxOrder] = {0};
   int64_t total = 0;                   // prod s
@@ -60,6 +61,7 @@ struct Plan {
   size_t off_g = 0, off_v = 0, off_r = 0, off_z = 0, off_w = 0, off_q = 0;
   size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0, off_w1 = 0, off_r1 = 0;
   size_t off_slots = 0;
+  size_t off_krp = 0;                  // outer Khatri-Rao tables of the bfloat16 MTTKRP
   size_t bytes = 0;
 };
 
@@ -123,6 +125,16 @@ struct MttkrpGeom {
   int64_t HS;             // max wavefronts sharing one outer index within a row tile
 };
 MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt);
+MttkrpGeom mttkrp_geom_bf16(const Plan& p, int mode);
+
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs).
+__host__ __device__ __forceinline__ uint16_t to_bf16_rne(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__host__ __device__ __forceinline__ float bf16_to_float(uint32_t h) {
+  return __builtin_bit_cast(float, h << 16);
+}
 int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
                          hipStream_t st);
 

@@ -340,8 +340,49 @@ struct ResArgs {
   int64_t O, K, KB;
   int64_t s[kMaxOrder];
   int N, Rp;
+  int64_t xplane;               // split bfloat16 tensor: elements between the hi and lo planes
   double* red;                  // [2][kRedSlots]
 };
+
+// Entry e of X in the compute precision T. XK: 0 = stored as T; 1 = bfloat16; 2 = two
+// bfloat16 planes whose sum is the tensor (lo plane at X + plane).
+template <typename T, int XK>
+__device__ __forceinline__ T x_at(const void* X, int64_t e, int64_t plane) {
+  if constexpr (XK == 0) {
+    return ((const T*)X)[e];
+  } else {
+    const uint16_t* h = (const uint16_t*)X;
+    float v = bf16_to_float(h[e]);
+    if constexpr (XK == 2) v += bf16_to_float(h[plane + e]);
+    return (T)v;
+  }
+}
+
+// Four consecutive entries e..e+3 of X (e a multiple of 4, X 16-byte aligned for XK = 0 and
+// 8-byte aligned otherwise).
+template <typename T, int XK>
+__device__ __forceinline__ void x_at4(const void* X, int64_t e, int64_t plane, T (&out)[4]) {
+  if constexpr (XK == 0) {
+    typedef T tv4 __attribute__((ext_vector_type(4)));
+    const tv4 w = *(const tv4*)((const T*)X + e);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[v] = w[v];
+  } else {
+    const uint16_t* h = (const uint16_t*)X;
+    const uint2 w = *(const uint2*)(h + e);
+    float f[4] = {bf16_to_float(w.x & 0xffffu), bf16_to_float(w.x >> 16),
+                  bf16_to_float(w.y & 0xffffu), bf16_to_float(w.y >> 16)};
+    if constexpr (XK == 2) {
+      const uint2 l = *(const uint2*)(h + plane + e);
+      f[0] += bf16_to_float(l.x & 0xffffu);
+      f[1] += bf16_to_float(l.x >> 16);
+      f[2] += bf16_to_float(l.y & 0xffffu);
+      f[3] += bf16_to_float(l.y >> 16);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[v] = (T)f[v];
+  }
+}
 
 // Direct residual (Section 5): ||X - [[A]]||^2 and ||X||^2 in one pass over X. X is viewed as
 // [O][K] with K = s_N; the reconstruction is the product of the Khatri-Rao rows of the first N-1
@@ -366,7 +407,7 @@ struct ResX {
 // as B operand), which leaves lane 16 g + m with reconstructed entries (row m, columns 4 g + v):
 // four consecutive columns of one X row, read with one 16-byte load when K is a multiple of 4
 // (VX). FP64 keeps the direct form (its accumulator layout strides rows by 4).
-template <typename T, int NBR, bool VX>
+template <typename T, int NBR, bool VX, int XK>
 __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   constexpr int MB = ResCfg<T>::MB;
   constexpr bool SWAP = sizeof(T) == 4;
@@ -379,7 +420,7 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   };
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, m = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-  const T* X = (const T*)a.X;
+  const void* X = a.X;
   const T* B = (const T*)a.bpk;
   const int64_t ntiles = (a.O + 16 * MB - 1) / (16 * MB);
   const int64_t ngroups = (ntiles + 3) / 4;
@@ -416,13 +457,11 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
         for (int mb = 0; mb < MB; ++mb) {
           const int64_t off = off0 + (int64_t)(16 * mb) * a.K;
           if constexpr (VX) {
-            typedef T tv4 __attribute__((ext_vector_type(4)));
-            const tv4 w = *(const tv4*)(X + (off < last - 3 ? off : last - 3));
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xr.x[mb][v] = w[v];
+            x_at4<T, XK>(X, off < last - 3 ? off : last - 3, a.xplane, xr.x[mb]);
           } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xr.x[mb][v] = X[off + v < last ? off + v : last];
+            for (int v = 0; v < 4; ++v)
+              xr.x[mb][v] = x_at<T, XK>(X, off + v < last ? off + v : last, a.xplane);
           }
         }
       } else {
@@ -432,7 +471,7 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t off = off0 + (int64_t)(16 * mb + dv * v) * a.K;
-            xr.x[mb][v] = X[off < last ? off : last];
+            xr.x[mb][v] = x_at<T, XK>(X, off < last ? off : last, a.xplane);
           }
       }
     };
@@ -591,9 +630,8 @@ __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, 
 }
 
 // Fallback for R > 128: one thread per tensor entry, scalar FP64 reconstruction.
-template <typename T>
+template <typename T, int XK>
 __global__ void k_residual_scalar(ResArgs a, int R) {
-  const T* X = (const T*)a.X;
   double d2 = 0.0, x2 = 0.0;
   const int64_t total = a.O * a.K;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -610,7 +648,7 @@ __global__ void k_residual_scalar(ResArgs a, int R) {
       for (int q = 0; q < a.N; ++q) p *= (double)((const T*)a.apad[q])[idx[q] * a.Rp + r];
       xt += p;
     }
-    const double x = (double)X[e];
+    const double x = (double)x_at<T, XK>(a.X, e, a.xplane);
     d2 += (x - xt) * (x - xt);
     x2 += x * x;
   }
@@ -622,12 +660,12 @@ __global__ void k_residual_scalar(ResArgs a, int R) {
 }
 
 // sum of squares of X (for the expansion form).
-template <typename T>
-__global__ void k_sumsq(const T* __restrict__ X, int64_t total, double* red) {
+template <typename T, int XK>
+__global__ void k_sumsq(const void* __restrict__ X, int64_t total, double* red) {
   double x2 = 0.0, dummy = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double x = (double)X[e];
+    const double x = (double)x_at<T, XK>(X, e, total);
     x2 += x * x;
   }
   block_sum2(x2, dummy);
@@ -763,11 +801,12 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
   return (int)hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int XK>
 static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out, hipStream_t s) {
   constexpr int MB = ResCfg<T>::MB;
   ResArgs a{};
   a.X = X;
+  a.xplane = p.total;
   int64_t off = 0;
   for (int m = 0; m < p.N; ++m) {
     a.apad[m] = ws + p.off_apad + off * p.esz;
@@ -788,12 +827,12 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     const int64_t items = ((a.O + 16 * MB - 1) / (16 * MB) + 3) / 4 * a.KB;
     int64_t blocks = items;
     if (blocks > ResCfg<T>::OCC * kNumCU) blocks = ResCfg<T>::OCC * kNumCU;   // one resident round
-    const bool vx = a.K % 4 == 0 && ((uintptr_t)X % 16) == 0;
+    const bool vx = a.K % 4 == 0 && ((uintptr_t)X % (XK ? 8 : 16)) == 0;
     switch (p.NBt) {
 #define CPGN_RES(k)                                                                         \
   case k:                                                                                   \
-    if (vx) hipLaunchKernelGGL((k_residual<T, k, true>), dim3(blocks), dim3(256), 0, s, a);  \
-    else hipLaunchKernelGGL((k_residual<T, k, false>), dim3(blocks), dim3(256), 0, s, a);    \
+    if (vx) hipLaunchKernelGGL((k_residual<T, k, true, XK>), dim3(blocks), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((k_residual<T, k, false, XK>), dim3(blocks), dim3(256), 0, s, a);   \
     break;
       CPGN_RES(1) CPGN_RES(2) CPGN_RES(3) CPGN_RES(4) CPGN_RES(5) CPGN_RES(6) CPGN_RES(7)
       CPGN_RES(8)
@@ -803,24 +842,29 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, (int)blocks, a.red, out);
   } else {
     const int blocks = grid1(p.total, kRedSlots);
-    hipLaunchKernelGGL(k_residual_scalar<T>, dim3(blocks), dim3(256), 0, s, a, p.R);
+    hipLaunchKernelGGL((k_residual_scalar<T, XK>), dim3(blocks), dim3(256), 0, s, a, p.R);
     hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, blocks, a.red, out);
   }
   return (int)hipGetLastError();
 }
 
 int launch_residual_direct(const Plan& p, const void* X, void* ws, double* out, hipStream_t s) {
-  if (p.dtype == CP_F32) return launch_residual_t<float>(p, X, (char*)ws, out, s);
-  return launch_residual_t<double>(p, X, (char*)ws, out, s);
+  if (p.xk == 1) return launch_residual_t<float, 1>(p, X, (char*)ws, out, s);
+  if (p.xk == 2) return launch_residual_t<float, 2>(p, X, (char*)ws, out, s);
+  if (p.dtype == CP_F32) return launch_residual_t<float, 0>(p, X, (char*)ws, out, s);
+  return launch_residual_t<double, 0>(p, X, (char*)ws, out, s);
 }
 
 int launch_sumsq(const Plan& p, const void* X, double* red, hipStream_t s, int* nblocks) {
   const int blocks = grid1(p.total, kRedSlots);
-  if (p.dtype == CP_F32)
-    hipLaunchKernelGGL(k_sumsq<float>, dim3(blocks), dim3(256), 0, s, (const float*)X, p.total, red);
+  if (p.xk == 1)
+    hipLaunchKernelGGL((k_sumsq<float, 1>), dim3(blocks), dim3(256), 0, s, X, p.total, red);
+  else if (p.xk == 2)
+    hipLaunchKernelGGL((k_sumsq<float, 2>), dim3(blocks), dim3(256), 0, s, X, p.total, red);
+  else if (p.dtype == CP_F32)
+    hipLaunchKernelGGL((k_sumsq<float, 0>), dim3(blocks), dim3(256), 0, s, X, p.total, red);
   else
-    hipLaunchKernelGGL(k_sumsq<double>, dim3(blocks), dim3(256), 0, s, (const double*)X, p.total,
-                       red);
+    hipLaunchKernelGGL((k_sumsq<double, 0>), dim3(blocks), dim3(256), 0, s, X, p.total, red);
   *nblocks = blocks;
   return (int)hipGetLastError();
 }

@@ -398,6 +398,11 @@ __global__ __launch_bounds__(256) void k_mttkrp_reduce(const T* __restrict__ par
 // Padded factor copies [s_m][Rp] in the compute precision, optional FP64 copies [s_m][R], and
 // the packed B-operand layout of modes N-1 and N-2:
 //   fpk[chunk][cb][lane][t] = A(q)[16*chunk + 4*(lane/16) + t][16*cb + lane%16]  (0 outside).
+// For a bfloat16 tensor (xk != 0) the packs hold bfloat16 values instead, 8 per lane and chunk
+// of 32 rows, A(q)[32*chunk + 8*(lane/16) + t][16*cb + lane%16], rounded to nearest even, with
+// a second plane of the rounding remainders (also rounded) for the split form; and each mode's
+// outer Khatri-Rao rows krp_n[o][r] = prod over outer modes m of A(m)[i_m(o)][r] in FP32 (outer
+// modes: all but n and its inner mode, ascending, the last one fastest).
 struct PrepArgs {
   const void* src[kMaxOrder];
   int src_dtype;
@@ -405,10 +410,13 @@ struct PrepArgs {
   double* a64[kMaxOrder];
   void* fpk_last;
   void* fpk_prev;
+  float* krp;
   int64_t s[kMaxOrder];
-  int64_t seg[kMaxOrder + 3];   // cumulative segment starts: modes' apad, then the two packs
-  int N, R, Rp, NBt;
+  int64_t seg[kMaxOrder + 4];   // cumulative segment starts: modes' apad, the two packs, tables
+  int64_t krp_seg[kMaxOrder + 1];
+  int N, R, Rp, NBt, xk;
   int64_t qc_last, qc_prev;
+  int64_t fplane_last, fplane_prev;   // bfloat16 elements per plane of each pack
 };
 
 template <typename T>
@@ -419,7 +427,7 @@ __device__ __forceinline__ double src_at(const PrepArgs& a, int mode, int64_t i,
 
 template <typename T>
 __global__ void k_prepare(PrepArgs a) {
-  const int64_t total = a.seg[a.N + 2];
+  const int64_t total = a.seg[a.N + 3];
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     if (idx < a.seg[a.N]) {
@@ -431,19 +439,53 @@ __global__ void k_prepare(PrepArgs a) {
       const double v = c < a.R ? src_at<T>(a, mode, i, c) : 0.0;
       ((T*)a.apad[mode])[e] = (T)v;
       if (a.a64[mode] && c < a.R) a.a64[mode][i * a.R + c] = v;
-    } else {
+    } else if (idx < a.seg[a.N + 2]) {
       const bool last = idx < a.seg[a.N + 1];
       const int q = last ? a.N - 1 : a.N - 2;
       const int64_t e = idx - (last ? a.seg[a.N] : a.seg[a.N + 1]);
-      const int t = (int)(e & 3);
-      const int lane = (int)((e >> 2) & 63);
-      const int64_t rest = e >> 8;
-      const int cb = (int)(rest % a.NBt);
-      const int64_t chunk = rest / a.NBt;
-      const int64_t row = 16 * chunk + 4 * (lane >> 4) + t;
-      const int col = 16 * cb + (lane & 15);
-      const double v = (row < a.s[q] && col < a.R) ? src_at<T>(a, q, row, col) : 0.0;
-      ((T*)(last ? a.fpk_last : a.fpk_prev))[e] = (T)v;
+      if (a.xk == 0) {
+        const int t = (int)(e & 3);
+        const int lane = (int)((e >> 2) & 63);
+        const int64_t rest = e >> 8;
+        const int cb = (int)(rest % a.NBt);
+        const int64_t chunk = rest / a.NBt;
+        const int64_t row = 16 * chunk + 4 * (lane >> 4) + t;
+        const int col = 16 * cb + (lane & 15);
+        const double v = (row < a.s[q] && col < a.R) ? src_at<T>(a, q, row, col) : 0.0;
+        ((T*)(last ? a.fpk_last : a.fpk_prev))[e] = (T)v;
+      } else {
+        const int t = (int)(e & 7);
+        const int lane = (int)((e >> 3) & 63);
+        const int64_t rest = e >> 9;
+        const int cb = (int)(rest % a.NBt);
+        const int64_t chunk = rest / a.NBt;
+        const int64_t row = 32 * chunk + 8 * (lane >> 4) + t;
+        const int col = 16 * cb + (lane & 15);
+        const float v = (row < a.s[q] && col < a.R) ? (float)src_at<T>(a, q, row, col) : 0.0f;
+        const uint16_t hi = to_bf16_rne(v);
+        uint16_t* out = (uint16_t*)(last ? a.fpk_last : a.fpk_prev);
+        out[e] = hi;
+        if (a.xk == 2) {   // v - hi is exact in FP32
+          const float rem = v - bf16_to_float(hi);
+          out[e + (last ? a.fplane_last : a.fplane_prev)] = to_bf16_rne(rem);
+        }
+      }
+    } else {
+      const int64_t e0 = idx - a.seg[a.N + 2];
+      int n = 0;
+      while (e0 >= a.krp_seg[n + 1]) ++n;
+      const int64_t e = e0 - a.krp_seg[n];
+      const int q = n == a.N - 1 ? a.N - 2 : a.N - 1;
+      int64_t o = e / a.Rp;
+      const int c = (int)(e - o * a.Rp);
+      double v = c < a.R ? 1.0 : 0.0;
+      for (int m = a.N - 1; m >= 0 && c < a.R; --m) {
+        if (m == n || m == q) continue;
+        const int64_t im = o % a.s[m];
+        o /= a.s[m];
+        v *= (double)(float)src_at<T>(a, m, im, c);
+      }
+      a.krp[e0] = (float)v;
     }
   }
 }
@@ -617,8 +659,18 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   return (int)hipGetLastError();
 }
 
+void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int Rp, int64_t J,
+                              int R, double* m64, void* mout, int mout_dtype, hipStream_t st) {
+  hipLaunchKernelGGL(k_mttkrp_reduce<float>, dim3(grid_for(8 * J * R)), dim3(256), 0, st, part,
+                     nparts, Jpad, Rp, J, R, m64, mout, mout_dtype);
+}
+
+int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
+                       hipStream_t st);
+
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
                   hipStream_t st) {
+  if (p.xk != 0) return launch_mttkrp_bf16(p, X, mode, ws, m64, mout, st);
   if (p.dtype == CP_F32)
     return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
   return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
@@ -627,7 +679,7 @@ int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64,
 // Order 3, one pass over X: M(0) and, through the dimension tree, M(1) (FP64 outputs).
 int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
                          hipStream_t st) {
-  if (p.N != 3 || !vec_ok(p, 0, X)) {
+  if (p.N != 3 || p.xk != 0 || !vec_ok(p, 0, X)) {
     const int rc = launch_mttkrp(p, X, 0, ws, m64_0, nullptr, st);
     return rc ? rc : launch_mttkrp(p, X, 1, ws, m64_1, nullptr, st);
   }
@@ -646,6 +698,7 @@ int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dt
   a.R = p.R;
   a.Rp = p.Rp;
   a.NBt = p.NBt;
+  a.xk = p.xk;
   a.qc_last = p.qc_last;
   a.qc_prev = p.qc_prev;
   int64_t off = 0, a64off = 0;
@@ -661,9 +714,24 @@ int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dt
   }
   a.fpk_last = ws + p.off_fpk_last;
   a.fpk_prev = ws + p.off_fpk_prev;
-  a.seg[p.N + 1] = a.seg[p.N] + p.qc_last * p.NBt * 256;
-  a.seg[p.N + 2] = a.seg[p.N + 1] + p.qc_prev * p.NBt * 256;
-  const int grid = grid_for(a.seg[p.N + 2]);
+  if (p.xk == 0) {
+    a.seg[p.N + 1] = a.seg[p.N] + p.qc_last * p.NBt * 256;
+    a.seg[p.N + 2] = a.seg[p.N + 1] + p.qc_prev * p.NBt * 256;
+    a.seg[p.N + 3] = a.seg[p.N + 2];
+  } else {
+    a.fplane_last = (p.s[p.N - 1] + 31) / 32 * p.NBt * 512;
+    a.fplane_prev = (p.s[p.N - 2] + 31) / 32 * p.NBt * 512;
+    a.seg[p.N + 1] = a.seg[p.N] + a.fplane_last;
+    a.seg[p.N + 2] = a.seg[p.N + 1] + a.fplane_prev;
+    a.krp = (float*)(ws + p.off_krp);
+    a.krp_seg[0] = 0;
+    for (int n = 0; n < p.N; ++n) {
+      const int q = n == p.N - 1 ? p.N - 2 : p.N - 1;
+      a.krp_seg[n + 1] = a.krp_seg[n] + p.total / p.s[n] / p.s[q] * p.Rp;
+    }
+    a.seg[p.N + 3] = a.seg[p.N + 2] + a.krp_seg[p.N];
+  }
+  const int grid = grid_for(a.seg[p.N + 3]);
   if (p.dtype == CP_F32) hipLaunchKernelGGL(k_prepare<float>, dim3(grid), dim3(256), 0, st, a);
   else hipLaunchKernelGGL(k_prepare<double>, dim3(grid), dim3(256), 0, st, a);
   return (int)hipGetLastError();

@@ -1,0 +1,451 @@
+// Reduced-precision MTTKRP (the contraction of Section 2.2) on the gfx950 bf16 matrix cores:
+// X stored in bfloat16, as one plane or as the two-plane split X = X_hi + X_lo; factors in
+// FP32; every product is accumulated in FP32.
+//
+// Formulation. As in the FP32/FP64 kernels, the contraction is split into an inner mode q,
+// whose factor is the MFMA B operand, and outer modes:
+//   M(n)[j, r] = sum_o KRP_outer[o, r] * T_o[j, r],   T_o[j, r] = sum_k X[o, j, k] A(q)[k, r].
+// T_o is formed on the matrix cores (16x16x32 bf16 products) from X and the inner factor
+// rounded to bfloat16, and is folded into the FP32 result with the FP32 outer Khatri-Rao row
+// once the wavefront leaves outer index o. Only the inner factor is rounded; the outer
+// Khatri-Rao rows stay in FP32 (they are precomputed per outer index in the workspace).
+// In the split form the inner factor is split like X, F = F_hi + F_lo, and each tile takes the
+// three products X_lo F_hi + X_hi F_lo + X_hi F_hi; the dropped X_lo F_lo term and the
+// remainder of F's split are O(2^-16) relative.
+//   case A (n < N-1): q = N-1, the inner index is contiguous along X rows; lane (m, g) loads
+//     the 8 inner elements [32 c + 8 g, +8) of output row 16 mb + m with one 16-byte load.
+//   case B (n = N-1): q = N-2, the output index is contiguous; lane (m, g) loads 4 consecutive
+//     output rows 4 m + mb for each of its 8 inner indices (8-byte loads) and regroups them
+//     into one A operand per row block.
+// The packed inner factor of this launch's column blocks is staged in LDS once per workgroup
+// when it fits (else read from L2 per item). Wavefronts own a contiguous range of
+// (outer index, inner chunk) items of one row tile; the four wavefronts of a workgroup are
+// summed in LDS in a fixed order into one partial tile, and the partial tiles are added in
+// FP64 in a fixed order, so the results are bitwise reproducible.
+#include "cpgn_internal.h"
+
+namespace cpgn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBfNB = 4;              // column blocks of 16 per launch
+constexpr int kBfLdsF = 64 * 1024;    // largest inner factor staged in LDS (bytes)
+
+struct Bf16Args {
+  const uint16_t* X;            // hi plane (or the only plane)
+  int64_t xplane;               // elements between the hi and lo planes (split form)
+  const uint4* fpk;             // packed inner factor [QC][NBt][64 lanes] x 8 bf16; lo plane after
+  int64_t fplane;               // uint4 entries per plane of fpk
+  const float* krp;             // outer Khatri-Rao rows [O][Rp], FP32
+  float* part;                  // partial tiles [SW][Jpad][Rp]
+  int64_t J, Jpad, s_in, QC, nitems, Rr, nbo;
+  int Rp, NBt, cb0, nb;         // nb: column blocks of this launch (<= kBfNB)
+  int nsplit;                   // wavefronts along the item split (= 4 * gridDim.x)
+  int flds;                     // inner factor staged in LDS
+};
+
+template <bool CASE_B> struct BfTile {
+  static constexpr int MB = CASE_B ? 4 : 5;
+};
+
+__device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <bool CASE_B, int NP>
+struct BfBuf {
+  static constexpr int MB = BfTile<CASE_B>::MB;
+  uint4 x[NP][MB];       // A operands (8 bf16 of one output row) per plane and row block
+  float kr[kBfNB];       // outer Khatri-Rao row of the item's outer index (this lane's columns)
+};
+
+// X fragment of one item. Out-of-range lanes read a clamped in-bounds address and select 0,
+// so the loads carry no branches.
+template <bool CASE_B, int NP, bool VEC>
+__device__ __forceinline__ void bf_load_x(const Bf16Args& a, int64_t base, int64_t chunk,
+                                          int64_t j0, int g, int m, BfBuf<CASE_B, NP>& b) {
+  constexpr int MB = BfTile<CASE_B>::MB;
+  const int64_t in0 = chunk * 32 + 8 * g;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint16_t* X = a.X + p * a.xplane;
+    if constexpr (!CASE_B) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int64_t j = j0 + 16 * mb + m;
+        if constexpr (VEC) {
+          const bool ok = j < a.J && in0 < a.s_in;
+          const uint4 w = *(const uint4*)(X + (ok ? base + j * a.Rr + in0 : 0));
+          b.x[p][mb] = ok ? w : uint4{0, 0, 0, 0};
+        } else {
+          u16x8 h;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const bool ok = j < a.J && in0 + t < a.s_in;
+            const uint16_t w = X[ok ? base + j * a.Rr + in0 + t : 0];
+            h[t] = ok ? w : (uint16_t)0;
+          }
+          b.x[p][mb] = __builtin_bit_cast(uint4, h);
+        }
+      }
+    } else {
+      // r[kk][v]: output row jb + v at inner index in0 + kk (16-bit values in 32-bit lanes)
+      const int64_t jb = j0 + 4 * m;
+      uint32_t lo16[8][2], hi16[8][2];   // dword d of the 4-row group: rows 2d (lo), 2d+1 (hi)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int64_t inn = in0 + kk;
+        if constexpr (VEC) {
+          const bool ok = inn < a.s_in && jb < a.J;
+          const uint2 w = *(const uint2*)(X + (ok ? base + inn * a.J + jb : 0));
+          const uint32_t w0 = ok ? w.x : 0u, w1 = ok ? w.y : 0u;
+          lo16[kk][0] = w0 & 0xffffu;
+          hi16[kk][0] = w0 >> 16;
+          lo16[kk][1] = w1 & 0xffffu;
+          hi16[kk][1] = w1 >> 16;
+        } else {
+          u16x4 h;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = inn < a.s_in && jb + v < a.J;
+            const uint16_t w = X[ok ? base + inn * a.J + jb + v : 0];
+            h[v] = ok ? w : (uint16_t)0;
+          }
+          const uint2 w = __builtin_bit_cast(uint2, h);
+          lo16[kk][0] = w.x & 0xffffu;
+          hi16[kk][0] = w.x >> 16;
+          lo16[kk][1] = w.y & 0xffffu;
+          hi16[kk][1] = w.y >> 16;
+        }
+      }
+      // row block mb = output rows jb + mb: 8 inner values, two per dword
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        uint32_t d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t e0 = (mb & 1) ? hi16[2 * q][mb >> 1] : lo16[2 * q][mb >> 1];
+          const uint32_t e1 = (mb & 1) ? hi16[2 * q + 1][mb >> 1] : lo16[2 * q + 1][mb >> 1];
+          d[q] = e0 | (e1 << 16);
+        }
+        b.x[p][mb] = uint4{d[0], d[1], d[2], d[3]};
+      }
+    }
+  }
+}
+
+template <bool CASE_B, int NB, bool X3, bool VEC>
+__global__ __launch_bounds__(256, (!X3 && VEC) ? 2 : 1) void k_mttkrp_bf16(Bf16Args a) {
+  constexpr int MB = BfTile<CASE_B>::MB;
+  constexpr int NP = X3 ? 2 : 1;
+  typedef BfBuf<CASE_B, NP> Buf;
+  extern __shared__ uint4 smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, m = lane & 15;
+  const int split = blockIdx.x * 4 + wave;
+  const int64_t j0 = (int64_t)blockIdx.y * 16 * MB;
+  const int64_t it0 = a.nitems * split / a.nsplit;
+  const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
+
+  // Stage the packed inner factor of this launch's column blocks: sF[p][chunk][nb][lane].
+  if (a.flds) {
+    const int64_t n = (int64_t)NP * a.QC * NB * kWave;
+    for (int64_t e = threadIdx.x; e < n; e += 256) {
+      const int l = (int)(e % kWave);
+      const int64_t r = e / kWave;
+      const int nb = (int)(r % NB);
+      const int64_t pc = r / NB;
+      const int p = (int)(pc / a.QC);
+      const int64_t c = pc - p * a.QC;
+      smem[e] = a.fpk[p * a.fplane + (c * a.NBt + a.cb0 + nb) * kWave + l];
+    }
+    __syncthreads();
+  }
+
+  f4 acc[MB][NB], tacc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      acc[mb][nb] = f4{0, 0, 0, 0};
+      tacc[mb][nb] = f4{0, 0, 0, 0};
+    }
+
+  auto issue = [&](Buf& b, int64_t o, int64_t chunk, int64_t base) {
+    bf_load_x<CASE_B, NP, VEC>(a, base, chunk, j0, g, m, b);
+    const float* kr = a.krp + o * a.Rp + 16 * a.cb0 + m;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b.kr[nb] = kr[16 * nb];
+  };
+  auto consume = [&](const Buf& b, int64_t chunk) {
+    uint4 f[NP][NB];
+    if (a.flds) {
+      const uint4* s = smem + chunk * NB * kWave + lane;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f[p][nb] = s[(p * a.QC * NB + nb) * kWave];
+    } else {
+      const uint4* s = a.fpk + (chunk * a.NBt + a.cb0) * kWave + lane;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f[p][nb] = s[p * a.fplane + nb * kWave];
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        if constexpr (X3) {
+          tacc[mb][nb] = mfma_bf16(b.x[1][mb], f[0][nb], tacc[mb][nb]);
+          tacc[mb][nb] = mfma_bf16(b.x[0][mb], f[1][nb], tacc[mb][nb]);
+        }
+        tacc[mb][nb] = mfma_bf16(b.x[0][mb], f[0][nb], tacc[mb][nb]);
+      }
+  };
+  // Fold T_o into the result with the outer row of o (that of the item just consumed).
+  auto flush = [&](const Buf& b) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[mb][nb][v] = fmaf(tacc[mb][nb][v], b.kr[nb], acc[mb][nb][v]);
+        tacc[mb][nb] = f4{0, 0, 0, 0};
+      }
+  };
+
+  struct Pos {
+    int64_t o, chunk, bo, base;
+  };
+  auto advance = [&](Pos q) {
+    q.chunk += 1;
+    const bool wrap = q.chunk == a.QC;
+    q.chunk = wrap ? 0 : q.chunk;
+    q.o += wrap ? 1 : 0;
+    if constexpr (CASE_B) {
+      q.base += wrap ? a.s_in * a.J : 0;
+    } else {
+      q.bo += wrap ? 1 : 0;
+      q.base += wrap ? a.s_in : 0;
+      const bool carry = q.bo == a.nbo;
+      q.bo = carry ? 0 : q.bo;
+      q.base += carry ? (a.J - 1) * a.Rr : 0;
+    }
+    return q;
+  };
+
+  Buf b0, b1;
+  Pos p0{0, 0, 0, 0};
+  if (it0 < it1) {
+    p0.o = it0 / a.QC;
+    p0.chunk = it0 - p0.o * a.QC;
+    if constexpr (CASE_B) {
+      p0.base = p0.o * a.s_in * a.J;
+    } else {
+      const int64_t aa = p0.o / a.nbo;
+      p0.bo = p0.o - aa * a.nbo;
+      p0.base = aa * a.J * a.Rr + p0.bo * a.s_in;
+    }
+    issue(b0, p0.o, p0.chunk, p0.base);
+  }
+  // Ping-pong: the next item's loads are in flight while the current one is multiplied. The
+  // item after the last one is the last one again (a harmless re-load).
+  for (int64_t it = it0; it < it1; it += 2) {
+    Pos p1 = advance(p0);
+    const bool last0 = it + 1 >= it1;
+    if (last0) p1 = p0;
+    issue(b1, p1.o, p1.chunk, p1.base);
+    consume(b0, p0.chunk);
+    if (last0 || p1.o != p0.o) flush(b0);
+    if (last0) break;
+    Pos p2 = advance(p1);
+    const bool last1 = it + 2 >= it1;
+    if (last1) p2 = p1;
+    issue(b0, p2.o, p2.chunk, p2.base);
+    consume(b1, p1.chunk);
+    if (last1 || p2.o != p1.o) flush(b1);
+    p0 = p2;
+  }
+
+  // Fixed-order sum of the four wavefronts, (w0 + w2) + (w1 + w3), through LDS (the staged
+  // factor is dead once every wavefront has passed the barrier).
+  __syncthreads();
+  f4* red = (f4*)smem;   // [2][MB * NB][64]
+  if (wave >= 2) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) red[((wave - 2) * MB * NB + mb * NB + nb) * kWave + lane] = acc[mb][nb];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] += red[(wave * MB * NB + mb * NB + nb) * kWave + lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) red[(mb * NB + nb) * kWave + lane] = acc[mb][nb];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float* P = a.part + (int64_t)blockIdx.x * a.Jpad * a.Rp;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f4 tot = acc[mb][nb] + red[(mb * NB + nb) * kWave + lane];
+        const int col = 16 * (a.cb0 + nb) + m;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * g + v;   // accumulator row of element v
+          const int64_t row = CASE_B ? j0 + 4 * i + mb : j0 + 16 * mb + i;
+          P[row * a.Rp + col] = tot[v];
+        }
+      }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------
+void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int Rp, int64_t J,
+                              int R, double* m64, void* mout, int mout_dtype, hipStream_t st);
+
+MttkrpGeom mttkrp_geom_bf16(const Plan& p, int mode) {
+  MttkrpGeom g{};
+  const bool caseB = mode == p.N - 1;
+  const int q = caseB ? p.N - 2 : p.N - 1;
+  const int64_t J = p.s[mode];
+  g.MB = caseB ? BfTile<true>::MB : BfTile<false>::MB;
+  g.rows_per_tile = 16 * g.MB;
+  g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
+  g.QC = (p.s[q] + 31) / 32;
+  g.O = p.total / J / p.s[q];
+  g.nitems = g.O * g.QC;
+  const int64_t wgs = (int64_t)kNumCU * (p.xk == 2 ? 1 : 2);   // one resident round
+  int64_t sw = wgs / g.RT;
+  const int64_t max_sw = (g.nitems + 7) / 8;
+  if (sw > max_sw) sw = max_sw;
+  if (sw > kRedSlots) sw = kRedSlots;
+  if (sw < 1) sw = 1;
+  g.SW = sw;
+  g.HS = 0;
+  return g;
+}
+
+static bool bf_vec_ok(const Plan& p, int mode, const void* X) {
+  if (mode == p.N - 1) return ((uintptr_t)X % 8) == 0 && p.s[mode] % 4 == 0;
+  return ((uintptr_t)X % 16) == 0 && p.s[p.N - 1] % 8 == 0;
+}
+
+template <bool CASE_B, bool X3, bool VEC>
+static void bf_launch_nb(int NB, dim3 grid, size_t lds, hipStream_t st, const Bf16Args& a) {
+  switch (NB) {
+#define CPGN_NB(k)                                                                          \
+  case k:                                                                                   \
+    hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC>), grid, dim3(256), lds, st, a); \
+    break;
+    CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4)
+#undef CPGN_NB
+    default: break;
+  }
+}
+
+template <bool CASE_B>
+static void bf_launch(bool x3, bool vec, int NB, dim3 grid, size_t lds, hipStream_t st,
+                      const Bf16Args& a) {
+  if (x3) {
+    if (vec) bf_launch_nb<CASE_B, true, true>(NB, grid, lds, st, a);
+    else bf_launch_nb<CASE_B, true, false>(NB, grid, lds, st, a);
+  } else {
+    if (vec) bf_launch_nb<CASE_B, false, true>(NB, grid, lds, st, a);
+    else bf_launch_nb<CASE_B, false, false>(NB, grid, lds, st, a);
+  }
+}
+
+// Element offset of mode n's outer Khatri-Rao table in the workspace region (FP32 [O_n][Rp]).
+int64_t bf16_krp_offset(const Plan& p, int mode) {
+  int64_t off = 0;
+  for (int n = 0; n < mode; ++n) {
+    const int q = n == p.N - 1 ? p.N - 2 : p.N - 1;
+    off += p.total / p.s[n] / p.s[q] * p.Rp;
+  }
+  return off;
+}
+
+int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double* m64, void* mout,
+                       hipStream_t st) {
+  char* ws = (char*)wsv;
+  const bool caseB = mode == p.N - 1;
+  const int q = caseB ? p.N - 2 : p.N - 1;
+  const bool x3 = p.xk == 2;
+  const bool vec = bf_vec_ok(p, mode, X);
+  const MttkrpGeom G = mttkrp_geom_bf16(p, mode);
+  Bf16Args a{};
+  a.X = (const uint16_t*)X;
+  a.xplane = p.total;
+  a.fpk = (const uint4*)(ws + (caseB ? p.off_fpk_prev : p.off_fpk_last));
+  a.fplane = G.QC * p.NBt * kWave;
+  a.krp = (const float*)(ws + p.off_krp) + bf16_krp_offset(p, mode);
+  a.part = (float*)(ws + p.off_part);
+  a.J = p.s[mode];
+  a.Jpad = G.RT * G.rows_per_tile;
+  a.s_in = p.s[q];
+  a.QC = G.QC;
+  a.nitems = G.nitems;
+  a.Rr = 1;
+  for (int m = mode + 1; m < p.N; ++m) a.Rr *= p.s[m];
+  a.nbo = caseB ? 1 : a.Rr / a.s_in;
+  a.Rp = p.Rp;
+  a.NBt = p.NBt;
+  a.nsplit = (int)(4 * G.SW);
+  const int np = x3 ? 2 : 1;
+  for (int cb0 = 0; cb0 < p.NBt; cb0 += kBfNB) {
+    const int NB = p.NBt - cb0 < kBfNB ? p.NBt - cb0 : kBfNB;
+    a.cb0 = cb0;
+    a.nb = NB;
+    const size_t fbytes = (size_t)np * G.QC * NB * kWave * 16;
+    const size_t rbytes = (size_t)2 * G.MB * NB * kWave * 16;
+    a.flds = fbytes <= (size_t)kBfLdsF ? 1 : 0;
+    const size_t lds = a.flds && fbytes > rbytes ? fbytes : rbytes;
+    const dim3 grid((unsigned)G.SW, (unsigned)G.RT);
+    if (caseB) bf_launch<true>(x3, vec, NB, grid, lds, st, a);
+    else bf_launch<false>(x3, vec, NB, grid, lds, st, a);
+  }
+  launch_mttkrp_reduce_f32(a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, CP_F32, st);
+  return (int)hipGetLastError();
+}
+
+__global__ void k_to_bf16(const float* __restrict__ X, int64_t n, int split,
+                          uint16_t* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float x = X[e];
+    const uint16_t hi = to_bf16_rne(x);
+    out[e] = hi;
+    if (split) out[n + e] = to_bf16_rne(x - bf16_to_float(hi));
+  }
+}
+
+}  // namespace cpgn
+
+extern "C" int cp_tensor_to_bf16(const float* X, int64_t n, int split, void* out, void* stream) {
+  if (n < 0 || (n > 0 && (!X || !out))) return CP_EINVAL;
+  if (n == 0) return CP_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(cpgn::k_to_bf16, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     X, n, split, (uint16_t*)out);
+  return hipGetLastError() == hipSuccess ? CP_OK : CP_EHIP;
+}

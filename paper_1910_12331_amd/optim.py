@@ -132,7 +132,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
         prev = r
     if hist and hist[-1][1] <= target:
         return opt.A, hist
-    A_high = [a.to(X_high.dtype) for a in opt.A]
+    A_high = [a.to(api.factor_dtype(X_high)) for a in opt.A]
     high = GaussNewton(X_high, A_high, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping))
     while opt.steps + high.steps < max_steps:
         high.step()

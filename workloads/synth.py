@@ -28,6 +28,9 @@ __all__ = [
     "make_problem",
     "WORKLOADS",
     "batched_problems",
+    "bf16_round",
+    "bf16_planes",
+    "bf16_values",
 ]
 
 
@@ -147,6 +150,35 @@ def batched_problems(count=64, workload=5, lo=60, hi=200, ranks=(8, 16, 32, 64),
         rank = int(srng.choice(ranks))
         out.append(make_problem(dims, rank, workload=workload, problem=i, noise=noise))
     return out
+
+
+def bf16_round(x):
+    """Bits of float32(x) rounded to the nearest bfloat16, ties to even (finite values): the
+    storage format of the bfloat16 tensor forms. Returns a uint16 array."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    return ((u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) >> np.uint32(16)).astype(np.uint16)
+
+
+def _bf16_to_f32(h):
+    return (h.astype(np.uint32) << np.uint32(16)).view(np.float32)
+
+
+def bf16_planes(x, split=False):
+    """Storage of tensor x as bfloat16: the rounded values (hi) and, with split=True, the rounded
+    remainder lo = bf16(float32(x) - hi) as a second plane, stacked as (2, *shape)."""
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    hi = bf16_round(x32)
+    if not split:
+        return hi
+    lo = bf16_round(x32 - _bf16_to_f32(hi))
+    return np.stack([hi, lo])
+
+
+def bf16_values(planes, split=False):
+    """The float64 tensor a bfloat16 storage represents: hi, or hi + lo for a split (2, ...)
+    array."""
+    v = _bf16_to_f32(np.asarray(planes)).astype(np.float64)
+    return v[0] + v[1] if split else v
 
 
 # The five workloads: (dims, rank, kind, noise, storage dtype).
