@@ -28,7 +28,8 @@ int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t
 int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
 void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
                                    const double*, double*, hipStream_t);
-int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipStream_t, bool);
+int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipStream_t, bool,
+                               unsigned krp_modes = ~0u);
 size_t cg_slot_bytes(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
               double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
@@ -99,12 +100,11 @@ int make_plan(const cp_problem* prob, Plan* p) {
     return at;
   };
   p->off_apad = take((size_t)p->sum_s * p->Rp * p->esz);
-  // packed inner factors: 16-row chunks in the compute precision, or 32-row chunks of
-  // bfloat16 (two planes for the split form)
-  const size_t np = p->xk == 2 ? 2 : 1;
-  const size_t fl = p->xk ? (size_t)(p->s[p->N - 1] + 31) / 32 * p->NBt * 1024 * np
+  // packed inner factors: 16-row chunks in the compute precision, or FP32 32-row chunks for
+  // a bfloat16 tensor
+  const size_t fl = p->xk ? (size_t)(p->s[p->N - 1] + 31) / 32 * p->NBt * 2048
                           : (size_t)p->qc_last * p->NBt * 256 * p->esz;
-  const size_t fp = p->xk ? (size_t)(p->s[p->N - 2] + 31) / 32 * p->NBt * 1024 * np
+  const size_t fp = p->xk ? (size_t)(p->s[p->N - 2] + 31) / 32 * p->NBt * 2048
                           : (size_t)p->qc_prev * p->NBt * 256 * p->esz;
   p->off_fpk_last = take(fl);
   p->off_fpk_prev = take(fp);
@@ -294,7 +294,7 @@ int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int m
   if (!X || !M || mode < 0 || mode >= p.N) return CP_EINVAL;
   if ((rc = check_ptrs(p, A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
-  launch_prepare_factors_src(p, A, p.dtype, ws, st, false);
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, false, 1u << mode);
   launch_mttkrp(p, X, mode, ws, nullptr, M, st);
   return hip_status();
 }
@@ -391,7 +391,7 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
   const Ws w = carve(p, ws);
   const int64_t RR = (int64_t)p.R * p.R;
   launch_state_reset(w.st, st);
-  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true, 1u);
   launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
   int64_t off = 0;
   for (int n = 0; n < p.N; ++n) {
@@ -409,7 +409,7 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
     a.skip_if_status = 1;
     launch_rowmm(d, a, w.st, st);
     // refresh the padded/packed copies, the FP64 copy and the Gram of the updated mode
-    launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+    launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true, 1u << (n + 1));
     launch_gram2(d, w.a64, w.a64, w.S, n, nullptr, st);
     off += p.s[n];
   }
@@ -428,7 +428,8 @@ int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);
   const Ws w = carve(p, ws);
-  launch_prepare_factors_src(p, A, p.dtype, ws, st, method == CP_RESIDUAL_EXPANSION);
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, method == CP_RESIDUAL_EXPANSION,
+                             method == CP_RESIDUAL_EXPANSION ? 1u : 0u);
   if (method == CP_RESIDUAL_DIRECT) {
     launch_residual_direct(p, X, ws, out_dev, st);
   } else {

@@ -364,45 +364,58 @@ __global__ __launch_bounds__(256, 1) void k_mttkrp_tree(MttkrpArgs a) {
   mttkrp_body<T, false, MB, NB, true, true>(a);
 }
 
-// M[j, r] = sum over partial tiles, in FP64, fixed order: lane q of an 8-lane group adds the
-// tiles p = q, q+8, q+16, ... and the 8 lane sums are combined in a fixed butterfly.
-// Writes the FP64 result and/or a copy in the caller's precision.
+// M[j, r] = sum over partial tiles, in FP64, in a fixed order. A workgroup of 16 wavefronts owns
+// 64 consecutive outputs (flattened over j, r < R; one coalesced load per tile and wavefront);
+// wavefront w adds the tiles p = w, w + 16, w + 32, ... in order, and the 16 wavefront sums are
+// added in a fixed tree. Writes the FP64 result and/or a copy in the caller's precision.
+constexpr int kRedWaves = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_mttkrp_reduce(const T* __restrict__ part, int nparts,
-                                                       int64_t Jpad, int Rp, int64_t J, int R,
-                                                       double* __restrict__ m64, void* mout,
-                                                       int mout_dtype) {
-  const int q = threadIdx.x & 7;
+__global__ __launch_bounds__(1024) void k_mttkrp_reduce(const T* __restrict__ part, int nparts,
+                                                        int64_t Jpad, int Rp, int64_t J, int R,
+                                                        double* __restrict__ m64, void* mout,
+                                                        int mout_dtype) {
+  __shared__ double sh[kRedWaves][kWave];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = J * R;
-  for (int64_t idx = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 3; idx < n;
-       idx += ((int64_t)gridDim.x * blockDim.x) >> 3) {
-    const int64_t j = idx / R;
-    const int r = (int)(idx - j * R);
-    const T* p = part + j * Rp + r;
-    const int64_t stride = Jpad * Rp;
-    double s = 0.0;
-    for (int k = q; k < nparts; k += 8) s += (double)p[(int64_t)k * stride];
-    s += __shfl_xor(s, 1, 8);
-    s += __shfl_xor(s, 2, 8);
-    s += __shfl_xor(s, 4, 8);
-    if (q == 0) {
-      if (m64) m64[idx] = s;
+  const int64_t idx = (int64_t)blockIdx.x * kWave + lane;
+  const bool ok = idx < n;
+  const int64_t j = ok ? idx / R : 0;
+  const int r = ok ? (int)(idx - j * R) : 0;
+  const T* p = part + j * Rp + r;
+  const int64_t stride = Jpad * Rp;
+  double s = 0.0;
+#pragma unroll 8
+  for (int k = w; k < nparts; k += kRedWaves) s += (double)p[(int64_t)k * stride];
+  sh[w][lane] = s;
+  __syncthreads();
+  if (w == 0) {
+    double t[kRedWaves];
+#pragma unroll
+    for (int i = 0; i < kRedWaves; ++i) t[i] = sh[i][lane];
+#pragma unroll
+    for (int h = kRedWaves / 2; h >= 1; h /= 2)
+#pragma unroll
+      for (int i = 0; i < h; ++i) t[i] += t[i + h];
+    if (ok) {
+      if (m64) m64[idx] = t[0];
       if (mout) {
-        if (mout_dtype == CP_F64) ((double*)mout)[idx] = s;
-        else ((float*)mout)[idx] = (float)s;
+        if (mout_dtype == CP_F64) ((double*)mout)[idx] = t[0];
+        else ((float*)mout)[idx] = (float)t[0];
       }
     }
   }
 }
 
+static unsigned reduce_grid(int64_t J, int R) { return (unsigned)((J * R + kWave - 1) / kWave); }
+
 // Padded factor copies [s_m][Rp] in the compute precision, optional FP64 copies [s_m][R], and
 // the packed B-operand layout of modes N-1 and N-2:
 //   fpk[chunk][cb][lane][t] = A(q)[16*chunk + 4*(lane/16) + t][16*cb + lane%16]  (0 outside).
-// For a bfloat16 tensor (xk != 0) the packs hold bfloat16 values instead, 8 per lane and chunk
-// of 32 rows, A(q)[32*chunk + 8*(lane/16) + t][16*cb + lane%16], rounded to nearest even, with
-// a second plane of the rounding remainders (also rounded) for the split form; and each mode's
-// outer Khatri-Rao rows krp_n[o][r] = prod over outer modes m of A(m)[i_m(o)][r] in FP32 (outer
-// modes: all but n and its inner mode, ascending, the last one fastest).
+// For a bfloat16 tensor (xk != 0) the packs hold FP32 values in chunks of 32 rows, 8 per lane,
+// A(q)[32*chunk + 8*(lane/16) + t][16*cb + lane%16], and each mode's outer Khatri-Rao rows
+// krp_n[o][r] = prod over outer modes m of A(m)[i_m(o)][r] are written in FP32 (outer modes: all
+// but n and its inner mode, ascending, the last one fastest).
 struct PrepArgs {
   const void* src[kMaxOrder];
   int src_dtype;
@@ -413,10 +426,12 @@ struct PrepArgs {
   float* krp;
   int64_t s[kMaxOrder];
   int64_t seg[kMaxOrder + 4];   // cumulative segment starts: modes' apad, the two packs, tables
-  int64_t krp_seg[kMaxOrder + 1];
+  int64_t krp_seg[kMaxOrder + 1];   // table elements enumerated per mode (0 for skipped modes)
+  int64_t krp_dst[kMaxOrder];       // element offset of each mode's table
+  int small32;                      // every outer index and mode size fits in 32 bits
   int N, R, Rp, NBt, xk;
   int64_t qc_last, qc_prev;
-  int64_t fplane_last, fplane_prev;   // bfloat16 elements per plane of each pack
+  int64_t fplane_last, fplane_prev;   // FP32 elements of each pack (bfloat16 tensor forms)
 };
 
 template <typename T>
@@ -462,13 +477,7 @@ __global__ void k_prepare(PrepArgs a) {
         const int64_t row = 32 * chunk + 8 * (lane >> 4) + t;
         const int col = 16 * cb + (lane & 15);
         const float v = (row < a.s[q] && col < a.R) ? (float)src_at<T>(a, q, row, col) : 0.0f;
-        const uint16_t hi = to_bf16_rne(v);
-        uint16_t* out = (uint16_t*)(last ? a.fpk_last : a.fpk_prev);
-        out[e] = hi;
-        if (a.xk == 2) {   // v - hi is exact in FP32
-          const float rem = v - bf16_to_float(hi);
-          out[e + (last ? a.fplane_last : a.fplane_prev)] = to_bf16_rne(rem);
-        }
+        ((float*)(last ? a.fpk_last : a.fpk_prev))[e] = v;
       }
     } else {
       const int64_t e0 = idx - a.seg[a.N + 2];
@@ -476,16 +485,28 @@ __global__ void k_prepare(PrepArgs a) {
       while (e0 >= a.krp_seg[n + 1]) ++n;
       const int64_t e = e0 - a.krp_seg[n];
       const int q = n == a.N - 1 ? a.N - 2 : a.N - 1;
-      int64_t o = e / a.Rp;
+      const int64_t o = e / a.Rp;
       const int c = (int)(e - o * a.Rp);
       double v = c < a.R ? 1.0 : 0.0;
-      for (int m = a.N - 1; m >= 0 && c < a.R; --m) {
-        if (m == n || m == q) continue;
-        const int64_t im = o % a.s[m];
-        o /= a.s[m];
-        v *= (double)(float)src_at<T>(a, m, im, c);
+      if (a.small32) {
+        uint32_t rem = (uint32_t)o;
+        for (int m = a.N - 1; m >= 0 && c < a.R; --m) {
+          if (m == n || m == q) continue;
+          const uint32_t sm = (uint32_t)a.s[m];
+          const uint32_t im = rem % sm;
+          rem /= sm;
+          v *= (double)(float)src_at<T>(a, m, im, c);
+        }
+      } else {
+        int64_t rem = o;
+        for (int m = a.N - 1; m >= 0 && c < a.R; --m) {
+          if (m == n || m == q) continue;
+          const int64_t im = rem % a.s[m];
+          rem /= a.s[m];
+          v *= (double)(float)src_at<T>(a, m, im, c);
+        }
       }
-      a.krp[e0] = (float)v;
+      a.krp[a.krp_dst[n] + e] = (float)v;
     }
   }
 }
@@ -650,7 +671,7 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
     a.cb0 = cb0;
     launch_variant<T>(caseB, vec, G.MB, NB, dim3((unsigned)G.SW, (unsigned)G.RT), st, a);
   }
-  hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(grid_for(8 * a.J * p.R)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(reduce_grid(a.J, p.R)), dim3(1024), 0, st,
                      (const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);
   if (dt)
     hipLaunchKernelGGL(k_dt_reduce<T>, dim3(grid_for(G.O * p.R)), dim3(256), 0, st,
@@ -661,7 +682,7 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
 
 void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int Rp, int64_t J,
                               int R, double* m64, void* mout, int mout_dtype, hipStream_t st) {
-  hipLaunchKernelGGL(k_mttkrp_reduce<float>, dim3(grid_for(8 * J * R)), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(k_mttkrp_reduce<float>, dim3(reduce_grid(J, R)), dim3(1024), 0, st, part,
                      nparts, Jpad, Rp, J, R, m64, mout, mout_dtype);
 }
 
@@ -690,7 +711,7 @@ int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, 
 
 // Source factors may be the caller's buffers (compute precision) or FP64 copies.
 int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dtype, void* wsv,
-                               hipStream_t st, bool also_a64) {
+                               hipStream_t st, bool also_a64, unsigned krp_modes) {
   char* ws = (char*)wsv;
   PrepArgs a{};
   a.src_dtype = src_dtype;
@@ -725,9 +746,15 @@ int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dt
     a.seg[p.N + 2] = a.seg[p.N + 1] + a.fplane_prev;
     a.krp = (float*)(ws + p.off_krp);
     a.krp_seg[0] = 0;
+    a.small32 = 1;
+    int64_t dst = 0;
     for (int n = 0; n < p.N; ++n) {
       const int q = n == p.N - 1 ? p.N - 2 : p.N - 1;
-      a.krp_seg[n + 1] = a.krp_seg[n] + p.total / p.s[n] / p.s[q] * p.Rp;
+      const int64_t O = p.total / p.s[n] / p.s[q];
+      if (O >= ((int64_t)1 << 32) || p.s[n] >= ((int64_t)1 << 32)) a.small32 = 0;
+      a.krp_dst[n] = dst;
+      dst += O * p.Rp;
+      a.krp_seg[n + 1] = a.krp_seg[n] + (((krp_modes >> n) & 1u) ? O * p.Rp : 0);
     }
     a.seg[p.N + 3] = a.seg[p.N + 2] + a.krp_seg[p.N];
   }
@@ -739,7 +766,7 @@ int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dt
 
 int launch_prepare_factors(const Plan& p, const void* const* A, void* ws, hipStream_t st,
                            bool also_a64) {
-  return launch_prepare_factors_src(p, A, p.dtype, ws, st, also_a64);
+  return launch_prepare_factors_src(p, A, p.dtype, ws, st, also_a64, ~0u);
 }
 
 }  // namespace cpgn

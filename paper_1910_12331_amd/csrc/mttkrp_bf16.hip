@@ -3,25 +3,23 @@
 // FP32; every product is accumulated in FP32.
 //
 // Formulation. As in the FP32/FP64 kernels, the contraction is split into an inner mode q,
-// whose factor is the MFMA B operand, and outer modes:
-//   M(n)[j, r] = sum_o KRP_outer[o, r] * T_o[j, r],   T_o[j, r] = sum_k X[o, j, k] A(q)[k, r].
-// T_o is formed on the matrix cores (16x16x32 bf16 products) from X and the inner factor
-// rounded to bfloat16, and is folded into the FP32 result with the FP32 outer Khatri-Rao row
-// once the wavefront leaves outer index o. Only the inner factor is rounded; the outer
-// Khatri-Rao rows stay in FP32 (they are precomputed per outer index in the workspace).
-// In the split form the inner factor is split like X, F = F_hi + F_lo, and each tile takes the
-// three products X_lo F_hi + X_hi F_lo + X_hi F_hi; the dropped X_lo F_lo term and the
-// remainder of F's split are O(2^-16) relative.
+// whose factor is the MFMA B operand, and outer modes whose Khatri-Rao row is fixed per outer
+// index o:  M(n)[j, r] = sum_{o, k} X[o, j, k] K[o, k, r],  K[o, k, r] = A(q)[k, r] P_o[r],
+// with P_o the FP32 Khatri-Rao row of the outer modes (precomputed per o in the workspace).
+// Each B operand entry K is formed in FP32 from the inner factor (staged in LDS) and P_o and
+// rounded to bfloat16 once; in the split form it is split as K = K_hi + K_lo like X, and each
+// tile takes the three products X_lo K_hi + X_hi K_lo + X_hi K_hi (the dropped X_lo K_lo term
+// and the remainder of K's split are O(2^-16) relative). The products accumulate directly in
+// FP32 registers; nothing else touches the accumulators until the end.
 //   case A (n < N-1): q = N-1, the inner index is contiguous along X rows; lane (m, g) loads
 //     the 8 inner elements [32 c + 8 g, +8) of output row 16 mb + m with one 16-byte load.
 //   case B (n = N-1): q = N-2, the output index is contiguous; lane (m, g) loads 4 consecutive
 //     output rows 4 m + mb for each of its 8 inner indices (8-byte loads) and regroups them
 //     into one A operand per row block.
-// The packed inner factor of this launch's column blocks is staged in LDS once per workgroup
-// when it fits (else read from L2 per item). Wavefronts own a contiguous range of
-// (outer index, inner chunk) items of one row tile; the four wavefronts of a workgroup are
-// summed in LDS in a fixed order into one partial tile, and the partial tiles are added in
-// FP64 in a fixed order, so the results are bitwise reproducible.
+// Wavefronts own a contiguous range of (outer index, inner chunk) items of one row tile and keep
+// the loads of the next items in flight in a ring of register buffers; the four wavefronts of a
+// workgroup are summed in LDS in a fixed order into one partial tile, and the partial tiles are
+// added in FP64 in a fixed order, so the results are bitwise reproducible.
 #include "cpgn_internal.h"
 
 namespace cpgn {
@@ -30,6 +28,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBfNB = 4;              // column blocks of 16 per launch
 constexpr int kBfLdsF = 64 * 1024;    // largest inner factor staged in LDS (bytes)
@@ -37,14 +38,13 @@ constexpr int kBfLdsF = 64 * 1024;    // largest inner factor staged in LDS (byt
 struct Bf16Args {
   const uint16_t* X;            // hi plane (or the only plane)
   int64_t xplane;               // elements between the hi and lo planes (split form)
-  const uint4* fpk;             // packed inner factor [QC][NBt][64 lanes] x 8 bf16; lo plane after
-  int64_t fplane;               // uint4 entries per plane of fpk
+  const f8* fpk;                // packed inner factor [QC][NBt][64 lanes] x 8 floats
   const float* krp;             // outer Khatri-Rao rows [O][Rp], FP32
   float* part;                  // partial tiles [SW][Jpad][Rp]
   int64_t J, Jpad, s_in, QC, nitems, Rr, nbo;
   int Rp, NBt, cb0, nb;         // nb: column blocks of this launch (<= kBfNB)
   int nsplit;                   // wavefronts along the item split (= 4 * gridDim.x)
-  int flds;                     // inner factor staged in LDS
+  int flds;                     // inner factor staged in LDS (else read per item)
 };
 
 template <bool CASE_B> struct BfTile {
@@ -56,71 +56,84 @@ __device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-template <bool CASE_B, int NP>
+template <bool CASE_B, int NP, bool FLDS, int NB>
 struct BfBuf {
   static constexpr int MB = BfTile<CASE_B>::MB;
-  uint4 x[NP][MB];       // A operands (8 bf16 of one output row) per plane and row block
-  float kr[kBfNB];       // outer Khatri-Rao row of the item's outer index (this lane's columns)
+  uint4 x[NP][MB];             // A operands (8 bf16 of one output row) per plane and row block
+  float kr[NB];                // outer Khatri-Rao row of the item's outer index (lane's columns)
+  f8 f[FLDS ? 1 : NB];         // inner factor rows when the factor is not staged in LDS
 };
 
-// X fragment of one item. Out-of-range lanes read a clamped in-bounds address and select 0,
-// so the loads carry no branches.
-template <bool CASE_B, int NP, bool VEC>
+// Eight FP32 values rounded to bfloat16 (nearest even) and packed as an MFMA operand; with a
+// remainder plane, lo = bf16(v - hi) as well.
+__device__ __forceinline__ uint4 pack_bf16(const f8& v) {
+  uint32_t d[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    d[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{v[2 * i], v[2 * i + 1]}, bf16x2));
+  return uint4{d[0], d[1], d[2], d[3]};
+}
+__device__ __forceinline__ f8 unpack_bf16(uint4 h) {
+  const uint32_t d[4] = {h.x, h.y, h.z, h.w};
+  f8 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __builtin_bit_cast(float, d[i] << 16);
+    v[2 * i + 1] = __builtin_bit_cast(float, d[i] & 0xffff0000u);
+  }
+  return v;
+}
+
+// X fragment of one item. Every load is issued unconditionally from an in-bounds address: an
+// inner index past s_in is clamped into the same row (the packed factor is zero there, so it
+// contributes nothing for finite X), and an output row past J reads row J-1 (its result lands in
+// a padding row of the partial tile that is never read). Without per-lane selects the loads stay
+// branch-free, and the wait counts before each multiply cover only the item being consumed.
+template <bool CASE_B, int NP, bool VEC, typename Buf>
 __device__ __forceinline__ void bf_load_x(const Bf16Args& a, int64_t base, int64_t chunk,
-                                          int64_t j0, int g, int m, BfBuf<CASE_B, NP>& b) {
+                                          int64_t j0, int g, int m, Buf& b) {
   constexpr int MB = BfTile<CASE_B>::MB;
   const int64_t in0 = chunk * 32 + 8 * g;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    const uint16_t* X = a.X + p * a.xplane;
+    const uint16_t* X = a.X + p * a.xplane + base;
     if constexpr (!CASE_B) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const int64_t j = j0 + 16 * mb + m;
+        int64_t j = j0 + 16 * mb + m;
+        j = j < a.J ? j : a.J - 1;
         if constexpr (VEC) {
-          const bool ok = j < a.J && in0 < a.s_in;
-          const uint4 w = *(const uint4*)(X + (ok ? base + j * a.Rr + in0 : 0));
-          b.x[p][mb] = ok ? w : uint4{0, 0, 0, 0};
+          const int64_t i = in0 < a.s_in ? in0 : a.s_in - 8;
+          b.x[p][mb] = *(const uint4*)(X + j * a.Rr + i);
         } else {
           u16x8 h;
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
-            const bool ok = j < a.J && in0 + t < a.s_in;
-            const uint16_t w = X[ok ? base + j * a.Rr + in0 + t : 0];
-            h[t] = ok ? w : (uint16_t)0;
+            const int64_t i = in0 + t < a.s_in ? in0 + t : a.s_in - 1;
+            h[t] = X[j * a.Rr + i];
           }
           b.x[p][mb] = __builtin_bit_cast(uint4, h);
         }
       }
     } else {
-      // r[kk][v]: output row jb + v at inner index in0 + kk (16-bit values in 32-bit lanes)
       const int64_t jb = j0 + 4 * m;
       uint32_t lo16[8][2], hi16[8][2];   // dword d of the 4-row group: rows 2d (lo), 2d+1 (hi)
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
-        const int64_t inn = in0 + kk;
+        const int64_t inn = in0 + kk < a.s_in ? in0 + kk : a.s_in - 1;
+        uint2 w;
         if constexpr (VEC) {
-          const bool ok = inn < a.s_in && jb < a.J;
-          const uint2 w = *(const uint2*)(X + (ok ? base + inn * a.J + jb : 0));
-          const uint32_t w0 = ok ? w.x : 0u, w1 = ok ? w.y : 0u;
-          lo16[kk][0] = w0 & 0xffffu;
-          hi16[kk][0] = w0 >> 16;
-          lo16[kk][1] = w1 & 0xffffu;
-          hi16[kk][1] = w1 >> 16;
+          w = *(const uint2*)(X + inn * a.J + (jb < a.J ? jb : a.J - 4));
         } else {
           u16x4 h;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const bool ok = inn < a.s_in && jb + v < a.J;
-            const uint16_t w = X[ok ? base + inn * a.J + jb + v : 0];
-            h[v] = ok ? w : (uint16_t)0;
-          }
-          const uint2 w = __builtin_bit_cast(uint2, h);
-          lo16[kk][0] = w.x & 0xffffu;
-          hi16[kk][0] = w.x >> 16;
-          lo16[kk][1] = w.y & 0xffffu;
-          hi16[kk][1] = w.y >> 16;
+          for (int v = 0; v < 4; ++v) h[v] = X[inn * a.J + (jb + v < a.J ? jb + v : a.J - 1)];
+          w = __builtin_bit_cast(uint2, h);
         }
+        lo16[kk][0] = w.x & 0xffffu;
+        hi16[kk][0] = w.x >> 16;
+        lo16[kk][1] = w.y & 0xffffu;
+        hi16[kk][1] = w.y >> 16;
       }
       // row block mb = output rows jb + mb: 8 inner values, two per dword
 #pragma unroll
@@ -138,11 +151,11 @@ __device__ __forceinline__ void bf_load_x(const Bf16Args& a, int64_t base, int64
   }
 }
 
-template <bool CASE_B, int NB, bool X3, bool VEC>
-__global__ __launch_bounds__(256, (!X3 && VEC) ? 2 : 1) void k_mttkrp_bf16(Bf16Args a) {
+template <bool CASE_B, int NB, bool X3, bool VEC, bool FLDS>
+__global__ __launch_bounds__(256, 1) void k_mttkrp_bf16(Bf16Args a) {
   constexpr int MB = BfTile<CASE_B>::MB;
   constexpr int NP = X3 ? 2 : 1;
-  typedef BfBuf<CASE_B, NP> Buf;
+  typedef BfBuf<CASE_B, NP, FLDS, NB> Buf;
   extern __shared__ uint4 smem[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -152,72 +165,56 @@ __global__ __launch_bounds__(256, (!X3 && VEC) ? 2 : 1) void k_mttkrp_bf16(Bf16A
   const int64_t it0 = a.nitems * split / a.nsplit;
   const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
 
-  // Stage the packed inner factor of this launch's column blocks: sF[p][chunk][nb][lane].
-  if (a.flds) {
-    const int64_t n = (int64_t)NP * a.QC * NB * kWave;
+  // Stage the packed inner factor of this launch's column blocks: sF[chunk][nb][lane] (8 floats).
+  f8* sF = (f8*)smem;
+  if constexpr (FLDS) {
+    const int64_t n = a.QC * NB * kWave;
     for (int64_t e = threadIdx.x; e < n; e += 256) {
       const int l = (int)(e % kWave);
       const int64_t r = e / kWave;
       const int nb = (int)(r % NB);
-      const int64_t pc = r / NB;
-      const int p = (int)(pc / a.QC);
-      const int64_t c = pc - p * a.QC;
-      smem[e] = a.fpk[p * a.fplane + (c * a.NBt + a.cb0 + nb) * kWave + l];
+      const int64_t c = r / NB;
+      sF[e] = a.fpk[(c * a.NBt + a.cb0 + nb) * kWave + l];
     }
     __syncthreads();
   }
 
-  f4 acc[MB][NB], tacc[MB][NB];
+  f4 acc[MB][NB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      acc[mb][nb] = f4{0, 0, 0, 0};
-      tacc[mb][nb] = f4{0, 0, 0, 0};
-    }
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
 
   auto issue = [&](Buf& b, int64_t o, int64_t chunk, int64_t base) {
     bf_load_x<CASE_B, NP, VEC>(a, base, chunk, j0, g, m, b);
     const float* kr = a.krp + o * a.Rp + 16 * a.cb0 + m;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) b.kr[nb] = kr[16 * nb];
+    if constexpr (!FLDS) {
+      const f8* f = a.fpk + (chunk * a.NBt + a.cb0) * kWave + lane;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b.f[nb] = f[nb * kWave];
+    }
   };
   auto consume = [&](const Buf& b, int64_t chunk) {
-    uint4 f[NP][NB];
-    if (a.flds) {
-      const uint4* s = smem + chunk * NB * kWave + lane;
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+    for (int nb = 0; nb < NB; ++nb) {
+      f8 fv;
+      if constexpr (FLDS) fv = sF[(chunk * NB + nb) * kWave + lane];
+      else fv = b.f[nb];
+      const f8 kv = fv * b.kr[nb];   // Khatri-Rao entries of this lane's 8 inner rows, FP32
+      const uint4 khi = pack_bf16(kv);
+      uint4 klo;
+      if constexpr (X3) klo = pack_bf16(kv - unpack_bf16(khi));   // exact difference
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) f[p][nb] = s[(p * a.QC * NB + nb) * kWave];
-    } else {
-      const uint4* s = a.fpk + (chunk * a.NBt + a.cb0) * kWave + lane;
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) f[p][nb] = s[p * a.fplane + nb * kWave];
-    }
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
+      for (int mb = 0; mb < MB; ++mb) {
         if constexpr (X3) {
-          tacc[mb][nb] = mfma_bf16(b.x[1][mb], f[0][nb], tacc[mb][nb]);
-          tacc[mb][nb] = mfma_bf16(b.x[0][mb], f[1][nb], tacc[mb][nb]);
+          acc[mb][nb] = mfma_bf16(b.x[1][mb], khi, acc[mb][nb]);
+          acc[mb][nb] = mfma_bf16(b.x[0][mb], klo, acc[mb][nb]);
         }
-        tacc[mb][nb] = mfma_bf16(b.x[0][mb], f[0][nb], tacc[mb][nb]);
+        acc[mb][nb] = mfma_bf16(b.x[0][mb], khi, acc[mb][nb]);
       }
-  };
-  // Fold T_o into the result with the outer row of o (that of the item just consumed).
-  auto flush = [&](const Buf& b) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[mb][nb][v] = fmaf(tacc[mb][nb][v], b.kr[nb], acc[mb][nb][v]);
-        tacc[mb][nb] = f4{0, 0, 0, 0};
-      }
+    }
   };
 
   struct Pos {
@@ -240,37 +237,48 @@ __global__ __launch_bounds__(256, (!X3 && VEC) ? 2 : 1) void k_mttkrp_bf16(Bf16A
     return q;
   };
 
-  Buf b0, b1;
-  Pos p0{0, 0, 0, 0};
+  // Ring of D item buffers: the loads of the next D - 1 items are in flight while the current
+  // one is multiplied (one wavefront per SIMD, so the in-flight bytes come from depth rather
+  // than from other wavefronts). Items past the range repeat the last one (harmless re-loads,
+  // never multiplied).
+  constexpr int D = !FLDS ? 2 : X3 ? 3 : 4;
+  Buf buf[D];
+  Pos pos[D];
   if (it0 < it1) {
-    p0.o = it0 / a.QC;
-    p0.chunk = it0 - p0.o * a.QC;
+    Pos q{0, 0, 0, 0};
+    q.o = it0 / a.QC;
+    q.chunk = it0 - q.o * a.QC;
     if constexpr (CASE_B) {
-      p0.base = p0.o * a.s_in * a.J;
+      q.base = q.o * a.s_in * a.J;
     } else {
-      const int64_t aa = p0.o / a.nbo;
-      p0.bo = p0.o - aa * a.nbo;
-      p0.base = aa * a.J * a.Rr + p0.bo * a.s_in;
+      const int64_t aa = q.o / a.nbo;
+      q.bo = q.o - aa * a.nbo;
+      q.base = aa * a.J * a.Rr + q.bo * a.s_in;
     }
-    issue(b0, p0.o, p0.chunk, p0.base);
-  }
-  // Ping-pong: the next item's loads are in flight while the current one is multiplied. The
-  // item after the last one is the last one again (a harmless re-load).
-  for (int64_t it = it0; it < it1; it += 2) {
-    Pos p1 = advance(p0);
-    const bool last0 = it + 1 >= it1;
-    if (last0) p1 = p0;
-    issue(b1, p1.o, p1.chunk, p1.base);
-    consume(b0, p0.chunk);
-    if (last0 || p1.o != p0.o) flush(b0);
-    if (last0) break;
-    Pos p2 = advance(p1);
-    const bool last1 = it + 2 >= it1;
-    if (last1) p2 = p1;
-    issue(b0, p2.o, p2.chunk, p2.base);
-    consume(b1, p1.chunk);
-    if (last1 || p2.o != p1.o) flush(b1);
-    p0 = p2;
+    Pos nx = q;                 // next position to issue
+    int64_t inx = it0;          // its item index
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k) {
+      pos[k] = nx;
+      issue(buf[k], nx.o, nx.chunk, nx.base);
+      if (inx + 1 < it1) {
+        nx = advance(nx);
+        ++inx;
+      }
+    }
+    for (int64_t it = it0; it < it1; it += D) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int ki = (k + D - 1) % D;   // buffer of item it + k + D - 1
+        pos[ki] = nx;
+        issue(buf[ki], nx.o, nx.chunk, nx.base);
+        if (inx + 1 < it1) {
+          nx = advance(nx);
+          ++inx;
+        }
+        if (it + k < it1) consume(buf[k], pos[k].chunk);
+      }
+    }
   }
 
   // Fixed-order sum of the four wavefronts, (w0 + w2) + (w1 + w3), through LDS (the staged
@@ -333,7 +341,7 @@ MttkrpGeom mttkrp_geom_bf16(const Plan& p, int mode) {
   g.QC = (p.s[q] + 31) / 32;
   g.O = p.total / J / p.s[q];
   g.nitems = g.O * g.QC;
-  const int64_t wgs = (int64_t)kNumCU * (p.xk == 2 ? 1 : 2);   // one resident round
+  const int64_t wgs = kNumCU;   // one resident round: one workgroup (a wavefront per SIMD) per CU
   int64_t sw = wgs / g.RT;
   const int64_t max_sw = (g.nitems + 7) / 8;
   if (sw > max_sw) sw = max_sw;
@@ -352,9 +360,12 @@ static bool bf_vec_ok(const Plan& p, int mode, const void* X) {
 template <bool CASE_B, bool X3, bool VEC>
 static void bf_launch_nb(int NB, dim3 grid, size_t lds, hipStream_t st, const Bf16Args& a) {
   switch (NB) {
-#define CPGN_NB(k)                                                                          \
-  case k:                                                                                   \
-    hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC>), grid, dim3(256), lds, st, a); \
+#define CPGN_NB(k)                                                                            \
+  case k:                                                                                     \
+    if (a.flds)                                                                               \
+      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, true>), grid, dim3(256), lds, st, a); \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, false>), grid, dim3(256), lds, st, a); \
     break;
     CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4)
 #undef CPGN_NB
@@ -395,8 +406,7 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
   Bf16Args a{};
   a.X = (const uint16_t*)X;
   a.xplane = p.total;
-  a.fpk = (const uint4*)(ws + (caseB ? p.off_fpk_prev : p.off_fpk_last));
-  a.fplane = G.QC * p.NBt * kWave;
+  a.fpk = (const f8*)(ws + (caseB ? p.off_fpk_prev : p.off_fpk_last));
   a.krp = (const float*)(ws + p.off_krp) + bf16_krp_offset(p, mode);
   a.part = (float*)(ws + p.off_part);
   a.J = p.s[mode];
@@ -410,12 +420,11 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
   a.Rp = p.Rp;
   a.NBt = p.NBt;
   a.nsplit = (int)(4 * G.SW);
-  const int np = x3 ? 2 : 1;
   for (int cb0 = 0; cb0 < p.NBt; cb0 += kBfNB) {
     const int NB = p.NBt - cb0 < kBfNB ? p.NBt - cb0 : kBfNB;
     a.cb0 = cb0;
     a.nb = NB;
-    const size_t fbytes = (size_t)np * G.QC * NB * kWave * 16;
+    const size_t fbytes = (size_t)G.QC * NB * kWave * 32;
     const size_t rbytes = (size_t)2 * G.MB * NB * kWave * 16;
     a.flds = fbytes <= (size_t)kBfLdsF ? 1 : 0;
     const size_t lds = a.flds && fbytes > rbytes ? fbytes : rbytes;

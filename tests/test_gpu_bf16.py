@@ -2,14 +2,15 @@
 the C ABI, against the FP64 oracle on the values the bfloat16 storage represents.
 
 Error bound. The stored tensor is exact (the oracle takes hi, or hi + lo, in FP64). The library
-rounds only the inner factor to bfloat16 (relative error <= 2^-8; <= 2^-16 for its hi + lo split),
-drops the lo*lo product in the split form (<= 2^-16 (1 + 2^-8)^2 relative to |X||F|), and adds
-in FP32 along chains of at most s_in terms (the inner contraction) and O terms (outer indices of
-one wavefront), plus the fixed four-wavefront and FP64 partial sums. Elementwise, with
-Mabs = MTTKRP(|X|, |A|):
-    |M_gpu - M| <= gamma * Mabs,  gamma = u_f + 2 (s_in + O + 64) 2^-24,
-u_f = 2^-8 (single plane) or 1.1 * 2^-15 (split). A dropped term or a wrong operand layout
-exceeds it by orders of magnitude.
+forms each Khatri-Rao entry K = A(q)[k, r] * P_o[r] in FP32 (P_o, the outer modes' row, rounded
+once to FP32) and rounds it to bfloat16 (relative error <= 2^-8; <= 2^-16 for its hi + lo split),
+drops the lo*lo product in the split form (<= 2^-16 (1 + 2^-8)^2 relative to |X||K|), and sums in
+FP32: 32 products per matrix instruction into an accumulator that runs over the L items of one
+wavefront, then the fixed four-wavefront sum; the partial tiles are added in FP64. Elementwise,
+with Mabs = MTTKRP(|X|, |A|):
+    |M_gpu - M| <= gamma * Mabs,  gamma = u_f + 2 (L + 48) 2^-24,
+u_f = 2^-8 (single plane) or 1.1 * 2^-15 (split); L is computed from the launch geometry below.
+A dropped term or a wrong operand layout exceeds it by orders of magnitude.
 """
 import numpy as np
 import pytest
@@ -45,11 +46,24 @@ def f32(arrs):
     return [np.asarray(a, dtype=np.float32).astype(np.float64) for a in arrs]
 
 
-def gamma(dims, mode, split):
+def items_per_wavefront(dims, mode):
+    """Largest number of (outer index, 32-wide inner chunk) items one wavefront accumulates:
+    row tiles of 80 rows (64 for the last mode), one resident workgroup of four wavefronts per
+    compute unit (256) split over the tiles, at least two items per wavefront."""
     N = len(dims)
-    q = N - 2 if mode == N - 1 else N - 1
-    outer = int(np.prod(dims)) // dims[mode] // dims[q]
-    return (1.1 * 2.0 ** -15 if split else 2.0 ** -8) + 2 * (dims[q] + outer + 64) * 2.0 ** -24
+    caseB = mode == N - 1
+    q = N - 2 if caseB else N - 1
+    J = dims[mode]
+    outer = int(np.prod(dims)) // J // dims[q]
+    nitems = outer * ((dims[q] + 31) // 32)
+    rt = -(-J // (64 if caseB else 80))
+    sw = max(1, min(256 // rt, -(-nitems // 8), 1024))
+    return -(-nitems // (4 * sw))
+
+
+def gamma(dims, mode, split):
+    L = items_per_wavefront(dims, mode)
+    return (1.1 * 2.0 ** -15 if split else 2.0 ** -8) + 2 * (L + 48) * 2.0 ** -24
 
 
 def stored(p, split):
