@@ -6,6 +6,12 @@ Gauss-Newton iteration (all-mode MTTKRP, Grams, gradient, preconditioned CG with
 and at most 20 iterations, factor update) followed by the direct relative residual that the
 stopping test reads. Inputs are resident in HBM before timing starts.
 
+Further legs (reported beside the headline value): MTTKRP TFLOP/s per mode in FP32 and FP64;
+time to relative residual 1e-8 with FP64 storage against the mixed FP32 -> FP64 run; 64 uneven
+problems advanced together on HIP streams; an 80^4 order-4 rank-64 tensor stored in bfloat16,
+split bfloat16, FP32 and FP64 (MTTKRP time and error, GN step time, per-step residual error
+against the FP64-storage run); the CPU oracle on a bounded sample of the headline workload.
+
 Prints one JSON line. Run: python bench.py [--steps K] [--warmup W]
 """
 from __future__ import annotations
@@ -44,6 +50,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-streams", type=int, default=8)
+    ap.add_argument("--no-order4", action="store_true",
+                    help="skip the 80^4 R=64 bfloat16 / split-bfloat16 leg")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run each single-mode MTTKRP and one device copy of X of known size "
                          "(the workload the rocprofv3 counter runs are taken on), then exit")
@@ -107,9 +115,76 @@ def mttkrp_times(P, Xd, A, reps, stream):
 # counter reads for a device copy of X (256 MB read + 256 MB written), so 1.0 = exact bytes.
 # Valid only for the kernel source it was taken on.
 MTTKRP_TRAFFIC = {
-    "source_sha256": "8d4e096dd73042c45a9cb4b55d0762ae3346a14f90a549c6743acdfd94bf0a61",
-    "bytes_per_launch": 308163053,   # mean over the three modes of the main kernel
+    "source_sha256": "4b3ca6a86f6a06dd8c065c7d084cd98f2c48a95d3d4774b45f50f1056ab398f6",
+    "bytes_per_launch": 308249863,   # mean over the three modes of the main kernel
 }
+
+
+def order4_leg(P, torch, reps, stream):
+    """80^4 order-4 tensor, rank 64, log-uniform column norms, noise 1e-3: MTTKRP per mode and
+    GN steps with the tensor stored in bfloat16, split bfloat16, FP32 and FP64 (factors FP32,
+    FP64 for FP64 storage), and the per-step error of each against the FP64-storage run."""
+    from workloads import make_problem
+    dims, R = (80, 80, 80, 80), 64
+    p = make_problem(dims, R, workload=4, problem=0, kind="lognorm", noise=1e-3)
+    X64 = torch.from_numpy(p.x).cuda()
+    X32 = X64.float()
+    forms = {"bf16": P.to_bf16(X32), "bf16x3": P.to_bf16(X32, split=True), "f32": X32, "f64": X64}
+    xbytes = {"bf16": 2, "bf16x3": 4, "f32": 4, "f64": 8}
+    # start: the planted factors with 10% relative elementwise perturbation (an N(0,1) start is
+    # scaled far off the column norms of up to 100 and sends the first steps away)
+    rng = np.random.default_rng(4500)
+    A32 = [torch.tensor(b * (1.0 + 0.1 * rng.standard_normal(b.shape)), dtype=torch.float32,
+                        device="cuda") for b in p.planted]
+    A64 = [a.double() for a in A32]
+    flops = 2.0 * float(np.prod(dims)) * R
+    ws = P.Workspace()
+    M64 = [P.mttkrp(X64, A64, n, ws=ws) for n in range(4)]
+    out = {}
+    for name, X in forms.items():
+        A = A64 if name == "f64" else A32
+        modes = {}
+        for n in range(4):
+            M = torch.empty((dims[n], R), dtype=A[0].dtype, device="cuda")
+            for _ in range(3):
+                P.mttkrp(X, A, n, out=M, ws=ws)
+            ts = event_samples(lambda: P.mttkrp(X, A, n, out=M, ws=ws), reps, stream)
+            t = float(np.median(ts))
+            err = float(torch.linalg.norm(M.double() - M64[n]) / torch.linalg.norm(M64[n]))
+            modes[f"mode{n}"] = dict(median_ms=t * 1e3, tflops=flops / t / 1e12,
+                                     x_read_gbs=float(np.prod(dims)) * xbytes[name] / t / 1e9,
+                                     rel_err_vs_fp64_storage=err)
+        # GN steps from the same start and damping schedule; the first eight steps' direct
+        # residual against the FP64 master tensor, and the step time (20 CG iterations)
+        Ag = [a.clone() for a in A]
+        gn = P.GaussNewton(X, Ag, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+        traj = []
+        for _ in range(8):
+            gn.step()
+            r = P.residual(X64, [a.double() for a in gn.A], ws=ws).cpu()
+            traj.append(float(r[0] / r[1]))
+        At = [a.clone() for a in A]
+        sb = P.stats_buffer(X64.device)
+        ws2 = P.Workspace()
+        for _ in range(2):
+            P.gn_step(X, At, 1e-4, 0.0, 20, stats=sb, ws=ws2)
+        tstep = event_time(lambda: P.gn_step(X, At, 1e-4, 0.0, 20, stats=sb, ws=ws2), 5, stream)
+        out[name] = dict(mttkrp=modes, gn_step_20cg_ms=tstep * 1e3, residual_first_steps=traj)
+        del Ag, gn, At
+    for name in out:
+        out[name]["residual_err_vs_fp64_per_step"] = [
+            abs(a - b) / b for a, b in zip(out[name]["residual_first_steps"], out["f64"]["residual_first_steps"])]
+    log("[bench] 80^4 R=64 MTTKRP per mode (ms): " + "; ".join(
+        f"{k} " + " ".join(f"{v['mttkrp'][f'mode{n}']['median_ms']:.4f}" for n in range(4)) for k, v in out.items()))
+    log("[bench] 80^4 MTTKRP rel. error vs FP64 storage (mode 0): " + ", ".join(
+        f"{k} {v['mttkrp']['mode0']['rel_err_vs_fp64_storage']:.2e}" for k, v in out.items()))
+    del X64, X32, forms, M64
+    log("[bench] 80^4 GN residual after 8 steps: " + ", ".join(
+        f"{k} {v['residual_first_steps'][-1]:.3e}" for k, v in out.items()))
+    return dict(workload="dense 80^4 tensor, rank-64 CP with N(0,1) factors whose columns are "
+                         "scaled log-uniformly over [1,100], noise 1e-3; rank-64 GN-CG from the "
+                         "planted factors with 10% relative perturbation",
+                hbm_peak_gbs=PEAK_HBM_GBS, **out)
 
 
 def kernel_source_hash():
@@ -282,6 +357,9 @@ def main():
             f"p50 {res[args.batched_streams]['step_ms_p50']:.3f} ms, p99 {res[args.batched_streams]['step_ms_p99']:.3f} ms")
         del devs
 
+    # ---- order-4 workload in bfloat16 / split bfloat16 / FP32 / FP64 storage
+    order4 = None if args.no_order4 else order4_leg(P, torch, args.mttkrp_reps, stream)
+
     # ---- CPU baseline: the oracle on host cores, bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -348,6 +426,7 @@ def main():
         "residual_after": r_now,
         "time_to_1e-8": ttt,
         "batched": batched,
+        "order4_bf16": order4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
