@@ -17,7 +17,7 @@
 //     output rows 4 m + mb for each of its 8 inner indices (8-byte loads) and regroups them
 //     into one A operand per row block.
 // Wavefronts own a contiguous range of (outer index, inner chunk) items of one row tile and keep
-// the loads of the next items in flight in a ring of register buffers; the four wavefronts of a
+// the loads of the next items in flight in a ring of register buffers; the wavefronts of a
 // workgroup are summed in LDS in a fixed order into one partial tile, and the partial tiles are
 // added in FP64 in a fixed order, so the results are bitwise reproducible.
 #include "cpgn_internal.h"
@@ -33,6 +33,7 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBfNB = 4;              // column blocks of 16 per launch
+
 constexpr int kBfLdsF = 64 * 1024;    // largest inner factor staged in LDS (bytes)
 
 struct Bf16Args {
@@ -43,12 +44,18 @@ struct Bf16Args {
   float* part;                  // partial tiles [SW][Jpad][Rp]
   int64_t J, Jpad, s_in, QC, nitems, Rr, nbo;
   int Rp, NBt, cb0, nb;         // nb: column blocks of this launch (<= kBfNB)
-  int nsplit;                   // wavefronts along the item split (= 4 * gridDim.x)
+  int nsplit;                   // wavefronts along the item split (= waves per workgroup x gridDim.x)
   int flds;                     // inner factor staged in LDS (else read per item)
 };
 
+// Tile and launch shape per case (measured at 80^4 R=64): case A keeps one wavefront per SIMD
+// with a deep ring of in-flight items; case B, whose items need more regrouping work, runs two
+// wavefronts per SIMD with a shallower ring. One workgroup per CU in both.
 template <bool CASE_B> struct BfTile {
-  static constexpr int MB = CASE_B ? 4 : 5;
+  static constexpr int MB = CASE_B ? 4 : 5;       // 16-row blocks per wavefront tile
+  static constexpr int W = CASE_B ? 8 : 4;        // wavefronts per workgroup
+  static constexpr int D1 = CASE_B ? 2 : 4;       // ring depth, single plane
+  static constexpr int D3 = CASE_B ? 2 : 3;       // ring depth, split form
 };
 
 __device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
@@ -152,29 +159,35 @@ __device__ __forceinline__ void bf_load_x(const Bf16Args& a, int64_t base, int64
 }
 
 template <bool CASE_B, int NB, bool X3, bool VEC, bool FLDS>
-__global__ __launch_bounds__(256, 1) void k_mttkrp_bf16(Bf16Args a) {
+__global__ __launch_bounds__(BfTile<CASE_B>::W * 64, 1) void k_mttkrp_bf16(Bf16Args a) {
   constexpr int MB = BfTile<CASE_B>::MB;
+  constexpr int kBfWaves = BfTile<CASE_B>::W;
+  constexpr int kBfThreads = kBfWaves * 64;
   constexpr int NP = X3 ? 2 : 1;
   typedef BfBuf<CASE_B, NP, FLDS, NB> Buf;
   extern __shared__ uint4 smem[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, m = lane & 15;
-  const int split = blockIdx.x * 4 + wave;
+  const int split = blockIdx.x * kBfWaves + wave;
   const int64_t j0 = (int64_t)blockIdx.y * 16 * MB;
   const int64_t it0 = a.nitems * split / a.nsplit;
   const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
 
-  // Stage the packed inner factor of this launch's column blocks: sF[chunk][nb][lane] (8 floats).
-  f8* sF = (f8*)smem;
+  // Stage the packed inner factor of this launch's column blocks as sF[chunk][nb][half][lane]:
+  // each lane's 8 floats in two 16-byte halves, so that a wavefront's read of one half covers
+  // 1 KB of consecutive LDS (no bank conflicts).
+  uint4* sF = smem;
   if constexpr (FLDS) {
     const int64_t n = a.QC * NB * kWave;
-    for (int64_t e = threadIdx.x; e < n; e += 256) {
+    for (int64_t e = threadIdx.x; e < n; e += kBfThreads) {
       const int l = (int)(e % kWave);
       const int64_t r = e / kWave;
       const int nb = (int)(r % NB);
       const int64_t c = r / NB;
-      sF[e] = a.fpk[(c * a.NBt + a.cb0 + nb) * kWave + l];
+      const f8 v = a.fpk[(c * a.NBt + a.cb0 + nb) * kWave + l];
+      sF[(2 * r) * kWave + l] = __builtin_bit_cast(uint4, f4{v[0], v[1], v[2], v[3]});
+      sF[(2 * r + 1) * kWave + l] = __builtin_bit_cast(uint4, f4{v[4], v[5], v[6], v[7]});
     }
     __syncthreads();
   }
@@ -200,8 +213,13 @@ __global__ __launch_bounds__(256, 1) void k_mttkrp_bf16(Bf16Args a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       f8 fv;
-      if constexpr (FLDS) fv = sF[(chunk * NB + nb) * kWave + lane];
-      else fv = b.f[nb];
+      if constexpr (FLDS) {
+        const f4 h0 = __builtin_bit_cast(f4, sF[(2 * (chunk * NB + nb)) * kWave + lane]);
+        const f4 h1 = __builtin_bit_cast(f4, sF[(2 * (chunk * NB + nb) + 1) * kWave + lane]);
+        fv = f8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+      } else {
+        fv = b.f[nb];
+      }
       const f8 kv = fv * b.kr[nb];   // Khatri-Rao entries of this lane's 8 inner rows, FP32
       const uint4 khi = pack_bf16(kv);
       uint4 klo;
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(256, 1) void k_mttkrp_bf16(Bf16Args a) {
   // one is multiplied (one wavefront per SIMD, so the in-flight bytes come from depth rather
   // than from other wavefronts). Items past the range repeat the last one (harmless re-loads,
   // never multiplied).
-  constexpr int D = !FLDS ? 2 : X3 ? 3 : 4;
+  constexpr int D = !FLDS ? 2 : X3 ? BfTile<CASE_B>::D3 : BfTile<CASE_B>::D1;
   Buf buf[D];
   Pos pos[D];
   if (it0 < it1) {
@@ -281,38 +299,37 @@ __global__ __launch_bounds__(256, 1) void k_mttkrp_bf16(Bf16Args a) {
     }
   }
 
-  // Fixed-order sum of the four wavefronts, (w0 + w2) + (w1 + w3), through LDS (the staged
-  // factor is dead once every wavefront has passed the barrier).
-  __syncthreads();
+  // Fixed-order sum of the wavefronts through LDS (the staged factor is dead once every
+  // wavefront has passed the first barrier): at level h, wavefront w < h adds wavefront w + h,
+  // two source wavefronts per round through two LDS slots.
   f4* red = (f4*)smem;   // [2][MB * NB][64]
-  if (wave >= 2) {
+  for (int h = kBfWaves / 2; h >= 1; h /= 2) {
+    for (int r0 = 0; r0 < h; r0 += 2) {
+      __syncthreads();
+      if (wave >= h + r0 && wave < h + r0 + 2) {
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) red[((wave - 2) * MB * NB + mb * NB + nb) * kWave + lane] = acc[mb][nb];
+          for (int nb = 0; nb < NB; ++nb)
+            red[((wave - h - r0) * MB * NB + mb * NB + nb) * kWave + lane] = acc[mb][nb];
+      }
+      __syncthreads();
+      if (wave >= r0 && wave < r0 + 2 && wave < h) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] += red[((wave - r0) * MB * NB + mb * NB + nb) * kWave + lane];
+      }
+    }
   }
-  __syncthreads();
-  if (wave < 2) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] += red[(wave * MB * NB + mb * NB + nb) * kWave + lane];
-  }
-  __syncthreads();
-  if (wave == 1) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) red[(mb * NB + nb) * kWave + lane] = acc[mb][nb];
-  }
-  __syncthreads();
   if (wave == 0) {
     float* P = a.part + (int64_t)blockIdx.x * a.Jpad * a.Rp;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const f4 tot = acc[mb][nb] + red[(mb * NB + nb) * kWave + lane];
+        const f4 tot = acc[mb][nb];
         const int col = 16 * (a.cb0 + nb) + m;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -336,14 +353,15 @@ MttkrpGeom mttkrp_geom_bf16(const Plan& p, int mode) {
   const int q = caseB ? p.N - 2 : p.N - 1;
   const int64_t J = p.s[mode];
   g.MB = caseB ? BfTile<true>::MB : BfTile<false>::MB;
+  const int waves = caseB ? BfTile<true>::W : BfTile<false>::W;
   g.rows_per_tile = 16 * g.MB;
   g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
   g.QC = (p.s[q] + 31) / 32;
   g.O = p.total / J / p.s[q];
   g.nitems = g.O * g.QC;
-  const int64_t wgs = kNumCU;   // one resident round: one workgroup (a wavefront per SIMD) per CU
+  const int64_t wgs = kNumCU;   // one resident round: one workgroup per CU
   int64_t sw = wgs / g.RT;
-  const int64_t max_sw = (g.nitems + 7) / 8;
+  const int64_t max_sw = (g.nitems + 2 * waves - 1) / (2 * waves);
   if (sw > max_sw) sw = max_sw;
   if (sw > kRedSlots) sw = kRedSlots;
   if (sw < 1) sw = 1;
@@ -363,9 +381,11 @@ static void bf_launch_nb(int NB, dim3 grid, size_t lds, hipStream_t st, const Bf
 #define CPGN_NB(k)                                                                            \
   case k:                                                                                     \
     if (a.flds)                                                                               \
-      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, true>), grid, dim3(256), lds, st, a); \
+      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, true>), grid,                  \
+                         dim3(BfTile<CASE_B>::W * 64), lds, st, a);                             \
     else                                                                                      \
-      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, false>), grid, dim3(256), lds, st, a); \
+      hipLaunchKernelGGL((k_mttkrp_bf16<CASE_B, k, X3, VEC, false>), grid,                 \
+                         dim3(BfTile<CASE_B>::W * 64), lds, st, a);                             \
     break;
     CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4)
 #undef CPGN_NB
@@ -419,7 +439,7 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
   a.nbo = caseB ? 1 : a.Rr / a.s_in;
   a.Rp = p.Rp;
   a.NBt = p.NBt;
-  a.nsplit = (int)(4 * G.SW);
+  a.nsplit = (int)((caseB ? BfTile<true>::W : BfTile<false>::W) * G.SW);
   for (int cb0 = 0; cb0 < p.NBt; cb0 += kBfNB) {
     const int NB = p.NBt - cb0 < kBfNB ? p.NBt - cb0 : kBfNB;
     a.cb0 = cb0;

@@ -48,8 +48,9 @@ def f32(arrs):
 
 def items_per_wavefront(dims, mode):
     """Largest number of (outer index, 32-wide inner chunk) items one wavefront accumulates:
-    row tiles of 80 rows (64 for the last mode), one resident workgroup of four wavefronts per
-    compute unit (256) split over the tiles, at least two items per wavefront."""
+    row tiles of 80 rows (64 for the last mode), one resident workgroup per compute unit (256)
+    split over the tiles, four wavefronts per workgroup (eight for the last mode), at least two
+    items per wavefront."""
     N = len(dims)
     caseB = mode == N - 1
     q = N - 2 if caseB else N - 1
@@ -57,8 +58,9 @@ def items_per_wavefront(dims, mode):
     outer = int(np.prod(dims)) // J // dims[q]
     nitems = outer * ((dims[q] + 31) // 32)
     rt = -(-J // (64 if caseB else 80))
-    sw = max(1, min(256 // rt, -(-nitems // 8), 1024))
-    return -(-nitems // (4 * sw))
+    w = 8 if caseB else 4
+    sw = max(1, min(256 // rt, -(-nitems // (2 * w)), 1024))
+    return -(-nitems // (w * sw))
 
 
 def gamma(dims, mode, split):
