@@ -197,9 +197,8 @@ def kernel_source_hash():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported in this build "
-              "(the decomposition runs on a single MI355X; see the design notes for sharding).",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported. The decomposition "
+              "runs on a single MI355X; no multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
 
