@@ -85,7 +85,8 @@ enum {
   CP_OP_GN_JTJ_MATVEC = 2,
   CP_OP_GN_STEP = 3,
   CP_OP_ALS_SWEEP = 4,
-  CP_OP_RESIDUAL = 5
+  CP_OP_RESIDUAL = 5,
+  CP_OP_MTTKRP_ALL = 6
 };
 
 /* Residual methods for cp_residual. */
@@ -134,6 +135,16 @@ int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes);
  */
 int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int mode, void* M,
               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * All-mode MTTKRP: M^(n) = X_(n) P^(n) (Section 2.2, eq. (1)) for every mode n at one point, the
+ * contractions that form the gradient of Algorithm 1. For an order-3 tensor, modes 0 and 1 come
+ * from one pass over X (a dimension tree, Section 2.2: the partial contraction with A^(2) is
+ * shared) and mode 2 from a second pass; other orders take one pass per mode.
+ *   M: N device pointers, M[n] is dims[n] x rank, f_dtype, written.
+ */
+int cp_mttkrp_all(const cp_problem* prob, const void* X, const void* const* A, void* const* M,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Gradient of f (eq. (3)) for every mode at one point, Algorithm 1:

@@ -11,11 +11,11 @@ MAX_ORDER = 8
 CP_F64, CP_F32, CP_BF16, CP_BF16X3 = 0, 1, 2, 3
 CP_OK, CP_EINVAL, CP_EUNSUPPORTED, CP_EWORKSPACE, CP_EHIP = 0, -1, -2, -3, -4
 CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
-OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL = range(6)
+OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL, OP_MTTKRP_ALL = range(7)
 GN_DIAG_DAMPING = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
-EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
+EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
            "cp_als_sweep", "cp_residual", "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -57,6 +57,8 @@ def load(path: str = LIB_PATH):
     lib.cp_workspace_bytes.argtypes = [P(CpProblem), i32, P(sz)]
     lib.cp_mttkrp.restype = i32
     lib.cp_mttkrp.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
+    lib.cp_mttkrp_all.restype = i32
+    lib.cp_mttkrp_all.argtypes = [P(CpProblem), vp, PTRS, PTRS, vp, sz, vp]
     lib.cp_gn_gradient.restype = i32
     lib.cp_gn_gradient.argtypes = [P(CpProblem), vp, PTRS, PTRS, vp, vp, sz, vp]
     lib.cp_gn_jtj_matvec.restype = i32

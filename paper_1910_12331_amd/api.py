@@ -178,6 +178,23 @@ def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=N
     return out
 
 
+def mttkrp_all(X, A: Sequence[torch.Tensor], out=None, ws=None):
+    """M(n) for every mode at one point (order 3: modes 0 and 1 from one pass over X through a
+    dimension tree). Returns the list of dims[n] x R tensors."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    fd = factor_dtype(X)
+    _factors(A, X.shape, fd, R)
+    prob = _problem(X, R)
+    if out is None:
+        out = [torch.empty((s, R), dtype=fd, device=X.device) for s in X.shape]
+    _factors(out, X.shape, fd, R, "out")
+    w, nb = _ws(prob, L.OP_MTTKRP_ALL, X.device, ws)
+    _check(L.load().cp_mttkrp_all(C.byref(prob), X.data_ptr(), _ptrs(A), _ptrs(out), w, nb,
+                                  _stream()), "cp_mttkrp_all")
+    return out
+
+
 def gn_gradient(X: torch.Tensor, A: Sequence[torch.Tensor], ws=None):
     """G(n) = A(n) Gamma(n,n) - M(n) for every mode (Algorithm 1). Returns (G list, sum ||G||)."""
     _dev(X, "X")

@@ -278,7 +278,7 @@ const char* cp_status_string(int s) {
 
 int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes) {
   if (!bytes) return CP_EINVAL;
-  if (op < CP_OP_MTTKRP || op > CP_OP_RESIDUAL) return CP_EINVAL;
+  if (op < CP_OP_MTTKRP || op > CP_OP_MTTKRP_ALL) return CP_EINVAL;
   Plan p;
   const int rc = make_plan(prob, &p);
   if (rc) return rc;
@@ -296,6 +296,27 @@ int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int m
   hipStream_t st = (hipStream_t)stream;
   launch_prepare_factors_src(p, A, p.dtype, ws, st, false, 1u << mode);
   launch_mttkrp(p, X, mode, ws, nullptr, M, st);
+  return hip_status();
+}
+
+int cp_mttkrp_all(const cp_problem* prob, const void* X, const void* const* A, void* const* M,
+                  void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ptrs(p, (const void* const*)M)) ||
+      (rc = check_ws(p, ws, ws_bytes)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, false);
+  if (p.N == 3) {
+    // dimension tree: one pass over X gives M(0) and M(1), a second one M(2)
+    launch_mttkrp_pair01(p, X, ws, nullptr, nullptr, st, M[0], M[1]);
+    launch_mttkrp(p, X, 2, ws, nullptr, M[2], st);
+  } else {
+    for (int n = 0; n < p.N; ++n) launch_mttkrp(p, X, n, ws, nullptr, M[n], st);
+  }
   return hip_status();
 }
 

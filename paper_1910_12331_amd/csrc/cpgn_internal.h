@@ -136,6 +136,6 @@ __host__ __device__ __forceinline__ float bf16_to_float(uint32_t h) {
   return __builtin_bit_cast(float, h << 16);
 }
 int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
-                         hipStream_t st);
+                         hipStream_t st, void* mout_0 = nullptr, void* mout_1 = nullptr);
 
 }  // namespace cpgn

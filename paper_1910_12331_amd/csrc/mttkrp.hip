@@ -353,14 +353,15 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
 }
 
 // Plain form: one accumulator set, two wavefronts per SIMD. Dimension-tree form: two
-// accumulator sets, one wavefront per SIMD.
+// accumulator sets of 32-row tiles, two wavefronts per SIMD in FP32 (one in FP64, whose
+// accumulators take twice the registers).
 template <typename T, bool CASE_B, int MB, int NB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
   mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a);
 }
 
 template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256, 1) void k_mttkrp_tree(MttkrpArgs a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_mttkrp_tree(MttkrpArgs a) {
   mttkrp_body<T, false, MB, NB, true, true>(a);
 }
 
@@ -526,16 +527,16 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   const bool caseB = mode == p.N - 1;
   const int q = caseB ? p.N - 2 : p.N - 1;
   const int64_t J = p.s[mode];
-  g.MB = p.dtype == CP_F64 ? 2 : 4;
+  g.MB = (p.dtype == CP_F64 || dt) ? 2 : 4;
   (void)vec_ok;
   g.rows_per_tile = 16 * g.MB;
   g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
   g.QC = (p.s[q] + 15) / 16;
   g.O = p.total / J / p.s[q];
   g.nitems = g.O * g.QC;
-  // One resident round of 4-wave workgroups: two per CU for the plain form (<= 256 registers
-  // per lane), one per CU for the dimension-tree form (two accumulator sets).
-  const int64_t wgs = (int64_t)kNumCU * (dt ? 1 : 2);
+  // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane), except
+  // one per CU for the FP64 dimension-tree form (two FP64 accumulator sets).
+  const int64_t wgs = (int64_t)kNumCU * ((dt && p.dtype == CP_F64) ? 1 : 2);
   int64_t sw = wgs / g.RT;
   const int64_t max_sw = (g.nitems + 7) / 8;
   if (sw > max_sw) sw = max_sw;
@@ -575,7 +576,7 @@ template <typename T>
 static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipStream_t st,
                            const MttkrpArgs& a) {
   if (a.dt) {   // order-3 dimension tree: mode 0 with vector loads only
-    launch_tree_nb<T, sizeof(T) == 8 ? 2 : 4>(NB, grid, st, a);
+    launch_tree_nb<T, 2>(NB, grid, st, a);
     return;
   }
   if constexpr (sizeof(T) == 8) {
@@ -629,7 +630,8 @@ static bool vec_ok(const Plan& p, int mode, const void* X) {
 
 template <typename T>
 static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, double* m64,
-                           void* mout, bool dt, double* m64_outer, hipStream_t st) {
+                           void* mout, bool dt, double* m64_outer, void* mout_outer,
+                           hipStream_t st) {
   const bool vec = vec_ok(p, mode, X);
   const MttkrpGeom G = mttkrp_geom(p, mode, vec, dt);
   const bool caseB = mode == p.N - 1;
@@ -676,7 +678,7 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   if (dt)
     hipLaunchKernelGGL(k_dt_reduce<T>, dim3(grid_for(G.O * p.R)), dim3(256), 0, st,
                        (const T*)a.p1, G.RT, G.O, G.HS, p.Rp, p.R, G.QC, G.nitems,
-                       (int64_t)a.nsplit, m64_outer, nullptr, p.dtype);
+                       (int64_t)a.nsplit, m64_outer, mout_outer, p.dtype);
   return (int)hipGetLastError();
 }
 
@@ -693,20 +695,21 @@ int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64,
                   hipStream_t st) {
   if (p.xk != 0) return launch_mttkrp_bf16(p, X, mode, ws, m64, mout, st);
   if (p.dtype == CP_F32)
-    return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
-  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, st);
+    return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st);
+  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st);
 }
 
-// Order 3, one pass over X: M(0) and, through the dimension tree, M(1) (FP64 outputs).
+// Order 3, one pass over X: M(0) and, through the dimension tree, M(1). Each mode's result goes
+// to its FP64 buffer and/or its caller-precision buffer (either may be null).
 int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
-                         hipStream_t st) {
+                         hipStream_t st, void* mout_0, void* mout_1) {
   if (p.N != 3 || p.xk != 0 || !vec_ok(p, 0, X)) {
-    const int rc = launch_mttkrp(p, X, 0, ws, m64_0, nullptr, st);
-    return rc ? rc : launch_mttkrp(p, X, 1, ws, m64_1, nullptr, st);
+    const int rc = launch_mttkrp(p, X, 0, ws, m64_0, mout_0, st);
+    return rc ? rc : launch_mttkrp(p, X, 1, ws, m64_1, mout_1, st);
   }
   if (p.dtype == CP_F32)
-    return launch_mttkrp_t<float>(p, X, 0, (char*)ws, m64_0, nullptr, true, m64_1, st);
-  return launch_mttkrp_t<double>(p, X, 0, (char*)ws, m64_0, nullptr, true, m64_1, st);
+    return launch_mttkrp_t<float>(p, X, 0, (char*)ws, m64_0, mout_0, true, m64_1, mout_1, st);
+  return launch_mttkrp_t<double>(p, X, 0, (char*)ws, m64_0, mout_0, true, m64_1, mout_1, st);
 }
 
 // Source factors may be the caller's buffers (compute precision) or FP64 copies.

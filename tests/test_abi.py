@@ -78,7 +78,7 @@ def ws_bytes(lib, p, op=L.OP_GN_STEP):
 def test_workspace_queries(lib):
     rc, n = ws_bytes(lib, prob())
     assert rc == 0 and n > 0 and n % 256 == 0
-    for op in range(6):
+    for op in range(7):
         assert ws_bytes(lib, prob(), op)[0] == 0
     assert ws_bytes(lib, prob(), 17)[0] == L.CP_EINVAL
     big = ws_bytes(lib, prob((400, 400, 400), 100, L.CP_F32))[1]
@@ -92,6 +92,10 @@ def test_workspace_queries(lib):
     (lambda p: p.dims.__setitem__(1, 0), L.CP_EINVAL),
     (lambda p: setattr(p, "f_dtype", L.CP_F32), L.CP_EUNSUPPORTED),
     (lambda p: (setattr(p, "x_dtype", 2), setattr(p, "f_dtype", 2)), L.CP_EUNSUPPORTED),
+    (lambda p: (setattr(p, "x_dtype", L.CP_BF16X3), setattr(p, "f_dtype", L.CP_F64)), L.CP_EUNSUPPORTED),
+    (lambda p: (setattr(p, "x_dtype", 4), setattr(p, "f_dtype", L.CP_F32)), L.CP_EUNSUPPORTED),
+    (lambda p: (setattr(p, "x_dtype", L.CP_BF16), setattr(p, "f_dtype", L.CP_F32)), L.CP_OK),
+    (lambda p: (setattr(p, "x_dtype", L.CP_BF16X3), setattr(p, "f_dtype", L.CP_F32)), L.CP_OK),
 ])
 def test_problem_validation(lib, mut, code):
     p = prob()
@@ -121,6 +125,17 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, ws, need - 1, None) == L.CP_EWORKSPACE
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, C.c_void_p(0x40010), need, None) == L.CP_EINVAL
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, None, need, None) == L.CP_EINVAL
+    # all-mode MTTKRP: null output pointer, null tensor, small workspace
+    Ms = fake_ptrs()
+    Ms[2] = 0
+    assert lib.cp_mttkrp_all(C.byref(p), X, A, Ms, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp_all(C.byref(p), None, A, fake_ptrs(), ws, need, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp_all(C.byref(p), X, A, fake_ptrs(), ws, need - 1, None) == L.CP_EWORKSPACE
+    # storage conversion: negative count, null pointers
+    assert lib.cp_tensor_to_bf16(X, -1, 0, M, None) == L.CP_EINVAL
+    assert lib.cp_tensor_to_bf16(None, 10, 0, M, None) == L.CP_EINVAL
+    assert lib.cp_tensor_to_bf16(X, 10, 1, None, None) == L.CP_EINVAL
+    assert lib.cp_tensor_to_bf16(None, 0, 0, None, None) == L.CP_OK
     # Gauss-Newton parameters
     st = C.c_void_p(0x50000)
     for prm in [L.CpGnParams(-1.0, 1e-3, 20, 0), L.CpGnParams(1e-3, -1.0, 20, 0),

@@ -113,6 +113,20 @@ def test_mttkrp_within_bound(dims, rank, split):
 
 
 @pytest.mark.parametrize("split", [False, True], ids=["bf16", "bf16x3"])
+def test_mttkrp_all_within_bound(split):
+    dims, rank = (28, 22, 24, 16), 20
+    p = make_problem(dims, rank, workload=4, problem=21, kind="lognorm", noise=1e-3)
+    planes, xv = stored(p, split)
+    A = f32(p.init)
+    absA = [np.abs(a) for a in A]
+    Ms = P.mttkrp_all(dev_x(planes, split), dev_f(A))
+    for n, M in enumerate(Ms):
+        ref = O.mttkrp(xv, A, n)
+        bound = gamma(dims, n, split) * O.mttkrp(np.abs(xv), absA, n) + 1e-30
+        assert np.all(np.abs(M.double().cpu().numpy() - ref) <= bound), n
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["bf16", "bf16x3"])
 def test_mttkrp_full_size_sampled_rows(split):
     """80^4, R = 64, log-uniform column norms, noise 1e-3 (the benchmark's launch shape): rows
     of every mode's MTTKRP against the oracle on the one-row slices."""
@@ -205,3 +219,40 @@ def test_gn_step_matches_oracle_on_stored_tensor(split):
     for a, r, a0 in zip(Ad, ref, A):
         upd = a.double().cpu().numpy() - a0
         assert np.linalg.norm(upd - (r - a0)) <= tol * np.linalg.norm(r - a0) + 1e-6 * np.linalg.norm(a0)
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["bf16", "bf16x3"])
+def test_als_sweep_matches_oracle_on_stored_tensor(split):
+    """One ALS sweep (Section 2.2) on the bfloat16 tensor against the oracle's sweep on the values
+    it stores. Mode n's update M(n) (Gamma(n) + lam I)^-1 inherits the MTTKRP error: relative
+    error <= kappa_n gamma ||Mabs(n)|| / ||M(n)|| (kappa_n the condition number of
+    Gamma(n) + lam I); the three modes of a sweep feed each other, so the test allows the sum
+    over modes of those terms, times 2."""
+    dims, rank, lam = (36, 30, 40), 4, 1e-3
+    p = make_problem(dims, rank, workload=4, problem=11, noise=1e-2)
+    planes, xv = stored(p, split)
+    A = f32(p.init)
+    Ad = dev_f(A)
+    st = P.als_sweep(dev_x(planes, split), Ad, lam)
+    assert int(st.item()) == 0
+    ref = O.als_sweep(xv, A, lam)
+    # the bound's ingredients, along the oracle's own sweep
+    cur = [a.copy() for a in A]
+    budget = 0.0
+    for n in range(3):
+        S = [c.T @ c for c in cur]
+        G = np.ones((rank, rank))
+        for m in range(3):
+            if m != n:
+                G = G * S[m]
+        kappa = np.linalg.cond(G + lam * np.eye(rank))
+        M = O.mttkrp(xv, cur, n)
+        Mabs = O.mttkrp(np.abs(xv), [np.abs(c) for c in cur], n)
+        budget += kappa * gamma(dims, n, split) * np.linalg.norm(Mabs) / np.linalg.norm(M)
+        cur[n] = ref[n]
+    for a, r in zip(Ad, ref):
+        assert rel(a.double().cpu().numpy(), r) <= 2 * budget
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
