@@ -171,6 +171,26 @@ def order4_leg(P, torch, reps, stream):
         tstep = event_time(lambda: P.gn_step(X, At, 1e-4, 0.0, 20, stats=sb, ws=ws2), 5, stream)
         out[name] = dict(mttkrp=modes, gn_step_20cg_ms=tstep * 1e3, residual_first_steps=traj)
         del Ag, gn, At
+    # time to relative residual 2e-3 (twice the noise level) from the same start: FP64 storage
+    # alone, and the precision ladder bfloat16 -> split bfloat16 -> FP64
+    target = 2e-3
+    Af = [a.clone() for a in A64]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, h64 = P.gn_to_target(X64, Af, target, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), max_steps=40)
+    t64 = time.perf_counter() - t0
+    Al = [a.clone() for a in A32]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Alad, hl = P.gn_ladder_to_target([forms["bf16"], forms["bf16x3"], X64], Al, target,
+                                     P.GNConfig(cg_tol=1e-3, cg_maxiter=20), max_steps=40)
+    tl = time.perf_counter() - t0
+    rl = P.residual(X64, [a.double() for a in Alad], ws=ws).cpu()
+    ladder = dict(target=target, fp64_seconds=t64, fp64_steps=len(h64), fp64_residual=h64[-1],
+                  ladder_seconds=tl, ladder_steps=[(k, r, ok) for k, r, ok in hl],
+                  ladder_residual=float(rl[0] / rl[1]), speedup=t64 / tl)
+    log(f"[bench] 80^4 time to residual {target}: FP64 {t64 * 1e3:.1f} ms in {len(h64)} steps; ladder "
+        f"{tl * 1e3:.1f} ms, steps " + " ".join(f"{k}{'' if ok else '(rejected)'}" for k, _, ok in hl))
     for name in out:
         out[name]["residual_err_vs_fp64_per_step"] = [
             abs(a - b) / b for a, b in zip(out[name]["residual_first_steps"], out["f64"]["residual_first_steps"])]
@@ -184,6 +204,7 @@ def order4_leg(P, torch, reps, stream):
     return dict(workload="dense 80^4 tensor, rank-64 CP with N(0,1) factors whose columns are "
                          "scaled log-uniformly over [1,100], noise 1e-3; rank-64 GN-CG from the "
                          "planted factors with 10% relative perturbation",
+                time_to_target=ladder,
                 hbm_peak_gbs=PEAK_HBM_GBS, **out)
 
 
@@ -237,8 +258,20 @@ def main():
     X64d = torch.from_numpy(X64).cuda()
     A64m = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
     mt64 = mttkrp_times(P, X64d, A64m, args.mttkrp_reps, stream)
-    del X64d, A64m
     log(f"[bench] MTTKRP FP64 per-mode median ms {[round(v[0] * 1e3, 4) for v in mt64.values()]}")
+
+    # all-mode MTTKRP as a GN step runs it (modes 0 and 1 from one dimension-tree pass)
+    def all_mode_time(Xt, At):
+        out_ = [torch.empty((s, R), dtype=At[0].dtype, device="cuda") for _ in range(3)]
+        ws_ = P.Workspace()
+        for _ in range(3):
+            P.mttkrp_all(Xt, At, out=out_, ws=ws_)
+        return float(np.median(event_samples(lambda: P.mttkrp_all(Xt, At, out=out_, ws=ws_),
+                                             args.mttkrp_reps, stream)))
+    tall32 = all_mode_time(Xd, A)
+    tall64 = all_mode_time(X64d, A64m)
+    del X64d, A64m
+    log(f"[bench] all-mode MTTKRP median ms: FP32 {tall32 * 1e3:.4f}, FP64 {tall64 * 1e3:.4f}")
 
     # launch floor: an event-timed one-element fill kernel
     one = torch.zeros(1, device="cuda")
@@ -414,6 +447,15 @@ def main():
                                      "tflops_median": flops / v[0] / 1e12,
                                      "frac_fp64_peak": flops / v[0] / 1e12 / PEAK_FP64_MFMA_TFLOPS}
                         for n, v in mt64.items()},
+        "mttkrp_all_modes": {
+            "fp32_median_ms": tall32 * 1e3, "fp64_median_ms": tall64 * 1e3,
+            "note": "one cp_mttkrp_all call; tree_tflops counts the dimension tree's 4 s^3 R flops "
+                    "(two bottleneck contractions), per_mode_equivalent_tflops three separate "
+                    "MTTKRPs (6 s^3 R)",
+            "fp32_tree_tflops": 4.0 * s ** 3 * R / tall32 / 1e12,
+            "fp32_per_mode_equivalent_tflops": 6.0 * s ** 3 * R / tall32 / 1e12,
+            "fp64_tree_tflops": 4.0 * s ** 3 * R / tall64 / 1e12,
+            "fp64_per_mode_equivalent_tflops": 6.0 * s ** 3 * R / tall64 / 1e12},
         "gn_step_20cg_ms": t20 * 1e3,
         "gn_steps_per_s_20cg": 1.0 / t20,
         "cg_iteration_ms": (t20 - t0cg) / 20 * 1e3,

@@ -8,8 +8,8 @@ from .api import (CpError, SplitBF16Tensor, Workspace, als_sweep, factor_dtype, 
                   gn_step, jtj_matvec, mttkrp, mttkrp_all, read_stats, residual, stats_buffer, to_bf16)
 from .autograd import CPObjective, cp_objective
 from .optim import (ALS, BatchedGaussNewton, DampingSchedule, GaussNewton, GNConfig,
-                    gn_mixed_to_target, gn_to_target)
+                    gn_ladder_to_target, gn_mixed_to_target, gn_to_target)
 
 __all__ = ["CpError", "SplitBF16Tensor", "factor_dtype", "to_bf16", "Workspace", "als_sweep", "gn_gradient", "gn_step", "jtj_matvec", "mttkrp", "mttkrp_all",
            "read_stats", "residual", "stats_buffer", "ALS", "DampingSchedule", "GaussNewton",
-           "GNConfig", "BatchedGaussNewton", "gn_to_target", "gn_mixed_to_target", "CPObjective", "cp_objective"]
+           "GNConfig", "BatchedGaussNewton", "gn_to_target", "gn_mixed_to_target", "gn_ladder_to_target", "CPObjective", "cp_objective"]

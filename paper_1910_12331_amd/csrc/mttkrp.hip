@@ -353,15 +353,15 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
 }
 
 // Plain form: one accumulator set, two wavefronts per SIMD. Dimension-tree form: two
-// accumulator sets of 32-row tiles, two wavefronts per SIMD in FP32 (one in FP64, whose
-// accumulators take twice the registers).
+// accumulator sets, on 32-row tiles in FP32 and 16-row tiles in FP64 (whose accumulators take
+// twice the registers), also two wavefronts per SIMD.
 template <typename T, bool CASE_B, int MB, int NB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
   mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a);
 }
 
 template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_mttkrp_tree(MttkrpArgs a) {
+__global__ __launch_bounds__(256, 2) void k_mttkrp_tree(MttkrpArgs a) {
   mttkrp_body<T, false, MB, NB, true, true>(a);
 }
 
@@ -527,16 +527,15 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   const bool caseB = mode == p.N - 1;
   const int q = caseB ? p.N - 2 : p.N - 1;
   const int64_t J = p.s[mode];
-  g.MB = (p.dtype == CP_F64 || dt) ? 2 : 4;
+  g.MB = dt ? (p.dtype == CP_F64 ? 1 : 2) : (p.dtype == CP_F64 ? 2 : 4);
   (void)vec_ok;
   g.rows_per_tile = 16 * g.MB;
   g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
   g.QC = (p.s[q] + 15) / 16;
   g.O = p.total / J / p.s[q];
   g.nitems = g.O * g.QC;
-  // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane), except
-  // one per CU for the FP64 dimension-tree form (two FP64 accumulator sets).
-  const int64_t wgs = (int64_t)kNumCU * ((dt && p.dtype == CP_F64) ? 1 : 2);
+  // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane).
+  const int64_t wgs = (int64_t)kNumCU * 2;
   int64_t sw = wgs / g.RT;
   const int64_t max_sw = (g.nitems + 7) / 8;
   if (sw > max_sw) sw = max_sw;
@@ -576,7 +575,7 @@ template <typename T>
 static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipStream_t st,
                            const MttkrpArgs& a) {
   if (a.dt) {   // order-3 dimension tree: mode 0 with vector loads only
-    launch_tree_nb<T, 2>(NB, grid, st, a);
+    launch_tree_nb<T, sizeof(T) == 8 ? 1 : 2>(NB, grid, st, a);
     return;
   }
   if constexpr (sizeof(T) == 8) {

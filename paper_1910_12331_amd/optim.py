@@ -143,6 +143,73 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     return high.A, hist
 
 
+# Relative residual at which each storage form is taken to be at its rounding floor: about the
+# relative accuracy of its MTTKRP (bfloat16 3e-3, split bfloat16 5e-6, FP32 5e-7 measured at
+# 80^4), times a margin; FP64 has none.
+_RUNG_FLOOR = {"bf16": 1e-2, "bf16x3": 3e-5, "torch.float32": 1e-6, "torch.float64": 0.0}
+
+
+def _rung_name(X) -> str:
+    if isinstance(X, api.SplitBF16Tensor):
+        return "bf16x3"
+    if X.dtype == torch.bfloat16:
+        return "bf16"
+    return str(X.dtype)
+
+
+def gn_ladder_to_target(rungs, A, target, config: GNConfig | None = None, max_steps: int = 300):
+    """Gauss-Newton over a ladder of storage precisions of one tensor, lowest first (e.g. a
+    bfloat16 tensor, its split form, FP64). One damping schedule runs through all rungs.
+
+    After each step the direct residual is read on the current rung. A step that raises it is
+    rejected (factors and damping state restored) and the run moves up a rung; so does an accepted
+    step whose residual is below the rung's floor (_RUNG_FLOOR), or above half the previous one
+    while within 100x of that floor. A lower rung ends the run only if its floor is at most a tenth
+    of the target (its residual, measured on its own rounded tensor, then certifies the target).
+    The top rung takes every step until the residual is <= target or max_steps steps were taken.
+    Returns (factors, history of (rung, residual, accepted))."""
+    cfg = config or GNConfig()
+    sched = cfg.schedule or DampingSchedule()
+    A = list(A)
+    hist = []
+    steps = 0
+    prev = float("inf")
+    for i, X in enumerate(rungs):
+        top = i == len(rungs) - 1
+        name = _rung_name(X)
+        floor = _RUNG_FLOOR.get(name, 0.0)
+        A = [a.to(api.factor_dtype(X)) for a in A]
+        opt = GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping))
+        if i > 0:
+            prev = opt.residual()
+        while steps < max_steps:
+            keep = [a.clone() for a in opt.A]
+            state = sched.state_dict()
+            opt.step()
+            steps += 1
+            r = opt.residual()
+            if not top and not (r <= prev):      # rejected (also catches NaN)
+                for a, k in zip(opt.A, keep):
+                    a.copy_(k)
+                sched.load_state_dict(state)
+                hist.append((name, r, False))
+                break
+            hist.append((name, r, True))
+            if r <= target and (top or floor <= 0.1 * target):
+                return opt.A, hist
+            if r <= target:          # this rung cannot certify the target: move up
+                prev = r
+                break
+            if not top and (r <= floor or (r > 0.5 * prev and r < 100.0 * floor)):
+                prev = r
+                break
+            prev = r
+        A = opt.A
+        if steps >= max_steps:
+            break
+    return A, hist
+
+
 class BatchedGaussNewton:
     """Independent Gauss-Newton decompositions advanced together (many random restarts or
     many small tensors). Problem i runs on HIP stream i % n_streams with its own workspace and

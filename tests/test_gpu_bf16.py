@@ -256,3 +256,26 @@ def test_als_sweep_matches_oracle_on_stored_tensor(split):
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def test_precision_ladder_reaches_target():
+    """The ladder bfloat16 -> split bfloat16 -> FP64 from a perturbed planted start reaches a
+    residual target twice the noise level on the FP64 tensor; accepted steps on the lower rungs
+    never raise the residual, and the run ends on a rung able to certify the target."""
+    dims, rank, target = (40, 36, 32, 40), 16, 2e-3
+    p = make_problem(dims, rank, workload=4, problem=31, kind="lognorm", noise=1e-3)
+    rng = np.random.default_rng(4531)
+    A0 = [b * (1.0 + 0.1 * rng.standard_normal(b.shape)) for b in p.planted]
+    X64 = torch.tensor(p.x, device="cuda")
+    X32 = X64.float()
+    rungs = [P.to_bf16(X32), P.to_bf16(X32, split=True), X64]
+    A, hist = P.gn_ladder_to_target(rungs, dev_f(A0), target, max_steps=40)
+    num, den = O.residual(p.x, [a.double().cpu().numpy() for a in A])
+    assert num / den <= target * (1 + 1e-9)
+    assert hist[-1][0] in ("bf16x3", "torch.float64") and hist[-1][2]
+    last = {}
+    for name, r, ok in hist:
+        if ok and name != "torch.float64" and name in last:
+            assert r <= last[name]
+        if ok:
+            last[name] = r
