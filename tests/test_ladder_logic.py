@@ -1,0 +1,85 @@
+"""Host logic of the precision ladder (gn_ladder_to_target), without a GPU: the Gauss-Newton
+optimizer is replaced by a stand-in whose residual sequence per storage form is scripted, so the
+acceptance, rejection, restore and switching rules can be checked exactly."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1910_12331_amd import optim  # noqa: E402
+
+
+class FakeTensor:
+    """Storage form stand-in: a name and the residuals its steps produce, in order."""
+
+    def __init__(self, name, residuals, start):
+        self.name, self.residuals, self.start = name, list(residuals), start
+
+
+@pytest.fixture
+def fake(monkeypatch):
+    log = []
+
+    class FakeGN:
+        def __init__(self, X, A, config):
+            self.X, self.A, self.cfg, self.k = X, list(A), config, 0
+            self.schedule = config.schedule
+            self.r = X.start
+
+        def step(self):
+            self.r = self.X.residuals[self.k]
+            self.k += 1
+            for a in self.A:
+                a.add_(1.0)             # every step moves the factors
+            self.schedule.advance()
+            log.append((self.X.name, self.r))
+
+        def residual(self):
+            return self.r
+
+    monkeypatch.setattr(optim, "GaussNewton", FakeGN)
+    monkeypatch.setattr(optim, "_rung_name", lambda X: X.name)
+    monkeypatch.setattr(optim.api, "factor_dtype", lambda X: torch.float32)
+    return log
+
+
+def test_rejected_step_restores_and_moves_up(fake):
+    low = FakeTensor("bf16", [0.3, 0.1, 0.05, 1e9], start=1.0)
+    top = FakeTensor("torch.float64", [1e-2, 1e-3], start=0.05)
+    A = [torch.zeros(3, 2)]
+    sched = optim.DampingSchedule()
+    out, hist = optim.gn_ladder_to_target([low, top], A, 2e-3, optim.GNConfig(schedule=sched))
+    assert [h[:1] + h[2:] for h in hist] == [("bf16", True)] * 3 + [("bf16", False)] + \
+        [("torch.float64", True)] * 2
+    # three accepted low steps and two top steps moved the factors; the rejected one did not
+    assert torch.equal(out[0], torch.full((3, 2), 5.0))
+    # the damping schedule advanced once per accepted step only
+    ref = optim.DampingSchedule()
+    for _ in range(5):
+        ref.advance()
+    assert sched.value == ref.value and sched.decreasing == ref.decreasing
+
+
+def test_floor_and_stall_switch_up(fake):
+    low = FakeTensor("bf16", [0.5, 0.009, 0.0085], start=1.0)           # 0.009 <= floor 1e-2
+    mid = FakeTensor("bf16x3", [4e-3, 2.5e-3], start=0.009)   # 2.5e-3: no halving, < 100 floor
+    top = FakeTensor("torch.float64", [1e-3, 5e-4], start=2.5e-3)
+    A = [torch.zeros(2, 2)]
+    _, hist = optim.gn_ladder_to_target([low, mid, top], A, 6e-4)
+    names = [h[0] for h in hist]
+    assert names == ["bf16", "bf16", "bf16x3", "bf16x3", "torch.float64", "torch.float64"]
+    assert all(ok for _, _, ok in hist) and hist[-1][1] <= 6e-4
+
+
+def test_low_rung_cannot_certify_a_tighter_target(fake):
+    low = FakeTensor("bf16", [1e-3], start=1.0)        # below target, but floor 1e-2 > target/10
+    top = FakeTensor("torch.float64", [5e-4], start=1e-3)
+    _, hist = optim.gn_ladder_to_target([low, top], [torch.zeros(1, 1)], 2e-3)
+    assert [h[0] for h in hist] == ["bf16", "torch.float64"]
+
+
+def test_nan_step_is_rejected(fake):
+    low = FakeTensor("bf16x3", [float("nan")], start=1.0)
+    top = FakeTensor("torch.float64", [1e-6], start=1.0)
+    out, hist = optim.gn_ladder_to_target([low, top], [torch.zeros(1, 1)], 1e-5)
+    assert hist[0][2] is False and hist[1] == ("torch.float64", 1e-6, True)
+    assert torch.equal(out[0], torch.ones(1, 1))
