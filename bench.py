@@ -365,10 +365,11 @@ def main():
         devs = [(torch.tensor(p_.x, dtype=torch.float32, device="cuda"),
                  [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p_.init]) for p_ in probs]
         res = {}
-        for ns in (1, args.batched_streams):
+        for ns, graphs in ((1, False), (args.batched_streams, False), (args.batched_streams, True)):
             cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
             torch.cuda.synchronize()
-            bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns)
+            bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns,
+                                       graphs=graphs)
             for _ in range(2):
                 bgn.step()
             bgn.synchronize()
@@ -379,14 +380,18 @@ def main():
                 bgn.synchronize()
                 per += [e0.elapsed_time(e1) for e0, e1 in ev]
             el = time.perf_counter() - t0
-            res[ns] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
-                           step_ms_p99=float(np.percentile(per, 99)))
+            key = f"streams_{ns}" + ("_graphs" if graphs else "")
+            res[key] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
+                            step_ms_p99=float(np.percentile(per, 99)))
             del bgn, cur
         batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
-                       streams_1=res[1], **{f"streams_{args.batched_streams}": res[args.batched_streams]})
-        log(f"[bench] batched workload: {res[args.batched_streams]['problem_steps_per_s']:.0f} problem-steps/s on "
-            f"{args.batched_streams} streams ({res[1]['problem_steps_per_s']:.0f} on one); per-problem step "
-            f"p50 {res[args.batched_streams]['step_ms_p50']:.3f} ms, p99 {res[args.batched_streams]['step_ms_p99']:.3f} ms")
+                       note="_graphs: each problem's GN step and damping update replayed from a "
+                            "captured HIP graph", **res)
+        kb, kg = f"streams_{args.batched_streams}", f"streams_{args.batched_streams}_graphs"
+        log(f"[bench] batched workload: {res[kg]['problem_steps_per_s']:.0f} problem-steps/s on "
+            f"{args.batched_streams} streams with graph replay, {res[kb]['problem_steps_per_s']:.0f} "
+            f"without, {res['streams_1']['problem_steps_per_s']:.0f} on one stream; per-problem step "
+            f"p50 {res[kg]['step_ms_p50']:.3f} ms, p99 {res[kg]['step_ms_p99']:.3f} ms (graphs)")
         del devs
 
     # ---- order-4 workload in bfloat16 / split bfloat16 / FP32 / FP64 storage

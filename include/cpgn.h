@@ -177,6 +177,25 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
                cp_gn_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * cp_gn_step with the damping read from device memory when the step runs, for callers that
+ * replay the step from a captured HIP graph (its kernel arguments are then fixed): lambda_dev
+ * points to one device double (>= 0, finite); params->lambda is ignored. A negative or non-finite
+ * value there is reported as CP_EINVAL in stats->status and leaves the factors unchanged.
+ * Everything else is as for cp_gn_step.
+ */
+int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
+                      const cp_gn_params* params, const double* lambda_dev, cp_gn_stats* stats,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The varying damping of Section 3.2 advanced once on the device (one tiny kernel, so a captured
+ * graph can carry the schedule with the step). state_dev: device double[5] =
+ * {lambda, lower, upper, mu, decreasing (1.0 or 0.0)}; while decreasing, lambda /= mu and the
+ * direction turns when lambda <= lower; otherwise lambda *= mu and it turns when lambda >= upper.
+ */
+int cp_damping_advance(double* state_dev, void* stream);
+
+/*
  * One ALS sweep, Section 2.2: for n = 0..N-1 in order, A^(n) = M^(n) (Gamma^(n) + lambda I)^-1
  * with M^(n) computed from the latest factors; the inverse comes from an FP64 Cholesky factor.
  *   A: N device pointers, read and overwritten in place. lambda >= 0 (0 = plain ALS).

@@ -5,11 +5,11 @@ this package is its Python binding.
 """
 from . import _lib
 from .api import (CpError, SplitBF16Tensor, Workspace, als_sweep, factor_dtype, gn_gradient,
-                  gn_step, jtj_matvec, mttkrp, mttkrp_all, read_stats, residual, stats_buffer, to_bf16)
+                  gn_step, gn_step_devlam, damping_advance, jtj_matvec, mttkrp, mttkrp_all, read_stats, residual, stats_buffer, to_bf16)
 from .autograd import CPObjective, cp_objective
 from .optim import (ALS, BatchedGaussNewton, DampingSchedule, GaussNewton, GNConfig,
                     gn_ladder_to_target, gn_mixed_to_target, gn_to_target)
 
-__all__ = ["CpError", "SplitBF16Tensor", "factor_dtype", "to_bf16", "Workspace", "als_sweep", "gn_gradient", "gn_step", "jtj_matvec", "mttkrp", "mttkrp_all",
+__all__ = ["CpError", "SplitBF16Tensor", "factor_dtype", "to_bf16", "Workspace", "als_sweep", "gn_gradient", "gn_step", "gn_step_devlam", "damping_advance", "jtj_matvec", "mttkrp", "mttkrp_all",
            "read_stats", "residual", "stats_buffer", "ALS", "DampingSchedule", "GaussNewton",
            "GNConfig", "BatchedGaussNewton", "gn_to_target", "gn_mixed_to_target", "gn_ladder_to_target", "CPObjective", "cp_objective"]

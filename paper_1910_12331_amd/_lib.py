@@ -16,7 +16,8 @@ GN_DIAG_DAMPING = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_als_sweep", "cp_residual", "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
+           "cp_gn_step_devlam", "cp_damping_advance", "cp_als_sweep", "cp_residual",
+           "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
 class CpProblem(C.Structure):
@@ -65,6 +66,10 @@ def load(path: str = LIB_PATH):
     lib.cp_gn_jtj_matvec.argtypes = [P(CpProblem), PTRS, PTRS, C.c_double, PTRS, vp, sz, vp]
     lib.cp_gn_step.restype = i32
     lib.cp_gn_step.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, sz, vp]
+    lib.cp_gn_step_devlam.restype = i32
+    lib.cp_gn_step_devlam.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, vp, sz, vp]
+    lib.cp_damping_advance.restype = i32
+    lib.cp_damping_advance.argtypes = [vp, vp]
     lib.cp_als_sweep.restype = i32
     lib.cp_als_sweep.argtypes = [P(CpProblem), vp, PTRS, C.c_double, vp, vp, sz, vp]
     lib.cp_residual.restype = i32

@@ -257,6 +257,35 @@ def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: floa
     return stats
 
 
+def gn_step_devlam(X, A: Sequence[torch.Tensor], lam_dev: torch.Tensor, cg_tol: float = 1e-3,
+                   cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity"):
+    """gn_step with the damping read from device memory (lam_dev: a one-element float64 GPU
+    tensor) when the step runs, so that a captured graph of the step follows a changing lambda."""
+    if damping not in ("identity", "diagonal"):
+        raise ValueError("damping must be 'identity' or 'diagonal'")
+    _dev(X, "X")
+    _dev(lam_dev, "lam_dev", torch.float64)
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, factor_dtype(X), R)
+    prob = _problem(X, R)
+    prm = L.CpGnParams(0.0, float(cg_tol), int(cg_maxiter),
+                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+    if stats is None:
+        stats = stats_buffer(X.device)
+    w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
+    _check(L.load().cp_gn_step_devlam(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),
+                                      lam_dev.data_ptr(), stats.data_ptr(), w, nb, _stream()),
+           "cp_gn_step_devlam")
+    return stats
+
+
+def damping_advance(state: torch.Tensor):
+    """Advance a device damping state {lambda, lower, upper, mu, decreasing} (float64[5]) once."""
+    _dev(state, "state", torch.float64, (5,))
+    _check(L.load().cp_damping_advance(state.data_ptr(), _stream()), "cp_damping_advance")
+    return state
+
+
 def als_sweep(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float = 0.0, status=None, ws=None):
     """One ALS sweep in place on A (Section 2.2); returns the device int32 status."""
     _dev(X, "X")

@@ -23,7 +23,8 @@ void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stat
 void launch_status_out(const CgState*, int32_t*, hipStream_t);
 int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
-                   hipStream_t, bool diag_damping = false);
+                   hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr);
+void launch_damping_advance(double*, hipStream_t);
 int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t);
 int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
 void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
@@ -33,7 +34,7 @@ int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipS
 size_t cg_slot_bytes(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
               double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
-              double, int, bool, hipStream_t);
+              double, int, bool, hipStream_t, const double* lam_dev = nullptr);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 
@@ -364,14 +365,17 @@ int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* c
   return hip_status();
 }
 
-int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_gn_params* prm,
-               cp_gn_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+// One Gauss-Newton step; the damping is prm->lambda, or *lam_dev read on the device.
+static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
+                        const cp_gn_params* prm, const double* lam_dev, cp_gn_stats* stats,
+                        void* ws, size_t ws_bytes, void* stream) {
   Plan p;
   int rc = make_plan(prob, &p);
   if (rc) return rc;
   if (!X || !prm || !stats) return CP_EINVAL;
-  if (!(prm->lambda >= 0.0) || !isfinite(prm->lambda) || !(prm->cg_tol >= 0.0) ||
-      !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 || (prm->flags & ~CP_GN_DIAG_DAMPING) != 0)
+  if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
+  if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
+      (prm->flags & ~CP_GN_DIAG_DAMPING) != 0)
     return CP_EINVAL;
   if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
@@ -380,22 +384,41 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
   const Ws w = carve(p, ws);
   const int64_t RR = (int64_t)p.R * p.R;
   const int nb = rowmm_blocks(d);
+  const double lam = lam_dev ? 0.0 : prm->lambda;
 
   launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
   PerMode<void*> none{};
   gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
   // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
   const bool diag = (prm->flags & CP_GN_DIAG_DAMPING) != 0;
-  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, prm->lambda, w.pinv, RR, 0, p.N, w.st, st,
-                 diag);
+  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
+                 lam_dev);
   // CG: three launches per iteration, scalars kept on the device.
   launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
-            (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, prm->lambda,
-            prm->cg_maxiter, diag, st);
+            (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, lam,
+            prm->cg_maxiter, diag, st, lam_dev);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
   launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
   launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
+  return hip_status();
+}
+
+int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_gn_params* prm,
+               cp_gn_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  return gn_step_impl(prob, X, A, prm, nullptr, stats, ws, ws_bytes, stream);
+}
+
+int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
+                      const cp_gn_params* prm, const double* lambda_dev, cp_gn_stats* stats,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (!lambda_dev) return CP_EINVAL;
+  return gn_step_impl(prob, X, A, prm, lambda_dev, stats, ws, ws_bytes, stream);
+}
+
+int cp_damping_advance(double* state_dev, void* stream) {
+  if (!state_dev) return CP_EINVAL;
+  launch_damping_advance(state_dev, (hipStream_t)stream);
   return hip_status();
 }
 

@@ -228,10 +228,12 @@ __global__ void k_status_out(const CgState* st, int32_t* out) {
 // registers; each step publishes the pivot row r and column c through double-buffered LDS (one
 // barrier), applies a_ik -= (c_i / p) r_k to every entry, and sets the pivot row to r / p, the
 // pivot column to -c / p and the pivot to 1 / p (the Gauss-Jordan update).
-// A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done.
+// A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done. With lam_dev
+// the damping is read from device memory (a negative or non-finite value records CP_EINVAL).
 template <int NBK>
 __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restrict__ Gin,
                                                  int64_t g_stride, double lambda,
+                                                 const double* __restrict__ lam_dev,
                                                  double* __restrict__ Pout, int64_t p_stride,
                                                  int first_mode, CgState* st, int diag_damping) {
   constexpr int RP = 32 * NBK;
@@ -241,7 +243,15 @@ __global__ __launch_bounds__(1024) void k_spd_inv(int R, const double* __restric
   const double* G = Gin + n * g_stride;
   double* P = Pout + n * p_stride;
   const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
-  if (t == 0) sbad = st->status != CP_OK;   // one read: another workgroup may set it meanwhile
+  if (lam_dev) lambda = *lam_dev;
+  if (t == 0) {
+    sbad = st->status != CP_OK;   // one read: another workgroup may set it meanwhile
+    if (!sbad && (!(lambda >= 0.0) || !isfinite(lambda))) {
+      st->status = CP_EINVAL;
+      st->done = 1;
+      sbad = 1;
+    }
+  }
   __syncthreads();
   if (sbad) return;
   double a[NBK][NBK];
@@ -777,6 +787,28 @@ void launch_gn_stats(const Dims& d, int nblocks, const double* red_nrm, const Cg
   hipLaunchKernelGGL(k_gn_stats, dim3(1), dim3(256), 0, s, d.N, nblocks, red_nrm, st, out);
 }
 
+// Damping schedule of Section 3.2 on the device: state = {value, lower, upper, mu, decreasing}.
+// One thread; the same IEEE operations as the host schedule, so both give the same sequence.
+__global__ void k_damping_advance(double* state) {
+  if (threadIdx.x != 0) return;
+  double v = state[0];
+  const double lower = state[1], upper = state[2], mu = state[3];
+  bool dec = state[4] != 0.0;
+  if (dec) {
+    v = v / mu;
+    if (v <= lower) dec = false;
+  } else {
+    v = v * mu;
+    if (v >= upper) dec = true;
+  }
+  state[0] = v;
+  state[4] = dec ? 1.0 : 0.0;
+}
+
+void launch_damping_advance(double* state, hipStream_t s) {
+  hipLaunchKernelGGL(k_damping_advance, dim3(1), dim3(64), 0, s, state);
+}
+
 void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, st, out);
 }
@@ -786,13 +818,13 @@ int spd_inv_supported(int R) { return R >= 1 && R <= 128; }
 
 int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
                    int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
-                   bool diag_damping) {
+                   bool diag_damping, const double* lam_dev) {
   const int nbk = (R + 31) / 32;
   switch (nbk) {
 #define CPGN_SPD(k)                                                                          \
   case k:                                                                                    \
     hipLaunchKernelGGL((k_spd_inv<k>), dim3(count), dim3(1024), 0, s, R, G, g_stride, lambda, \
-                       P, p_stride, first_mode, st, diag_damping ? 1 : 0);                   \
+                       lam_dev, P, p_stride, first_mode, st, diag_damping ? 1 : 0);          \
     break;
     CPGN_SPD(1) CPGN_SPD(2) CPGN_SPD(3) CPGN_SPD(4)
 #undef CPGN_SPD

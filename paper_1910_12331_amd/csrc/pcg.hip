@@ -50,6 +50,7 @@ struct CgArgs {
   double* slot_nrm;
   CgState* st;
   double lambda;
+  const double* lam_dev;  // when set, the damping is read from here (device memory)
   int diag_damping;       // damping lambda diag(Gamma(n,n)) instead of lambda I
   int TB;                 // 16-column tiles of R
   int nslot;              // row blocks x TB
@@ -415,8 +416,8 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
     wd[v] = colok && row < s ? W[(rbase + row) * R + c0 + m] : 0.0;
   }
   // damping of this lane's column: lambda, or lambda Gamma(n,n)[c][c] (diagonal of J^T J)
-  const double lam_c = a.diag_damping && colok ? a.lambda * Gnn[(int64_t)(c0 + m) * (R + 1)]
-                                               : a.lambda;
+  const double lam = a.lam_dev ? *a.lam_dev : a.lambda;
+  const double lam_c = a.diag_damping && colok ? lam * Gnn[(int64_t)(c0 + m) * (R + 1)] : lam;
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     const int e = t + 256 * i, c = e / KP, k = e - c * KP;
@@ -489,7 +490,7 @@ static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
 int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
               const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
               double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
-              int maxiter, bool diag_damping, hipStream_t s) {
+              int maxiter, bool diag_damping, hipStream_t s, const double* lam_dev) {
   CgArgs a{};
   a.d = d;
   a.A64 = A64;
@@ -505,6 +506,7 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
   a.B = B;
   a.st = st;
   a.lambda = lambda;
+  a.lam_dev = lam_dev;
   a.diag_damping = diag_damping ? 1 : 0;
   a.TB = cg_tiles(p);
   a.rb_off[0] = 0;

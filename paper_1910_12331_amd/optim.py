@@ -36,6 +36,16 @@ class DampingSchedule:
         return dict(value=self.value, lower=self.lower, upper=self.upper, mu=self.mu,
                     decreasing=self.decreasing)
 
+    def to_device(self, device) -> torch.Tensor:
+        """The state as the float64[5] device array that cp_damping_advance advances."""
+        return torch.tensor([self.value, self.lower, self.upper, self.mu,
+                             1.0 if self.decreasing else 0.0], dtype=torch.float64, device=device)
+
+    def load_device(self, state: torch.Tensor):
+        v = state.cpu().tolist()
+        self.value, self.lower, self.upper, self.mu = v[0], v[1], v[2], v[3]
+        self.decreasing = v[4] != 0.0
+
     def load_state_dict(self, d):
         self.value, self.lower, self.upper, self.mu = d["value"], d["lower"], d["upper"], d["mu"]
         self.decreasing = d["decreasing"]
@@ -215,10 +225,16 @@ class BatchedGaussNewton:
     many small tensors). Problem i runs on HIP stream i % n_streams with its own workspace and
     damping schedule, so small problems overlap on the GPU; each problem's iterates are the ones
     a single-stream run produces (the kernels are deterministic). All streams have the default
-    priority."""
+    priority.
 
-    def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8):
+    With graphs=True one Gauss-Newton step of each problem, together with its damping update
+    (read and advanced on the device), is captured once as a HIP graph and replayed per step: the
+    host then issues one graph launch per problem instead of every kernel launch of the step."""
+
+    def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8,
+                 graphs: bool = False):
         cfg = config or GNConfig()
+        self.cfg = cfg
         torch.cuda.current_stream().synchronize()   # inputs were written on the current stream
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
         self.opts = []
@@ -226,6 +242,27 @@ class BatchedGaussNewton:
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
                 self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter,
                                                              damping=cfg.damping)))
+        self.graphs = None
+        if graphs:
+            self._capture()
+
+    def _capture(self):
+        self.lam_state, self.graphs = [], []
+        for i, opt in enumerate(self.opts):
+            s = self.streams[i % len(self.streams)]
+            state = opt.schedule.to_device(opt.X.device)
+            # allocate the workspace before capture (nothing may be allocated inside it)
+            prob = api._problem(opt.X, int(opt.A[0].shape[1]))
+            api._ws(prob, api.L.OP_GN_STEP, opt.X.device, opt.ws)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                api.gn_step_devlam(opt.X, opt.A, state[0:1], self.cfg.cg_tol, self.cfg.cg_maxiter,
+                                   stats=opt.stats_buf, ws=opt.ws, damping=self.cfg.damping)
+                api.damping_advance(state)
+            self.lam_state.append(state)
+            self.graphs.append(g)
+        torch.cuda.synchronize()
 
     def step(self, timed: bool = False):
         """One Gauss-Newton step of every problem. With timed=True returns one (start, end) pair
@@ -237,7 +274,11 @@ class BatchedGaussNewton:
                 if timed:
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(s)
-                opt.step()
+                if self.graphs is not None:
+                    self.graphs[i].replay()
+                    opt.steps += 1
+                else:
+                    opt.step()
                 if timed:
                     e1.record(s)
                     events.append((e0, e1))
@@ -246,6 +287,9 @@ class BatchedGaussNewton:
     def synchronize(self):
         for s in self.streams:
             s.synchronize()
+        if self.graphs is not None:   # keep the host schedules in step with the device ones
+            for opt, state in zip(self.opts, self.lam_state):
+                opt.schedule.load_device(state)
 
     def residuals(self):
         out = []

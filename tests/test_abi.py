@@ -131,6 +131,11 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_mttkrp_all(C.byref(p), X, A, Ms, ws, need, None) == L.CP_EINVAL
     assert lib.cp_mttkrp_all(C.byref(p), None, A, fake_ptrs(), ws, need, None) == L.CP_EINVAL
     assert lib.cp_mttkrp_all(C.byref(p), X, A, fake_ptrs(), ws, need - 1, None) == L.CP_EWORKSPACE
+    # device damping: null pointers
+    good0 = L.CpGnParams(0.0, 1e-3, 20, 0)
+    assert lib.cp_gn_step_devlam(C.byref(p), X, A, C.byref(good0), None, C.c_void_p(0x50000), ws,
+                                 need, None) == L.CP_EINVAL
+    assert lib.cp_damping_advance(None, None) == L.CP_EINVAL
     # storage conversion: negative count, null pointers
     assert lib.cp_tensor_to_bf16(X, -1, 0, M, None) == L.CP_EINVAL
     assert lib.cp_tensor_to_bf16(None, 10, 0, M, None) == L.CP_EINVAL

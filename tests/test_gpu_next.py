@@ -135,3 +135,59 @@ def test_batched_streams_match_single_stream_runs():
     for opt, A2 in zip(b.opts, seq):
         for a, a2 in zip(opt.A, A2):
             assert torch.equal(a, a2)
+
+
+# ------------------------------------------------------------------ graph-replayable steps
+def test_device_damping_schedule_matches_host():
+    """cp_damping_advance gives bitwise the host schedule's sequence (both directions)."""
+    sched = P.DampingSchedule(1e-4, 1e-10, 1e-4, 2.0)
+    state = sched.to_device("cuda")
+    for _ in range(90):
+        P.damping_advance(state)
+        sched.advance()
+        v = state.cpu().tolist()
+        assert v[0] == sched.value and (v[4] != 0.0) == sched.decreasing
+
+
+def test_gn_step_devlam_matches_gn_step():
+    p = make_problem((30, 26, 22), 6, workload=0, problem=6, noise=1e-2)
+    X = torch.tensor(p.x, device="cuda")
+    A1, A2 = dev(p.init, torch.float64), dev(p.init, torch.float64)
+    for lam, damping in ((1e-3, "identity"), (2.5e-4, "diagonal")):
+        P.gn_step(X, A1, lam, 1e-3, 20, damping=damping)
+        P.gn_step_devlam(X, A2, torch.tensor([lam], dtype=torch.float64, device="cuda"), 1e-3, 20,
+                         damping=damping)
+        for a, b in zip(A1, A2):
+            assert torch.equal(a, b)
+
+
+def test_gn_step_devlam_rejects_negative_lambda_on_device():
+    p = make_problem((12, 10, 8), 3, workload=0, problem=3, noise=1e-2)
+    X = torch.tensor(p.x, device="cuda")
+    A = dev(p.init, torch.float64)
+    st = P.gn_step_devlam(X, A, torch.tensor([-1.0], dtype=torch.float64, device="cuda"))
+    assert P.read_stats(st)["status"] == -1   # CP_EINVAL
+    for a, a0 in zip(A, p.init):
+        assert np.array_equal(a.cpu().numpy(), a0)
+
+
+def test_batched_graph_replays_match_eager_steps():
+    """Each problem's captured step (GN step + device damping update) replayed three times, with
+    eager work and synchronisations between replays, gives bitwise the eager batched iterates."""
+    from workloads import batched_problems
+    probs = batched_problems(5)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    eager = P.BatchedGaussNewton(mk(), n_streams=3)
+    graph = P.BatchedGaussNewton(mk(), n_streams=3, graphs=True)
+    for k in range(3):
+        eager.step()
+        eager.synchronize()
+        graph.step()
+        graph.synchronize()
+        _ = graph.residuals()          # eager library work on the same streams between replays
+        torch.cuda.synchronize()
+        for oe, og in zip(eager.opts, graph.opts):
+            assert og.schedule.value == oe.schedule.value
+            for a, b in zip(oe.A, og.A):
+                assert torch.equal(a, b), k
