@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--batched-streams", type=int, default=8)
     ap.add_argument("--no-order4", action="store_true",
                     help="skip the 80^4 R=64 bfloat16 / split-bfloat16 leg")
+    ap.add_argument("--profile-bf16", action="store_true",
+                    help="only run 3 cp_mttkrp calls per mode on the 80^4 R=64 tensor in bfloat16 "
+                         "and split bfloat16 (for counter runs)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run each single-mode MTTKRP and one device copy of X of known size "
                          "(the workload the rocprofv3 counter runs are taken on), then exit")
@@ -229,6 +232,20 @@ def main():
     P._lib.load()
     s, R = args.size, args.rank
     dev_name = torch.cuda.get_device_name(0)
+    if args.profile_bf16:
+        from workloads import make_problem
+        p4 = make_problem((80, 80, 80, 80), 64, workload=4, problem=0, kind="lognorm", noise=1e-3)
+        X4 = torch.tensor(p4.x, dtype=torch.float32, device="cuda")
+        A4 = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p4.init]
+        ws = P.Workspace()
+        for Xq in (P.to_bf16(X4), P.to_bf16(X4, split=True)):
+            for n in range(4):
+                for _ in range(3):
+                    P.mttkrp(Xq, A4, n, ws=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_bf16": "3 x cp_mttkrp per mode, 80^4 R=64, bfloat16 and split"}),
+              flush=True)
+        return
     log(f"[bench] device {dev_name}; building {s}^3 rank-{R} planted FP32 tensor")
     X64, A0, Xd = make_inputs(s, R, np.float32)
     stream = torch.cuda.current_stream()
