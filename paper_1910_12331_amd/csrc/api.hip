@@ -37,6 +37,9 @@ int launch_cg(const Plan&, const Dims&, const double*, const double*, const doub
               double, int, bool, hipStream_t, const double* lam_dev = nullptr);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
+int64_t ttm_rows(const Plan&);
+int launch_ttm_last(const Plan&, const void*, void*, void*, hipStream_t);
+void launch_ttm_contract(const Plan&, const void*, const double*, int, double*, hipStream_t);
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -131,6 +134,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_slots = take(cg_slot_bytes(*p));
   p->off_krp = take((size_t)krp * 4);
   p->bytes = off;
+  if (p->N == 3 && p->xk == 0) p->t_bytes = align256((size_t)ttm_rows(*p) * p->Rp * p->esz);
   return CP_OK;
 }
 
@@ -283,7 +287,7 @@ int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes) {
   Plan p;
   const int rc = make_plan(prob, &p);
   if (rc) return rc;
-  *bytes = p.bytes;
+  *bytes = p.bytes + (op == CP_OP_ALS_SWEEP ? p.t_bytes : 0);
   return CP_OK;
 }
 
@@ -437,11 +441,20 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
   launch_state_reset(w.st, st);
   launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true, 1u);
   launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
+  // Order 3 with room for T (the ALS workspace query includes it): modes 0 and 1 share
+  // T = X x_3 A(2) (Section 2.2, dimension tree), since A(2) changes only at the end of the
+  // sweep; M(0) and M(1) are then O(s0 s1 R) contractions of T with the latest factors.
+  const bool tree = p.t_bytes > 0 && ws_bytes >= p.bytes + p.t_bytes;
+  void* Tbuf = w.base + p.bytes;
+  if (tree) launch_ttm_last(p, X, ws, Tbuf, st);
   int64_t off = 0;
   for (int n = 0; n < p.N; ++n) {
     launch_gamma(d, w.S, w.gam, st);
     double* m64n = w.m64 + off * p.R;
-    launch_mttkrp(p, X, n, ws, m64n, nullptr, st);
+    if (tree && n < 2)
+      launch_ttm_contract(p, Tbuf, w.a64 + (n == 0 ? p.s[0] * p.R : 0), n, m64n, st);
+    else
+      launch_mttkrp(p, X, n, ws, m64n, nullptr, st);
     launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, n, 1, w.st, st);
     RowMM a{};
     a.l1 = w.m64;

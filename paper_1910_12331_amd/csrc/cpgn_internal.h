@@ -63,6 +63,7 @@ struct Plan {
   size_t off_slots = 0;
   size_t off_krp = 0;                  // outer Khatri-Rao tables of the bfloat16 MTTKRP
   size_t bytes = 0;
+  size_t t_bytes = 0;                  // ALS dimension tree (order 3): T = X x_3 A(2), after `bytes`
 };
 
 // Device-resident CG state (FP64 scalars never leave the device during a step).

@@ -690,6 +690,102 @@ void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int R
 int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
                        hipStream_t st);
 
+// Order 3: T = X x_3 A(2) as the [s0 s1][Rp] matrix (compute precision), for the ALS dimension
+// tree. It is the mode-0 MTTKRP of X viewed as the two-way tensor [s0 s1, s2]: one workgroup per
+// row tile sums all inner chunks, so each tile of T is written once and no reduction follows.
+template <typename T>
+static int launch_ttm_last_t(const Plan& p, const void* X, char* ws, void* Tout, hipStream_t st) {
+  const int MB = p.dtype == CP_F64 ? 2 : 4;
+  const int64_t J = p.s[0] * p.s[1], s_in = p.s[2];
+  const bool vec = ((uintptr_t)X % 16) == 0 && s_in % 4 == 0;
+  MttkrpArgs a{};
+  a.X = X;
+  a.fpk = ws + p.off_fpk_last;
+  a.part = Tout;
+  a.J = J;
+  a.s_in = s_in;
+  a.QC = (s_in + 15) / 16;
+  a.nitems = a.QC;
+  a.O = 1;
+  a.Rr = s_in;
+  a.nbo = 1;
+  a.n_outer = 0;
+  a.Rp = p.Rp;
+  a.NBt = p.NBt;
+  a.nsplit = 4;
+  a.dt = 0;
+  const int64_t RT = (J + 16 * MB - 1) / (16 * MB);
+  a.Jpad = RT * 16 * MB;
+  for (int cb0 = 0; cb0 < p.NBt; cb0 += 8) {
+    const int NB = p.NBt - cb0 < 8 ? p.NBt - cb0 : 8;
+    a.cb0 = cb0;
+    launch_variant<T>(false, vec, MB, NB, dim3(1, (unsigned)RT), st, a);
+  }
+  return (int)hipGetLastError();
+}
+
+// Rows of T padded to whole tiles (the T buffer holds ttm_rows(p) x Rp elements).
+int64_t ttm_rows(const Plan& p) {
+  const int64_t rows = 16 * (p.dtype == CP_F64 ? 2 : 4);
+  return (p.s[0] * p.s[1] + rows - 1) / rows * rows;
+}
+
+int launch_ttm_last(const Plan& p, const void* X, void* ws, void* T, hipStream_t st) {
+  if (p.dtype == CP_F32) return launch_ttm_last_t<float>(p, X, (char*)ws, T, st);
+  return launch_ttm_last_t<double>(p, X, (char*)ws, T, st);
+}
+
+// M(n) for n = 0 or 1 from T = X x_3 A(2): M(0)[i0][r] = sum_i1 T[i0 s1 + i1][r] F[i1][r],
+// M(1)[i1][r] = sum_i0 T[i0 s1 + i1][r] F[i0][r], F the other mode's FP64 factor. One workgroup
+// per output row: lane r of group g adds the terms b = g, g + 8, ... in order in FP64 (each
+// step a coalesced read of one T row segment), and the 8 group sums are added in a fixed tree.
+constexpr int kTtmGroups = 8;
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ttm_contract(const T* __restrict__ Tm,
+                                                       const double* __restrict__ F,
+                                                       int64_t n_loop, int64_t stride_out,
+                                                       int64_t stride_loop, int R,
+                                                       double* __restrict__ out) {
+  __shared__ double part[kTtmGroups][128];
+  const int r = threadIdx.x & 127, g = threadIdx.x >> 7;
+  const int64_t i = blockIdx.x;
+  double acc = 0.0;
+  if (r < R) {
+    const T* base = Tm + i * stride_out + r;
+#pragma unroll 4
+    for (int64_t b = g; b < n_loop; b += kTtmGroups)
+      acc = fma((double)base[b * stride_loop], F[b * R + r], acc);
+  }
+  part[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && r < R) {
+    double t[kTtmGroups];
+#pragma unroll
+    for (int q = 0; q < kTtmGroups; ++q) t[q] = part[q][r];
+#pragma unroll
+    for (int h = kTtmGroups / 2; h >= 1; h /= 2)
+#pragma unroll
+      for (int q = 0; q < h; ++q) t[q] += t[q + h];
+    out[i * R + r] = t[0];
+  }
+}
+
+// R <= 128 (the rank limit of the ALS sweep).
+void launch_ttm_contract(const Plan& p, const void* T, const double* F, int mode, double* out,
+                         hipStream_t st) {
+  const int64_t s1Rp = p.s[1] * p.Rp;
+  const int64_t n_out = mode == 0 ? p.s[0] : p.s[1];
+  const int64_t n_loop = mode == 0 ? p.s[1] : p.s[0];
+  const int64_t so = mode == 0 ? s1Rp : p.Rp, sl = mode == 0 ? p.Rp : s1Rp;
+  if (p.dtype == CP_F32)
+    hipLaunchKernelGGL(k_ttm_contract<float>, dim3((unsigned)n_out), dim3(1024), 0, st,
+                       (const float*)T, F, n_loop, so, sl, p.R, out);
+  else
+    hipLaunchKernelGGL(k_ttm_contract<double>, dim3((unsigned)n_out), dim3(1024), 0, st,
+                       (const double*)T, F, n_loop, so, sl, p.R, out);
+}
+
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
                   hipStream_t st) {
   if (p.xk != 0) return launch_mttkrp_bf16(p, X, mode, ws, m64, mout, st);

@@ -394,3 +394,37 @@ def test_als_end_to_end_config1_monotone():
             break
         opt.step()
     assert last <= 1e-10
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_als_sweep_dimension_tree_and_per_mode_paths_match_oracle(dt):
+    """Order 3: with the ALS workspace (room for T = X x_3 A(3)) modes 1 and 2 come from T; with
+    the smaller workspace of the other operations each mode takes its own pass over X. Both
+    sweeps match the oracle."""
+    import ctypes as C
+    from paper_1910_12331_amd import _lib as L
+    from paper_1910_12331_amd import api
+    p = make_problem((36, 28, 44), 9, workload=0, problem=9, noise=1e-2)
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    ref = O.als_sweep(Xh, Ah, 1e-3)
+    X = to_dev([p.x], dt)[0]
+    prob = api._problem(X, 9)
+    sizes = []
+    for op in (L.OP_ALS_SWEEP, L.OP_GN_STEP):
+        n = C.c_size_t(0)
+        assert L.load().cp_workspace_bytes(C.byref(prob), op, C.byref(n)) == 0
+        sizes.append(int(n.value))
+    assert sizes[0] > sizes[1]
+    ws = torch.empty(sizes[0] + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    tol = 1e-12 if dt == torch.float64 else 1e-4
+    for nbytes in sizes:
+        Ad = to_dev(p.init, dt)
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        rc = L.load().cp_als_sweep(C.byref(prob), X.data_ptr(), api._ptrs(Ad), 1e-3, status.data_ptr(),
+                                   base, nbytes, api._stream())
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        for a, r in zip(host(Ad), ref):
+            assert rel(a, r) < tol, nbytes
