@@ -177,6 +177,10 @@ def order4_leg(P, torch, reps, stream):
     # time to relative residual 2e-3 (twice the noise level) from the same start: FP64 storage
     # alone, and the precision ladder bfloat16 -> split bfloat16 -> FP64
     target = 2e-3
+    # untimed runs first, so that the timed ones reuse cached workspace allocations
+    P.gn_to_target(X64, [a.clone() for a in A64], target, max_steps=40)
+    P.gn_ladder_to_target([forms["bf16"], forms["bf16x3"], X64], [a.clone() for a in A32], target,
+                          max_steps=40)
     Af = [a.clone() for a in A64]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -350,13 +354,18 @@ def main():
         t20_64 = event_time(lambda: P.gn_step(X64d, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 3, stream)
         del A20
         A64 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
+        # one untimed step of each driver first, so that the timed runs reuse cached workspace
+        # allocations instead of allocating inside the timed region
+        X32d = X64d.float()
+        P.gn_to_target(X64d, [a.clone() for a in A64], 1e-8, max_steps=1)
+        P.gn_mixed_to_target(X32d, X64d, [torch.tensor(a, dtype=torch.float32, device="cuda")
+                                          for a in A0], 1.0, 1.0, max_steps=2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g64, h64 = P.gn_to_target(X64d, A64, 1e-8, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
         fp64_s = time.perf_counter() - t0
         # mixed: FP32 storage until its residual is <= 1e-6 (or stalls near the FP32 rounding
         # floor), then FP64 from the same factors and damping schedule
-        X32d = X64d.float()
         A32 = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
