@@ -92,6 +92,7 @@ SHAPES = [
     ((96, 96, 96), 16),       # several row tiles and items per wavefront, ragged tiles
     ((50, 47), 7),            # order 2
     ((6, 5, 7, 4, 8), 5),     # order 5
+    ((20, 18, 16), 130),      # R = 130: three launches (4 + 4 + 1 column blocks)
 ]
 
 
