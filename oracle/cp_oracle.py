@@ -36,7 +36,7 @@ __all__ = [
     "objective", "gradient", "jtj_matvec", "preconditioner", "pcg", "PCGResult", "gn_step",
     "GNStepStats", "LambdaSchedule", "als_sweep", "residual", "residual_expansion", "gn", "als",
     "jacobian", "jtj_dense", "flatten_factors", "unflatten_factors", "OracleError",
-    "damping_matrix",
+    "damping_matrix", "gn_step_armijo", "ArmijoResult",
 ]
 
 
@@ -293,6 +293,56 @@ def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity"):
     return newA, GNStepStats(cg_iters=res.iters, grad_norm_sum=res.grad_norm_sum,
                              cg_res_norm_sum=res.res_norm_sum, alpha_last=res.alpha_last,
                              beta_last=res.beta_last, lam=lam, update_norm=upd)
+
+
+@dataclass
+class ArmijoResult:
+    A: list                # factors after the step (the input ones if no step size was accepted)
+    alpha: float           # accepted step size (0 if none)
+    trials: int            # objective evaluations made
+    accepted: bool
+    f0: float              # f at the start point, eq. (3)
+    f: float               # f at the returned point
+    gv: float              # directional derivative sum_n <G(n), V(n)> along the GN direction
+    V: list                # the Gauss-Newton direction
+    stats: GNStepStats
+
+
+def gn_step_armijo(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity", c=1e-4, shrink=0.5,
+                   max_trials=10):
+    """Gauss-Newton step with Armijo step-size control (the variant Section 5 uses for the
+    matrix-multiplication tensors): the direction V of Algorithm 1, then the step sizes
+    alpha = 1, shrink, shrink^2, ... (at most max_trials of them) are tried in that order and the
+    first one with f(A + alpha V) <= f(A) + c alpha <G, V> is taken (Armijo's sufficient-decrease
+    condition; f is eq. (3), G its gradient). The paper gives no constants: c, shrink and
+    max_trials are parameters. If <G, V> is not negative (no descent, e.g. V = 0) or no trial
+    passes, the factors are returned unchanged with accepted = False."""
+    N = len(A)
+    S = grams(A)
+    Gam = gamma_set(S)
+    M = [mttkrp(X, A, n) for n in range(N)]
+    G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
+    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping)
+    f0 = objective(X, A)
+    gv = sum(_inner(G[n], res.V[n]) for n in range(N))
+    alpha, trials, accepted, f, out = 1.0, 0, False, f0, [a.copy() for a in A]
+    if gv < 0.0 and math.isfinite(f0):
+        while trials < max_trials:
+            trial = [A[n] + alpha * res.V[n] for n in range(N)]
+            ft = objective(X, trial)
+            trials += 1
+            if ft <= f0 + c * alpha * gv:
+                accepted, f, out = True, ft, trial
+                break
+            alpha *= shrink
+    if not accepted:
+        alpha = 0.0
+    upd = alpha * math.sqrt(sum(float(np.sum(v * v)) for v in res.V))
+    st = GNStepStats(cg_iters=res.iters, grad_norm_sum=res.grad_norm_sum,
+                     cg_res_norm_sum=res.res_norm_sum, alpha_last=res.alpha_last,
+                     beta_last=res.beta_last, lam=lam, update_norm=upd)
+    return ArmijoResult(A=out, alpha=alpha, trials=trials, accepted=accepted, f0=f0, f=f, gv=gv,
+                        V=res.V, stats=st)
 
 
 class LambdaSchedule:

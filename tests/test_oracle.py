@@ -461,3 +461,77 @@ def test_diagonal_damping_scale_invariance_of_the_damping_term():
     G1, G2 = O.gamma_set(O.grams(A)), O.gamma_set(O.grams(B))
     d1, d2 = O.damping_matrix(G1, 0, "diagonal"), O.damping_matrix(G2, 0, "diagonal")
     assert abs(d2[0, 0] - 9.0 * d1[0, 0]) <= 1e-12 * d2[0, 0] and abs(d2[1, 1] - d1[1, 1]) < 1e-14
+
+
+# ---------------------------------------------------------------- Armijo step control
+def _objective_einsum(X, A):
+    """f of eq. (3) for an order-3 tensor, the reconstruction written as one einsum (not the
+    oracle's component-by-component sum)."""
+    d = X - np.einsum("ir,jr,kr->ijk", *A)
+    return 0.5 * float(np.sum(d * d))
+
+
+def _small_start(seed, scale):
+    rng = np.random.default_rng(seed)
+    dims, R = (6, 5, 7), 4
+    X = rng.standard_normal(dims)
+    return X, [scale * rng.standard_normal((s, R)) for s in dims]
+
+
+@pytest.mark.parametrize("c,expect_alpha", [(1e-4, 0.125), (0.4, 0.0625)])
+def test_armijo_choice_by_brute_force(c, expect_alpha):
+    # a start at a small scale, where the full Gauss-Newton step overshoots
+    X, A = _small_start(3, 0.3)
+    res = O.gn_step_armijo(X, A, 1e-6, eps_cg=1e-6, maxiter=50, c=c)
+    # <G, V> is the derivative of alpha -> f(A + alpha V) at 0: central differences
+    h = 1e-6
+    fp = _objective_einsum(X, [a + h * v for a, v in zip(A, res.V)])
+    fm = _objective_einsum(X, [a - h * v for a, v in zip(A, res.V)])
+    gfd = (fp - fm) / (2 * h)
+    assert gfd < 0 and abs(res.gv - gfd) < 1e-7 * abs(gfd)
+    # the first of 1, 1/2, 1/4, ... meeting the sufficient-decrease condition, each trial kept
+    # well away from its threshold so that the choice is unambiguous
+    f0 = _objective_einsum(X, A)
+    alpha, k = 1.0, 0
+    while True:
+        ft = _objective_einsum(X, [a + alpha * v for a, v in zip(A, res.V)])
+        thr = f0 + c * alpha * gfd
+        assert abs(ft - thr) > 1e-3 * f0
+        k += 1
+        if ft <= thr:
+            break
+        alpha *= 0.5
+    assert alpha == expect_alpha            # the c term decides between the two cases
+    assert res.accepted and res.alpha == alpha and res.trials == k
+    assert abs(res.f0 - f0) < 1e-12 * f0 and abs(res.f - ft) < 1e-12 * f0 and res.f < f0
+    for a, v, out in zip(A, res.V, res.A):
+        assert np.array_equal(out, a + alpha * v)
+
+
+def test_armijo_descends_where_the_full_step_explodes():
+    X, A = _small_start(0, 0.05)
+    res = O.gn_step_armijo(X, A, 1e-6, eps_cg=1e-6, maxiter=50)
+    full_step = _objective_einsum(X, [a + v for a, v in zip(A, res.V)])
+    assert full_step > 1e6 * res.f0                    # plain Gauss-Newton diverges here
+    assert res.accepted and res.alpha < 0.01 and res.f < res.f0
+
+
+def test_armijo_full_step_near_solution_is_the_gn_step():
+    p = make_problem((12, 10, 11), 3, workload=0, problem=4)
+    rng = np.random.default_rng(5)
+    A = [b + 1e-3 * rng.standard_normal(b.shape) for b in p.planted]
+    res = O.gn_step_armijo(p.x, A, 1e-6, eps_cg=1e-10, maxiter=500)
+    ref, _ = O.gn_step(p.x, A, 1e-6, eps_cg=1e-10, maxiter=500)
+    assert res.accepted and res.alpha == 1.0 and res.trials == 1
+    assert all(np.array_equal(a, b) for a, b in zip(res.A, ref))
+    assert res.f < 1e-6 * res.f0                       # quadratic convergence region
+
+
+def test_armijo_without_descent_direction_or_passing_trial_keeps_factors():
+    X, A = _small_start(3, 0.3)
+    none = O.gn_step_armijo(X, A, 1e-6, maxiter=0)     # V = 0: <G, V> = 0 is no descent
+    assert not none.accepted and none.alpha == 0.0 and none.trials == 0
+    one = O.gn_step_armijo(X, A, 1e-6, eps_cg=1e-6, maxiter=50, max_trials=1)   # alpha = 1 fails
+    assert not one.accepted and one.alpha == 0.0 and one.trials == 1 and one.f == one.f0
+    for res in (none, one):
+        assert all(np.array_equal(a, b) for a, b in zip(res.A, A))
