@@ -187,6 +187,46 @@ int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
                       const cp_gn_params* params, const double* lambda_dev, cp_gn_stats* stats,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* Armijo step-size control of a Gauss-Newton step (Section 5). */
+typedef struct cp_armijo_params {
+  double c;             /* sufficient-decrease constant, 0 < c < 1 (e.g. 1e-4)                 */
+  double shrink;        /* factor between successive step sizes, 0 < shrink < 1 (e.g. 0.5)     */
+  int32_t max_trials;   /* objective evaluations at most, 0..64                                */
+  int32_t reserved;     /* must be 0                                                           */
+} cp_armijo_params;
+
+typedef struct cp_armijo_stats {
+  double alpha;         /* accepted step size; 0 if none was accepted                          */
+  double f0;            /* f = 1/2 ||X - [[A]]||_F^2 (eq. (3)) at the start point               */
+  double f;             /* f at the returned point (f0 if no step size was accepted)           */
+  double gv;            /* sum_n <G(n), V(n)>: slope of f along the Gauss-Newton direction V    */
+  double x_norm;        /* ||X||_F                                                             */
+  int32_t trials;       /* objective evaluations made                                          */
+  int32_t accepted;     /* 1 if a step size passed the test                                    */
+} cp_armijo_stats;
+
+/*
+ * Gauss-Newton step with Armijo step-size control, the variant Section 5 uses for the
+ * matrix-multiplication tensors. The direction V is the one cp_gn_step computes (Algorithm 1 with
+ * CG, same params and damping flags); the step sizes alpha = 1, shrink, shrink^2, ... (at most
+ * max_trials) are then tried in that order and the first with
+ *     f(A + alpha V) <= f(A) + c alpha sum_n <G(n), V(n)>
+ * (f of eq. (3) evaluated directly, G the gradient) is applied: A(n) <- A(n) + alpha V(n). No trial
+ * runs when the CG status is a failure, when sum <G, V> >= 0 (no descent, e.g. V = 0 with
+ * cg_maxiter = 0) or when f(A) is not finite; then, and when no trial passes, the factors are left
+ * unchanged and accepted = 0. The search runs on the device without host synchronisation: every
+ * trial is launched and the ones after a passing trial return at once.
+ *   A: N device pointers, read and overwritten in place (f_dtype).
+ *   params, ls: HOST pointers. stats: DEVICE pointer to one cp_gn_stats (update_norm is
+ *   ||alpha V||). ls_stats: DEVICE pointer to one cp_armijo_stats.
+ *   ws: at least cp_workspace_bytes(CP_OP_GN_STEP).
+ *   Errors: CP_EINVAL for null pointers or parameters out of range (before any launch);
+ *   rank > 128: CP_EUNSUPPORTED.
+ */
+int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
+                      const cp_gn_params* params, const cp_armijo_params* ls, cp_gn_stats* stats,
+                      cp_armijo_stats* ls_stats, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * The varying damping of Section 3.2 advanced once on the device (one tiny kernel, so a captured
  * graph can carry the schedule with the step). state_dev: device double[5] =

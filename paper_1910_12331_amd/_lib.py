@@ -16,7 +16,7 @@ GN_DIAG_DAMPING = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_gn_step_devlam", "cp_damping_advance", "cp_als_sweep", "cp_residual",
+           "cp_gn_step_devlam", "cp_gn_step_armijo", "cp_damping_advance", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -34,6 +34,16 @@ class CpGnStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("cg_iters", C.c_int32), ("grad_norm_sum", C.c_double),
                 ("cg_res_norm_sum", C.c_double), ("alpha_last", C.c_double),
                 ("beta_last", C.c_double), ("update_norm", C.c_double)]
+
+
+class CpArmijoParams(C.Structure):
+    _fields_ = [("c", C.c_double), ("shrink", C.c_double), ("max_trials", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class CpArmijoStats(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("f0", C.c_double), ("f", C.c_double), ("gv", C.c_double),
+                ("x_norm", C.c_double), ("trials", C.c_int32), ("accepted", C.c_int32)]
 
 
 PTRS = C.c_void_p * MAX_ORDER
@@ -68,6 +78,9 @@ def load(path: str = LIB_PATH):
     lib.cp_gn_step.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, sz, vp]
     lib.cp_gn_step_devlam.restype = i32
     lib.cp_gn_step_devlam.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, vp, sz, vp]
+    lib.cp_gn_step_armijo.restype = i32
+    lib.cp_gn_step_armijo.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), P(CpArmijoParams),
+                                      vp, vp, vp, sz, vp]
     lib.cp_damping_advance.restype = i32
     lib.cp_damping_advance.argtypes = [vp, vp]
     lib.cp_als_sweep.restype = i32

@@ -257,6 +257,46 @@ def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: floa
     return stats
 
 
+ARMIJO_FIELDS = ("alpha", "f0", "f", "gv", "x_norm", "trials", "accepted")
+
+
+def armijo_stats_buffer(device) -> torch.Tensor:
+    return torch.zeros(C.sizeof(L.CpArmijoStats), dtype=torch.uint8, device=device)
+
+
+def read_armijo_stats(buf: torch.Tensor) -> dict:
+    s = L.CpArmijoStats.from_buffer_copy(bytes(buf.cpu().numpy().tobytes()))
+    return {f: getattr(s, f) for f in ARMIJO_FIELDS}
+
+
+def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
+                   cg_maxiter: int = 20, c: float = 1e-4, shrink: float = 0.5,
+                   max_trials: int = 10, stats=None, ls_stats=None, ws=None,
+                   damping: str = "identity"):
+    """Gauss-Newton step with Armijo step-size control (Section 5), in place on A: the direction
+    of gn_step, then the first of alpha = 1, shrink, shrink^2, ... (at most max_trials) with
+    f(A + alpha V) <= f(A) + c alpha <G, V>. Returns (stats buffer, Armijo stats buffer), both on
+    the device (read_stats, read_armijo_stats)."""
+    if damping not in ("identity", "diagonal"):
+        raise ValueError("damping must be 'identity' or 'diagonal'")
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, factor_dtype(X), R)
+    prob = _problem(X, R)
+    prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
+                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+    ls = L.CpArmijoParams(float(c), float(shrink), int(max_trials), 0)
+    if stats is None:
+        stats = stats_buffer(X.device)
+    if ls_stats is None:
+        ls_stats = armijo_stats_buffer(X.device)
+    w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
+    _check(L.load().cp_gn_step_armijo(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),
+                                      C.byref(ls), stats.data_ptr(), ls_stats.data_ptr(), w, nb,
+                                      _stream()), "cp_gn_step_armijo")
+    return stats, ls_stats
+
+
 def gn_step_devlam(X, A: Sequence[torch.Tensor], lam_dev: torch.Tensor, cg_tol: float = 1e-3,
                    cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity"):
     """gn_step with the damping read from device memory (lam_dev: a one-element float64 GPU

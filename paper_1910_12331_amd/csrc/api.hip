@@ -25,7 +25,15 @@ int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
                    hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr);
 void launch_damping_advance(double*, hipStream_t);
-int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t);
+void launch_ls_gv(const Dims&, const double*, const double*, double*, CgState*, hipStream_t);
+void launch_ls_init(int, const double*, CgState*, hipStream_t);
+void launch_ls_trial(const Dims&, const double*, const double*, const PerMode<void*>&, int, void*,
+                     const CgState*, hipStream_t);
+void launch_ls_check(int, const double*, CgState*, double, double, hipStream_t);
+void launch_ls_final(const Dims&, const double*, const double*, const PerMode<void*>&, int,
+                     double*, const CgState*, cp_armijo_stats*, hipStream_t);
+int launch_residual_direct(const Plan&, const void*, void*, double*, hipStream_t,
+                           const int32_t* skip = nullptr, int* nblocks = nullptr);
 int launch_sumsq(const Plan&, const void*, double*, hipStream_t, int*);
 void launch_fin_residual_expansion(const Dims&, int, const double*, const double*, const double*,
                                    const double*, double*, hipStream_t);
@@ -372,13 +380,20 @@ int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* c
 }
 
 // One Gauss-Newton step; the damping is prm->lambda, or *lam_dev read on the device.
+// One Gauss-Newton step: the direction V of Algorithm 1, then either the full step A += V or,
+// with ls, the Armijo search along V (Section 5).
 static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
                         const cp_gn_params* prm, const double* lam_dev, cp_gn_stats* stats,
-                        void* ws, size_t ws_bytes, void* stream) {
+                        void* ws, size_t ws_bytes, void* stream,
+                        const cp_armijo_params* ls = nullptr, cp_armijo_stats* ls_stats = nullptr) {
   Plan p;
   int rc = make_plan(prob, &p);
   if (rc) return rc;
   if (!X || !prm || !stats) return CP_EINVAL;
+  if (ls && (!ls_stats || !(ls->c > 0.0 && ls->c < 1.0) ||
+             !(ls->shrink > 0.0 && ls->shrink < 1.0) || ls->max_trials < 0 ||
+             ls->max_trials > 64 || ls->reserved != 0))
+    return CP_EINVAL;
   if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
   if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
       (prm->flags & ~CP_GN_DIAG_DAMPING) != 0)
@@ -405,7 +420,24 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
             prm->cg_maxiter, diag, st, lam_dev);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
-  launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
+  if (!ls) {
+    launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
+    launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
+    return hip_status();
+  }
+  // Armijo search along V: the slope <G, V>, f at the start point (the padded factor copies still
+  // hold it), then max_trials trial points, each skipped on the device once one has passed.
+  launch_ls_gv(d, w.g, w.v, w.red_dot, w.st, st);
+  int rb = 0;
+  launch_residual_direct(p, X, ws, nullptr, st, nullptr, &rb);
+  launch_ls_init(rb, w.red_dot, w.st, st);
+  const int32_t* done = &w.st->ls_done;
+  for (int k = 0; k < ls->max_trials; ++k) {
+    launch_ls_trial(d, w.a64, w.v, aout, p.dtype, w.base + p.off_apad, w.st, st);
+    launch_residual_direct(p, X, ws, nullptr, st, done, &rb);
+    launch_ls_check(rb, w.red_dot, w.st, ls->c, ls->shrink, st);
+  }
+  launch_ls_final(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, ls_stats, st);
   launch_gn_stats(d, nb, w.red_nrm, w.st, stats, st);
   return hip_status();
 }
@@ -420,6 +452,13 @@ int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
                       void* ws, size_t ws_bytes, void* stream) {
   if (!lambda_dev) return CP_EINVAL;
   return gn_step_impl(prob, X, A, prm, lambda_dev, stats, ws, ws_bytes, stream);
+}
+
+int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
+                      const cp_gn_params* prm, const cp_armijo_params* ls, cp_gn_stats* stats,
+                      cp_armijo_stats* ls_stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!ls) return CP_EINVAL;
+  return gn_step_impl(prob, X, A, prm, nullptr, stats, ws, ws_bytes, stream, ls, ls_stats);
 }
 
 int cp_damping_advance(double* state_dev, void* stream) {

@@ -215,6 +215,127 @@ __global__ void k_gn_stats(int N, int nblocks, const double* red_nrm, const CgSt
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Armijo step-size control (Section 5): after the direction V of Algorithm 1 is known, the step
+// sizes alpha = 1, shrink, shrink^2, ... are tried in order and the first one with
+// f(A + alpha V) <= f(A) + c alpha <G, V> is taken; f is eq. (3), G its gradient. Every trial is
+// launched; once one has passed (ls_done) the remaining launches return at once, so the search
+// needs no host synchronisation.
+// ------------------------------------------------------------------------------------------
+
+// Partials of <G, V> over the packed gradient and direction.
+__global__ __launch_bounds__(256) void k_ls_dot(int64_t cnt, const double* __restrict__ G,
+                                                const double* __restrict__ V, double* red) {
+  double s = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    s = fma(G[e], V[e], s);
+  block_sum2(s, dummy);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+__global__ void k_ls_gv(int nblocks, const double* red, CgState* st) {
+  const double gv = sum_slots(red, nblocks);
+  if (threadIdx.x == 0) st->ls_gv = gv;
+}
+
+// Start of the search from the residual partials at the start point (slots [0] = squared
+// differences, [kRedSlots] = squares of X). No trial runs when CG failed, when V is not a
+// descent direction (<G, V> >= 0, e.g. V = 0) or when f is not finite.
+__global__ void k_ls_init(int nblocks, const double* red, CgState* st) {
+  const double d2 = sum_slots(red, nblocks);
+  const double x2 = sum_slots(red + kRedSlots, nblocks);
+  if (threadIdx.x == 0) {
+    const double f0 = 0.5 * d2;
+    st->ls_f0 = f0;
+    st->ls_x2 = x2;
+    st->ls_f = f0;
+    st->ls_alpha = 1.0;
+    st->ls_trials = 0;
+    st->ls_accepted = 0;
+    const double gv = st->ls_gv;
+    st->ls_done = (st->status != CP_OK || !(gv < 0.0) || !isfinite(f0)) ? 1 : 0;
+  }
+}
+
+// Trial point A + alpha V: the caller's factors (f_dtype) and the padded compute-precision
+// copies the residual reads (columns below R; the zero padding is left as it is).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ls_trial(Dims d, const double* __restrict__ A64,
+                                                  const double* __restrict__ V,
+                                                  PerMode<void*> Aout, int dtype, T* apad,
+                                                  const CgState* st) {
+  if (st->ls_done) return;
+  const int n = blockIdx.y;
+  const double alpha = st->ls_alpha;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  T* ap = apad + d.off[n] * d.Rp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double a = A64[base + e] + alpha * V[base + e];
+    const int64_t row = e / d.R, col = e - row * d.R;
+    ap[row * d.Rp + col] = (T)a;
+    if (dtype == CP_F64) ((double*)Aout.p[n])[e] = a;
+    else ((float*)Aout.p[n])[e] = (float)a;
+  }
+}
+
+// Armijo test of the current trial from its residual partials; on failure the step size shrinks.
+__global__ void k_ls_check(int nblocks, const double* red, CgState* st, double c, double shrink) {
+  if (st->ls_done) return;
+  const double d2 = sum_slots(red, nblocks);
+  if (threadIdx.x == 0) {
+    const double f = 0.5 * d2;
+    const double alpha = st->ls_alpha;
+    st->ls_trials += 1;
+    if (f <= st->ls_f0 + c * alpha * st->ls_gv) {
+      st->ls_f = f;
+      st->ls_accepted = 1;
+      st->ls_done = 1;
+    } else {
+      st->ls_alpha = alpha * shrink;
+    }
+  }
+}
+
+// End of the search: without an accepted step the caller's factors are restored from the FP64
+// copy of the start point (exact, it was read from them); partials of ||alpha V||^2 for the stats.
+__global__ __launch_bounds__(256) void k_ls_final(Dims d, const double* __restrict__ A64,
+                                                  const double* __restrict__ V,
+                                                  PerMode<void*> Aout, int dtype, double* red_nrm,
+                                                  const CgState* st) {
+  const int n = blockIdx.y;
+  const bool acc = st->ls_accepted != 0;
+  const bool restore = !acc && st->ls_trials > 0;
+  const double alpha = acc ? st->ls_alpha : 0.0;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  double nrm = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = alpha * V[base + e];
+    nrm += v * v;
+    if (restore) {
+      const double a = A64[base + e];
+      if (dtype == CP_F64) ((double*)Aout.p[n])[e] = a;
+      else ((float*)Aout.p[n])[e] = (float)a;
+    }
+  }
+  block_sum2(nrm, dummy);
+  if (threadIdx.x == 0) red_nrm[n * kRedSlots + blockIdx.x] = nrm;
+}
+
+__global__ void k_ls_stats(const CgState* st, cp_armijo_stats* out) {
+  if (threadIdx.x != 0) return;
+  const bool acc = st->ls_accepted != 0;
+  out->alpha = acc ? st->ls_alpha : 0.0;
+  out->f0 = st->ls_f0;
+  out->f = st->ls_f;
+  out->gv = st->ls_gv;
+  out->x_norm = sqrt(st->ls_x2);
+  out->trials = st->ls_trials;
+  out->accepted = acc ? 1 : 0;
+}
+
 __global__ void k_status_out(const CgState* st, int32_t* out) {
   if (threadIdx.x == 0) *out = st->status;
 }
@@ -352,6 +473,7 @@ struct ResArgs {
   int N, Rp;
   int64_t xplane;               // split bfloat16 tensor: elements between the hi and lo planes
   double* red;                  // [2][kRedSlots]
+  const int32_t* skip;          // when set and nonzero the kernels do nothing (a finished search)
 };
 
 // Entry e of X in the compute precision T. XK: 0 = stored as T; 1 = bfloat16; 2 = two
@@ -428,6 +550,7 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
   struct ResB {
     T v[BSH];
   };
+  if (a.skip && *a.skip) return;   // uniform over the grid
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, m = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const void* X = a.X;
@@ -625,7 +748,8 @@ __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
 // (lane group g owns the contiguous k-range [g RS, (g+1) RS) of the contraction).
 template <typename T>
 __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, int64_t KB,
-                            T* __restrict__ bpk) {
+                            T* __restrict__ bpk, const int32_t* skip) {
+  if (skip && *skip) return;
   const int RS = Rp / 4;
   const int64_t total = KB * RS * kWave;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -642,6 +766,7 @@ __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, 
 // Fallback for R > 128: one thread per tensor entry, scalar FP64 reconstruction.
 template <typename T, int XK>
 __global__ void k_residual_scalar(ResArgs a, int R) {
+  if (a.skip && *a.skip) return;
   double d2 = 0.0, x2 = 0.0;
   const int64_t total = a.O * a.K;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -843,10 +968,12 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
 }
 
 template <typename T, int XK>
-static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out, hipStream_t s) {
+static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out, hipStream_t s,
+                             const int32_t* skip, int* nblocks) {
   constexpr int MB = ResCfg<T>::MB;
   ResArgs a{};
   a.X = X;
+  a.skip = skip;
   a.xplane = p.total;
   int64_t off = 0;
   for (int m = 0; m < p.N; ++m) {
@@ -864,7 +991,8 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     // the packed last factor reuses the MTTKRP partial region
     a.bpk = ws + p.off_part;
     hipLaunchKernelGGL(k_pack_last<T>, dim3(grid1(a.KB * p.Rp / 4 * kWave, 1024)), dim3(256), 0,
-                       s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part));
+                       s, (const T*)a.apad[p.N - 1], a.K, p.Rp, a.KB, (T*)(ws + p.off_part),
+                       skip);
     const int64_t items = ((a.O + 16 * MB - 1) / (16 * MB) + 3) / 4 * a.KB;
     int64_t blocks = items;
     if (blocks > ResCfg<T>::OCC * kNumCU) blocks = ResCfg<T>::OCC * kNumCU;   // one resident round
@@ -880,20 +1008,28 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
 #undef CPGN_RES
       default: break;
     }
-    hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, (int)blocks, a.red, out);
+    if (out)
+      hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, (int)blocks, a.red, out);
+    if (nblocks) *nblocks = (int)blocks;
   } else {
     const int blocks = grid1(p.total, kRedSlots);
     hipLaunchKernelGGL((k_residual_scalar<T, XK>), dim3(blocks), dim3(256), 0, s, a, p.R);
-    hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, blocks, a.red, out);
+    if (out) hipLaunchKernelGGL(k_fin_residual_direct, dim3(1), dim3(256), 0, s, blocks, a.red, out);
+    if (nblocks) *nblocks = blocks;
   }
   return (int)hipGetLastError();
 }
 
-int launch_residual_direct(const Plan& p, const void* X, void* ws, double* out, hipStream_t s) {
-  if (p.xk == 1) return launch_residual_t<float, 1>(p, X, (char*)ws, out, s);
-  if (p.xk == 2) return launch_residual_t<float, 2>(p, X, (char*)ws, out, s);
-  if (p.dtype == CP_F32) return launch_residual_t<float, 0>(p, X, (char*)ws, out, s);
-  return launch_residual_t<double, 0>(p, X, (char*)ws, out, s);
+// Direct residual: out = {||X - [[A]]||, ||X||}. With out null only the partial sums of squares
+// are left in the reduction slots (nblocks of each); with skip set the launches do nothing once
+// *skip is nonzero on the device.
+int launch_residual_direct(const Plan& p, const void* X, void* ws, double* out, hipStream_t s,
+                           const int32_t* skip, int* nblocks) {
+  char* w = (char*)ws;
+  if (p.xk == 1) return launch_residual_t<float, 1>(p, X, w, out, s, skip, nblocks);
+  if (p.xk == 2) return launch_residual_t<float, 2>(p, X, w, out, s, skip, nblocks);
+  if (p.dtype == CP_F32) return launch_residual_t<float, 0>(p, X, w, out, s, skip, nblocks);
+  return launch_residual_t<double, 0>(p, X, w, out, s, skip, nblocks);
 }
 
 int launch_sumsq(const Plan& p, const void* X, double* red, hipStream_t s, int* nblocks) {
@@ -914,6 +1050,42 @@ void launch_fin_residual_expansion(const Dims& d, int nblocks, const double* red
                                    const double* A64, const double* S, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_residual_expansion, dim3(1), dim3(256), 0, s, d, nblocks, red, M0, A64,
                      S, out);
+}
+
+void launch_ls_gv(const Dims& d, const double* G, const double* V, double* red, CgState* st,
+                  hipStream_t s) {
+  const int64_t cnt = d.off[d.N] * d.R;
+  const int blocks = grid1(cnt, kRedSlots);
+  hipLaunchKernelGGL(k_ls_dot, dim3(blocks), dim3(256), 0, s, cnt, G, V, red);
+  hipLaunchKernelGGL(k_ls_gv, dim3(1), dim3(256), 0, s, blocks, red, st);
+}
+
+void launch_ls_init(int nblocks, const double* red, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(256), 0, s, nblocks, red, st);
+}
+
+void launch_ls_trial(const Dims& d, const double* A64, const double* V, const PerMode<void*>& Aout,
+                     int dtype, void* apad, const CgState* st, hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), d.N);
+  if (dtype == CP_F64)
+    hipLaunchKernelGGL(k_ls_trial<double>, grid, dim3(256), 0, s, d, A64, V, Aout, dtype,
+                       (double*)apad, st);
+  else
+    hipLaunchKernelGGL(k_ls_trial<float>, grid, dim3(256), 0, s, d, A64, V, Aout, dtype,
+                       (float*)apad, st);
+}
+
+void launch_ls_check(int nblocks, const double* red, CgState* st, double c, double shrink,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_ls_check, dim3(1), dim3(256), 0, s, nblocks, red, st, c, shrink);
+}
+
+void launch_ls_final(const Dims& d, const double* A64, const double* V, const PerMode<void*>& Aout,
+                     int dtype, double* red_nrm, const CgState* st, cp_armijo_stats* out,
+                     hipStream_t s) {
+  dim3 grid(rowmm_blocks(d), d.N);
+  hipLaunchKernelGGL(k_ls_final, grid, dim3(256), 0, s, d, A64, V, Aout, dtype, red_nrm, st);
+  hipLaunchKernelGGL(k_ls_stats, dim3(1), dim3(64), 0, s, st, out);
 }
 
 }  // namespace cpgn

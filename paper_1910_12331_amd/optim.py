@@ -51,12 +51,41 @@ class DampingSchedule:
         self.decreasing = d["decreasing"]
 
 
+class ConstantDamping:
+    """A fixed damping lambda (Section 5 runs Gauss-Newton with Armijo's condition at a constant
+    lambda); the same interface as DampingSchedule."""
+
+    def __init__(self, value: float):
+        if not value >= 0.0:
+            raise ValueError("need lambda >= 0")
+        self.value = float(value)
+
+    def advance(self) -> float:
+        return self.value
+
+    def state_dict(self):
+        return dict(value=self.value)
+
+    def load_state_dict(self, d):
+        self.value = d["value"]
+
+
+@dataclass
+class Armijo:
+    """Armijo step-size control (Section 5): step sizes 1, shrink, shrink^2, ... (at most
+    max_trials) until f(A + alpha V) <= f(A) + c alpha <G, V>."""
+    c: float = 1e-4
+    shrink: float = 0.5
+    max_trials: int = 10
+
+
 @dataclass
 class GNConfig:
     cg_tol: float = 1e-3
     cg_maxiter: int = 20
-    schedule: DampingSchedule | None = None
+    schedule: DampingSchedule | ConstantDamping | None = None
     damping: str = "identity"       # or "diagonal": lam diag(J^T J) (Section 3.2)
+    line_search: Armijo | None = None
 
 
 class GaussNewton:
@@ -68,17 +97,28 @@ class GaussNewton:
         self.schedule = self.cfg.schedule or DampingSchedule()
         self.ws = api.Workspace()
         self.stats_buf = api.stats_buffer(X.device)
+        self.ls_buf = api.armijo_stats_buffer(X.device) if self.cfg.line_search else None
         self.steps = 0
 
     def step(self) -> torch.Tensor:
-        api.gn_step(self.X, self.A, self.schedule.value, self.cfg.cg_tol, self.cfg.cg_maxiter,
-                    stats=self.stats_buf, ws=self.ws, damping=self.cfg.damping)
+        ls = self.cfg.line_search
+        if ls is None:
+            api.gn_step(self.X, self.A, self.schedule.value, self.cfg.cg_tol, self.cfg.cg_maxiter,
+                        stats=self.stats_buf, ws=self.ws, damping=self.cfg.damping)
+        else:
+            api.gn_step_armijo(self.X, self.A, self.schedule.value, self.cfg.cg_tol,
+                               self.cfg.cg_maxiter, ls.c, ls.shrink, ls.max_trials,
+                               stats=self.stats_buf, ls_stats=self.ls_buf, ws=self.ws,
+                               damping=self.cfg.damping)
         self.schedule.advance()
         self.steps += 1
         return self.stats_buf
 
     def stats(self) -> dict:
-        return api.read_stats(self.stats_buf)
+        out = api.read_stats(self.stats_buf)
+        if self.ls_buf is not None:
+            out.update({"ls_" + k: v for k, v in api.read_armijo_stats(self.ls_buf).items()})
+        return out
 
     def residual(self) -> float:
         r = api.residual(self.X, self.A, ws=self.ws).cpu()
@@ -129,7 +169,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     X_high hold the same tensor. Returns (factors, history of (precision, residual))."""
     cfg = config or GNConfig()
     sched = cfg.schedule or DampingSchedule()
-    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping)
+    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping, cfg.line_search)
     opt = GaussNewton(X_low, A, low_cfg)
     hist = []
     prev = float("inf")
@@ -143,7 +183,8 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     if hist and hist[-1][1] <= target:
         return opt.A, hist
     A_high = [a.to(api.factor_dtype(X_high)) for a in opt.A]
-    high = GaussNewton(X_high, A_high, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping))
+    high = GaussNewton(X_high, A_high,
+                       GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping, cfg.line_search))
     while opt.steps + high.steps < max_steps:
         high.step()
         r = high.residual()
@@ -189,7 +230,8 @@ def gn_ladder_to_target(rungs, A, target, config: GNConfig | None = None, max_st
         name = _rung_name(X)
         floor = _RUNG_FLOOR.get(name, 0.0)
         A = [a.to(api.factor_dtype(X)) for a in A]
-        opt = GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping))
+        opt = GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping,
+                                         cfg.line_search))
         if i > 0:
             prev = opt.residual()
         while steps < max_steps:
@@ -234,6 +276,8 @@ class BatchedGaussNewton:
     def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8,
                  graphs: bool = False):
         cfg = config or GNConfig()
+        if graphs and cfg.line_search is not None:
+            raise ValueError("graph replay covers the plain Gauss-Newton step only")
         self.cfg = cfg
         torch.cuda.current_stream().synchronize()   # inputs were written on the current stream
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
@@ -241,7 +285,8 @@ class BatchedGaussNewton:
         for i, (X, A) in enumerate(problems):
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
                 self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter,
-                                                             damping=cfg.damping)))
+                                                             damping=cfg.damping,
+                                                             line_search=cfg.line_search)))
         self.graphs = None
         if graphs:
             self._capture()

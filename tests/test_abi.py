@@ -47,6 +47,9 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(cp_problem, x_dtype), offsetof(cp_problem, f_dtype), sizeof(cp_gn_params));\n"
         'printf("%zu %zu %zu\\n", sizeof(cp_gn_stats), offsetof(cp_gn_stats, grad_norm_sum),'
         " offsetof(cp_gn_stats, update_norm));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(cp_armijo_params), offsetof(cp_armijo_params,'
+        ' max_trials), sizeof(cp_armijo_stats), offsetof(cp_armijo_stats, x_norm),'
+        " offsetof(cp_armijo_stats, accepted));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -57,6 +60,10 @@ def test_struct_layout_matches_header(tmp_path):
                  L.CpProblem.f_dtype.offset, C.sizeof(L.CpGnParams)]
     assert b == [C.sizeof(L.CpGnStats), L.CpGnStats.grad_norm_sum.offset,
                  L.CpGnStats.update_norm.offset]
+    c = list(map(int, lines[2].split()))
+    assert c == [C.sizeof(L.CpArmijoParams), L.CpArmijoParams.max_trials.offset,
+                 C.sizeof(L.CpArmijoStats), L.CpArmijoStats.x_norm.offset,
+                 L.CpArmijoStats.accepted.offset]
 
 
 def prob(dims=(8, 9, 10), rank=5, dt=L.CP_F64):
@@ -150,6 +157,25 @@ def test_call_validation_without_launch(lib):
     good = L.CpGnParams(1e-3, 1e-3, 20, 0)
     assert lib.cp_gn_step(C.byref(p), X, A, C.byref(good), None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_step(C.byref(p), X, A, C.byref(good), st, ws, need // 2, None) == L.CP_EWORKSPACE
+    # Armijo step control: null search parameters or stats, constants out of range
+    ls_st = C.c_void_p(0x70000)
+    ok_ls = L.CpArmijoParams(1e-4, 0.5, 10, 0)
+    assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), None, st, ls_st, ws, need,
+                                 None) == L.CP_EINVAL
+    assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), C.byref(ok_ls), st, None, ws,
+                                 need, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), C.byref(ok_ls), None, ls_st, ws,
+                                 need, None) == L.CP_EINVAL
+    for bad in [L.CpArmijoParams(0.0, 0.5, 10, 0), L.CpArmijoParams(1.0, 0.5, 10, 0),
+                L.CpArmijoParams(1e-4, 0.0, 10, 0), L.CpArmijoParams(1e-4, 1.0, 10, 0),
+                L.CpArmijoParams(float("nan"), 0.5, 10, 0), L.CpArmijoParams(1e-4, 0.5, -1, 0),
+                L.CpArmijoParams(1e-4, 0.5, 65, 0), L.CpArmijoParams(1e-4, 0.5, 10, 1)]:
+        assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), C.byref(bad), st, ls_st, ws,
+                                     need, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(L.CpGnParams(-1.0, 1e-3, 20, 0)),
+                                 C.byref(ok_ls), st, ls_st, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), C.byref(ok_ls), st, ls_st, ws,
+                                 need // 2, None) == L.CP_EWORKSPACE
     assert lib.cp_als_sweep(C.byref(p), X, A, -1.0, None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_residual(C.byref(p), X, A, 2, C.c_void_p(0x60000), ws, need, None) == L.CP_EINVAL
     assert lib.cp_residual(C.byref(p), X, A, 0, None, ws, need, None) == L.CP_EINVAL
@@ -159,6 +185,8 @@ def test_call_validation_without_launch(lib):
     pr = prob(rank=200)
     _, need2 = ws_bytes(lib, pr)
     assert lib.cp_gn_step(C.byref(pr), X, A, C.byref(good), st, ws, need2, None) == L.CP_EUNSUPPORTED
+    assert lib.cp_gn_step_armijo(C.byref(pr), X, A, C.byref(good), C.byref(ok_ls), st, ls_st, ws,
+                                 need2, None) == L.CP_EUNSUPPORTED
 
 
 def test_status_strings(lib):
