@@ -119,7 +119,7 @@ def mttkrp_times(P, Xd, A, reps, stream):
 # Valid only for the kernel source it was taken on.
 MTTKRP_TRAFFIC = {
     "source_sha256": "32a42572a3fcb157b60a2417ffaa6a8749962e8408b4cd73cb5c5b5d960ae69c",
-    "bytes_per_launch": 308227972,   # mean over the three modes of the main kernel
+    "bytes_per_launch": 308246963,   # mean over the three modes of the main kernel
 }
 
 
@@ -304,6 +304,18 @@ def main():
     for _ in range(2):
         P.als_sweep(Xd, Aals, 0.0, ws=ws_als)
     als_t = event_time(lambda: P.als_sweep(Xd, Aals, 0.0, ws=ws_als), 5, stream)
+
+    # ---- GN step with Armijo step control (Section 5): f at the start point and at every trial
+    # point is part of the step, so it also yields the residual of the new point
+    Aarm = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+    garm = P.GaussNewton(Xd, Aarm, P.GNConfig(cg_tol=1e-3, cg_maxiter=20, line_search=P.Armijo()))
+    for _ in range(2):
+        garm.step()
+    arm_t = event_time(garm.step, 5, stream)
+    arm_st = garm.stats()
+    del garm, Aarm
+    log(f"[bench] GN step with Armijo control: {arm_t * 1e3:.3f} ms "
+        f"(last step: {arm_st['ls_trials']} trial(s), alpha {arm_st['ls_alpha']})")
 
     # ---- GN steps: warmup, then K timed steps (GN step + direct residual)
     A = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
@@ -493,6 +505,10 @@ def main():
         "launch_floor_ms": floor * 1e3,
         "residual_ms": res_t * 1e3,
         "als_sweep_ms": als_t * 1e3,
+        "gn_armijo_step_ms": arm_t * 1e3,
+        "gn_armijo_last": {"trials": arm_st["ls_trials"], "alpha": arm_st["ls_alpha"],
+                           "note": "GN step with Armijo control (c 1e-4, shrink 0.5, <=10 trials), "
+                                   "f at the start and trial points included"},
         "cg_iters_mean": float(np.mean(iters)),
         "cg_iters": iters,
         "residual_after": r_now,
