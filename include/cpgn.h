@@ -31,8 +31,9 @@
  *     non-finite values) are written as a status code into device memory (the `status` field
  *     of cp_gn_stats, or `status_dev`); the caller reads it after synchronising the stream.
  *     On such a failure the factors are left unchanged.
- *   - cp_gn_step and cp_als_sweep need rank <= 128 (their R x R factorizations are held in one
- *     workgroup's registers) and return CP_EUNSUPPORTED otherwise; the other calls take any rank.
+ *   - The Gauss-Newton steps and cp_als_sweep need rank <= 208 (their R x R inverse is held in
+ *     one workgroup's registers, and so are the CG operand rows) and return CP_EUNSUPPORTED
+ *     otherwise; the other calls take any rank.
  *
  * Precision
  *   - x_dtype equals f_dtype, CP_F64 or CP_F32; or f_dtype = CP_F32 and x_dtype = CP_BF16 or
@@ -221,7 +222,7 @@ typedef struct cp_armijo_stats {
  *   ||alpha V||). ls_stats: DEVICE pointer to one cp_armijo_stats.
  *   ws: at least cp_workspace_bytes(CP_OP_GN_STEP).
  *   Errors: CP_EINVAL for null pointers or parameters out of range (before any launch);
- *   rank > 128: CP_EUNSUPPORTED.
+ *   rank > 208: CP_EUNSUPPORTED.
  */
 int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
                       const cp_gn_params* params, const cp_armijo_params* ls, cp_gn_stats* stats,

@@ -142,8 +142,10 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_slots = take(cg_slot_bytes(*p));
   p->off_krp = take((size_t)krp * 4);
   p->bytes = off;
-  // the T pass launches one grid row per row tile of s0 s1 (at most 65535)
-  if (p->N == 3 && p->xk == 0 && ttm_rows(*p) / (16 * (p->dtype == CP_F64 ? 2 : 4)) <= 65535)
+  // the T pass launches one grid row per row tile of s0 s1 (at most 65535); the contraction of
+  // T keeps one output row's R values in one workgroup's lanes (R <= 128)
+  if (p->N == 3 && p->xk == 0 && p->R <= 128 &&
+      ttm_rows(*p) / (16 * (p->dtype == CP_F64 ? 2 : 4)) <= 65535)
     p->t_bytes = align256((size_t)ttm_rows(*p) * p->Rp * p->esz);
   return CP_OK;
 }

@@ -13,6 +13,9 @@ namespace cpgn {
 constexpr int kWave = 64;
 constexpr int kMaxOrder = CP_MAX_ORDER;
 constexpr int kRedSlots = 1024;   // max blocks contributing to one deterministic reduction
+// Largest rank of the Gauss-Newton step and the ALS sweep: their R x R inverse and the CG
+// kernels' operand rows are held in registers, 16 columns per block, at most 13 blocks.
+constexpr int kMaxGnRank = 208;
 constexpr int kNumCU = 256;       // compute units of an MI355X (8 XCDs x 32)
 
 // ------------------------------------------------------------------------------------------

@@ -341,7 +341,7 @@ __global__ void k_status_out(const CgState* st, int32_t* out) {
 }
 
 // ------------------------------------------------------------------------------------------
-// P = (G + lambda I)^-1 for an R x R SPD matrix (R <= 128), one workgroup per matrix, FP64.
+// P = (G + lambda I)^-1 for an R x R SPD matrix (R <= 208), one workgroup per matrix, FP64.
 // In-place Gauss-Jordan inversion without pivoting: for an SPD matrix its pivots are the
 // Cholesky pivots (the diagonals of the successive Schur complements), so "pivot > 0" is the
 // same positive-definiteness test, and R steps give the inverse directly. Thread (ty, tx) of
@@ -938,8 +938,8 @@ void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, st, out);
 }
 
-// GN and ALS need R <= 128 (the inverse is register-resident in one workgroup).
-int spd_inv_supported(int R) { return R >= 1 && R <= 128; }
+// GN and ALS need R <= kMaxGnRank (the inverse is register-resident in one workgroup).
+int spd_inv_supported(int R) { return R >= 1 && R <= kMaxGnRank; }
 
 #ifndef CPGN_SPD_TD
 #define CPGN_SPD_TD 32
@@ -950,6 +950,21 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
   // Thread grid TD x TD, each thread an NBK x NBK block. 32 x 32 (1024 threads) measured faster
   // than 16 x 16 at R = 50, 100 and 128 (the same arithmetic, so the same bits).
   constexpr int TD = CPGN_SPD_TD;
+  if (R > 128) {
+    // 16 x 16 threads (one wavefront per SIMD), each a block of up to 13 x 13 entries: 255
+    // VGPRs and about 170 AGPRs at R = 208, no scratch.
+    switch ((R + 15) / 16) {
+#define CPGN_SPD16(k)                                                                         \
+  case k:                                                                                     \
+    hipLaunchKernelGGL((k_spd_inv<k, 16>), dim3(count), dim3(256), 0, s, R, G, g_stride,      \
+                       lambda, lam_dev, P, p_stride, first_mode, st, diag_damping ? 1 : 0);   \
+    break;
+      CPGN_SPD16(9) CPGN_SPD16(10) CPGN_SPD16(11) CPGN_SPD16(12) CPGN_SPD16(13)
+#undef CPGN_SPD16
+      default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+  }
   const int nbk = (R + TD - 1) / TD;
   switch (nbk) {
 #define CPGN_SPD(k)                                                                           \

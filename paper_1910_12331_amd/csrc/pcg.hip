@@ -525,6 +525,12 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
     case 6: launch_kb<6>(a, p.N, maxiter, s); break;
     case 7: launch_kb<7>(a, p.N, maxiter, s); break;
     case 8: launch_kb<8>(a, p.N, maxiter, s); break;
+    // 128 < R <= 208: operand rows of up to 52 doubles per lane (no scratch; part in AGPRs)
+    case 9: launch_kb<9>(a, p.N, maxiter, s); break;
+    case 10: launch_kb<10>(a, p.N, maxiter, s); break;
+    case 11: launch_kb<11>(a, p.N, maxiter, s); break;
+    case 12: launch_kb<12>(a, p.N, maxiter, s); break;
+    case 13: launch_kb<13>(a, p.N, maxiter, s); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

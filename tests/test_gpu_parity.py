@@ -237,11 +237,30 @@ def test_gn_step_diagonal_damping_fixed_iterations_fp64(maxiter):
 
 
 @pytest.mark.parametrize("damping", ["identity", "diagonal"])
-def test_gn_step_high_rank_rank_exceeds_mode_size(damping):
-    """The high-rank regime of Section 5 (s = 80, R = 120 > s): each Gram has rank 80 < R, the
-    damped systems stay SPD. CG with the tolerance test, both damping forms, FP64."""
-    p = make_problem((80, 80, 80), 120, workload=0, problem=120, noise=1e-2)
+@pytest.mark.parametrize("dims,rank", [((80, 80, 80), 120), ((60, 50, 70), 150),
+                                       ((150, 150, 150), 200)])
+def test_gn_step_high_rank_rank_exceeds_mode_size(dims, rank, damping):
+    """The high-rank regime of Section 5 (s = 80, R = 120 and s = 150, R = 200, both above the
+    mode sizes): each Gram has rank s < R, the damped systems stay SPD. Above R = 128 the inverse
+    and the CG operand rows take 9 to 13 register blocks of 16 columns. CG with the tolerance
+    test, both damping forms, FP64."""
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
     gn_compare(p, torch.float64, 1e-2, 1e-3, 20, "sensitivity", damping=damping)
+
+
+@pytest.mark.parametrize("dims,rank", [((60, 50, 70), 150), ((150, 150, 150), 200)])
+def test_als_sweep_high_rank(dims, rank):
+    """ALS above R = 128 (each mode takes its own pass over X; the inverse has 13 register
+    blocks at R = 200), held to 10x the oracle's own spread under a 1e-15 input perturbation."""
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
+    Ad = to_dev(p.init, torch.float64)
+    status = P.als_sweep(to_dev([p.x], torch.float64)[0], Ad, 1e-2)
+    assert int(status.item()) == 0
+    ref = O.als_sweep(p.x, p.init, 1e-2)
+    rng = np.random.default_rng(2)
+    ref2 = O.als_sweep(p.x, [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in p.init], 1e-2)
+    for a, r, r2 in zip(host(Ad), ref, ref2):
+        assert rel(a, r) < max(1e-12, 10 * rel(r2, r))
 
 
 def test_gn_step_past_cg_rounding_floor_fp64():
