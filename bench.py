@@ -215,6 +215,32 @@ def order4_leg(P, torch, reps, stream):
                 hbm_peak_gbs=PEAK_HBM_GBS, **out)
 
 
+def high_rank_leg(P, torch, stream):
+    """Section 5's high-rank regime at s = 150, R = 200 (R above every mode size), FP64: one
+    Gauss-Newton step, one ALS sweep and the direct residual, HIP-event timed."""
+    from workloads import make_problem
+    p = make_problem((150, 150, 150), 200, workload=0, problem=200, noise=1e-2)
+    X = torch.tensor(p.x, dtype=torch.float64, device="cuda")
+    gn = P.GaussNewton(X, [torch.tensor(a, device="cuda") for a in p.init],
+                       P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    for _ in range(2):
+        gn.step()
+    t_gn = event_time(gn.step, 5, stream)
+    cg_iters = gn.stats()["cg_iters"]
+    als = P.ALS(X, [torch.tensor(a, device="cuda") for a in p.init], 1e-2)
+    als.step()
+    t_als = event_time(als.step, 5, stream)
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    P.residual(X, gn.A, out=out, ws=gn.ws)
+    t_res = event_time(lambda: P.residual(X, gn.A, out=out, ws=gn.ws), 5, stream)
+    log(f"[bench] 150^3 R=200 FP64: GN step {t_gn * 1e3:.3f} ms ({cg_iters} CG its last step), "
+        f"ALS sweep {t_als * 1e3:.3f} ms, direct residual {t_res * 1e3:.3f} ms")
+    return {"workload": "dense 150^3 FP64 tensor, rank-200 CP with N(0,1) factors, noise 1e-2; "
+                        "rank 200 > s (Section 5's high-rank regime)",
+            "gn_step_ms": t_gn * 1e3, "gn_cg_iters_last": cg_iters, "als_sweep_ms": t_als * 1e3,
+            "residual_ms": t_res * 1e3}
+
+
 def kernel_source_hash():
     import hashlib
     path = os.path.join(ROOT, "paper_1910_12331_amd", "csrc", "mttkrp.hip")
@@ -316,6 +342,8 @@ def main():
     del garm, Aarm
     log(f"[bench] GN step with Armijo control: {arm_t * 1e3:.3f} ms "
         f"(last step: {arm_st['ls_trials']} trial(s), alpha {arm_st['ls_alpha']})")
+
+    high_rank = high_rank_leg(P, torch, stream)
 
     # ---- GN steps: warmup, then K timed steps (GN step + direct residual)
     A = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
@@ -509,6 +537,7 @@ def main():
         "gn_armijo_last": {"trials": arm_st["ls_trials"], "alpha": arm_st["ls_alpha"],
                            "note": "GN step with Armijo control (c 1e-4, shrink 0.5, <=10 trials), "
                                    "f at the start and trial points included"},
+        "high_rank_150_r200_fp64": high_rank,
         "cg_iters_mean": float(np.mean(iters)),
         "cg_iters": iters,
         "residual_after": r_now,

@@ -529,6 +529,9 @@ __device__ __forceinline__ void x_at4(const void* X, int64_t e, int64_t plane, T
 template <typename T> struct ResCfg;
 template <> struct ResCfg<float> { static constexpr int MB = 3, OCC = 2; };
 template <> struct ResCfg<double> { static constexpr int MB = 2, OCC = 1; };
+// Sub-tiles per wavefront: one above 8 column blocks (R > 128), where the Khatri-Rao rows alone
+// take 4 NBR registers per sub-tile and lane.
+template <typename T> constexpr int res_mb(int nbr) { return nbr > 8 ? 1 : ResCfg<T>::MB; }
 
 template <typename T, int MB>
 struct ResX {
@@ -541,7 +544,7 @@ struct ResX {
 // (VX). FP64 keeps the direct form (its accumulator layout strides rows by 4).
 template <typename T, int NBR, bool VX, int XK>
 __global__ __launch_bounds__(256, ResCfg<T>::OCC) void k_residual(ResArgs a) {
-  constexpr int MB = ResCfg<T>::MB;
+  constexpr int MB = res_mb<T>(NBR);
   constexpr bool SWAP = sizeof(T) == 4;
   constexpr int RS = 4 * NBR;          // MFMA steps (R padded to 16 NBR, 4 per step)
   constexpr int BSH = RS * kWave / 256;   // B elements per thread per item (= NBR)
@@ -763,7 +766,7 @@ __global__ void k_pack_last(const T* __restrict__ apad_last, int64_t K, int Rp, 
   }
 }
 
-// Fallback for R > 128: one thread per tensor entry, scalar FP64 reconstruction.
+// Fallback for R > 208: one thread per tensor entry, scalar FP64 reconstruction.
 template <typename T, int XK>
 __global__ void k_residual_scalar(ResArgs a, int R) {
   if (a.skip && *a.skip) return;
@@ -985,7 +988,7 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
 template <typename T, int XK>
 static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out, hipStream_t s,
                              const int32_t* skip, int* nblocks) {
-  constexpr int MB = ResCfg<T>::MB;
+  const int MB = res_mb<T>(p.NBt);
   ResArgs a{};
   a.X = X;
   a.skip = skip;
@@ -1002,7 +1005,7 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
   a.O = p.total / a.K;
   a.KB = (a.K + 15) / 16;
   a.red = (double*)(ws + p.off_red);
-  if (p.R <= 128) {
+  if (p.R <= kMaxGnRank) {
     // the packed last factor reuses the MTTKRP partial region
     a.bpk = ws + p.off_part;
     hipLaunchKernelGGL(k_pack_last<T>, dim3(grid1(a.KB * p.Rp / 4 * kWave, 1024)), dim3(256), 0,
@@ -1019,7 +1022,7 @@ static int launch_residual_t(const Plan& p, const void* X, char* ws, double* out
     else hipLaunchKernelGGL((k_residual<T, k, false, XK>), dim3(blocks), dim3(256), 0, s, a);   \
     break;
       CPGN_RES(1) CPGN_RES(2) CPGN_RES(3) CPGN_RES(4) CPGN_RES(5) CPGN_RES(6) CPGN_RES(7)
-      CPGN_RES(8)
+      CPGN_RES(8) CPGN_RES(9) CPGN_RES(10) CPGN_RES(11) CPGN_RES(12) CPGN_RES(13)
 #undef CPGN_RES
       default: break;
     }

@@ -105,6 +105,16 @@ def test_armijo_step_fp64(dims, rank, scale, seed, alpha):
     assert ref.alpha == alpha and ls["f"] < ls["f0"]
 
 
+@pytest.mark.parametrize("dims,rank,scale,seed,alpha", [((30, 26, 35), 150, 0.3, 1, 0.5),
+                                                        ((40, 30, 36), 200, 0.2, 3, 0.25)])
+def test_armijo_step_high_rank_fp64(dims, rank, scale, seed, alpha):
+    """Above R = 128 (13 register blocks of 16 columns at R = 200); the oracle's own spread under
+    a 1e-15 input perturbation is about 3e-13 here."""
+    X, A = small_start(dims, rank, scale, seed)
+    ref, _ = armijo_compare(X, A, torch.float64, 1e-6, 1e-3, 50)
+    assert ref.alpha == alpha
+
+
 @pytest.mark.parametrize("dims,rank,scale,seed", [((37, 29, 45), 12, 0.3, 2),
                                                   ((9, 11, 7, 13), 5, 0.3, 2),
                                                   ((30, 26, 35), 70, 0.1, 1)])

@@ -355,8 +355,11 @@ def test_als_sweep_config2_fp64():
 
 
 # ------------------------------------------------------------------------------------ residual
+# R = 130, 200, 208: the MFMA kernel with 9 to 13 column blocks (one 16-row sub-tile per
+# wavefront); R = 230: the scalar kernel.
 RES_CASES = [((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4),
-             ((12, 10, 9), 130), ((24, 20, 18), 100)]
+             ((12, 10, 9), 130), ((24, 20, 18), 100), ((23, 19, 41), 200),
+             ((9, 11, 7, 13), 208), ((14, 12, 10), 230)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
