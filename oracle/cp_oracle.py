@@ -36,7 +36,7 @@ __all__ = [
     "objective", "gradient", "jtj_matvec", "preconditioner", "pcg", "PCGResult", "gn_step",
     "GNStepStats", "LambdaSchedule", "als_sweep", "residual", "residual_expansion", "gn", "als",
     "jacobian", "jtj_dense", "flatten_factors", "unflatten_factors", "OracleError",
-    "damping_matrix", "gn_step_armijo", "ArmijoResult",
+    "damping_matrix", "gn_step_armijo", "ArmijoResult", "cholesky_factors", "cholesky_apply",
 ]
 
 
@@ -198,6 +198,26 @@ def preconditioner(Gam, lam, damping="identity"):
     return out
 
 
+def cholesky_factors(Gam, lam, damping="identity"):
+    """Lower Cholesky factors L(n) of Gamma(n,n) + lam D(n), for the preconditioner applied by
+    triangular solves (the alternative Section 3.3 describes and sets aside for its parallel
+    depth). Raises OracleError when the shifted matrix is not SPD."""
+    out = []
+    for n in range(len(Gam)):
+        g = Gam[n][n] + lam * damping_matrix(Gam, n, damping)
+        try:
+            out.append(scipy.linalg.cholesky(g, lower=True))
+        except np.linalg.LinAlgError as e:
+            raise OracleError(f"Gamma({n},{n}) + lambda I is not positive definite") from e
+    return out
+
+
+def cholesky_apply(L, Rn):
+    """Z = R (L L^T)^-1 row by row: the forward solve L y = r^T, then the back solve L^T z = y."""
+    y = scipy.linalg.solve_triangular(L, Rn.T, lower=True)
+    return scipy.linalg.solve_triangular(L.T, y, lower=False).T
+
+
 def _fro(m):
     return math.sqrt(float(np.sum(m * m)))
 
@@ -217,7 +237,7 @@ class PCGResult:
     history: list = field(default_factory=list)
 
 
-def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity"):
+def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity", precond="inverse"):
     """Algorithm 2 (CP-CG): preconditioned implicit CG for (J^T J + lam D) V = -G, with D the
     identity or (damping == "diagonal") the diagonal of J^T J.
 
@@ -228,14 +248,24 @@ def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity"):
 
     beta uses the standard preconditioned-CG ratio (the printed denominator sum<W,Q> is read as
     a typo). A non-positive curvature sum<W,Q> <= 0 raises OracleError.
+
+    precond="cholesky" applies the same preconditioner by triangular solves with the Cholesky
+    factor of Gamma(n,n) + lam D(n) instead of multiplying by its explicit inverse.
     """
     N = len(A)
     if Gam is None:
         Gam = gamma_set(grams(A))
-    P = preconditioner(Gam, lam, damping)
+    if precond == "inverse":
+        P = preconditioner(Gam, lam, damping)
+        apply = lambda n, Rn: Rn @ P[n]   # noqa: E731
+    elif precond == "cholesky":
+        Lf = cholesky_factors(Gam, lam, damping)
+        apply = lambda n, Rn: cholesky_apply(Lf[n], Rn)   # noqa: E731
+    else:
+        raise ValueError(precond)
     V = [np.zeros_like(g) for g in G]
     R = [-g for g in G]
-    Z = [R[n] @ P[n] for n in range(N)]
+    Z = [apply(n, R[n]) for n in range(N)]
     W = [z.copy() for z in Z]
     gsum = sum(_fro(g) for g in G)
     rz = sum(_inner(R[n], Z[n]) for n in range(N))
@@ -252,7 +282,7 @@ def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity"):
         for n in range(N):
             V[n] = V[n] + alpha * W[n]
             R[n] = R[n] - alpha * Q[n]
-            Z[n] = R[n] @ P[n]
+            Z[n] = apply(n, R[n])
         rz_new = sum(_inner(R[n], Z[n]) for n in range(N))
         beta = rz_new / rz
         for n in range(N):
@@ -276,7 +306,7 @@ class GNStepStats:
     update_norm: float
 
 
-def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity"):
+def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity", precond="inverse"):
     """One loop body of Algorithm 1 (CP-GN): all M(n) at the current point, Gamma(n,p),
     G(n) = A(n) Gamma(n,n) - M(n), V = CP-CG(G, A, Gamma, eps_cg, lam), A(n) += V(n).
 
@@ -287,7 +317,7 @@ def gn_step(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity"):
     Gam = gamma_set(S)
     M = [mttkrp(X, A, n) for n in range(N)]
     G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
-    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping)
+    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping, precond)
     newA = [A[n] + res.V[n] for n in range(N)]
     upd = math.sqrt(sum(float(np.sum(v * v)) for v in res.V))
     return newA, GNStepStats(cg_iters=res.iters, grad_norm_sum=res.grad_norm_sum,

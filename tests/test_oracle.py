@@ -535,3 +535,38 @@ def test_armijo_without_descent_direction_or_passing_trial_keeps_factors():
     assert not one.accepted and one.alpha == 0.0 and one.trials == 1 and one.f == one.f0
     for res in (none, one):
         assert all(np.array_equal(a, b) for a, b in zip(res.A, A))
+
+
+# ---------------------------------------------------------------- Cholesky preconditioner
+@pytest.mark.parametrize("k", [1, 3, 7])
+@pytest.mark.parametrize("damping", ["identity", "diagonal"])
+def test_pcg_cholesky_preconditioner_matches_dense(k, damping):
+    """The preconditioner applied by triangular solves (Section 3.3's alternative) gives the
+    iterates of textbook dense PCG with the block-diagonal preconditioner."""
+    dims, rank, lam = (3, 4, 3), 2, 0.05
+    A = factors(dims, rank, 23)
+    X = rnd(dims, 24)
+    G = O.gradient(X, A)
+    res = O.pcg(G, A, lam, eps_cg=0.0, maxiter=k, damping=damping, precond="cholesky")
+    assert res.iters == k
+    J = O.jtj_dense(A)
+    D = np.diag(np.diag(J)) if damping == "diagonal" else np.eye(J.shape[0])
+    H = J + lam * D
+    n = H.shape[0]
+    P = np.zeros((n, n))
+    offs = np.cumsum([0] + [s * rank for s in dims])
+    for m in range(len(dims)):
+        sl = slice(offs[m], offs[m + 1])
+        P[sl, sl] = np.linalg.inv(J[sl, sl] + lam * D[sl, sl])   # the diagonal block of H
+    ref = _dense_pcg(H, P, O.flatten_factors(G), k)
+    assert rel(O.flatten_factors(res.V), ref) < 1e-11
+
+
+def test_cholesky_apply_is_a_solve():
+    rng = np.random.default_rng(25)
+    B = rng.standard_normal((6, 6))
+    M = B @ B.T + 6 * np.eye(6)
+    L = O.cholesky_factors([[M]], 0.0)[0]
+    assert np.allclose(L, np.tril(L)) and rel(L @ L.T, M) < 1e-15
+    Rn = rng.standard_normal((9, 6))
+    assert rel(O.cholesky_apply(L, Rn), np.linalg.solve(M, Rn.T).T) < 1e-14
