@@ -98,6 +98,11 @@ enum { CP_RESIDUAL_DIRECT = 0, CP_RESIDUAL_EXPANSION = 1 };
    (eq. (5)), so the CG system becomes (J^T J + lambda D) V = -G with D^(n) = diag(Gamma^(n,n)),
    and the preconditioner (Gamma^(n,n) + lambda diag(Gamma^(n,n)))^-1. */
 #define CP_GN_DIAG_DAMPING 1u
+/* CP_GN_CHOL_PRECOND: apply the preconditioner (Gamma^(n,n) + lambda D^(n))^-1 by a forward and a
+   back triangular solve with its Cholesky factor instead of multiplying by its explicit inverse
+   (the alternative Section 3.3 describes and sets aside for its parallel depth: each solve is
+   sequential in R). Same CG iterates up to rounding; rank <= 128 (CP_EUNSUPPORTED above). */
+#define CP_GN_CHOL_PRECOND 2u
 
 typedef struct {
   int32_t order;                 /* N, 2 <= N <= CP_MAX_ORDER                               */
@@ -111,7 +116,7 @@ typedef struct {
   double lambda;                 /* Tikhonov damping of J^T J + lambda I (>= 0), Section 3.2 */
   double cg_tol;                 /* eps_cg: CG runs while sum||R(n)|| > eps_cg sum||G(n)||   */
   int32_t cg_maxiter;            /* cap on CG iterations (>= 0)                              */
-  uint32_t flags;                /* 0 or CP_GN_DIAG_DAMPING; other bits must be 0            */
+  uint32_t flags;                /* CP_GN_DIAG_DAMPING | CP_GN_CHOL_PRECOND; others must be 0 */
 } cp_gn_params;
 
 /* Written to DEVICE memory by cp_gn_step. */

@@ -13,6 +13,7 @@ CP_OK, CP_EINVAL, CP_EUNSUPPORTED, CP_EWORKSPACE, CP_EHIP = 0, -1, -2, -3, -4
 CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
 OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL, OP_MTTKRP_ALL = range(7)
 GN_DIAG_DAMPING = 1
+GN_CHOL_PRECOND = 2
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",

@@ -237,10 +237,22 @@ def read_stats(buf: torch.Tensor) -> dict:
     return {f: getattr(s, f) for f in STATS_FIELDS}
 
 
+def _gn_flags(damping: str, preconditioner: str) -> int:
+    if damping not in ("identity", "diagonal"):
+        raise ValueError("damping must be 'identity' or 'diagonal'")
+    if preconditioner not in ("inverse", "cholesky"):
+        raise ValueError("preconditioner must be 'inverse' or 'cholesky'")
+    return ((L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+            | (L.GN_CHOL_PRECOND if preconditioner == "cholesky" else 0))
+
+
 def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
-            cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity"):
+            cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity",
+            preconditioner: str = "inverse"):
     """One Algorithm 1 step in place on A; returns the device stats buffer (cp_gn_stats).
-    damping: "identity" (lam I) or "diagonal" (lam diag(J^T J), Section 3.2)."""
+    damping: "identity" (lam I) or "diagonal" (lam diag(J^T J), Section 3.2).
+    preconditioner: "inverse" (explicit inverse, Section 3.3) or "cholesky" (triangular solves
+    with the Cholesky factor, R <= 128)."""
     if damping not in ("identity", "diagonal"):
         raise ValueError("damping must be 'identity' or 'diagonal'")
     _dev(X, "X")
@@ -248,7 +260,7 @@ def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: floa
     _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
-                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+                       _gn_flags(damping, preconditioner))
     if stats is None:
         stats = stats_buffer(X.device)
     w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
@@ -272,7 +284,7 @@ def read_armijo_stats(buf: torch.Tensor) -> dict:
 def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
                    cg_maxiter: int = 20, c: float = 1e-4, shrink: float = 0.5,
                    max_trials: int = 10, stats=None, ls_stats=None, ws=None,
-                   damping: str = "identity"):
+                   damping: str = "identity", preconditioner: str = "inverse"):
     """Gauss-Newton step with Armijo step-size control (Section 5), in place on A: the direction
     of gn_step, then the first of alpha = 1, shrink, shrink^2, ... (at most max_trials) with
     f(A + alpha V) <= f(A) + c alpha <G, V>. Returns (stats buffer, Armijo stats buffer), both on
@@ -284,7 +296,7 @@ def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_to
     _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
-                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+                       _gn_flags(damping, preconditioner))
     ls = L.CpArmijoParams(float(c), float(shrink), int(max_trials), 0)
     if stats is None:
         stats = stats_buffer(X.device)
@@ -298,7 +310,8 @@ def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_to
 
 
 def gn_step_devlam(X, A: Sequence[torch.Tensor], lam_dev: torch.Tensor, cg_tol: float = 1e-3,
-                   cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity"):
+                   cg_maxiter: int = 20, stats=None, ws=None, damping: str = "identity",
+                   preconditioner: str = "inverse"):
     """gn_step with the damping read from device memory (lam_dev: a one-element float64 GPU
     tensor) when the step runs, so that a captured graph of the step follows a changing lambda."""
     if damping not in ("identity", "diagonal"):
@@ -309,7 +322,7 @@ def gn_step_devlam(X, A: Sequence[torch.Tensor], lam_dev: torch.Tensor, cg_tol: 
     _factors(A, X.shape, factor_dtype(X), R)
     prob = _problem(X, R)
     prm = L.CpGnParams(0.0, float(cg_tol), int(cg_maxiter),
-                       L.GN_DIAG_DAMPING if damping == "diagonal" else 0)
+                       _gn_flags(damping, preconditioner))
     if stats is None:
         stats = stats_buffer(X.device)
     w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)

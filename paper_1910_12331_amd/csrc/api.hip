@@ -24,6 +24,8 @@ void launch_status_out(const CgState*, int32_t*, hipStream_t);
 int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
                    hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr);
+int launch_spd_chol(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
+                    hipStream_t, bool diag_damping, const double* lam_dev);
 void launch_damping_advance(double*, hipStream_t);
 void launch_ls_gv(const Dims&, const double*, const double*, double*, CgState*, hipStream_t);
 void launch_ls_init(int, const double*, CgState*, hipStream_t);
@@ -42,7 +44,7 @@ int launch_prepare_factors_src(const Plan&, const void* const*, int, void*, hipS
 size_t cg_slot_bytes(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
               double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
-              double, int, bool, hipStream_t, const double* lam_dev = nullptr);
+              double, int, bool, hipStream_t, const double* lam_dev = nullptr, bool chol = false);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 int64_t ttm_rows(const Plan&);
@@ -398,9 +400,10 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
     return CP_EINVAL;
   if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
   if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
-      (prm->flags & ~CP_GN_DIAG_DAMPING) != 0)
+      (prm->flags & ~(CP_GN_DIAG_DAMPING | CP_GN_CHOL_PRECOND)) != 0)
     return CP_EINVAL;
   if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
+  if ((prm->flags & CP_GN_CHOL_PRECOND) && p.R > 128) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);
@@ -414,12 +417,17 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
   gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
   // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
   const bool diag = (prm->flags & CP_GN_DIAG_DAMPING) != 0;
-  launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
-                 lam_dev);
+  const bool chol = (prm->flags & CP_GN_CHOL_PRECOND) != 0;
+  if (chol)   // Cholesky factors in place of the inverse, applied by triangular solves in CG
+    launch_spd_chol(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
+                    lam_dev);
+  else
+    launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
+                   lam_dev);
   // CG: three launches per iteration, scalars kept on the device.
   launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
             (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, lam,
-            prm->cg_maxiter, diag, st, lam_dev);
+            prm->cg_maxiter, diag, st, lam_dev, chol);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
   if (!ls) {

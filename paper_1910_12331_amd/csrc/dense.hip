@@ -458,6 +458,102 @@ __global__ __launch_bounds__(TD * TD) void k_spd_inv(int R, const double* __rest
 }
 
 // ------------------------------------------------------------------------------------------
+// Lower Cholesky factor L of G + lambda I (or G + lambda diag(G)), R <= 128, for the
+// preconditioner applied by triangular solves (the alternative to the explicit inverse that
+// Section 3.3 describes). Same thread layout as k_spd_inv: thread (ty, tx) keeps the entries
+// (ty + TD ai, tx + TD bk) in registers. Step j publishes column j through double-buffered LDS
+// (one barrier), sets L[j][j] = sqrt(p), L[i][j] = c_i / sqrt(p) below it, and updates the
+// trailing block a_ik -= c_i c_k / p (right-looking Cholesky). Entries above the diagonal are
+// written as 0. A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done.
+// ------------------------------------------------------------------------------------------
+template <int NBK, int TD>
+__global__ __launch_bounds__(TD * TD) void k_spd_chol(int R, const double* __restrict__ Gin,
+                                                  int64_t g_stride, double lambda,
+                                                  const double* __restrict__ lam_dev,
+                                                  double* __restrict__ Lout, int64_t l_stride,
+                                                  int first_mode, CgState* st, int diag_damping) {
+  constexpr int RP = TD * NBK;
+  __shared__ double colbuf[2][RP];
+  __shared__ int sbad;
+  const int n = first_mode + blockIdx.x;
+  const double* G = Gin + n * g_stride;
+  double* L = Lout + n * l_stride;
+  const int t = threadIdx.x, tx = t % TD, ty = t / TD;
+  if (lam_dev) lambda = *lam_dev;
+  if (t == 0) {
+    sbad = st->status != CP_OK;
+    if (!sbad && (!(lambda >= 0.0) || !isfinite(lambda))) {
+      st->status = CP_EINVAL;
+      st->done = 1;
+      sbad = 1;
+    }
+  }
+  __syncthreads();
+  if (sbad) return;
+  double a[NBK][NBK];
+#pragma unroll
+  for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+    for (int bk = 0; bk < NBK; ++bk) {
+      const int i = ty + TD * ai, k = tx + TD * bk;
+      a[ai][bk] = (i < R && k < R)
+                      ? G[i * R + k] + (i == k ? (diag_damping ? lambda * G[i * R + i] : lambda) : 0.0)
+                      : (i == k ? 1.0 : 0.0);
+    }
+  for (int j = 0; j < R; ++j) {
+    const int b = j & 1, jb = j / TD, jt = j % TD;
+    if (tx == jt) {
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk)
+        if (bk == jb) {
+#pragma unroll
+          for (int ai = 0; ai < NBK; ++ai) colbuf[b][ty + TD * ai] = a[ai][bk];
+        }
+    }
+    __syncthreads();
+    const double piv = colbuf[b][j];
+    if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
+      if (t == 0) {
+        st->status = CP_ENOTSPD;
+        st->done = 1;
+      }
+      return;
+    }
+    const double d = sqrt(piv);
+    double u[NBK], v[NBK];
+#pragma unroll
+    for (int q = 0; q < NBK; ++q) {
+      const int i = ty + TD * q, k = tx + TD * q;
+      u[q] = i > j ? colbuf[b][i] / piv : 0.0;
+      v[q] = k > j ? colbuf[b][k] : 0.0;
+    }
+#pragma unroll
+    for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk) a[ai][bk] -= u[ai] * v[bk];
+    if (tx == jt) {   // column j of L: rows below the pivot, and the pivot itself
+#pragma unroll
+      for (int bk = 0; bk < NBK; ++bk)
+        if (bk == jb) {
+#pragma unroll
+          for (int ai = 0; ai < NBK; ++ai) {
+            const int i = ty + TD * ai;
+            if (i > j) a[ai][bk] = colbuf[b][i] / d;
+            else if (i == j) a[ai][bk] = d;
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+    for (int bk = 0; bk < NBK; ++bk) {
+      const int i = ty + TD * ai, k = tx + TD * bk;
+      if (i < R && k < R) L[i * R + k] = k <= i ? a[ai][bk] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Direct residual ||X - [[A]]||_F^2 and ||X||_F^2 (Section 5). The reconstruction tile
 // Xt[o][k] = sum_r KRP(o, r) A(N)[k, r] (o runs over all modes but the last) is built on the
 // matrix cores: the Khatri-Rao rows of a 16*MB-row tile stay in registers as A operands, the
@@ -980,6 +1076,23 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
     CPGN_SPD(5) CPGN_SPD(6) CPGN_SPD(7) CPGN_SPD(8)
 #endif
 #undef CPGN_SPD
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+// Cholesky factors of all modes' G + lambda I in one launch (R <= 128; 32 x 32 threads).
+int launch_spd_chol(int R, const double* G, int64_t g_stride, double lambda, double* L,
+                    int64_t l_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                    bool diag_damping, const double* lam_dev) {
+  switch ((R + 31) / 32) {
+#define CPGN_CHOL(k)                                                                          \
+  case k:                                                                                     \
+    hipLaunchKernelGGL((k_spd_chol<k, 32>), dim3(count), dim3(1024), 0, s, R, G, g_stride,    \
+                       lambda, lam_dev, L, l_stride, first_mode, st, diag_damping ? 1 : 0);   \
+    break;
+    CPGN_CHOL(1) CPGN_CHOL(2) CPGN_CHOL(3) CPGN_CHOL(4)
+#undef CPGN_CHOL
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

@@ -167,7 +167,9 @@ __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, do
 // rewritten). Otherwise alpha = rho / sum <W,Q> from k_cg_matvec's partials.
 // grid: nslot workgroups of 256 threads; block b covers row block b / TB, columns 16 (b % TB).
 // ---------------------------------------------------------------------------------------------
-template <int KB, bool INIT, bool EVEN>
+// CHOL: the preconditioner is applied afterwards by k_cg_trsv (triangular solves); this kernel
+// then writes V, R_new and the norm partials only.
+template <int KB, bool INIT, bool EVEN, bool CHOL>
 __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   constexpr int KQ = 4 * KB;    // MFMA steps (k values per lane)
   constexpr int KP = 16 * KB;   // padded contraction length
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     const int e = t + 256 * i, k = e >> 4, c = e & 15;
-    ps[i] = (k < R && c0 + c < R) ? P[(int64_t)k * R + c0 + c] : 0.0;
+    ps[i] = (!CHOL && k < R && c0 + c < R) ? P[(int64_t)k * R + c0 + c] : 0.0;
   }
   // This lane's outputs: rows k0 + g + 4v, column c0 + m.
   const bool colok = c0 + m < R;
@@ -243,9 +245,11 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   }
   __syncthreads();
   dv4 acc = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (!CHOL) {
 #pragma unroll
-  for (int j = 0; j < KQ; ++j)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ro[j], Ps[sidx(kstep(j, g), m)], acc, 0, 0, 0);
+    for (int j = 0; j < KQ; ++j)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ro[j], Ps[sidx(kstep(j, g), m)], acc, 0, 0, 0);
+  }
   double dot = 0.0, nrm = 0.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -259,17 +263,80 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
         a.V[e] = __fma_rn(alpha, wd[v], vd[v]);
         Rout[e] = rn;
       }
-      a.Z[e] = acc[v];
-      dot += acc[v] * rn;
+      if constexpr (!CHOL) {
+        a.Z[e] = acc[v];
+        dot += acc[v] * rn;
+      }
       nrm += rn * rn;
     }
   }
   double v2[2] = {dot, nrm};
   block_sum(v2);
   if (t == 0) {
-    a.slot_rz[blockIdx.x] = v2[0];
+    if constexpr (!CHOL) a.slot_rz[blockIdx.x] = v2[0];
     a.slot_nrm[blockIdx.x] = v2[1];
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// k_cg_trsv: Z = R (L L^T)^-1 for one 64-row block of a mode, L the lower Cholesky factor of
+// Gamma(n,n) + lambda D (stored in a.pinv). One wavefront; lane k solves row k: the forward solve
+// L y = r^T, then the back solve L^T z = y, each entry (r_i - sum_j L_ij y_j) / L_ii with the sum
+// split over four accumulators. y lives in LDS column-major ([i][lane], 64 KB at R = 128, no bank
+// conflicts); L is read from global memory at wave-uniform addresses. The block's <R, Z> goes to
+// its first column-tile slot and 0 to the others (the slot layout of k_cg_update). R <= 128.
+// R_new is Rv[(it + 1) & 1], or Rv[0] for the initialisation.
+// ---------------------------------------------------------------------------------------------
+template <bool INIT>
+__global__ __launch_bounds__(64) void k_cg_trsv(CgArgs a, int it) {
+  __shared__ double Ys[128 * 64];
+  const int R = a.d.R, t = threadIdx.x;
+  const int rb = blockIdx.x;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows;
+  const int rows = (int)(s - k0 < kCgRows ? s - k0 : kCgRows);
+  const double* Rin = INIT ? a.Rv[0] : a.Rv[(it + 1) & 1];
+  // No workgroup of this launch writes the flag, so every lane reads the same value; the
+  // workgroup is one wavefront and Ys takes all 64 KB of its LDS (no barrier, no other LDS).
+  if (__builtin_amdgcn_readfirstlane(__builtin_nontemporal_load(&a.st->done)) != 0) return;
+  const double* L = a.pinv + (int64_t)n * R * R;
+  double dot = 0.0;
+  if (t < rows) {
+    const int64_t row = (a.d.off[n] + k0 + t) * R;
+    for (int i = 0; i < R; ++i) {   // forward: L y = r
+      const double* Li = L + (int64_t)i * R;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = 0;
+      for (; j + 3 < i; j += 4) {
+        s0 = fma(Li[j], Ys[j * 64 + t], s0);
+        s1 = fma(Li[j + 1], Ys[(j + 1) * 64 + t], s1);
+        s2 = fma(Li[j + 2], Ys[(j + 2) * 64 + t], s2);
+        s3 = fma(Li[j + 3], Ys[(j + 3) * 64 + t], s3);
+      }
+      for (; j < i; ++j) s0 = fma(Li[j], Ys[j * 64 + t], s0);
+      Ys[i * 64 + t] = (Rin[row + i] - ((s0 + s1) + (s2 + s3))) / Li[i];
+    }
+    for (int i = R - 1; i >= 0; --i) {   // back: L^T z = y (column i of L below the diagonal)
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = i + 1;
+      for (; j + 3 < R; j += 4) {
+        s0 = fma(L[(int64_t)j * R + i], Ys[j * 64 + t], s0);
+        s1 = fma(L[(int64_t)(j + 1) * R + i], Ys[(j + 1) * 64 + t], s1);
+        s2 = fma(L[(int64_t)(j + 2) * R + i], Ys[(j + 2) * 64 + t], s2);
+        s3 = fma(L[(int64_t)(j + 3) * R + i], Ys[(j + 3) * 64 + t], s3);
+      }
+      for (; j < R; ++j) s0 = fma(L[(int64_t)j * R + i], Ys[j * 64 + t], s0);
+      const double z = (Ys[i * 64 + t] - ((s0 + s1) + (s2 + s3))) / L[(int64_t)i * R + i];
+      Ys[i * 64 + t] = z;
+      a.Z[row + i] = z;
+      dot = fma(z, Rin[row + i], dot);
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o);   // same bits in every lane
+  if (t == 0)
+    for (int c = 0; c < a.TB; ++c) a.slot_rz[rb * a.TB + c] = c == 0 ? dot : 0.0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -469,28 +536,40 @@ size_t cg_slot_bytes(const Plan& p) {
   return (size_t)3 * cg_row_blocks(p) * cg_tiles(p) * sizeof(double);
 }
 
-template <int KB, bool EVEN>
+template <int KB, bool EVEN, bool CHOL>
 static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<KB, true, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, 0);
+  const int nrb = a.rb_off[N];
+  hipLaunchKernelGGL((k_cg_update<KB, true, EVEN, CHOL>), dim3(a.nslot), dim3(256), 0, s, a, 0);
+  if (CHOL) hipLaunchKernelGGL(k_cg_trsv<true>, dim3(nrb), dim3(64), 0, s, a, 0);
   for (int it = 0; it < maxiter; ++it) {
     hipLaunchKernelGGL(k_cg_proj, dim3(N * a.TB * a.TB), dim3(512), 0, s, a, it);
     hipLaunchKernelGGL((k_cg_matvec<KB, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, it);
-    hipLaunchKernelGGL((k_cg_update<KB, false, EVEN>), dim3(a.nslot), dim3(256), 0, s, a, it);
+    hipLaunchKernelGGL((k_cg_update<KB, false, EVEN, CHOL>), dim3(a.nslot), dim3(256), 0, s, a,
+                       it);
+    if (CHOL) hipLaunchKernelGGL(k_cg_trsv<false>, dim3(nrb), dim3(64), 0, s, a, it);
   }
   hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(512), 0, s, a, maxiter);
 }
 
 template <int KB>
-static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s) {
-  if (a.d.R % 2 == 0) launch_kb<KB, true>(a, N, maxiter, s);
-  else launch_kb<KB, false>(a, N, maxiter, s);
+static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s, bool chol) {
+  if (chol) {
+    if constexpr (KB <= 8) {
+      if (a.d.R % 2 == 0) launch_kb<KB, true, true>(a, N, maxiter, s);
+      else launch_kb<KB, false, true>(a, N, maxiter, s);
+    }
+    return;
+  }
+  if (a.d.R % 2 == 0) launch_kb<KB, true, false>(a, N, maxiter, s);
+  else launch_kb<KB, false, false>(a, N, maxiter, s);
 }
 
 // Enqueues CG initialisation, cg_maxiter iterations and the final state. R = -G must be in R0.
 int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
               const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
               double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
-              int maxiter, bool diag_damping, hipStream_t s, const double* lam_dev) {
+              int maxiter, bool diag_damping, hipStream_t s, const double* lam_dev, bool chol) {
+  if (chol && p.R > 128) return (int)hipErrorInvalidValue;
   CgArgs a{};
   a.d = d;
   a.A64 = A64;
@@ -517,20 +596,20 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
   a.slot_rz = a.slot_wq + a.nslot;
   a.slot_nrm = a.slot_rz + a.nslot;
   switch (a.TB) {
-    case 1: launch_kb<1>(a, p.N, maxiter, s); break;
-    case 2: launch_kb<2>(a, p.N, maxiter, s); break;
-    case 3: launch_kb<3>(a, p.N, maxiter, s); break;
-    case 4: launch_kb<4>(a, p.N, maxiter, s); break;
-    case 5: launch_kb<5>(a, p.N, maxiter, s); break;
-    case 6: launch_kb<6>(a, p.N, maxiter, s); break;
-    case 7: launch_kb<7>(a, p.N, maxiter, s); break;
-    case 8: launch_kb<8>(a, p.N, maxiter, s); break;
+    case 1: launch_kb<1>(a, p.N, maxiter, s, chol); break;
+    case 2: launch_kb<2>(a, p.N, maxiter, s, chol); break;
+    case 3: launch_kb<3>(a, p.N, maxiter, s, chol); break;
+    case 4: launch_kb<4>(a, p.N, maxiter, s, chol); break;
+    case 5: launch_kb<5>(a, p.N, maxiter, s, chol); break;
+    case 6: launch_kb<6>(a, p.N, maxiter, s, chol); break;
+    case 7: launch_kb<7>(a, p.N, maxiter, s, chol); break;
+    case 8: launch_kb<8>(a, p.N, maxiter, s, chol); break;
     // 128 < R <= 208: operand rows of up to 52 doubles per lane (no scratch; part in AGPRs)
-    case 9: launch_kb<9>(a, p.N, maxiter, s); break;
-    case 10: launch_kb<10>(a, p.N, maxiter, s); break;
-    case 11: launch_kb<11>(a, p.N, maxiter, s); break;
-    case 12: launch_kb<12>(a, p.N, maxiter, s); break;
-    case 13: launch_kb<13>(a, p.N, maxiter, s); break;
+    case 9: launch_kb<9>(a, p.N, maxiter, s, chol); break;
+    case 10: launch_kb<10>(a, p.N, maxiter, s, chol); break;
+    case 11: launch_kb<11>(a, p.N, maxiter, s, chol); break;
+    case 12: launch_kb<12>(a, p.N, maxiter, s, chol); break;
+    case 13: launch_kb<13>(a, p.N, maxiter, s, chol); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

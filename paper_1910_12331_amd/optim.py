@@ -3,7 +3,7 @@ drivers (Section 4): each step() is one ALS sweep or one Gauss-Newton iteration,
 libcpgn.so on the GPU."""
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import torch
 
@@ -86,6 +86,7 @@ class GNConfig:
     schedule: DampingSchedule | ConstantDamping | None = None
     damping: str = "identity"       # or "diagonal": lam diag(J^T J) (Section 3.2)
     line_search: Armijo | None = None
+    preconditioner: str = "inverse"  # or "cholesky": triangular solves (Section 3.3), R <= 128
 
 
 class GaussNewton:
@@ -104,12 +105,13 @@ class GaussNewton:
         ls = self.cfg.line_search
         if ls is None:
             api.gn_step(self.X, self.A, self.schedule.value, self.cfg.cg_tol, self.cfg.cg_maxiter,
-                        stats=self.stats_buf, ws=self.ws, damping=self.cfg.damping)
+                        stats=self.stats_buf, ws=self.ws, damping=self.cfg.damping,
+                        preconditioner=self.cfg.preconditioner)
         else:
             api.gn_step_armijo(self.X, self.A, self.schedule.value, self.cfg.cg_tol,
                                self.cfg.cg_maxiter, ls.c, ls.shrink, ls.max_trials,
                                stats=self.stats_buf, ls_stats=self.ls_buf, ws=self.ws,
-                               damping=self.cfg.damping)
+                               damping=self.cfg.damping, preconditioner=self.cfg.preconditioner)
         self.schedule.advance()
         self.steps += 1
         return self.stats_buf
@@ -169,7 +171,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     X_high hold the same tensor. Returns (factors, history of (precision, residual))."""
     cfg = config or GNConfig()
     sched = cfg.schedule or DampingSchedule()
-    low_cfg = GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping, cfg.line_search)
+    low_cfg = replace(cfg, schedule=sched)
     opt = GaussNewton(X_low, A, low_cfg)
     hist = []
     prev = float("inf")
@@ -183,8 +185,7 @@ def gn_mixed_to_target(X_low, X_high, A, target, switch_residual: float = 1e-6,
     if hist and hist[-1][1] <= target:
         return opt.A, hist
     A_high = [a.to(api.factor_dtype(X_high)) for a in opt.A]
-    high = GaussNewton(X_high, A_high,
-                       GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping, cfg.line_search))
+    high = GaussNewton(X_high, A_high, replace(cfg, schedule=sched))
     while opt.steps + high.steps < max_steps:
         high.step()
         r = high.residual()
@@ -230,8 +231,7 @@ def gn_ladder_to_target(rungs, A, target, config: GNConfig | None = None, max_st
         name = _rung_name(X)
         floor = _RUNG_FLOOR.get(name, 0.0)
         A = [a.to(api.factor_dtype(X)) for a in A]
-        opt = GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter, sched, cfg.damping,
-                                         cfg.line_search))
+        opt = GaussNewton(X, A, replace(cfg, schedule=sched))
         if i > 0:
             prev = opt.residual()
         while steps < max_steps:
@@ -284,9 +284,7 @@ class BatchedGaussNewton:
         self.opts = []
         for i, (X, A) in enumerate(problems):
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
-                self.opts.append(GaussNewton(X, A, GNConfig(cfg.cg_tol, cfg.cg_maxiter,
-                                                             damping=cfg.damping,
-                                                             line_search=cfg.line_search)))
+                self.opts.append(GaussNewton(X, A, replace(cfg, schedule=None)))
         self.graphs = None
         if graphs:
             self._capture()
@@ -303,7 +301,8 @@ class BatchedGaussNewton:
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=s):
                 api.gn_step_devlam(opt.X, opt.A, state[0:1], self.cfg.cg_tol, self.cfg.cg_maxiter,
-                                   stats=opt.stats_buf, ws=opt.ws, damping=self.cfg.damping)
+                                   stats=opt.stats_buf, ws=opt.ws, damping=self.cfg.damping,
+                                   preconditioner=self.cfg.preconditioner)
                 api.damping_advance(state)
             self.lam_state.append(state)
             self.graphs.append(g)

@@ -151,7 +151,7 @@ def test_call_validation_without_launch(lib):
     # Gauss-Newton parameters
     st = C.c_void_p(0x50000)
     for prm in [L.CpGnParams(-1.0, 1e-3, 20, 0), L.CpGnParams(1e-3, -1.0, 20, 0),
-                L.CpGnParams(1e-3, 1e-3, -1, 0), L.CpGnParams(1e-3, 1e-3, 20, 2),
+                L.CpGnParams(1e-3, 1e-3, -1, 0), L.CpGnParams(1e-3, 1e-3, 20, 4),
                 L.CpGnParams(float("nan"), 1e-3, 20, 0)]:
         assert lib.cp_gn_step(C.byref(p), X, A, C.byref(prm), st, ws, need, None) == L.CP_EINVAL
     good = L.CpGnParams(1e-3, 1e-3, 20, 0)
@@ -187,6 +187,11 @@ def test_call_validation_without_launch(lib):
     _, need2 = ws_bytes(lib, pr)
     assert lib.cp_gn_step(C.byref(pr), X, A, C.byref(good), st, ws, need2, None) == L.CP_EUNSUPPORTED
     assert lib.cp_als_sweep(C.byref(pr), X, A, 0.0, None, ws, need2, None) == L.CP_EUNSUPPORTED
+    # the triangular-solve preconditioner keeps its operands in 64 KB of LDS: R <= 128
+    pc = prob(rank=129)
+    _, need3 = ws_bytes(lib, pc)
+    chol = L.CpGnParams(1e-3, 1e-3, 20, L.GN_CHOL_PRECOND)
+    assert lib.cp_gn_step(C.byref(pc), X, A, C.byref(chol), st, ws, need3, None) == L.CP_EUNSUPPORTED
     assert lib.cp_gn_step_armijo(C.byref(pr), X, A, C.byref(good), C.byref(ok_ls), st, ls_st, ws,
                                  need2, None) == L.CP_EUNSUPPORTED
 
@@ -213,3 +218,5 @@ def test_gn_flag_constant_matches_header():
     text = open(os.path.join(ROOT, "include", "cpgn.h")).read()
     m = re.search(r"#define\s+CP_GN_DIAG_DAMPING\s+(\d+)u", text)
     assert m and int(m.group(1)) == L.GN_DIAG_DAMPING
+    m = re.search(r"#define\s+CP_GN_CHOL_PRECOND\s+(\d+)u", text)
+    assert m and int(m.group(1)) == L.GN_CHOL_PRECOND

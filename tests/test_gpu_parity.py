@@ -195,24 +195,28 @@ def test_jtj_matvec_matches_oracle(dims, rank, lam, dt):
 
 
 # ------------------------------------------------------------------------------------ GN step
-def oracle_sensitivity(Xh, Ah, lam, eps, maxiter, seed=1, damping="identity"):
+def oracle_sensitivity(Xh, Ah, lam, eps, maxiter, seed=1, damping="identity", precond="inverse"):
     """Change of the oracle's GN update when its input factors move by 1e-15 relative: the
     rounding-level spread that any implementation with another summation order inherits
     (large once CG iterates past its rounding floor and loses orthogonality)."""
     rng = np.random.default_rng(seed)
     A2 = [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in Ah]
-    v1 = O.flatten_factors([b - a for a, b in zip(Ah, O.gn_step(Xh, Ah, lam, eps, maxiter, damping)[0])])
-    v2 = O.flatten_factors([b - a for a, b in zip(A2, O.gn_step(Xh, A2, lam, eps, maxiter, damping)[0])])
+    v1 = O.flatten_factors([b - a for a, b in
+                            zip(Ah, O.gn_step(Xh, Ah, lam, eps, maxiter, damping, precond)[0])])
+    v2 = O.flatten_factors([b - a for a, b in
+                            zip(A2, O.gn_step(Xh, A2, lam, eps, maxiter, damping, precond)[0])])
     return float(np.linalg.norm(v1 - v2) / max(np.linalg.norm(v1), 1e-300))
 
 
-def gn_compare(p, dt, lam, eps, maxiter, tol_v, damping="identity"):
+def gn_compare(p, dt, lam, eps, maxiter, tol_v, damping="identity", precond="inverse"):
     Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
     if tol_v == "sensitivity":
-        tol_v = max(1e-12, 10 * oracle_sensitivity(Xh, Ah, lam, eps, maxiter, damping=damping))
+        tol_v = max(1e-12, 10 * oracle_sensitivity(Xh, Ah, lam, eps, maxiter, damping=damping,
+                                                   precond=precond))
     Ad = to_dev(p.init, dt)
-    st = P.read_stats(P.gn_step(to_dev([p.x], dt)[0], Ad, lam, eps, maxiter, damping=damping))
-    newA, ref = O.gn_step(Xh, Ah, lam, eps, maxiter, damping)
+    st = P.read_stats(P.gn_step(to_dev([p.x], dt)[0], Ad, lam, eps, maxiter, damping=damping,
+                                preconditioner=precond))
+    newA, ref = O.gn_step(Xh, Ah, lam, eps, maxiter, damping, precond)
     assert st["status"] == 0
     assert st["cg_iters"] == ref.cg_iters
     V = [a - b for a, b in zip(host(Ad), Ah)]
@@ -289,6 +293,59 @@ def test_gn_step_config2_fp64():
 def test_gn_step_fp32():
     p = make_problem((40, 40, 40), 5, workload=1)
     gn_compare(p, torch.float32, 1e-4, 0.0, 10, 1e-4)
+
+
+# ----------------------------------------------------- preconditioner by triangular solves
+@pytest.mark.parametrize("maxiter", [0, 1, 5, 10])
+def test_gn_step_cholesky_preconditioner_fixed_iterations_fp64(maxiter):
+    """CP_GN_CHOL_PRECOND: the Cholesky factor of Gamma(n,n) + lambda I and a forward and a back
+    triangular solve per CG application (Section 3.3's alternative to the explicit inverse)."""
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float64, 1e-4, 0.0, maxiter, 1e-12, precond="cholesky")
+
+
+@pytest.mark.parametrize("dims,rank,lam,damping", [
+    ((23, 18, 31), 6, 1e-2, "identity"), ((9, 7, 8, 6), 3, 1e-3, "identity"),
+    ((11, 13), 4, 1e-3, "diagonal"), ((130, 120, 110), 100, 1e-2, "identity"),
+    ((150, 140, 136), 128, 1e-2, "diagonal"), ((70, 65, 67), 33, 1e-3, "identity")])
+def test_gn_step_cholesky_preconditioner_cg_tolerance_fp64(dims, rank, lam, damping):
+    """Several 64-row blocks with ragged tails, orders 2 to 4, R up to 128 (the 64 KB LDS limit
+    of the solve kernel), odd R, both damping forms."""
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-3)
+    gn_compare(p, torch.float64, lam, 1e-3, 50, 1e-11, damping=damping, precond="cholesky")
+
+
+def test_gn_step_cholesky_preconditioner_fp32():
+    p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float32, 1e-4, 0.0, 10, 1e-4, precond="cholesky")
+
+
+def test_cholesky_and_inverse_preconditioners_agree_on_gpu():
+    """Both forms apply the same operator: the steps agree to rounding."""
+    p = make_problem((60, 50, 40), 20, workload=0, problem=20, noise=1e-3)
+    X = to_dev([p.x], torch.float64)[0]
+    out = []
+    for pc in ("inverse", "cholesky"):
+        Ad = to_dev(p.init, torch.float64)
+        st = P.read_stats(P.gn_step(X, Ad, 1e-3, 1e-3, 20, preconditioner=pc))
+        out.append((st, [a - b for a, b in zip(host(Ad), p.init)]))
+    assert out[0][0]["cg_iters"] == out[1][0]["cg_iters"]
+    assert rel(O.flatten_factors(out[1][1]), O.flatten_factors(out[0][1])) < 1e-11
+
+
+def test_gn_step_cholesky_preconditioner_not_spd_leaves_factors():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((6, 1))
+    A = [np.hstack([a, a]), rng.standard_normal((5, 2)), rng.standard_normal((4, 2))]
+    A[1][:, 1] = A[1][:, 0]
+    A[2][:, 1] = A[2][:, 0]
+    Ad = to_dev(A, torch.float64)
+    before = host(Ad)
+    st = P.read_stats(P.gn_step(to_dev([rng.standard_normal((6, 5, 4))], torch.float64)[0], Ad,
+                                0.0, 1e-3, 20, preconditioner="cholesky"))
+    assert st["status"] == P._lib.CP_ENOTSPD
+    for x, y in zip(host(Ad), before):
+        assert np.array_equal(x, y)
 
 
 def test_gn_step_zero_gradient_no_iteration():
