@@ -382,6 +382,12 @@ def main():
         P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20)
     t20 = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 5, stream)
     t0cg = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 0, stats=sb, ws=ws20), 5, stream)
+    # the same with the preconditioner applied by Cholesky triangular solves (Section 3.3)
+    P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20, preconditioner="cholesky")
+    t20c = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20,
+                                        preconditioner="cholesky"), 3, stream)
+    log(f"[bench] GN step with 20 CG iterations: {t20 * 1e3:.3f} ms with the explicit inverse, "
+        f"{t20c * 1e3:.3f} ms with Cholesky triangular solves")
     res_t = event_time(lambda: P.residual(Xd, gn.A, out=resid, ws=gn.ws), 10, stream)
 
     # ---- time to relative residual 1e-8, FP64 storage (the FP32 rounding floor is ~3e-8)
@@ -530,6 +536,7 @@ def main():
         "gn_step_20cg_ms": t20 * 1e3,
         "gn_steps_per_s_20cg": 1.0 / t20,
         "cg_iteration_ms": (t20 - t0cg) / 20 * 1e3,
+        "gn_step_20cg_cholesky_precond_ms": t20c * 1e3,
         "launch_floor_ms": floor * 1e3,
         "residual_ms": res_t * 1e3,
         "als_sweep_ms": als_t * 1e3,

@@ -463,7 +463,8 @@ __global__ __launch_bounds__(TD * TD) void k_spd_inv(int R, const double* __rest
 // Section 3.3 describes). Same thread layout as k_spd_inv: thread (ty, tx) keeps the entries
 // (ty + TD ai, tx + TD bk) in registers. Step j publishes column j through double-buffered LDS
 // (one barrier), sets L[j][j] = sqrt(p), L[i][j] = c_i / sqrt(p) below it, and updates the
-// trailing block a_ik -= c_i c_k / p (right-looking Cholesky). Entries above the diagonal are
+// trailing block a_ik -= c_i c_k / p (right-looking Cholesky); the divisions are products with
+// 1 / p and 1 / sqrt(p), formed once per step. Entries above the diagonal are
 // written as 0. A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done.
 // ------------------------------------------------------------------------------------------
 template <int NBK, int TD>
@@ -519,12 +520,12 @@ __global__ __launch_bounds__(TD * TD) void k_spd_chol(int R, const double* __res
       }
       return;
     }
-    const double d = sqrt(piv);
+    const double d = sqrt(piv), rp = 1.0 / piv, rd = 1.0 / d;
     double u[NBK], v[NBK];
 #pragma unroll
     for (int q = 0; q < NBK; ++q) {
       const int i = ty + TD * q, k = tx + TD * q;
-      u[q] = i > j ? colbuf[b][i] / piv : 0.0;
+      u[q] = i > j ? colbuf[b][i] * rp : 0.0;
       v[q] = k > j ? colbuf[b][k] : 0.0;
     }
 #pragma unroll
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(TD * TD) void k_spd_chol(int R, const double* __res
 #pragma unroll
           for (int ai = 0; ai < NBK; ++ai) {
             const int i = ty + TD * ai;
-            if (i > j) a[ai][bk] = colbuf[b][i] / d;
+            if (i > j) a[ai][bk] = colbuf[b][i] * rd;
             else if (i == j) a[ai][bk] = d;
           }
         }

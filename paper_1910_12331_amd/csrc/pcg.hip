@@ -282,14 +282,16 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
 // k_cg_trsv: Z = R (L L^T)^-1 for one 64-row block of a mode, L the lower Cholesky factor of
 // Gamma(n,n) + lambda D (stored in a.pinv). One wavefront; lane k solves row k: the forward solve
 // L y = r^T, then the back solve L^T z = y, each entry (r_i - sum_j L_ij y_j) / L_ii with the sum
-// split over four accumulators. y lives in LDS column-major ([i][lane], 64 KB at R = 128, no bank
-// conflicts); L is read from global memory at wave-uniform addresses. The block's <R, Z> goes to
-// its first column-tile slot and 0 to the others (the slot layout of k_cg_update). R <= 128.
-// R_new is Rv[(it + 1) & 1], or Rv[0] for the initialisation.
+// split over eight accumulators. The lower triangle of L (packed by rows, 66 KB at R = 128) and y
+// (column-major [i][lane], 64 KB, no bank conflicts) sit in LDS, so the sums read LDS only; the
+// 130 KB fit gfx950's 160 KB of LDS per workgroup. The block's <R, Z> goes to its first
+// column-tile slot and 0 to the others (the slot layout of k_cg_update). R <= 128. R_new is
+// Rv[(it + 1) & 1], or Rv[0] for the initialisation.
 // ---------------------------------------------------------------------------------------------
 template <bool INIT>
 __global__ __launch_bounds__(64) void k_cg_trsv(CgArgs a, int it) {
   __shared__ double Ys[128 * 64];
+  __shared__ double Lp[128 * 129 / 2];
   const int R = a.d.R, t = threadIdx.x;
   const int rb = blockIdx.x;
   int n = 0;
@@ -298,40 +300,76 @@ __global__ __launch_bounds__(64) void k_cg_trsv(CgArgs a, int it) {
   const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows;
   const int rows = (int)(s - k0 < kCgRows ? s - k0 : kCgRows);
   const double* Rin = INIT ? a.Rv[0] : a.Rv[(it + 1) & 1];
-  // No workgroup of this launch writes the flag, so every lane reads the same value; the
-  // workgroup is one wavefront and Ys takes all 64 KB of its LDS (no barrier, no other LDS).
+  // No workgroup of this launch writes the flag, so every lane reads the same value (the
+  // workgroup is one wavefront: the early exit is uniform).
   if (__builtin_amdgcn_readfirstlane(__builtin_nontemporal_load(&a.st->done)) != 0) return;
   const double* L = a.pinv + (int64_t)n * R * R;
+  for (int i0 = 0; i0 < R; i0 += 4) {   // rows i0..i0+3 of L's lower triangle: 8 loads in flight
+    double v[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = i0 + u, j = t + 64 * h;
+        v[u][h] = (i < R && j <= i) ? L[(int64_t)i * R + j] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = i0 + u, j = t + 64 * h;
+        if (i < R && j <= i) Lp[i * (i + 1) / 2 + j] = v[u][h];
+      }
+  }
+  const int64_t row = (a.d.off[n] + k0 + (t < rows ? t : 0)) * R;
+  for (int i0 = 0; i0 < R; i0 += 8) {   // this lane's row of R into Ys (rows past the mode: 0)
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (t < rows && i0 + u < R) ? Rin[row + i0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < R) Ys[(i0 + u) * 64 + t] = v[u];
+  }
+  __syncthreads();
   double dot = 0.0;
   if (t < rows) {
-    const int64_t row = (a.d.off[n] + k0 + t) * R;
     for (int i = 0; i < R; ++i) {   // forward: L y = r
-      const double* Li = L + (int64_t)i * R;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const double* Li = Lp + i * (i + 1) / 2;
+      double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       int j = 0;
-      for (; j + 3 < i; j += 4) {
-        s0 = fma(Li[j], Ys[j * 64 + t], s0);
-        s1 = fma(Li[j + 1], Ys[(j + 1) * 64 + t], s1);
-        s2 = fma(Li[j + 2], Ys[(j + 2) * 64 + t], s2);
-        s3 = fma(Li[j + 3], Ys[(j + 3) * 64 + t], s3);
+      for (; j + 7 < i; j += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = fma(Li[j + u], Ys[(j + u) * 64 + t], acc[u]);
       }
-      for (; j < i; ++j) s0 = fma(Li[j], Ys[j * 64 + t], s0);
-      Ys[i * 64 + t] = (Rin[row + i] - ((s0 + s1) + (s2 + s3))) / Li[i];
+      for (; j < i; ++j) acc[0] = fma(Li[j], Ys[j * 64 + t], acc[0]);
+      const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+      Ys[i * 64 + t] = (Ys[i * 64 + t] - sum) / Li[i];
     }
     for (int i = R - 1; i >= 0; --i) {   // back: L^T z = y (column i of L below the diagonal)
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       int j = i + 1;
-      for (; j + 3 < R; j += 4) {
-        s0 = fma(L[(int64_t)j * R + i], Ys[j * 64 + t], s0);
-        s1 = fma(L[(int64_t)(j + 1) * R + i], Ys[(j + 1) * 64 + t], s1);
-        s2 = fma(L[(int64_t)(j + 2) * R + i], Ys[(j + 2) * 64 + t], s2);
-        s3 = fma(L[(int64_t)(j + 3) * R + i], Ys[(j + 3) * 64 + t], s3);
+      for (; j + 7 < R; j += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          acc[u] = fma(Lp[(j + u) * (j + u + 1) / 2 + i], Ys[(j + u) * 64 + t], acc[u]);
       }
-      for (; j < R; ++j) s0 = fma(L[(int64_t)j * R + i], Ys[j * 64 + t], s0);
-      const double z = (Ys[i * 64 + t] - ((s0 + s1) + (s2 + s3))) / L[(int64_t)i * R + i];
-      Ys[i * 64 + t] = z;
-      a.Z[row + i] = z;
-      dot = fma(z, Rin[row + i], dot);
+      for (; j < R; ++j) acc[0] = fma(Lp[j * (j + 1) / 2 + i], Ys[j * 64 + t], acc[0]);
+      const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+      Ys[i * 64 + t] = (Ys[i * 64 + t] - sum) / Lp[i * (i + 1) / 2 + i];
+    }
+    for (int i0 = 0; i0 < R; i0 += 8) {   // Z and this row's <R, Z>
+      double rv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rv[u] = i0 + u < R ? Rin[row + i0 + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < R) {
+          const double z = Ys[(i0 + u) * 64 + t];
+          a.Z[row + i0 + u] = z;
+          dot = fma(z, rv[u], dot);
+        }
     }
   }
   for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o);   // same bits in every lane
