@@ -127,17 +127,39 @@ class GaussNewton:
         return float(r[0] / r[1])
 
 
-class ALS:
-    """Alternating least squares sweeps (Section 2.2)."""
+class StepDecay:
+    """A regularization that starts at `start` and is multiplied by `factor` after every `every`
+    sweeps: Section 5 runs ALS on the matrix-multiplication tensors with lambda = 0.01 halved
+    every 100 iterations. `value` is the lambda for the coming sweep."""
 
-    def __init__(self, X: torch.Tensor, A, lam: float = 0.0):
+    def __init__(self, start: float = 1e-2, factor: float = 0.5, every: int = 100):
+        if not (start >= 0.0 and 0.0 < factor and every >= 1):
+            raise ValueError("need start >= 0, factor > 0 and every >= 1")
+        self.value, self.factor, self.every, self.count = float(start), float(factor), int(every), 0
+
+    def advance(self) -> float:
+        self.count += 1
+        if self.count % self.every == 0:
+            self.value = self.value * self.factor
+        return self.value
+
+
+class ALS:
+    """Alternating least squares sweeps (Section 2.2), with a fixed Tikhonov lambda or a
+    schedule with `value` and `advance()` (e.g. StepDecay)."""
+
+    def __init__(self, X: torch.Tensor, A, lam: float = 0.0, schedule=None):
         self.X, self.A, self.lam = X, list(A), float(lam)
+        self.schedule = schedule
         self.ws = api.Workspace()
         self.status = torch.zeros(1, dtype=torch.int32, device=X.device)
         self.steps = 0
 
     def step(self) -> torch.Tensor:
-        api.als_sweep(self.X, self.A, self.lam, status=self.status, ws=self.ws)
+        lam = self.schedule.value if self.schedule is not None else self.lam
+        api.als_sweep(self.X, self.A, lam, status=self.status, ws=self.ws)
+        if self.schedule is not None:
+            self.schedule.advance()
         self.steps += 1
         return self.status
 

@@ -398,6 +398,22 @@ def test_als_sweep_matches_oracle(dims, rank, lam, dt):
         assert rel(a, r) < tol
 
 
+def test_als_with_step_decay_regularization_matches_oracle():
+    """ALS with lambda = 0.01 halved every 2 sweeps (the schedule of Section 5, compressed):
+    each sweep against the oracle's sweep with the same lambda."""
+    p = make_problem((30, 26, 34), 6, workload=0, problem=6, noise=1e-2)
+    X = to_dev([p.x], torch.float64)[0]
+    opt = P.ALS(X, to_dev(p.init, torch.float64), schedule=P.StepDecay(1e-2, 0.5, 2))
+    ref = [a.copy() for a in p.init]
+    for k in range(5):
+        lam = 1e-2 * 0.5 ** (k // 2)
+        assert opt.schedule.value == lam
+        assert int(opt.step().item()) == 0
+        ref = O.als_sweep(p.x, ref, lam)
+        for a, r in zip(host(opt.A), ref):
+            assert rel(a, r) < 1e-11
+
+
 def test_als_sweep_config2_fp64():
     """After the first mode the congruent data make the Grams ill-conditioned (cond ~1e9-1e11),
     so later modes are held to 10x the oracle's own spread under a 1e-15 input perturbation."""

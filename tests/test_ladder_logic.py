@@ -83,3 +83,15 @@ def test_nan_step_is_rejected(fake):
     out, hist = optim.gn_ladder_to_target([low, top], [torch.zeros(1, 1)], 1e-5)
     assert hist[0][2] is False and hist[1] == ("torch.float64", 1e-6, True)
     assert torch.equal(out[0], torch.ones(1, 1))
+
+
+def test_step_decay_schedule():
+    """lambda = start * factor^floor(k / every) for sweep k (Section 5: 0.01, halved every 100)."""
+    s = optim.StepDecay(1e-2, 0.5, 100)
+    seq = [s.value]
+    for _ in range(349):
+        seq.append(s.advance())
+    for k, v in enumerate(seq):
+        assert v == 1e-2 * 0.5 ** (k // 100)
+    with pytest.raises(ValueError):
+        optim.StepDecay(1e-2, 0.5, 0)
