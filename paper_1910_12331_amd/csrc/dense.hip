@@ -345,25 +345,25 @@ __global__ void k_status_out(const CgState* st, int32_t* out) {
 // In-place Gauss-Jordan inversion without pivoting: for an SPD matrix its pivots are the
 // Cholesky pivots (the diagonals of the successive Schur complements), so "pivot > 0" is the
 // same positive-definiteness test, and R steps give the inverse directly. Thread (ty, tx) of
-// the 32 x 32 grid keeps the entries (ty + 32 ai, tx + 32 bk) of the identity-padded matrix in
-// registers; each step publishes the pivot row r and column c through double-buffered LDS (one
-// barrier), applies a_ik -= (c_i / p) r_k to every entry, and sets the pivot row to r / p, the
-// pivot column to -c / p and the pivot to 1 / p (the Gauss-Jordan update).
+// the TDY x TDX grid keeps the entries (ty + TDY ai, tx + TDX bk) of the identity-padded matrix
+// in registers; each step publishes the pivot row r and column c through double-buffered LDS
+// (one barrier), applies a_ik -= (c_i / p) r_k to every entry, and sets the pivot row to r / p,
+// the pivot column to -c / p and the pivot to 1 / p (the Gauss-Jordan update).
 // A non-positive or non-finite pivot records CP_ENOTSPD and marks the state done. With lam_dev
 // the damping is read from device memory (a negative or non-finite value records CP_EINVAL).
-template <int NBK, int TD>
-__global__ __launch_bounds__(TD * TD) void k_spd_inv(int R, const double* __restrict__ Gin,
-                                                 int64_t g_stride, double lambda,
-                                                 const double* __restrict__ lam_dev,
-                                                 double* __restrict__ Pout, int64_t p_stride,
-                                                 int first_mode, CgState* st, int diag_damping) {
-  constexpr int RP = TD * NBK;
-  __shared__ double colbuf[2][RP], rowbuf[2][RP];
+template <int NBY, int NBX, int TDY, int TDX>
+__global__ __launch_bounds__(TDY * TDX) void k_spd_inv(int R, const double* __restrict__ Gin,
+                                                   int64_t g_stride, double lambda,
+                                                   const double* __restrict__ lam_dev,
+                                                   double* __restrict__ Pout, int64_t p_stride,
+                                                   int first_mode, CgState* st, int diag_damping) {
+  constexpr int RPY = TDY * NBY, RPX = TDX * NBX;
+  __shared__ double colbuf[2][RPY], rowbuf[2][RPX];
   __shared__ int sbad;
   const int n = first_mode + blockIdx.x;
   const double* G = Gin + n * g_stride;
   double* P = Pout + n * p_stride;
-  const int t = threadIdx.x, tx = t % TD, ty = t / TD;
+  const int t = threadIdx.x, tx = t % TDX, ty = t / TDX;
   if (lam_dev) lambda = *lam_dev;
   if (t == 0) {
     sbad = st->status != CP_OK;   // one read: another workgroup may set it meanwhile
@@ -375,84 +375,74 @@ __global__ __launch_bounds__(TD * TD) void k_spd_inv(int R, const double* __rest
   }
   __syncthreads();
   if (sbad) return;
-  double a[NBK][NBK];
+  double a[NBY][NBX];
 #pragma unroll
-  for (int ai = 0; ai < NBK; ++ai)
+  for (int ai = 0; ai < NBY; ++ai)
 #pragma unroll
-    for (int bk = 0; bk < NBK; ++bk) {
-      const int i = ty + TD * ai, k = tx + TD * bk;
+    for (int bk = 0; bk < NBX; ++bk) {
+      const int i = ty + TDY * ai, k = tx + TDX * bk;
       // lambda I, or lambda diag(G); G is read only inside the R x R block
       a[ai][bk] = (i < R && k < R)
                       ? G[i * R + k] + (i == k ? (diag_damping ? lambda * G[i * R + i] : lambda) : 0.0)
                       : (i == k ? 1.0 : 0.0);
     }
-  for (int j = 0; j < R; ++j) {
-    const int b = j & 1, jb = j / TD, jt = j % TD;
-    if (ty == jt) {
+  // Pivot j = TDY jb + jt: its row lives in register row jb of thread row jt, its column in
+  // register column jb TDY / TDX of thread column j % TDX (TDX is a multiple of TDY, so that
+  // register column is the same for the whole block jb). Unrolling jb makes every register index
+  // a constant: no selects over the register blocks.
 #pragma unroll
-      for (int ai = 0; ai < NBK; ++ai)
-        if (ai == jb) {
+  for (int jb = 0; jb < NBY; ++jb) {
+    constexpr int kRatio = TDX / TDY;
+    const int jbx = jb / kRatio;
+    for (int jt = 0; jt < TDY; ++jt) {
+      const int j = jb * TDY + jt;
+      if (j >= R) break;   // uniform
+      const int b = j & 1, jtx = j % TDX;
+      if (ty == jt) {
 #pragma unroll
-          for (int bk = 0; bk < NBK; ++bk) rowbuf[b][tx + TD * bk] = a[ai][bk];
-        }
-    }
-    if (tx == jt) {
-#pragma unroll
-      for (int bk = 0; bk < NBK; ++bk)
-        if (bk == jb) {
-#pragma unroll
-          for (int ai = 0; ai < NBK; ++ai) colbuf[b][ty + TD * ai] = a[ai][bk];
-        }
-    }
-    __syncthreads();
-    const double piv = rowbuf[b][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
-      if (t == 0) {
-        st->status = CP_ENOTSPD;
-        st->done = 1;
+        for (int bk = 0; bk < NBX; ++bk) rowbuf[b][tx + TDX * bk] = a[jb][bk];
       }
-      return;
-    }
-    const double rp = 1.0 / piv;
-    double u[NBK], v[NBK];
+      if (tx == jtx) {
 #pragma unroll
-    for (int q = 0; q < NBK; ++q) {
-      u[q] = colbuf[b][ty + TD * q] * rp;
-      v[q] = rowbuf[b][tx + TD * q];
-    }
-    // One FMA per entry; it leaves 0 in the pivot row and column, which their owners then set
-    // to r_k / p, -c_i / p and 1 / p.
-#pragma unroll
-    for (int ai = 0; ai < NBK; ++ai)
-#pragma unroll
-      for (int bk = 0; bk < NBK; ++bk) a[ai][bk] -= u[ai] * v[bk];
-    if (ty == jt) {
-#pragma unroll
-      for (int ai = 0; ai < NBK; ++ai)
-        if (ai == jb) {
-#pragma unroll
-          for (int bk = 0; bk < NBK; ++bk) a[ai][bk] = v[bk] * rp;
+        for (int ai = 0; ai < NBY; ++ai) colbuf[b][ty + TDY * ai] = a[ai][jbx];
+      }
+      __syncthreads();
+      const double piv = rowbuf[b][j];
+      if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
+        if (t == 0) {
+          st->status = CP_ENOTSPD;
+          st->done = 1;
         }
-    }
-    if (tx == jt) {
+        return;
+      }
+      const double rp = 1.0 / piv;
+      double u[NBY], v[NBX];
 #pragma unroll
-      for (int bk = 0; bk < NBK; ++bk)
-        if (bk == jb) {
+      for (int q = 0; q < NBY; ++q) u[q] = colbuf[b][ty + TDY * q] * rp;
 #pragma unroll
-          for (int ai = 0; ai < NBK; ++ai) a[ai][bk] = -u[ai];
-        }
-    }
-    if (ty == jt && tx == jt) {
+      for (int q = 0; q < NBX; ++q) v[q] = rowbuf[b][tx + TDX * q];
+      // One FMA per entry; it leaves 0 in the pivot row and column, which their owners then
+      // set to r_k / p, -c_i / p and 1 / p.
 #pragma unroll
-      for (int q = 0; q < NBK; ++q)
-        if (q == jb) a[q][q] = rp;
+      for (int ai = 0; ai < NBY; ++ai)
+#pragma unroll
+        for (int bk = 0; bk < NBX; ++bk) a[ai][bk] -= u[ai] * v[bk];
+      if (ty == jt) {
+#pragma unroll
+        for (int bk = 0; bk < NBX; ++bk) a[jb][bk] = v[bk] * rp;
+      }
+      if (tx == jtx) {
+#pragma unroll
+        for (int ai = 0; ai < NBY; ++ai) a[ai][jbx] = -u[ai];
+      }
+      if (ty == jt && tx == jtx) a[jb][jbx] = rp;
     }
   }
 #pragma unroll
-  for (int ai = 0; ai < NBK; ++ai)
+  for (int ai = 0; ai < NBY; ++ai)
 #pragma unroll
-    for (int bk = 0; bk < NBK; ++bk) {
-      const int i = ty + TD * ai, k = tx + TD * bk;
+    for (int bk = 0; bk < NBX; ++bk) {
+      const int i = ty + TDY * ai, k = tx + TDX * bk;
       if (i < R && k < R) P[i * R + k] = a[ai][bk];
     }
 }
@@ -1051,13 +1041,15 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
   // than 16 x 16 at R = 50, 100 and 128 (the same arithmetic, so the same bits).
   constexpr int TD = CPGN_SPD_TD;
   if (R > 128) {
-    // 16 x 16 threads (one wavefront per SIMD), each a block of up to 13 x 13 entries: 255
-    // VGPRs and about 170 AGPRs at R = 208, no scratch.
+    // 16 x 32 threads (two wavefronts per SIMD), each a block of up to 13 x 7 entries, without
+    // scratch or accumulation registers (a 16 x 16 grid of 13 x 13 blocks spilled to AGPRs and
+    // took 544 us at R = 200).
     switch ((R + 15) / 16) {
 #define CPGN_SPD16(k)                                                                         \
   case k:                                                                                     \
-    hipLaunchKernelGGL((k_spd_inv<k, 16>), dim3(count), dim3(256), 0, s, R, G, g_stride,      \
-                       lambda, lam_dev, P, p_stride, first_mode, st, diag_damping ? 1 : 0);   \
+    hipLaunchKernelGGL((k_spd_inv<k, (k + 1) / 2, 16, 32>), dim3(count), dim3(512), 0, s, R, G, \
+                       g_stride, lambda, lam_dev, P, p_stride, first_mode, st,               \
+                       diag_damping ? 1 : 0);                                                 \
     break;
       CPGN_SPD16(9) CPGN_SPD16(10) CPGN_SPD16(11) CPGN_SPD16(12) CPGN_SPD16(13)
 #undef CPGN_SPD16
@@ -1069,8 +1061,9 @@ int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, doub
   switch (nbk) {
 #define CPGN_SPD(k)                                                                           \
   case k:                                                                                     \
-    hipLaunchKernelGGL((k_spd_inv<k, TD>), dim3(count), dim3(TD * TD), 0, s, R, G, g_stride, \
-                       lambda, lam_dev, P, p_stride, first_mode, st, diag_damping ? 1 : 0);   \
+    hipLaunchKernelGGL((k_spd_inv<k, k, TD, TD>), dim3(count), dim3(TD * TD), 0, s, R, G,   \
+                       g_stride, lambda, lam_dev, P, p_stride, first_mode, st,               \
+                       diag_damping ? 1 : 0);                                                 \
     break;
     CPGN_SPD(1) CPGN_SPD(2) CPGN_SPD(3) CPGN_SPD(4)
 #if CPGN_SPD_TD == 16
