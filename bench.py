@@ -437,7 +437,14 @@ def main():
         devs = [(torch.tensor(p_.x, dtype=torch.float32, device="cuda"),
                  [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p_.init]) for p_ in probs]
         res = {}
-        for ns, graphs in ((1, False), (args.batched_streams, False), (args.batched_streams, True)):
+        # sweep-based autotuner over (streams, graph replay) for this batch's shape bucket; its
+        # pick is then timed like the fixed configurations below
+        tune = P.autotune_batched(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20),
+                                  stream_counts=(1, 2, 4, 8, 16), steps=3)
+        configs = [(1, False), (args.batched_streams, False), (args.batched_streams, True)]
+        if (tune.n_streams, tune.graphs) not in configs:
+            configs.append((tune.n_streams, tune.graphs))
+        for ns, graphs in configs:
             cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
             torch.cuda.synchronize()
             bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns,
@@ -456,6 +463,16 @@ def main():
             res[key] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
                             step_ms_p99=float(np.percentile(per, 99)))
             del bgn, cur
+        kt = f"streams_{tune.n_streams}" + ("_graphs" if tune.graphs else "")
+        res["autotuned"] = dict(choice=kt, problem_steps_per_s=res[kt]["problem_steps_per_s"],
+                                sweep_problem_steps_per_s={
+                                    f"streams_{k[0]}" + ("_graphs" if k[1] else ""): v
+                                    for k, v in tune.table.items()},
+                                note="sweep: 3 steps per configuration without per-problem "
+                                     "events; problem_steps_per_s: the timed loop of the fixed "
+                                     "configurations")
+        log(f"[bench] batched autotuner picks {kt}: {res[kt]['problem_steps_per_s']:.0f} "
+            f"problem-steps/s in the same timed loop")
         batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
                        note="_graphs: each problem's GN step and damping update replayed from a "
                             "captured HIP graph", **res)

@@ -363,3 +363,69 @@ class BatchedGaussNewton:
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
                 out.append(opt.residual())
         return out
+
+
+@dataclass
+class BatchedTuning:
+    """The launch configuration chosen for a batch: HIP streams, graph replay, the throughput
+    it measured and the whole sweep (problem-steps/s per (n_streams, graphs))."""
+    n_streams: int
+    graphs: bool
+    problem_steps_per_s: float
+    table: dict
+
+
+_TUNING_CACHE: dict = {}
+
+
+def _pow2_ceil(v: int) -> int:
+    return 1 << max(0, int(v) - 1).bit_length()
+
+
+def batch_key(problems) -> tuple:
+    """Shape bucket of a batch of (X, A) problems: the count, the storage type, and the ranks and
+    largest mode sizes rounded up to powers of two, so that batches of similar shapes share a
+    tuning."""
+    ranks = sorted(_pow2_ceil(int(A[0].shape[1])) for _, A in problems)
+    sizes = sorted(_pow2_ceil(max(int(s) for s in X.shape)) for X, _ in problems)
+    dtypes = sorted({str(getattr(X, "dtype", type(X).__name__)) for X, _ in problems})
+    return (len(problems), tuple(dtypes), tuple(ranks), tuple(sizes))
+
+
+def _time_batched(problems, config, n_streams, graphs, steps) -> float:
+    cur = [(X, [a.clone() for a in A]) for X, A in problems]   # the caller's factors stay as is
+    torch.cuda.synchronize()
+    bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs)
+    bgn.step()
+    bgn.synchronize()
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bgn.step()
+    bgn.synchronize()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def autotune_batched(problems, config: GNConfig | None = None, stream_counts=(1, 2, 4, 8, 16),
+                     graphs=(False, True), steps: int = 3, timer=None, cache=_TUNING_CACHE):
+    """Sweep-based tuning of the batched runner: every (n_streams, graphs) pair runs `steps`
+    Gauss-Newton steps of the whole batch on copies of its factors, timed by the wall clock, and
+    the fastest is returned (the first one on a tie). The result is cached per batch_key, so a
+    batch of a shape seen before is not timed again. The iterates do not depend on the choice
+    (the kernels are deterministic), only the throughput does."""
+    key = batch_key(problems)
+    if cache is not None and key in cache:
+        return cache[key]
+    timer = timer or _time_batched
+    table = {}
+    for ns in stream_counts:
+        for g in graphs:
+            table[(int(ns), bool(g))] = len(problems) * steps / timer(problems, config, ns, g, steps)
+    best = max(table, key=table.get)
+    out = BatchedTuning(n_streams=best[0], graphs=best[1], problem_steps_per_s=table[best],
+                        table=table)
+    if cache is not None:
+        cache[key] = out
+    return out

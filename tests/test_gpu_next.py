@@ -191,3 +191,33 @@ def test_batched_graph_replays_match_eager_steps():
             assert og.schedule.value == oe.schedule.value
             for a, b in zip(oe.A, og.A):
                 assert torch.equal(a, b), k
+
+
+def test_autotuned_batched_run_matches_single_stream():
+    """The autotuner leaves the caller's factors untouched, picks one of the candidates, and the
+    tuned runner gives the single-stream eager iterates bit for bit."""
+    rng = np.random.default_rng(3)
+    probs = []
+    for i in range(6):
+        dims, R = tuple(int(v) for v in rng.integers(20, 60, 3)), int(rng.choice([4, 8, 16]))
+        p = make_problem(dims, R, workload=5, problem=i, noise=1e-3)
+        probs.append((torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                      [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]))
+    before = [[a.clone() for a in A] for _, A in probs]
+    cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20)
+    tune = P.autotune_batched(probs, cfg, stream_counts=(1, 4), steps=2, cache={})
+    assert (tune.n_streams, tune.graphs) in tune.table and len(tune.table) == 4
+    for (_, A), B in zip(probs, before):
+        assert all(torch.equal(a, b) for a, b in zip(A, B))
+    tuned = [(X, [a.clone() for a in A]) for X, A in probs]
+    bgn = P.BatchedGaussNewton(tuned, cfg, n_streams=tune.n_streams, graphs=tune.graphs)
+    for _ in range(3):
+        bgn.step()
+    bgn.synchronize()
+    for (X, A), (_, At) in zip(probs, tuned):
+        ref = [a.clone() for a in A]
+        opt = P.GaussNewton(X, ref, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+        for _ in range(3):
+            opt.step()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(At, ref))

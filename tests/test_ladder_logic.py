@@ -95,3 +95,28 @@ def test_step_decay_schedule():
         assert v == 1e-2 * 0.5 ** (k // 100)
     with pytest.raises(ValueError):
         optim.StepDecay(1e-2, 0.5, 0)
+
+
+def test_autotune_batched_picks_fastest_and_caches():
+    """Host logic of the batched autotuner with a scripted timer (no GPU)."""
+    probs = [(torch.zeros(60, 70, 90), [torch.zeros(60, 8), torch.zeros(70, 8), torch.zeros(90, 8)]),
+             (torch.zeros(130, 70, 90), [torch.zeros(130, 40), torch.zeros(70, 40),
+                                         torch.zeros(90, 40)])]
+    secs = {(1, False): 4.0, (1, True): 3.0, (4, False): 2.0, (4, True): 1.0, (8, False): 1.5,
+            (8, True): 1.0}
+    calls = []
+
+    def timer(problems, config, ns, graphs, steps):
+        calls.append((ns, graphs))
+        assert problems is probs and steps == 3
+        return secs[(ns, graphs)]
+
+    cache = {}
+    out = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
+    assert (out.n_streams, out.graphs) == (4, True)           # first of the two fastest
+    assert out.problem_steps_per_s == 2 * 3 / 1.0 and len(out.table) == 6
+    assert len(calls) == 6
+    again = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
+    assert again is out and len(calls) == 6                   # served from the cache
+    # the bucket: ranks 8 and 40 -> 8 and 64, largest modes 90 and 130 -> 128 and 256
+    assert optim.batch_key(probs) == (2, ("torch.float32",), (8, 64), (128, 256))
