@@ -491,48 +491,47 @@ __global__ __launch_bounds__(TD * TD) void k_spd_chol(int R, const double* __res
                       ? G[i * R + k] + (i == k ? (diag_damping ? lambda * G[i * R + i] : lambda) : 0.0)
                       : (i == k ? 1.0 : 0.0);
     }
-  for (int j = 0; j < R; ++j) {
-    const int b = j & 1, jb = j / TD, jt = j % TD;
-    if (tx == jt) {
+  // Pivot j = TD jb + jt: its column is register column jb of thread column jt; unrolling jb
+  // makes every register index a constant.
 #pragma unroll
-      for (int bk = 0; bk < NBK; ++bk)
-        if (bk == jb) {
+  for (int jb = 0; jb < NBK; ++jb) {
+    for (int jt = 0; jt < TD; ++jt) {
+      const int j = jb * TD + jt;
+      if (j >= R) break;   // uniform
+      const int b = j & 1;
+      if (tx == jt) {
 #pragma unroll
-          for (int ai = 0; ai < NBK; ++ai) colbuf[b][ty + TD * ai] = a[ai][bk];
-        }
-    }
-    __syncthreads();
-    const double piv = colbuf[b][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
-      if (t == 0) {
-        st->status = CP_ENOTSPD;
-        st->done = 1;
+        for (int ai = 0; ai < NBK; ++ai) colbuf[b][ty + TD * ai] = a[ai][jb];
       }
-      return;
-    }
-    const double d = sqrt(piv), rp = 1.0 / piv, rd = 1.0 / d;
-    double u[NBK], v[NBK];
-#pragma unroll
-    for (int q = 0; q < NBK; ++q) {
-      const int i = ty + TD * q, k = tx + TD * q;
-      u[q] = i > j ? colbuf[b][i] * rp : 0.0;
-      v[q] = k > j ? colbuf[b][k] : 0.0;
-    }
-#pragma unroll
-    for (int ai = 0; ai < NBK; ++ai)
-#pragma unroll
-      for (int bk = 0; bk < NBK; ++bk) a[ai][bk] -= u[ai] * v[bk];
-    if (tx == jt) {   // column j of L: rows below the pivot, and the pivot itself
-#pragma unroll
-      for (int bk = 0; bk < NBK; ++bk)
-        if (bk == jb) {
-#pragma unroll
-          for (int ai = 0; ai < NBK; ++ai) {
-            const int i = ty + TD * ai;
-            if (i > j) a[ai][bk] = colbuf[b][i] * rd;
-            else if (i == j) a[ai][bk] = d;
-          }
+      __syncthreads();
+      const double piv = colbuf[b][j];
+      if (!(piv > 0.0) || !isfinite(piv)) {   // same value in every thread: uniform exit
+        if (t == 0) {
+          st->status = CP_ENOTSPD;
+          st->done = 1;
         }
+        return;
+      }
+      const double d = sqrt(piv), rp = 1.0 / piv, rd = 1.0 / d;
+      double u[NBK], v[NBK];
+#pragma unroll
+      for (int q = 0; q < NBK; ++q) {
+        const int i = ty + TD * q, k = tx + TD * q;
+        u[q] = i > j ? colbuf[b][i] * rp : 0.0;
+        v[q] = k > j ? colbuf[b][k] : 0.0;
+      }
+#pragma unroll
+      for (int ai = 0; ai < NBK; ++ai)
+#pragma unroll
+        for (int bk = 0; bk < NBK; ++bk) a[ai][bk] -= u[ai] * v[bk];
+      if (tx == jt) {   // column j of L: rows below the pivot, and the pivot itself
+#pragma unroll
+        for (int ai = 0; ai < NBK; ++ai) {
+          const int i = ty + TD * ai;
+          if (i > j) a[ai][jb] = colbuf[b][i] * rd;
+          else if (i == j) a[ai][jb] = d;
+        }
+      }
     }
   }
 #pragma unroll
