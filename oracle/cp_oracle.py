@@ -10,7 +10,7 @@ Gauss-Newton and Alternating Least Squares for CP Decomposition" (arXiv:1910.123
 numbers refer to that paper: (1) the Khatri-Rao product P^(n), (2) the Hadamard product of Grams
 Gamma^(n), (3) the objective f, (4) the Jacobian tensor, (5) the blocks of J^T J, (6) the
 generalised Gamma^(n,p), (7) the implicit matrix-vector contraction. Algorithm 1 is CP-GN,
-Algorithm 2 is CP-CG, Listing 1 is the per-pair einsum form of the matrix-vector product.
+Algorithm 2 is CP-CG.
 
 Conventions: a tensor is a C-order float64 ndarray of shape (s_1, ..., s_N); a factor list holds
 N arrays A[n] of shape (s_n, R). Everything is computed in float64 in the order the paper
@@ -162,25 +162,24 @@ def damping_matrix(Gam, n, damping="identity"):
 
 
 def jtj_matvec(A, W, lam=0.0, Gam=None, damping="identity"):
-    """Q(n) = lam W(n) D(n) + sum_p MatVec(A(n), A(p), Gamma(n,p), W(p))  (Algorithm 2,
-    eq. (7)), with D(n) the damping matrix (identity, or the diagonal of J^T J).
+    """Q(n) = lam W(n) D(n) + sum_p (J^T J)(n,p) W(p): the damped Gauss-Newton matrix applied to
+    W block by block (Algorithm 2, eq. (7)), with D(n) the damping matrix (identity, or the
+    diagonal of J^T J).
 
-    Each (n, p) term is the Listing 1 contraction written out literally:
-      n == p:  U[k,r] = sum_z Gamma(n,n)[r,z] W(n)[k,z]
-      n != p:  U[k,r] = sum_{l,z} A(n)[k,z] A(p)[l,r] Gamma(n,p)[r,z] W(p)[l,z]
+    By eq. (5) the (n, n) block acts as W(n) Gamma(n,n). For p != n the block maps W(p) to the
+    rows sum_{l,z} A(n)[k,z] A(p)[l,r] Gamma(n,p)[r,z] W(p)[l,z]; summing over l first gives
+    A(n) (Gamma(n,p) * (W(p)^T A(p))), * the elementwise product (Gamma(n,p) is symmetric).
     """
     N = len(A)
     if Gam is None:
         Gam = gamma_set(grams(A))
     Q = []
     for n in range(N):
-        U = lam * (W[n] @ damping_matrix(Gam, n, damping))
+        q = lam * (W[n] @ damping_matrix(Gam, n, damping)) + W[n] @ Gam[n][n]
         for p in range(N):
-            if n == p:
-                U = U + np.einsum("rz,kz->kr", Gam[n][p], W[p])
-            else:
-                U = U + np.einsum("kz,lr,rz,lz->kr", A[n], A[p], Gam[n][p], W[p], optimize=True)
-        Q.append(U)
+            if p != n:
+                q = q + A[n] @ (Gam[n][p] * (W[p].T @ A[p]))
+        Q.append(q)
     return Q
 
 
