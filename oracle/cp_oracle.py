@@ -338,7 +338,7 @@ class ArmijoResult:
 
 
 def gn_step_armijo(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity", c=1e-4, shrink=0.5,
-                   max_trials=10):
+                   max_trials=10, precond="inverse"):
     """Gauss-Newton step with Armijo step-size control (the variant Section 5 uses for the
     matrix-multiplication tensors): the direction V of Algorithm 1, then the step sizes
     alpha = 1, shrink, shrink^2, ... (at most max_trials of them) are tried in that order and the
@@ -351,7 +351,7 @@ def gn_step_armijo(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity", c=1e-
     Gam = gamma_set(S)
     M = [mttkrp(X, A, n) for n in range(N)]
     G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
-    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping)
+    res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping, precond)
     f0 = objective(X, A)
     gv = sum(_inner(G[n], res.V[n]) for n in range(N))
     alpha, trials, accepted, f, out = 1.0, 0, False, f0, [a.copy() for a in A]

@@ -56,16 +56,18 @@ def trial_margins(X, A, ref, c, shrink):
 
 
 def armijo_compare(X, A, dt, lam, cg_tol, maxiter, c=1e-4, shrink=0.5, max_trials=10, tol=None,
-                   margin=1e-3):
+                   margin=1e-3, damping="identity", precond="inverse"):
     if tol is None:
         tol = 1e-9 if dt == torch.float64 else 2e-3
     if dt == torch.float32:   # the oracle sees the FP32-rounded inputs
         X = X.astype(np.float32).astype(np.float64)
         A = [a.astype(np.float32).astype(np.float64) for a in A]
-    ref = O.gn_step_armijo(X, A, lam, cg_tol, maxiter, c=c, shrink=shrink, max_trials=max_trials)
+    ref = O.gn_step_armijo(X, A, lam, cg_tol, maxiter, damping, c=c, shrink=shrink,
+                           max_trials=max_trials, precond=precond)
     assert all(abs(m) > margin for m in trial_margins(X, A, ref, c, shrink))
     Xd, Ad = dev([X], dt)[0], dev(A, dt)
-    st, ls = P.gn_step_armijo(Xd, Ad, lam, cg_tol, maxiter, c, shrink, max_trials)
+    st, ls = P.gn_step_armijo(Xd, Ad, lam, cg_tol, maxiter, c, shrink, max_trials,
+                              damping=damping, preconditioner=precond)
     st, ls = P.read_stats(st), P.read_armijo_stats(ls)
     assert st["status"] == 0
     assert ls["accepted"] == int(ref.accepted) and ls["trials"] == ref.trials
@@ -123,6 +125,16 @@ def test_armijo_step_fp32(dims, rank, scale, seed):
     X, A = small_start(dims, rank, scale, seed)
     ref, ls = armijo_compare(X, A, torch.float32, 1e-6, 0.0, 12)
     assert ref.accepted and ref.alpha < 1.0
+
+
+@pytest.mark.parametrize("damping,precond", [("diagonal", "inverse"), ("identity", "cholesky"),
+                                             ("diagonal", "cholesky")])
+def test_armijo_with_damping_and_preconditioner_forms(damping, precond):
+    """The search composes with diagonal damping and the triangular-solve preconditioner."""
+    X, A = small_start((37, 29, 45), 12, 0.3, 2)
+    ref, ls = armijo_compare(X, A, torch.float64, 1e-6, 1e-6, 50, damping=damping,
+                             precond=precond)
+    assert ref.accepted and ls["f"] < ls["f0"]
 
 
 def test_armijo_sufficient_decrease_constant_decides():
