@@ -220,3 +220,15 @@ def test_gn_flag_constant_matches_header():
     assert m and int(m.group(1)) == L.GN_DIAG_DAMPING
     m = re.search(r"#define\s+CP_GN_CHOL_PRECOND\s+(\d+)u", text)
     assert m and int(m.group(1)) == L.GN_CHOL_PRECOND
+
+
+def test_mode_longer_than_the_row_tile_grid_is_refused(lib):
+    """The MTTKRP grids hold at most 65535 row tiles per mode: a 2.2-million-row mode is refused
+    in FP64 (16-row tree tiles) and FP32 (32-row tree tiles) at the plan, before any launch; a
+    1-million-row mode is accepted."""
+    n = C.c_size_t(0)
+    for dt in (L.CP_F64, L.CP_F32):
+        p = prob(dims=(2_200_000, 3, 4), rank=4, dt=dt)
+        assert lib.cp_workspace_bytes(C.byref(p), L.OP_MTTKRP, C.byref(n)) == L.CP_EUNSUPPORTED
+        p = prob(dims=(1_000_000, 3, 4), rank=4, dt=dt)
+        assert lib.cp_workspace_bytes(C.byref(p), L.OP_MTTKRP, C.byref(n)) == L.CP_OK
