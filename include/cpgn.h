@@ -31,9 +31,6 @@
  *     non-finite values) are written as a status code into device memory (the `status` field
  *     of cp_gn_stats, or `status_dev`); the caller reads it after synchronising the stream.
  *     On such a failure the factors are left unchanged.
- *   - A mode may have at most 65535 MTTKRP row tiles of 16 to 64 rows (at least 1 million rows
- *     for every precision and launch form: 2.1 million for FP32, 1.05 million for FP64 in the
- *     order-3 tree pass); longer modes give CP_EUNSUPPORTED.
  *   - The Gauss-Newton steps and cp_als_sweep need rank <= 208 (their R x R inverse is held in
  *     one workgroup's registers, and so are the CG operand rows) and return CP_EUNSUPPORTED
  *     otherwise; the other calls take any rank.

@@ -85,11 +85,8 @@ int make_plan(const cp_problem* prob, Plan* p) {
   int64_t part = p->qc_last * 16 * p->Rp;   // residual's packed last factor reuses this region
   int64_t p1 = 0;
   int64_t krp = 0;
-  // The MTTKRP launches put the row tiles of a mode (16 to 64 rows each) in grid y, at most
-  // 65535 of them.
   for (int n = 0; n < p->N && p->xk != 0; ++n) {
     const MttkrpGeom g = mttkrp_geom_bf16(*p, n);
-    if (g.RT > 65535 || g.SW > 65535) return CP_EUNSUPPORTED;
     const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
     part = e > part ? e : part;
     krp += g.O * p->Rp;
@@ -99,7 +96,6 @@ int make_plan(const cp_problem* prob, Plan* p) {
       const bool dt = v >= 2;
       if (dt && !(n == 0 && p->N == 3)) continue;
       const MttkrpGeom g = mttkrp_geom(*p, n, (v & 1) == 1, dt);
-      if (g.RT > 65535 || g.SW > 65535) return CP_EUNSUPPORTED;
       const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
       part = e > part ? e : part;
       if (dt) {

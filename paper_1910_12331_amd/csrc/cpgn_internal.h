@@ -16,6 +16,8 @@ constexpr int kRedSlots = 1024;   // max blocks contributing to one deterministi
 // Largest rank of the Gauss-Newton step and the ALS sweep: their R x R inverse and the CG
 // kernels' operand rows are held in registers, 16 columns per block, at most 13 blocks.
 constexpr int kMaxGnRank = 208;
+// Largest grid y (and z) dimension of a launch.
+constexpr int64_t kMaxGridY = 65535;
 constexpr int kNumCU = 256;       // compute units of an MI355X (8 XCDs x 32)
 
 // ------------------------------------------------------------------------------------------

@@ -36,6 +36,7 @@ struct MttkrpArgs {
   int Rp, NBt, cb0;
   int nsplit;                   // wavefronts along the contraction split (= 4 * gridDim.x)
   int dt;                       // also emit the outer mode's MTTKRP partials (order 3)
+  int64_t rt0;                  // first row tile of this launch (grid y holds at most 65535)
 };
 
 template <typename T, int MB> struct VecLoad;
@@ -161,7 +162,8 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, m = lane & 15;
   const int split = blockIdx.x * 4 + wave;
-  const int64_t j0 = (int64_t)blockIdx.y * 16 * MB;
+  const int64_t rt = a.rt0 + blockIdx.y;
+  const int64_t j0 = rt * 16 * MB;
   const int64_t it0 = a.nitems * split / a.nsplit;
   const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
   const T* __restrict__ X = (const T*)a.X;
@@ -225,7 +227,7 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
     if constexpr (DT) {
       const T* W = (const T*)a.wfac + 16 * a.cb0 + m;
       const int64_t h = split - owner_split(o * a.QC, a.nitems, a.nsplit);
-      T* P1 = (T*)a.p1 + ((((int64_t)blockIdx.y * a.O + o) * a.HS + h) * a.Rp) + 16 * a.cb0 + m;
+      T* P1 = (T*)a.p1 + (((rt * a.O + o) * a.HS + h) * a.Rp) + 16 * a.cb0 + m;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         T sum = T(0);
@@ -670,7 +672,11 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   for (int cb0 = 0; cb0 < p.NBt; cb0 += 8) {
     const int NB = p.NBt - cb0 < 8 ? p.NBt - cb0 : 8;
     a.cb0 = cb0;
-    launch_variant<T>(caseB, vec, G.MB, NB, dim3((unsigned)G.SW, (unsigned)G.RT), st, a);
+    for (int64_t rt0 = 0; rt0 < G.RT; rt0 += kMaxGridY) {   // row tiles in chunks of grid y
+      a.rt0 = rt0;
+      const int64_t nrt = G.RT - rt0 < kMaxGridY ? G.RT - rt0 : kMaxGridY;
+      launch_variant<T>(caseB, vec, G.MB, NB, dim3((unsigned)G.SW, (unsigned)nrt), st, a);
+    }
   }
   hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(reduce_grid(a.J, p.R)), dim3(1024), 0, st,
                      (const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);

@@ -46,6 +46,7 @@ struct Bf16Args {
   int Rp, NBt, cb0, nb;         // nb: column blocks of this launch (<= kBfNB)
   int nsplit;                   // wavefronts along the item split (= waves per workgroup x gridDim.x)
   int flds;                     // inner factor staged in LDS (else read per item)
+  int64_t rt0;                  // first row tile of this launch (grid y holds at most 65535)
 };
 
 // Tile and launch shape per case (measured at 80^4 R=64): case A keeps one wavefront per SIMD
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(BfTile<CASE_B>::W * 64, 1) void k_mttkrp_bf16(Bf16A
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, m = lane & 15;
   const int split = blockIdx.x * kBfWaves + wave;
-  const int64_t j0 = (int64_t)blockIdx.y * 16 * MB;
+  const int64_t j0 = (a.rt0 + blockIdx.y) * 16 * MB;
   const int64_t it0 = a.nitems * split / a.nsplit;
   const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
 
@@ -448,9 +449,13 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
     const size_t rbytes = (size_t)2 * G.MB * NB * kWave * 16;
     a.flds = fbytes <= (size_t)kBfLdsF ? 1 : 0;
     const size_t lds = a.flds && fbytes > rbytes ? fbytes : rbytes;
-    const dim3 grid((unsigned)G.SW, (unsigned)G.RT);
-    if (caseB) bf_launch<true>(x3, vec, NB, grid, lds, st, a);
-    else bf_launch<false>(x3, vec, NB, grid, lds, st, a);
+    for (int64_t rt0 = 0; rt0 < G.RT; rt0 += kMaxGridY) {   // row tiles in chunks of grid y
+      a.rt0 = rt0;
+      const int64_t nrt = G.RT - rt0 < kMaxGridY ? G.RT - rt0 : kMaxGridY;
+      const dim3 grid((unsigned)G.SW, (unsigned)nrt);
+      if (caseB) bf_launch<true>(x3, vec, NB, grid, lds, st, a);
+      else bf_launch<false>(x3, vec, NB, grid, lds, st, a);
+    }
   }
   launch_mttkrp_reduce_f32(a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, CP_F32, st);
   return (int)hipGetLastError();

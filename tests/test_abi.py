@@ -222,13 +222,11 @@ def test_gn_flag_constant_matches_header():
     assert m and int(m.group(1)) == L.GN_CHOL_PRECOND
 
 
-def test_mode_longer_than_the_row_tile_grid_is_refused(lib):
-    """The MTTKRP grids hold at most 65535 row tiles per mode: a 2.2-million-row mode is refused
-    in FP64 (16-row tree tiles) and FP32 (32-row tree tiles) at the plan, before any launch; a
-    1-million-row mode is accepted."""
+def test_mode_longer_than_one_row_tile_grid_is_planned(lib):
+    """A 2.2-million-row mode needs more than 65535 MTTKRP row tiles (the grid-y limit) in FP64
+    and FP32: the launches are split into chunks of row tiles, so the plan accepts it."""
     n = C.c_size_t(0)
     for dt in (L.CP_F64, L.CP_F32):
         p = prob(dims=(2_200_000, 3, 4), rank=4, dt=dt)
-        assert lib.cp_workspace_bytes(C.byref(p), L.OP_MTTKRP, C.byref(n)) == L.CP_EUNSUPPORTED
-        p = prob(dims=(1_000_000, 3, 4), rank=4, dt=dt)
-        assert lib.cp_workspace_bytes(C.byref(p), L.OP_MTTKRP, C.byref(n)) == L.CP_OK
+        for op in range(7):
+            assert lib.cp_workspace_bytes(C.byref(p), op, C.byref(n)) == L.CP_OK

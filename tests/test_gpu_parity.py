@@ -554,3 +554,25 @@ def test_highest_orders_every_entry_point_fp64(dims, rank):
     out = P.residual(X, A).cpu().numpy()
     num, den = O.residual(p.x, p.init)
     assert abs(out[0] - num) / num < 1e-12 and abs(out[1] - den) / den < 1e-12
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_mode_longer_than_one_row_tile_grid(dt):
+    """2.2 million rows in mode 0: 68750 (FP64) and 34375 (FP32) row tiles per single-mode launch,
+    137500 and 68750 in the order-3 tree pass, so the launches run in chunks of at most 65535 row
+    tiles. MTTKRP of every mode, the all-mode call, the residual and a GN step against the
+    oracle."""
+    dims, R = (2_200_000, 3, 4), 4
+    p = make_problem(dims, R, workload=0, problem=41, noise=1e-2)
+    Xh, Ah = rounded([p.x], dt)[0], rounded(p.init, dt)
+    X = to_dev([p.x], dt)[0]
+    A = to_dev(p.init, dt)
+    tol = 1e-12 if dt == torch.float64 else 2e-5
+    for n in range(3):
+        assert rel(P.mttkrp(X, A, n).double().cpu().numpy(), O.mttkrp(Xh, Ah, n)) < tol
+    for n, m in enumerate(P.mttkrp_all(X, A)):
+        assert rel(m.double().cpu().numpy(), O.mttkrp(Xh, Ah, n)) < tol
+    out = P.residual(X, A).cpu().numpy()
+    num, den = O.residual(Xh, Ah)
+    assert abs(out[0] - num) / num < (1e-12 if dt == torch.float64 else 1e-5)
+    gn_compare(p, dt, 1e-3, 0.0, 3, 1e-11 if dt == torch.float64 else 1e-4)
