@@ -3,6 +3,7 @@ drivers (Section 4): each step() is one ALS sweep or one Gauss-Newton iteration,
 libcpgn.so on the GPU."""
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, replace
 
 import torch
@@ -399,7 +400,6 @@ def _time_batched(problems, config, n_streams, graphs, steps) -> float:
     bgn.step()
     bgn.synchronize()
     torch.cuda.synchronize()
-    import time
     t0 = time.perf_counter()
     for _ in range(steps):
         bgn.step()
