@@ -243,3 +243,26 @@ def test_batched_graph_replays_with_cholesky_preconditioner_match_eager():
         runs.append(cur)
     for (_, Ae), (_, Ag) in zip(*runs):
         assert all(torch.equal(a, b) for a, b in zip(Ae, Ag))
+
+
+@pytest.mark.parametrize("variant", ["cholesky", "armijo"])
+def test_gn_to_target_with_variants(variant):
+    """A full run to 1e-10 with the triangular-solve preconditioner (the same iterates up to
+    rounding: the plain run's number of steps to within 2), or with Armijo control (the residual
+    never rises; from this start it avoids the plain run's overshoots and needs 14 steps
+    instead of 21)."""
+    p = make_problem((40, 40, 40), 5, workload=1)
+    X = torch.tensor(p.x, device="cuda")
+    runs = {}
+    for name in ("plain", variant):
+        A = [torch.tensor(a, device="cuda") for a in p.init]
+        cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20,
+                         preconditioner="cholesky" if name == "cholesky" else "inverse",
+                         line_search=P.Armijo() if name == "armijo" else None)
+        opt, hist = P.gn_to_target(X, A, 1e-10, cfg, max_steps=200)
+        assert hist[-1] <= 1e-10 and opt.stats()["status"] == 0
+        if name == "armijo":   # every accepted Armijo step lowers f, so the residual falls
+            assert all(b <= a * (1 + 1e-9) for a, b in zip(hist, hist[1:]))
+        runs[name] = len(hist)
+    if variant == "cholesky":
+        assert abs(runs[variant] - runs["plain"]) <= 2
