@@ -419,7 +419,21 @@ def main():
                                       P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
         mixed_s = time.perf_counter() - t0
         n32 = sum(1 for p_, _ in hmx if p_ == "torch.float32")
+        # FP64 with Armijo control (Section 5): f at the accepted point gives the residual
+        Aar = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
+        arm_cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20, line_search=P.Armijo())
+        P.gn_to_target(X64d, [a.clone() for a in Aar], 1e-8, arm_cfg, max_steps=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, har = P.gn_to_target(X64d, Aar, 1e-8, P.GNConfig(cg_tol=1e-3, cg_maxiter=20,
+                                                           line_search=P.Armijo()))
+        armijo_s = time.perf_counter() - t0
+        del Aar
+        log(f"[bench] time to 1e-8 with Armijo control (FP64): {armijo_s:.3f} s in {len(har)} "
+            f"steps (r={har[-1]:.2e})")
         ttt = dict(fp64_seconds=fp64_s, fp64_steps=len(h64), fp64_residual=h64[-1],
+                   fp64_armijo_seconds=armijo_s, fp64_armijo_steps=len(har),
+                   fp64_armijo_residual=har[-1],
                    mixed_seconds=mixed_s, mixed_steps_fp32=n32, mixed_steps_fp64=len(hmx) - n32,
                    mixed_residual=hmx[-1][1], speedup=fp64_s / mixed_s,
                    fp64_gn_step_20cg_ms=t20_64 * 1e3)

@@ -3,6 +3,7 @@ drivers (Section 4): each step() is one ALS sweep or one Gauss-Newton iteration,
 libcpgn.so on the GPU."""
 from __future__ import annotations
 
+import math
 import time
 from dataclasses import dataclass, replace
 
@@ -124,6 +125,12 @@ class GaussNewton:
         return out
 
     def residual(self) -> float:
+        """Direct relative residual ||X - [[A]]|| / ||X|| at the current factors. After an Armijo
+        step it is read from the search's own evaluation at the returned point (the same direct
+        residual kernel), without another pass over X."""
+        if self.ls_buf is not None and self.steps > 0:
+            s = api.read_armijo_stats(self.ls_buf)
+            return math.sqrt(2.0 * max(s["f"], 0.0)) / s["x_norm"]
         r = api.residual(self.X, self.A, ws=self.ws).cpu()
         return float(r[0] / r[1])
 
