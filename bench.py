@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--profile-bf16", action="store_true",
                     help="only run 3 cp_mttkrp calls per mode on the 80^4 R=64 tensor in bfloat16 "
                          "and split bfloat16 (for counter runs)")
+    ap.add_argument("--trajectory", type=int, default=0, metavar="STEPS",
+                    help="only run STEPS plain Gauss-Newton steps from the seeded start of the "
+                         "headline workload, FP32 and FP64 storage, printing each step's damping, "
+                         "CG iterations, gradient and update norms and residual, then exit")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the oracle's MTTKRP, GN step, ALS sweep and residual at "
+                         "300^3 R=50 and 400^3 R=100 on the host and print them as JSON")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run each single-mode MTTKRP and one device copy of X of known size "
                          "(the workload the rocprofv3 counter runs are taken on), then exit")
@@ -241,6 +248,127 @@ def high_rank_leg(P, torch, stream):
             "residual_ms": t_res * 1e3}
 
 
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            return max(int(i.get("num_threads", 1)) for i in info), \
+                ", ".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info}))
+    except Exception:
+        pass
+    return os.cpu_count(), "unknown"
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X64, A0, gpu_iters, seconds):
+    """The oracle (NumPy/SciPy FP64 on the FP32-rounded inputs) doing the work of the timed GPU
+    steps: each step is the oracle's Gauss-Newton step with the CG iteration count the GPU step
+    took (eps_cg = 0 and that count as the cap), plus its direct residual. The residual, a sum of
+    squared differences over the tensor, is timed on one slab of a tenth of mode 0 and scaled by
+    ten; the steps run in the timed window's order until about `seconds` have passed."""
+    import oracle as O
+    Xh = X64.astype(np.float32).astype(np.float64)
+    Ah = [a.astype(np.float32).astype(np.float64) for a in A0]
+    O.mttkrp(Xh, Ah, 0)                       # warm-up (BLAS threads, page-in)
+    sched = O.LambdaSchedule()
+    n_cpu, t_steps = 0, 0.0
+    while t_steps < seconds and n_cpu < len(gpu_iters):
+        t0 = time.perf_counter()
+        Ah, _ = O.gn_step(Xh, Ah, sched.value, 0.0, int(gpu_iters[n_cpu]))
+        t_steps += time.perf_counter() - t0
+        sched.advance()
+        n_cpu += 1
+    slab = Xh.shape[0] // 10
+    t0 = time.perf_counter()
+    O.residual(Xh[:slab], [Ah[0][:slab]] + Ah[1:])
+    t_res = (time.perf_counter() - t0) * Xh.shape[0] / slab
+    per_step = t_steps / n_cpu + t_res
+    cores, blas = blas_threads()
+    return dict(value=1.0 / per_step, unit="GN steps/s", cores=cores, kind="oracle",
+                sample=f"{n_cpu} oracle GN steps with the timed GPU steps' CG iteration counts "
+                       f"({t_steps:.1f} s) + the oracle's direct residual on a {slab}-row slab of "
+                       f"mode 0 scaled by {Xh.shape[0] / slab:g} ({t_res:.1f} s per step); "
+                       f"FP64 on the FP32-rounded inputs",
+                step_seconds=t_steps / n_cpu, residual_seconds=t_res, cpu=cpu_model(), blas=blas)
+
+
+def cpu_table(shapes=((300, 50), (400, 100)), runs=10, warm=3):
+    """Oracle timings on the host for the operations of one Gauss-Newton step and one ALS sweep
+    (FP64, seeded inputs of each shape with N(0,1) planted factors and start): single-mode
+    MTTKRP, a GN step with exactly 20 CG iterations and with eps_cg = 1e-3 (at most 20), an ALS
+    sweep, and the direct residual (on a slab of a tenth of mode 0, scaled). `warm` untimed runs,
+    then median and mean over `runs` (the residual: 3 runs)."""
+    import oracle as O
+    from workloads import make_problem
+    out = dict(cpu=cpu_model(), threads=blas_threads()[0], blas=blas_threads()[1],
+               nproc=os.cpu_count(), shapes={})
+    for s, R in shapes:
+        p = make_problem((s, s, s), R, workload=3, problem=s)
+        X, A = p.x.astype(np.float32).astype(np.float64), [a.astype(np.float32).astype(np.float64)
+                                                            for a in p.init]
+        row = {}
+
+        def timeit(name, fn, n=runs, w=warm):
+            for _ in range(w):
+                fn()
+            ts = []
+            for _ in range(n):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+            row[name] = dict(median_s=float(np.median(ts)), mean_s=float(np.mean(ts)), runs=n)
+            log(f"[cpu-table] {s}^3 R={R} {name}: median {np.median(ts):.4f} s over {n}")
+
+        for n in range(3):
+            timeit(f"mttkrp_mode{n}", lambda n=n: O.mttkrp(X, A, n))
+        timeit("gn_step_20cg", lambda: O.gn_step(X, A, 1e-4, 0.0, 20))
+        its = O.gn_step(X, A, 1e-4, 1e-3, 20)[1].cg_iters
+        timeit("gn_step_eps1e-3", lambda: O.gn_step(X, A, 1e-4, 1e-3, 20))
+        row["gn_step_eps1e-3"]["cg_iters"] = its
+        timeit("als_sweep", lambda: O.als_sweep(X, A))
+        slab = s // 10
+        timeit("residual_slab", lambda: O.residual(X[:slab], [A[0][:slab]] + A[1:]), n=3, w=1)
+        row["residual_scaled_s"] = row["residual_slab"]["median_s"] * s / slab
+        out["shapes"][f"{s}^3 R={R}"] = row
+    return out
+
+
+def trajectory_table(P, torch, Xd, X64, A0, steps):
+    """Plain Gauss-Newton steps (damping schedule, eps_cg 1e-3, <= 20 CG iterations) from the
+    seeded start with FP32 and with FP64 storage; one JSON line per step with the damping, the
+    CG iteration count, sum ||G(n)||, the update norm, the factor norm and the relative residual.
+    Stops a run at a non-finite residual."""
+    X64d = torch.from_numpy(X64).cuda()
+    for name, X, dt in (("f32", Xd, torch.float32), ("f64", X64d, torch.float64)):
+        opt = P.GaussNewton(X, [torch.tensor(a, dtype=dt, device="cuda") for a in A0],
+                            P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+        for k in range(steps):
+            lam = opt.schedule.value
+            opt.step()
+            st = opt.stats()
+            r = opt.residual()
+            print(json.dumps(dict(storage=name, step=k, lam=lam, cg_iters=st["cg_iters"],
+                                  grad_norm_sum=st["grad_norm_sum"],
+                                  update_norm=st["update_norm"],
+                                  factor_norm=sum(float(torch.linalg.norm(a.double()))
+                                                  for a in opt.A),
+                                  residual=r)), flush=True)
+            if not np.isfinite(r):
+                break
+    del X64d
+
+
 def kernel_source_hash():
     import hashlib
     path = os.path.join(ROOT, "paper_1910_12331_amd", "csrc", "mttkrp.hip")
@@ -254,6 +382,9 @@ def main():
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported. The decomposition "
               "runs on a single MI355X; no multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_table:
+        print(json.dumps(cpu_table()), flush=True)
+        return
     import torch
 
     import paper_1910_12331_amd as P
@@ -281,6 +412,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     A = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+    if args.trajectory:
+        trajectory_table(P, torch, Xd, X64, A0, args.trajectory)
+        return
     if args.profile_kernels:
         ws = P.Workspace()
         for n in range(3):
@@ -345,34 +479,71 @@ def main():
 
     high_rank = high_rank_leg(P, torch, stream)
 
-    # ---- GN steps: warmup, then K timed steps (GN step + direct residual)
-    A = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
-    gn = P.GaussNewton(Xd, A, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
-    resid = torch.empty(2, dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
+    # ---- GN steps: warmup, then K timed steps. A step is one Gauss-Newton iteration (Algorithm 1
+    # body) followed by the direct relative residual that its stopping test reads on the host.
+    # Runs go from the seeded start until the residual reaches the FP32 floor target (1e-6, where
+    # the mixed-precision driver leaves FP32 storage); the next step then starts a new run from
+    # the same start (the factors copied back, the damping schedule reset). Past that floor the
+    # FP32 gradient is rounding noise, and a step taken there leaves the converged point.
+    target = 1e-6
+    A_start = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+    gn = P.GaussNewton(Xd, [a.clone() for a in A_start], P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    run_state = dict(runs=0, run_steps=0)
+
+    def headline_step():
         gn.step()
-        P.residual(Xd, gn.A, out=resid, ws=gn.ws)
+        r = gn.residual()
+        run_state["run_steps"] += 1
+        if r <= target or not np.isfinite(r):
+            for a, a0 in zip(gn.A, A_start):
+                a.copy_(a0)
+            gn.schedule = P.DampingSchedule()
+            run_state["runs"] += 1
+            run_state["run_steps"] = 0
+        return r
+
+    for _ in range(args.warmup):
+        headline_step()
     torch.cuda.synchronize()
-    iters = []
+    runs_before = run_state["runs"]
+    res_timed = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        gn.step()
-        P.residual(Xd, gn.A, out=resid, ws=gn.ws)
+        res_timed.append(headline_step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    r_now = float(resid[0] / resid[1])
     ms_step = elapsed / args.steps * 1e3
-    log(f"[bench] GN step + residual: {ms_step:.3f} ms; residual {r_now:.3e}")
+    r_now = res_timed[-1]
+    log(f"[bench] GN step + residual: {ms_step:.3f} ms; residuals of the timed steps "
+        + " ".join(f"{r:.2e}" for r in res_timed))
 
-    # CG iterations of the timed steps: the kernels are deterministic, so an untimed replay from
-    # the same start reads them step by step.
-    Ar = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
-    gr = P.GaussNewton(Xd, Ar, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    # CG iterations of the timed steps: the kernels are deterministic, so an untimed replay of
+    # the same runs reads them step by step (its residuals must equal the timed ones bitwise).
+    gr = P.GaussNewton(Xd, [a.clone() for a in A_start], P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    iters, replay_res = [], []
     for k in range(args.warmup + args.steps):
         gr.step()
+        r = gr.residual()
         if k >= args.warmup:
             iters.append(gr.stats()["cg_iters"])
-    del Ar, gr
+            replay_res.append(r)
+        if r <= target or not np.isfinite(r):
+            for a, a0 in zip(gr.A, A_start):
+                a.copy_(a0)
+            gr.schedule = P.DampingSchedule()
+    del gr
+    r0_ = P.residual(Xd, A_start, ws=gn.ws).cpu()
+    r_start = float(r0_[0] / r0_[1])
+    finite = bool(np.all(np.isfinite(res_timed)))
+    valid = finite and replay_res == res_timed and max(res_timed) < 10.0 * r_start
+    if not valid:
+        log("[bench] WARNING: a timed step left the converging runs")
+    trajectory = dict(start_residual=r_start, target=target, residuals=res_timed,
+                      runs_completed_in_timed_window=run_state["runs"] - runs_before,
+                      replay_equals_timed_run=replay_res == res_timed, valid=valid,
+                      note="relative residual after each timed step; a run restarts from the "
+                           "seeded start once its residual is <= target. valid: all finite, "
+                           "bitwise equal to an untimed replay, none above 10x the start")
 
     # ---- GN step with exactly 20 CG iterations (eps_cg = 0), FP32 and FP64
     A20 = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
@@ -388,6 +559,7 @@ def main():
                                         preconditioner="cholesky"), 3, stream)
     log(f"[bench] GN step with 20 CG iterations: {t20 * 1e3:.3f} ms with the explicit inverse, "
         f"{t20c * 1e3:.3f} ms with Cholesky triangular solves")
+    resid = torch.empty(2, dtype=torch.float64, device="cuda")
     res_t = event_time(lambda: P.residual(Xd, gn.A, out=resid, ws=gn.ws), 10, stream)
 
     # ---- time to relative residual 1e-8, FP64 storage (the FP32 rounding floor is ~3e-8)
@@ -503,26 +675,9 @@ def main():
     # ---- CPU baseline: the oracle on host cores, bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        Xh = X64.astype(np.float32).astype(np.float64)
-        Ah = [a.astype(np.float32).astype(np.float64) for a in A0]
-        sched = O.LambdaSchedule()
-        n_cpu, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < args.cpu_seconds and n_cpu < 50:
-            Ah, _ = O.gn_step(Xh, Ah, sched.value, 1e-3, 20)
-            O.residual(Xh, Ah)
-            sched.advance()
-            n_cpu += 1
-        cpu_el = time.perf_counter() - t0
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
-        except Exception:
-            cores = os.cpu_count()
-        cpu = dict(value=n_cpu / cpu_el, unit="GN steps/s", cores=cores, kind="oracle",
-                   sample=f"first {n_cpu} oracle GN steps (+ direct residual) of the same 400^3 R=100 "
-                          f"workload in FP64 on the FP32-rounded inputs, {cpu_el:.1f} s")
-        log(f"[bench] CPU oracle: {cpu['value']:.3f} GN steps/s on {cores} threads")
+        cpu = cpu_baseline(X64, A0, iters, args.cpu_seconds)
+        log(f"[bench] CPU oracle: {cpu['value']:.4f} GN steps/s on {cpu['cores']} threads "
+            f"({cpu['sample']})")
 
     traffic = None
     if MTTKRP_TRAFFIC is not None and MTTKRP_TRAFFIC["source_sha256"] == kernel_source_hash():
@@ -542,7 +697,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dense {s}x{s}x{s} FP32 tensor, exact rank-{R} CP with N(0,1) "
                                f"factors; GN-CG rank {R}, eps_cg 1e-3, <=20 CG its, varying lambda "
-                               f"1e-4..1e-10 (mu 2); step = GN step + direct residual",
+                               f"1e-4..1e-10 (mu 2); step = GN step + direct residual at the new "
+                               f"point, the step kept only if f decreases",
                    "dims": [s, s, s], "rank": R, "device": dev_name},
         "roofline": {"bound": "mfma", "achieved": flops / mean_t / 1e12,
                      "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -579,6 +735,7 @@ def main():
         "cg_iters_mean": float(np.mean(iters)),
         "cg_iters": iters,
         "residual_after": r_now,
+        "trajectory": trajectory,
         "time_to_1e-8": ttt,
         "batched": batched,
         "order4_bf16": order4,

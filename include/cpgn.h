@@ -198,8 +198,14 @@ typedef struct cp_armijo_params {
   double c;             /* sufficient-decrease constant, 0 < c < 1 (e.g. 1e-4)                 */
   double shrink;        /* factor between successive step sizes, 0 < shrink < 1 (e.g. 0.5)     */
   int32_t max_trials;   /* objective evaluations at most, 0..64                                */
-  int32_t reserved;     /* must be 0                                                           */
+  uint32_t flags;       /* 0 or CP_LS_F0_GIVEN; other bits must be 0                           */
 } cp_armijo_params;
+
+/* cp_armijo_params.flags bit. CP_LS_F0_GIVEN: f(A) and ||X||_F are read from the cp_armijo_stats
+   that the previous cp_gn_step_armijo call on these same factors wrote (its f and x_norm: f at
+   the point it returned), instead of one more direct residual pass over X at the start. The
+   caller guarantees that the factors have not changed since that call. */
+#define CP_LS_F0_GIVEN 1u
 
 typedef struct cp_armijo_stats {
   double alpha;         /* accepted step size; 0 if none was accepted                          */
@@ -221,7 +227,12 @@ typedef struct cp_armijo_stats {
  * runs when the CG status is a failure, when sum <G, V> >= 0 (no descent, e.g. V = 0 with
  * cg_maxiter = 0) or when f(A) is not finite; then, and when no trial passes, the factors are left
  * unchanged and accepted = 0. The search runs on the device without host synchronisation: every
- * trial is launched and the ones after a passing trial return at once.
+ * trial is launched and the ones after a passing trial return at once. With max_trials = 1 it is
+ * the accept-or-reject rule of a damped Gauss-Newton (Levenberg-Marquardt) iteration: the full
+ * step is taken only when it decreases f enough, so a run never leaves a converging trajectory
+ * when the gradient has become rounding noise. With CP_LS_F0_GIVEN in ls->flags, f(A) comes from
+ * the previous call's ls_stats (read on the device, stream-ordered) and the step costs one
+ * residual pass (the trial) instead of two.
  *   A: N device pointers, read and overwritten in place (f_dtype).
  *   params, ls: HOST pointers. stats: DEVICE pointer to one cp_gn_stats (update_norm is
  *   ||alpha V||). ls_stats: DEVICE pointer to one cp_armijo_stats.

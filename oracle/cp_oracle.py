@@ -37,6 +37,7 @@ __all__ = [
     "GNStepStats", "LambdaSchedule", "als_sweep", "residual", "residual_expansion", "gn", "als",
     "jacobian", "jtj_dense", "flatten_factors", "unflatten_factors", "OracleError",
     "damping_matrix", "gn_step_armijo", "ArmijoResult", "cholesky_factors", "cholesky_apply",
+    "block_norm_sum",
 ]
 
 
@@ -236,61 +237,79 @@ class PCGResult:
     history: list = field(default_factory=list)
 
 
+def block_norm_sum(blocks):
+    """sum_n ||B(n)||_F over the per-mode blocks: the norm Algorithms 1 and 2 use in their stop
+    tests (a sum of per-mode Frobenius norms, not one 2-norm of the stacked vector)."""
+    return sum(_fro(b) for b in blocks)
+
+
 def pcg(G, A, lam, eps_cg=1e-3, maxiter=20, Gam=None, damping="identity", precond="inverse"):
-    """Algorithm 2 (CP-CG): preconditioned implicit CG for (J^T J + lam D) V = -G, with D the
-    identity or (damping == "diagonal") the diagonal of J^T J.
+    """Preconditioned CG for (J^T J + lam D) V = -G, D the identity or (damping == "diagonal")
+    the diagonal of J^T J: the linear solve inside each step of Algorithm 1, with the block
+    preconditioner (Gamma(n,n) + lam D(n))^-1 and the stop test of Algorithm 2.
 
-    Steps, in the paper's order: P_inv(n) = (Gamma(n,n) + lam I)^-1; V = 0; R = -G;
-    Z = R P_inv; W = Z. While sum ||R(n)|| > eps_cg sum ||G(n)|| (and fewer than ``maxiter``
-    iterations): Q = lam W + MatVec(W); alpha = sum<R,Z> / sum<W,Q>; V += alpha W;
-    R -= alpha Q; Z = R P_inv; beta = sum<R,Z>_new / sum<R,Z>_old; W = Z + beta W.
-
-    beta uses the standard preconditioned-CG ratio (the printed denominator sum<W,Q> is read as
-    a typo). A non-positive curvature sum<W,Q> <= 0 raises OracleError.
+    The iteration is the textbook preconditioned conjugate-gradient recurrence (Y. Saad,
+    "Iterative Methods for Sparse Linear Systems", 2nd ed., SIAM 2003, Algorithm 9.1), run on the
+    unknowns stacked into one vector x of length sum_n s_n R, starting from x = 0: the operator is
+    eq. (7)'s product (jtj_matvec), the preconditioner acts block by block, and the inner
+    products are plain dot products of the stacked vectors. Its direction coefficient is the
+    textbook ratio of successive <r, z>; the printed Algorithm 2 divides by <W, Q> there instead,
+    which is read as a typo (that ratio does not converge). Iteration stops when the sum of the
+    per-mode residual norms is at most eps_cg times that of the gradient, or after maxiter
+    iterations. A non-positive curvature <p, H p> raises OracleError.
 
     precond="cholesky" applies the same preconditioner by triangular solves with the Cholesky
-    factor of Gamma(n,n) + lam D(n) instead of multiplying by its explicit inverse.
+    factor of Gamma(n,n) + lam D(n) (Section 3.3's alternative) instead of its explicit inverse.
     """
     N = len(A)
+    dims = [a.shape[0] for a in A]
+    rank = A[0].shape[1]
     if Gam is None:
         Gam = gamma_set(grams(A))
     if precond == "inverse":
         P = preconditioner(Gam, lam, damping)
-        apply = lambda n, Rn: Rn @ P[n]   # noqa: E731
+        blockwise = lambda n, rn: rn @ P[n]   # noqa: E731
     elif precond == "cholesky":
         Lf = cholesky_factors(Gam, lam, damping)
-        apply = lambda n, Rn: cholesky_apply(Lf[n], Rn)   # noqa: E731
+        blockwise = lambda n, rn: cholesky_apply(Lf[n], rn)   # noqa: E731
     else:
         raise ValueError(precond)
-    V = [np.zeros_like(g) for g in G]
-    R = [-g for g in G]
-    Z = [apply(n, R[n]) for n in range(N)]
-    W = [z.copy() for z in Z]
-    gsum = sum(_fro(g) for g in G)
-    rz = sum(_inner(R[n], Z[n]) for n in range(N))
-    rsum = sum(_fro(r) for r in R)
-    it = 0
-    alpha = beta = 0.0
-    hist = []
+
+    def split(v):
+        return unflatten_factors(v, dims, rank)
+
+    def op(v):          # y = (J^T J + lam D) v
+        return flatten_factors(jtj_matvec(A, split(v), lam, Gam, damping))
+
+    def prec(v):        # z = M^-1 v, one block per mode
+        return flatten_factors([blockwise(n, b) for n, b in enumerate(split(v))])
+
+    b = -flatten_factors(G)
+    x = np.zeros_like(b)
+    r = b.copy()                      # r0 = b - H x0 with x0 = 0
+    z = prec(r)
+    p = z.copy()
+    rz = float(r @ z)
+    gsum = block_norm_sum(G)
+    rsum = block_norm_sum(split(r))
+    it, alpha, beta, hist = 0, 0.0, 0.0, []
     while rsum > eps_cg * gsum and it < maxiter:
-        Q = jtj_matvec(A, W, lam, Gam, damping)
-        wq = sum(_inner(W[n], Q[n]) for n in range(N))
-        if not wq > 0.0:
-            raise OracleError("CG breakdown: sum <W,Q> <= 0")
-        alpha = rz / wq
-        for n in range(N):
-            V[n] = V[n] + alpha * W[n]
-            R[n] = R[n] - alpha * Q[n]
-            Z[n] = apply(n, R[n])
-        rz_new = sum(_inner(R[n], Z[n]) for n in range(N))
-        beta = rz_new / rz
-        for n in range(N):
-            W[n] = Z[n] + beta * W[n]
-        rz = rz_new
-        rsum = sum(_fro(r) for r in R)
+        hp = op(p)
+        curv = float(p @ hp)
+        if not curv > 0.0:
+            raise OracleError("CG breakdown: <p, H p> <= 0")
+        alpha = rz / curv
+        x = x + alpha * p
+        r = r - alpha * hp
+        z = prec(r)
+        rz_next = float(r @ z)
+        beta = rz_next / rz
+        p = z + beta * p
+        rz = rz_next
+        rsum = block_norm_sum(split(r))
         it += 1
         hist.append(dict(alpha=alpha, beta=beta, res_norm_sum=rsum))
-    return PCGResult(V=V, iters=it, res_norm_sum=rsum, grad_norm_sum=gsum,
+    return PCGResult(V=split(x), iters=it, res_norm_sum=rsum, grad_norm_sum=gsum,
                      alpha_last=alpha, beta_last=beta, history=hist)
 
 
@@ -338,21 +357,23 @@ class ArmijoResult:
 
 
 def gn_step_armijo(X, A, lam, eps_cg=1e-3, maxiter=20, damping="identity", c=1e-4, shrink=0.5,
-                   max_trials=10, precond="inverse"):
+                   max_trials=10, precond="inverse", f0=None):
     """Gauss-Newton step with Armijo step-size control (the variant Section 5 uses for the
     matrix-multiplication tensors): the direction V of Algorithm 1, then the step sizes
     alpha = 1, shrink, shrink^2, ... (at most max_trials of them) are tried in that order and the
     first one with f(A + alpha V) <= f(A) + c alpha <G, V> is taken (Armijo's sufficient-decrease
     condition; f is eq. (3), G its gradient). The paper gives no constants: c, shrink and
     max_trials are parameters. If <G, V> is not negative (no descent, e.g. V = 0) or no trial
-    passes, the factors are returned unchanged with accepted = False."""
+    passes, the factors are returned unchanged with accepted = False. f0, when given, is f(A)
+    (known from a previous evaluation at this point) and is not evaluated again."""
     N = len(A)
     S = grams(A)
     Gam = gamma_set(S)
     M = [mttkrp(X, A, n) for n in range(N)]
     G = [A[n] @ Gam[n][n] - M[n] for n in range(N)]
     res = pcg(G, A, lam, eps_cg, maxiter, Gam, damping, precond)
-    f0 = objective(X, A)
+    if f0 is None:
+        f0 = objective(X, A)
     gv = sum(_inner(G[n], res.V[n]) for n in range(N))
     alpha, trials, accepted, f, out = 1.0, 0, False, f0, [a.copy() for a in A]
     if gv < 0.0 and math.isfinite(f0):

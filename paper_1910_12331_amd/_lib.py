@@ -14,6 +14,7 @@ CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
 OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL, OP_MTTKRP_ALL = range(7)
 GN_DIAG_DAMPING = 1
 GN_CHOL_PRECOND = 2
+LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
@@ -39,7 +40,7 @@ class CpGnStats(C.Structure):
 
 class CpArmijoParams(C.Structure):
     _fields_ = [("c", C.c_double), ("shrink", C.c_double), ("max_trials", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_uint32)]
 
 
 class CpArmijoStats(C.Structure):

@@ -284,11 +284,13 @@ def read_armijo_stats(buf: torch.Tensor) -> dict:
 def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
                    cg_maxiter: int = 20, c: float = 1e-4, shrink: float = 0.5,
                    max_trials: int = 10, stats=None, ls_stats=None, ws=None,
-                   damping: str = "identity", preconditioner: str = "inverse"):
+                   damping: str = "identity", preconditioner: str = "inverse",
+                   f0_given: bool = False):
     """Gauss-Newton step with Armijo step-size control (Section 5), in place on A: the direction
     of gn_step, then the first of alpha = 1, shrink, shrink^2, ... (at most max_trials) with
     f(A + alpha V) <= f(A) + c alpha <G, V>. Returns (stats buffer, Armijo stats buffer), both on
-    the device (read_stats, read_armijo_stats)."""
+    the device (read_stats, read_armijo_stats). f0_given=True takes f(A) from ls_stats as the
+    previous call on these same factors left it (CP_LS_F0_GIVEN) instead of a residual pass."""
     if damping not in ("identity", "diagonal"):
         raise ValueError("damping must be 'identity' or 'diagonal'")
     _dev(X, "X")
@@ -297,10 +299,13 @@ def gn_step_armijo(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_to
     prob = _problem(X, R)
     prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
                        _gn_flags(damping, preconditioner))
-    ls = L.CpArmijoParams(float(c), float(shrink), int(max_trials), 0)
+    ls = L.CpArmijoParams(float(c), float(shrink), int(max_trials),
+                          L.LS_F0_GIVEN if f0_given else 0)
     if stats is None:
         stats = stats_buffer(X.device)
     if ls_stats is None:
+        if f0_given:
+            raise ValueError("f0_given needs the ls_stats buffer of the previous step")
         ls_stats = armijo_stats_buffer(X.device)
     w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
     _check(L.load().cp_gn_step_armijo(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),

@@ -29,6 +29,7 @@ int launch_spd_chol(int, const double*, int64_t, double, double*, int64_t, int, 
 void launch_damping_advance(double*, hipStream_t);
 void launch_ls_gv(const Dims&, const double*, const double*, double*, CgState*, hipStream_t);
 void launch_ls_init(int, const double*, CgState*, hipStream_t);
+void launch_ls_init_given(const cp_armijo_stats*, CgState*, hipStream_t);
 void launch_ls_trial(const Dims&, const double*, const double*, const PerMode<void*>&, int, void*,
                      const CgState*, hipStream_t);
 void launch_ls_check(int, const double*, CgState*, double, double, hipStream_t);
@@ -396,7 +397,7 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
   if (!X || !prm || !stats) return CP_EINVAL;
   if (ls && (!ls_stats || !(ls->c > 0.0 && ls->c < 1.0) ||
              !(ls->shrink > 0.0 && ls->shrink < 1.0) || ls->max_trials < 0 ||
-             ls->max_trials > 64 || ls->reserved != 0))
+             ls->max_trials > 64 || (ls->flags & ~CP_LS_F0_GIVEN) != 0))
     return CP_EINVAL;
   if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
   if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
@@ -436,11 +437,16 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
     return hip_status();
   }
   // Armijo search along V: the slope <G, V>, f at the start point (the padded factor copies still
-  // hold it), then max_trials trial points, each skipped on the device once one has passed.
+  // hold it; or the previous search's f), then max_trials trial points, each skipped on the
+  // device once one has passed.
   launch_ls_gv(d, w.g, w.v, w.red_dot, w.st, st);
   int rb = 0;
-  launch_residual_direct(p, X, ws, nullptr, st, nullptr, &rb);
-  launch_ls_init(rb, w.red_dot, w.st, st);
+  if (ls->flags & CP_LS_F0_GIVEN) {
+    launch_ls_init_given(ls_stats, w.st, st);
+  } else {
+    launch_residual_direct(p, X, ws, nullptr, st, nullptr, &rb);
+    launch_ls_init(rb, w.red_dot, w.st, st);
+  }
   const int32_t* done = &w.st->ls_done;
   for (int k = 0; k < ls->max_trials; ++k) {
     launch_ls_trial(d, w.a64, w.v, aout, p.dtype, w.base + p.off_apad, w.st, st);

@@ -86,7 +86,7 @@ struct CgState {
   double rho[2];     // sum <R,Z> of the last two CG iterations (by iteration parity)
   // Armijo step-size control (Section 5): f = 1/2 ||X - [[A]]||^2 (eq. (3)) at the start point,
   // the directional derivative <G, V>, the current trial step size and its objective value.
-  double ls_f0, ls_x2, ls_gv, ls_alpha, ls_f;
+  double ls_f0, ls_xn, ls_gv, ls_alpha, ls_f;   // ls_xn = ||X||_F
   int32_t ls_done;      // 1 once a step size passed or the search cannot start (no trial runs)
   int32_t ls_trials;    // objective evaluations made
   int32_t ls_accepted;

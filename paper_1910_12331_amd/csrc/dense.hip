@@ -239,23 +239,30 @@ __global__ void k_ls_gv(int nblocks, const double* red, CgState* st) {
   if (threadIdx.x == 0) st->ls_gv = gv;
 }
 
+__device__ void ls_start(CgState* st, double f0, double xn) {
+  st->ls_f0 = f0;
+  st->ls_xn = xn;
+  st->ls_f = f0;
+  st->ls_alpha = 1.0;
+  st->ls_trials = 0;
+  st->ls_accepted = 0;
+  const double gv = st->ls_gv;
+  st->ls_done = (st->status != CP_OK || !(gv < 0.0) || !isfinite(f0)) ? 1 : 0;
+}
+
 // Start of the search from the residual partials at the start point (slots [0] = squared
 // differences, [kRedSlots] = squares of X). No trial runs when CG failed, when V is not a
 // descent direction (<G, V> >= 0, e.g. V = 0) or when f is not finite.
 __global__ void k_ls_init(int nblocks, const double* red, CgState* st) {
   const double d2 = sum_slots(red, nblocks);
   const double x2 = sum_slots(red + kRedSlots, nblocks);
-  if (threadIdx.x == 0) {
-    const double f0 = 0.5 * d2;
-    st->ls_f0 = f0;
-    st->ls_x2 = x2;
-    st->ls_f = f0;
-    st->ls_alpha = 1.0;
-    st->ls_trials = 0;
-    st->ls_accepted = 0;
-    const double gv = st->ls_gv;
-    st->ls_done = (st->status != CP_OK || !(gv < 0.0) || !isfinite(f0)) ? 1 : 0;
-  }
+  if (threadIdx.x == 0) ls_start(st, 0.5 * d2, sqrt(x2));
+}
+
+// Start of the search with f at the start point and ||X|| taken from the stats of the previous
+// search on the same factors (f at the point it returned), instead of a residual pass.
+__global__ void k_ls_init_given(const cp_armijo_stats* prev, CgState* st) {
+  if (threadIdx.x == 0) ls_start(st, prev->f, prev->x_norm);
 }
 
 // Trial point A + alpha V: the caller's factors (f_dtype) and the padded compute-precision
@@ -331,7 +338,7 @@ __global__ void k_ls_stats(const CgState* st, cp_armijo_stats* out) {
   out->f0 = st->ls_f0;
   out->f = st->ls_f;
   out->gv = st->ls_gv;
-  out->x_norm = sqrt(st->ls_x2);
+  out->x_norm = st->ls_xn;
   out->trials = st->ls_trials;
   out->accepted = acc ? 1 : 0;
 }
@@ -1186,6 +1193,10 @@ void launch_ls_gv(const Dims& d, const double* G, const double* V, double* red, 
 
 void launch_ls_init(int nblocks, const double* red, CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(256), 0, s, nblocks, red, st);
+}
+
+void launch_ls_init_given(const cp_armijo_stats* prev, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_ls_init_given, dim3(1), dim3(64), 0, s, prev, st);
 }
 
 void launch_ls_trial(const Dims& d, const double* A64, const double* V, const PerMode<void*>& Aout,

@@ -75,10 +75,22 @@ class ConstantDamping:
 @dataclass
 class Armijo:
     """Armijo step-size control (Section 5): step sizes 1, shrink, shrink^2, ... (at most
-    max_trials) until f(A + alpha V) <= f(A) + c alpha <G, V>."""
+    max_trials) until f(A + alpha V) <= f(A) + c alpha <G, V>. With max_trials = 1 this is the
+    accept-or-reject rule of a damped Gauss-Newton iteration: a step that does not decrease f
+    enough leaves the factors as they were.
+
+    carry_objective: after the first step, f at the current point is the one the previous
+    search evaluated (the optimizer is the only writer of its factors), so each step costs one
+    residual pass per trial and none at the start."""
     c: float = 1e-4
     shrink: float = 0.5
     max_trials: int = 10
+    carry_objective: bool = True
+
+
+def Acceptance(c: float = 1e-4) -> Armijo:
+    """The full Gauss-Newton step, taken only if f(A + V) <= f(A) + c <G, V> (one trial)."""
+    return Armijo(c=c, shrink=0.5, max_trials=1, carry_objective=True)
 
 
 @dataclass
@@ -102,6 +114,11 @@ class GaussNewton:
         self.stats_buf = api.stats_buffer(X.device)
         self.ls_buf = api.armijo_stats_buffer(X.device) if self.cfg.line_search else None
         self.steps = 0
+        self._f_known = False    # ls_buf holds f at the current factors
+
+    def reset_objective(self):
+        """Call after changing the factors outside step(): the next search evaluates f anew."""
+        self._f_known = False
 
     def step(self) -> torch.Tensor:
         ls = self.cfg.line_search
@@ -113,7 +130,9 @@ class GaussNewton:
             api.gn_step_armijo(self.X, self.A, self.schedule.value, self.cfg.cg_tol,
                                self.cfg.cg_maxiter, ls.c, ls.shrink, ls.max_trials,
                                stats=self.stats_buf, ls_stats=self.ls_buf, ws=self.ws,
-                               damping=self.cfg.damping, preconditioner=self.cfg.preconditioner)
+                               damping=self.cfg.damping, preconditioner=self.cfg.preconditioner,
+                               f0_given=ls.carry_objective and self._f_known)
+            self._f_known = True
         self.schedule.advance()
         self.steps += 1
         return self.stats_buf
@@ -128,7 +147,7 @@ class GaussNewton:
         """Direct relative residual ||X - [[A]]|| / ||X|| at the current factors. After an Armijo
         step it is read from the search's own evaluation at the returned point (the same direct
         residual kernel), without another pass over X."""
-        if self.ls_buf is not None and self.steps > 0:
+        if self.ls_buf is not None and self._f_known:
             s = api.read_armijo_stats(self.ls_buf)
             return math.sqrt(2.0 * max(s["f"], 0.0)) / s["x_norm"]
         r = api.residual(self.X, self.A, ws=self.ws).cpu()

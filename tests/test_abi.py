@@ -169,7 +169,7 @@ def test_call_validation_without_launch(lib):
     for bad in [L.CpArmijoParams(0.0, 0.5, 10, 0), L.CpArmijoParams(1.0, 0.5, 10, 0),
                 L.CpArmijoParams(1e-4, 0.0, 10, 0), L.CpArmijoParams(1e-4, 1.0, 10, 0),
                 L.CpArmijoParams(float("nan"), 0.5, 10, 0), L.CpArmijoParams(1e-4, 0.5, -1, 0),
-                L.CpArmijoParams(1e-4, 0.5, 65, 0), L.CpArmijoParams(1e-4, 0.5, 10, 1)]:
+                L.CpArmijoParams(1e-4, 0.5, 65, 0), L.CpArmijoParams(1e-4, 0.5, 10, 2)]:
         assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(good), C.byref(bad), st, ls_st, ws,
                                      need, None) == L.CP_EINVAL
     assert lib.cp_gn_step_armijo(C.byref(p), X, A, C.byref(L.CpGnParams(-1.0, 1e-3, 20, 0)),

@@ -57,13 +57,25 @@ def trial_margins(X, A, ref, c, shrink):
 
 def armijo_compare(X, A, dt, lam, cg_tol, maxiter, c=1e-4, shrink=0.5, max_trials=10, tol=None,
                    margin=1e-3, damping="identity", precond="inverse"):
-    if tol is None:
-        tol = 1e-9 if dt == torch.float64 else 2e-3
     if dt == torch.float32:   # the oracle sees the FP32-rounded inputs
         X = X.astype(np.float32).astype(np.float64)
         A = [a.astype(np.float32).astype(np.float64) for a in A]
     ref = O.gn_step_armijo(X, A, lam, cg_tol, maxiter, damping, c=c, shrink=shrink,
                            max_trials=max_trials, precond=precond)
+    if tol is None:
+        if dt == torch.float64:
+            # 10x the oracle's own spread when its input factors move by 1e-15 relative
+            rng = np.random.default_rng(1)
+            A2 = [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in A]
+            ref2 = O.gn_step_armijo(X, A2, lam, cg_tol, maxiter, damping, c=c, shrink=shrink,
+                                    max_trials=max_trials, precond=precond)
+            sv = rel(O.flatten_factors([b - a for a, b in zip(A2, ref2.A)]),
+                     O.flatten_factors([b - a for a, b in zip(A, ref.A)])) if ref.accepted else 0.0
+            sg = abs(ref2.gv - ref.gv) / abs(ref.gv) if ref.gv != 0.0 else 0.0
+            spread = max(sv, sg, abs(ref2.f - ref.f) / ref.f0)
+            tol = max(1e-12, 10 * spread)
+        else:
+            tol = 2e-3
     assert all(abs(m) > margin for m in trial_margins(X, A, ref, c, shrink))
     Xd, Ad = dev([X], dt)[0], dev(A, dt)
     st, ls = P.gn_step_armijo(Xd, Ad, lam, cg_tol, maxiter, c, shrink, max_trials,

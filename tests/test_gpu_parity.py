@@ -227,6 +227,16 @@ def gn_compare(p, dt, lam, eps, maxiter, tol_v, damping="identity", precond="inv
     return st, ref
 
 
+def als_sensitivity_tol(Xh, Ah, lam, seed=2):
+    """max(1e-12, 10x the change of the oracle's sweep when its input factors move by 1e-15
+    relative): the rounding-level spread of a sweep whose later modes solve with Gamma(n) of
+    large condition number."""
+    rng = np.random.default_rng(seed)
+    ref = O.als_sweep(Xh, Ah, lam)
+    ref2 = O.als_sweep(Xh, [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in Ah], lam)
+    return max(1e-12, 10 * max(rel(r2, r) for r2, r in zip(ref2, ref)))
+
+
 @pytest.mark.parametrize("maxiter", [0, 1, 5, 10])
 def test_gn_step_fixed_iterations_fp64(maxiter):
     p = make_problem((40, 40, 40), 5, workload=1)
@@ -281,12 +291,12 @@ def test_gn_step_past_cg_rounding_floor_fp64():
                                            ((150, 140, 136), 128, 1e-2)])
 def test_gn_step_cg_tolerance_fp64(dims, rank, lam):
     p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-3)
-    gn_compare(p, torch.float64, lam, 1e-3, 50, 1e-11)
+    gn_compare(p, torch.float64, lam, 1e-3, 50, "sensitivity")
 
 
 def test_gn_step_config2_fp64():
     p = make_problem((300, 300, 300), 50, workload=2, kind="congruent", noise=1e-6)
-    st, ref = gn_compare(p, torch.float64, 1e-4, 1e-3, 20, 1e-10)
+    st, ref = gn_compare(p, torch.float64, 1e-4, 1e-3, 20, "sensitivity")
     assert st["cg_iters"] >= 1
 
 
@@ -312,7 +322,7 @@ def test_gn_step_cholesky_preconditioner_cg_tolerance_fp64(dims, rank, lam, damp
     """Several 64-row blocks with ragged tails, orders 2 to 4, R up to 128 (the 64 KB LDS limit
     of the solve kernel), odd R, both damping forms."""
     p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-3)
-    gn_compare(p, torch.float64, lam, 1e-3, 50, 1e-11, damping=damping, precond="cholesky")
+    gn_compare(p, torch.float64, lam, 1e-3, 50, "sensitivity", damping=damping, precond="cholesky")
 
 
 def test_gn_step_cholesky_preconditioner_fp32():
@@ -409,9 +419,10 @@ def test_als_with_step_decay_regularization_matches_oracle():
         lam = 1e-2 * 0.5 ** (k // 2)
         assert opt.schedule.value == lam
         assert int(opt.step().item()) == 0
+        tol = als_sensitivity_tol(p.x, ref, lam)
         ref = O.als_sweep(p.x, ref, lam)
         for a, r in zip(host(opt.A), ref):
-            assert rel(a, r) < 1e-11
+            assert rel(a, r) < tol
 
 
 def test_als_sweep_config2_fp64():
@@ -552,11 +563,12 @@ def test_highest_orders_every_entry_point(dims, rank, dt):
     Q = P.jtj_matvec(A, to_dev(W, dt), 1e-2)
     for q, qr in zip(Q, O.jtj_matvec(Ah, Wh, 1e-2)):
         assert rel(q.double().cpu().numpy(), qr) < (1e-12 if f64 else 1e-6)
-    gn_compare(p, dt, 1e-3, 0.0, 5, 1e-11 if f64 else 1e-4)
+    gn_compare(p, dt, 1e-3, 0.0, 5, "sensitivity" if f64 else 1e-4)
     Aals = to_dev(p.init, dt)
     assert int(P.als_sweep(X, Aals, 1e-3).item()) == 0
+    ta = als_sensitivity_tol(Xh, Ah, 1e-3) if f64 else 1e-4
     for a, r in zip(host(Aals), O.als_sweep(Xh, Ah, 1e-3)):
-        assert rel(a, r) < (1e-10 if f64 else 1e-4)
+        assert rel(a, r) < ta
     out = P.residual(X, A).cpu().numpy()
     num, den = O.residual(Xh, Ah)
     tr = 1e-12 if f64 else 1e-5
@@ -582,4 +594,4 @@ def test_mode_longer_than_one_row_tile_grid(dt):
     out = P.residual(X, A).cpu().numpy()
     num, den = O.residual(Xh, Ah)
     assert abs(out[0] - num) / num < (1e-12 if dt == torch.float64 else 1e-5)
-    gn_compare(p, dt, 1e-3, 0.0, 3, 1e-11 if dt == torch.float64 else 1e-4)
+    gn_compare(p, dt, 1e-3, 0.0, 3, "sensitivity" if dt == torch.float64 else 1e-4)
