@@ -76,7 +76,8 @@ enum {
   CP_EHIP = -4,
   CP_ENOTSPD = -5,      /* Gamma(n,n) + lambda I (or Gamma(n) + lambda I in ALS) not SPD  */
   CP_EBREAKDOWN = -6,   /* CG curvature sum <W,Q> <= 0                                     */
-  CP_ENONFINITE = -7    /* a NaN or Inf appeared in the gradient or the CG recurrences      */
+  CP_ENONFINITE = -7,   /* a NaN or Inf appeared in the gradient or the CG recurrences      */
+  CP_ESCRATCH = -8      /* the problem needs more than the built-in scratch buffer          */
 };
 
 /* Workspace queries: one per entry point. */
@@ -192,6 +193,25 @@ int cp_gn_step(const cp_problem* prob, const void* X, void* const* A, const cp_g
 int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
                       const cp_gn_params* params, const double* lambda_dev, cp_gn_stats* stats,
                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * cp_gn_step without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). The
+ * workspace is a device array built into the library, CP_NOALLOC_SCRATCH_BYTES long, of which
+ * every GPU the library runs on holds one copy until the process ends; the call allocates
+ * nothing. Its device address is looked up once per device, on the first call made with that
+ * device current (hipGetSymbolAddress); the stream must belong to the current device.
+ * Every call on one GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (concurrent streams, several threads) race and must be serialised by the
+ * caller. The step reads nothing from the array that it has not written in the same call.
+ *   Arguments and results as for cp_gn_step.
+ *   Errors: CP_ESCRATCH (before any launch) when cp_workspace_bytes(CP_OP_GN_STEP) exceeds
+ *   CP_NOALLOC_SCRATCH_BYTES (64 MiB: 400^3 at rank 100 needs 30 MiB in FP32, 44 MiB in FP64);
+ *   CP_EHIP when the scratch address cannot be obtained; otherwise as cp_gn_step.
+ */
+#define CP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cp_gn_step_noalloc(const cp_problem* prob, const void* X, void* const* A,
+                       const cp_gn_params* params, cp_gn_stats* stats, void* stream);
 
 /* Armijo step-size control of a Gauss-Newton step (Section 5). */
 typedef struct cp_armijo_params {

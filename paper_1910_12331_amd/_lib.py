@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(HERE, "libcpgn.so")
 MAX_ORDER = 8
 CP_F64, CP_F32, CP_BF16, CP_BF16X3 = 0, 1, 2, 3
 CP_OK, CP_EINVAL, CP_EUNSUPPORTED, CP_EWORKSPACE, CP_EHIP = 0, -1, -2, -3, -4
-CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE = -5, -6, -7
+CP_ENOTSPD, CP_EBREAKDOWN, CP_ENONFINITE, CP_ESCRATCH = -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES = 64 << 20
 OP_MTTKRP, OP_GN_GRADIENT, OP_GN_JTJ_MATVEC, OP_GN_STEP, OP_ALS_SWEEP, OP_RESIDUAL, OP_MTTKRP_ALL = range(7)
 GN_DIAG_DAMPING = 1
 GN_CHOL_PRECOND = 2
@@ -18,7 +19,7 @@ LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_gn_step_devlam", "cp_gn_step_armijo", "cp_damping_advance", "cp_als_sweep", "cp_residual",
+           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -80,6 +81,8 @@ def load(path: str = LIB_PATH):
     lib.cp_gn_step.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, sz, vp]
     lib.cp_gn_step_devlam.restype = i32
     lib.cp_gn_step_devlam.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, vp, sz, vp]
+    lib.cp_gn_step_noalloc.restype = i32
+    lib.cp_gn_step_noalloc.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp]
     lib.cp_gn_step_armijo.restype = i32
     lib.cp_gn_step_armijo.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), P(CpArmijoParams),
                                       vp, vp, vp, sz, vp]

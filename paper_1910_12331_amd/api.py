@@ -269,6 +269,25 @@ def gn_step(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: floa
     return stats
 
 
+def gn_step_noalloc(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float, cg_tol: float = 1e-3,
+                    cg_maxiter: int = 20, stats=None, damping: str = "identity",
+                    preconditioner: str = "inverse"):
+    """gn_step with the library's built-in device scratch as workspace (cp_gn_step_noalloc): no
+    device memory is allocated for the call (pass `stats` to allocate nothing at all). Calls that
+    overlap on one GPU share that scratch and must not run concurrently."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, factor_dtype(X), R)
+    prob = _problem(X, R)
+    prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter),
+                       _gn_flags(damping, preconditioner))
+    if stats is None:
+        stats = stats_buffer(X.device)
+    _check(L.load().cp_gn_step_noalloc(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),
+                                       stats.data_ptr(), _stream()), "cp_gn_step_noalloc")
+    return stats
+
+
 ARMIJO_FIELDS = ("alpha", "f0", "f", "gv", "x_norm", "trials", "accepted")
 
 

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "cpgn_internal.h"
 
 namespace cpgn {
@@ -292,6 +294,7 @@ const char* cp_status_string(int s) {
     case CP_ENOTSPD: return "matrix not symmetric positive definite (Cholesky pivot <= 0)";
     case CP_EBREAKDOWN: return "CG breakdown (sum <W,Q> <= 0)";
     case CP_ENONFINITE: return "non-finite value";
+    case CP_ESCRATCH: return "problem needs more than the built-in scratch buffer (64 MiB)";
     default: return "unknown status";
   }
 }
@@ -468,6 +471,46 @@ int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
                       void* ws, size_t ws_bytes, void* stream) {
   if (!lambda_dev) return CP_EINVAL;
   return gn_step_impl(prob, X, A, prm, lambda_dev, stats, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// Workspace of cp_gn_step_noalloc: one copy per GPU, resident until the process ends. Host code
+// never uses the array's name as an address: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[CP_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return CP_EHIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return CP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CP_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CP_OK;
+}
+
+extern "C" {
+
+int cp_gn_step_noalloc(const cp_problem* prob, const void* X, void* const* A,
+                       const cp_gn_params* prm, cp_gn_stats* stats, void* stream) {
+  size_t need = 0;
+  int rc = cp_workspace_bytes(prob, CP_OP_GN_STEP, &need);
+  if (rc) return rc;
+  if (need > CP_NOALLOC_SCRATCH_BYTES) return CP_ESCRATCH;
+  if (!X || !prm || !stats) return CP_EINVAL;
+  Plan p;
+  if ((rc = make_plan(prob, &p)) || (rc = check_ptrs(p, (const void* const*)A))) return rc;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return gn_step_impl(prob, X, A, prm, nullptr, stats, ws, CP_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,

@@ -230,3 +230,27 @@ def test_mode_longer_than_one_row_tile_grid_is_planned(lib):
         p = prob(dims=(2_200_000, 3, 4), rank=4, dt=dt)
         for op in range(7):
             assert lib.cp_workspace_bytes(C.byref(p), op, C.byref(n)) == L.CP_OK
+
+
+def test_noalloc_step_rejects_problems_beyond_its_scratch(lib):
+    """cp_gn_step_noalloc checks the problem against its built-in 64 MiB scratch before it
+    touches the device: a 1000^3 rank-208 FP64 step (about 289 MiB of workspace) is refused with
+    CP_ESCRATCH, and null pointers with CP_EINVAL."""
+    p = L.CpProblem()
+    p.order, p.rank = 3, 208
+    for i in range(3):
+        p.dims[i] = 1000
+    p.x_dtype = p.f_dtype = L.CP_F64
+    n = C.c_size_t(0)
+    assert lib.cp_workspace_bytes(C.byref(p), L.OP_GN_STEP, C.byref(n)) == L.CP_OK
+    assert n.value > L.NOALLOC_SCRATCH_BYTES
+    good = L.CpGnParams(1e-4, 1e-3, 20, 0)
+    X, st = C.c_void_p(0x10000), C.c_void_p(0x50000)
+    assert lib.cp_gn_step_noalloc(C.byref(p), X, fake_ptrs(), C.byref(good), st, None) == L.CP_ESCRATCH
+    assert "scratch" in L.status_string(L.CP_ESCRATCH)
+    q = prob()
+    assert lib.cp_gn_step_noalloc(C.byref(q), None, fake_ptrs(), C.byref(good), st, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_noalloc(C.byref(q), X, fake_ptrs(), None, st, None) == L.CP_EINVAL
+    A0 = fake_ptrs()
+    A0[1] = 0
+    assert lib.cp_gn_step_noalloc(C.byref(q), X, A0, C.byref(good), st, None) == L.CP_EINVAL
