@@ -274,13 +274,16 @@ int cp_damping_advance(double* state_dev, void* stream);
 
 /*
  * One ALS sweep, Section 2.2: for n = 0..N-1 in order, A^(n) = M^(n) (Gamma^(n) + lambda I)^-1
- * with M^(n) computed from the latest factors; the inverse comes from an FP64 Cholesky factor.
+ * with M^(n) computed from the latest factors: the FP64 Cholesky factor L L^T = Gamma^(n) +
+ * lambda I, then Y L^T = M^(n) and A^(n) L = Y by blocked substitution (16-column blocks; the
+ * 16 x 16 diagonal blocks of L act through their inverses). No explicit inverse of Gamma^(n).
  * For an order-3 FP32/FP64 tensor the workspace that cp_workspace_bytes(CP_OP_ALS_SWEEP) reports
  * also holds T = X x_3 A^(3) (dims[0] dims[1] x rank words): M^(1) and M^(2) are then formed from
  * T (a dimension tree: two passes over X per sweep instead of three). Given only the smaller
  * workspace of the other operations, the sweep takes one pass per mode.
  *   A: N device pointers, read and overwritten in place. lambda >= 0 (0 = plain ALS).
- *   status_dev: device int32 receiving CP_OK or CP_ENOTSPD (may be NULL).
+ *   status_dev: device int32 receiving CP_OK or CP_ENOTSPD (a pivot <= 0: that mode and the ones
+ *   after it keep their factors; may be NULL). Rank <= 208 (CP_EUNSUPPORTED above).
  */
 int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double lambda,
                  int32_t* status_dev, void* ws, size_t ws_bytes, void* stream);

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpgn.so")
-SOURCES = ["mttkrp.hip", "mttkrp_bf16.hip", "dense.hip", "dense64.hip", "pcg.hip", "api.hip"]
+SOURCES = ["mttkrp.hip", "mttkrp_bf16.hip", "dense.hip", "dense64.hip", "pcg.hip", "chol.hip",
+           "api.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for all device code.

@@ -50,6 +50,10 @@ int launch_cg(const Plan&, const Dims&, const double*, const double*, const doub
               double, int, bool, hipStream_t, const double* lam_dev = nullptr, bool chol = false);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
+int launch_chol_tiles(int, const double*, int64_t, double, double*, int64_t, double*, int64_t, int,
+                      int, CgState*, hipStream_t);
+int launch_chol_rows(int, int64_t, const double*, const double*, const double*, void*, int,
+                     const CgState*, hipStream_t);
 int64_t ttm_rows(const Plan&);
 int launch_ttm_last(const Plan&, const void*, void*, void*, hipStream_t);
 void launch_ttm_contract(const Plan&, const void*, const double*, int, double*, hipStream_t);
@@ -132,6 +136,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_s = take((size_t)p->N * RR * 8);
   p->off_gam = take((size_t)p->N * p->N * RR * 8);
   p->off_pinv = take((size_t)p->N * RR * 8);
+  p->off_dinv = take((size_t)p->N * ((p->R + 15) / 16) * 256 * 8);
   p->off_g = take(vec);
   p->off_v = take(vec);
   p->off_r = take(vec);
@@ -555,16 +560,14 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
       launch_ttm_contract(p, Tbuf, w.a64 + (n == 0 ? p.s[0] * p.R : 0), n, m64n, st);
     else
       launch_mttkrp(p, X, n, ws, m64n, nullptr, st);
-    launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, n, 1, w.st, st);
-    RowMM a{};
-    a.l1 = w.m64;
-    a.t1 = w.pinv;
-    a.t1_stride = RR;
-    a.cast_out.p[n] = A[n];
-    a.cast_dtype = p.dtype;
-    a.mode_only = n;
-    a.skip_if_status = 1;
-    launch_rowmm(d, a, w.st, st);
+    // A(n) = M(n) (Gamma(n) + lambda I)^-1: FP64 Cholesky factor L, then Y L^T = M(n) and
+    // A(n) L = Y by substitution (skipped, factors unchanged, when a pivot is not positive)
+    double* dinv = (double*)(w.base + p.off_dinv);
+    const int64_t dstride = (int64_t)((p.R + 15) / 16) * 256;
+    launch_chol_tiles(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, dinv, dstride, n,
+                      1, w.st, st);
+    launch_chol_rows(p.R, p.s[n], m64n, w.pinv + n * RR, dinv + n * dstride, A[n], p.dtype, w.st,
+                     st);
     // refresh the padded/packed copies, the FP64 copy and the Gram of the updated mode
     launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true, 1u << (n + 1));
     launch_gram2(d, w.a64, w.a64, w.S, n, nullptr, st);

@@ -1,0 +1,391 @@
+// FP64 Cholesky factorization of an ALS normal-equation matrix and the triangular solves that
+// apply it to the rows of M (Section 2.2: A(n) = M(n) (Gamma(n) + lambda I)^-1).
+//
+//   k_chol_tiles  L L^T = G + lambda I for R <= 208, one workgroup of eight wavefronts per matrix.
+//                 Right-looking and blocked by 16 x 16 tiles: the lower-triangle tiles live in
+//                 registers in the FP64 MFMA accumulator layout, spread over the wavefronts. Step
+//                 k factors the diagonal tile (one wavefront, in registers, values exchanged by
+//                 lane permutes), solves the tiles below it against that factor (by substitution
+//                 across the 16 lanes of a row group) and subtracts the outer products of that
+//                 panel from the trailing tiles on the matrix cores: two workgroup barriers per
+//                 16 columns instead of one per pivot.
+//   k_chol_rows   A = M (L L^T)^-1 for 16 rows per wavefront: Y L^T = M by forward substitution,
+//                 then A L = Y by back substitution, 16 columns at a time, with the 16 x 16
+//                 diagonal blocks applied through their inverses (as blocked triangular solvers
+//                 do), so every step is a product on the FP64 matrix cores. Wavefronts share
+//                 nothing but L, which a workgroup stages in LDS when it fits (R <= 128).
+//                 k_chol_tiles forms those 16 x 16 inverses by the same substitution on the
+//                 identity, beside the panel of each step.
+#include "mfma64.h"
+
+namespace cpgn {
+
+constexpr int kCholWaves = 8;
+constexpr int kCholMaxNT = (kMaxGnRank + 15) / 16;
+constexpr int kCholMaxSlots = (kCholMaxNT * (kCholMaxNT + 1) / 2 + kCholWaves - 1) / kCholWaves;
+
+// Orders the LDS accesses of one wavefront (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lower-triangle tile t = I (I + 1) / 2 + J -> (I, J).
+__host__ __device__ constexpr int tile_row(int t) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  return i;
+}
+__host__ __device__ constexpr int tile_col(int t) { return t - tile_row(t) * (tile_row(t) + 1) / 2; }
+
+// Entry (r, c) of G + lambda I, extended by the identity past R.
+__device__ __forceinline__ double shifted(const double* G, int R, double lambda, int r, int c) {
+  if (r < R && c < R) return G[r * R + c] + (r == c ? lambda : 0.0);
+  return r == c ? 1.0 : 0.0;
+}
+
+// The kernels below run once per launch over short dependency chains, so their code is kept
+// compact (runtime loops): fully unrolled variants spent most of their time fetching
+// instructions.
+
+// Forward substitution across the 16 lanes of each row group: rows of T (rows g + 4 v, column
+// m) become X with X L^T = T for a 16 x 16 lower-triangular L, given lmc(c) = L[m][c] and
+// rdl = 1 / L[m][m].
+template <typename LF>
+__device__ __forceinline__ void row_forward16(dv4& T, LF lmc, double rdl, int g, int m) {
+  // branch-free: the four exchanges of a step are issued together, the updates are selects
+#pragma unroll 1
+  for (int c = 0; c < 16; ++c) {
+    const double l = lmc(c);
+    double xb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xb[v] = __shfl(T[v] * rdl, 16 * g + c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double upd = T[v] - xb[v] * l;
+      T[v] = m > c ? upd : (m == c ? xb[v] : T[v]);
+    }
+  }
+}
+
+// Right-looking Cholesky of one 16 x 16 tile held by a wavefront in the accumulator layout
+// (lane (g, m): rows g + 4 v, column m). Pivot c: p = T[c][c] from its lane, column c of the
+// lane's rows and the entry T[m][c] for the lane's column from their owners; the trailing
+// entries lose c_i c_j / p, column c becomes c_i / sqrt(p) and the pivot sqrt(p). Returns false
+// (same in every lane) for a non-positive or non-finite pivot. Entries above the diagonal are
+// set to 0.
+__device__ __forceinline__ bool tile_cholesky(dv4& D, int g, int m) {
+  const int mv = m >> 2;
+#pragma unroll 1
+  for (int c = 0; c < 16; ++c) {
+    const int vc = c >> 2;
+    const double dvc = vc == 0 ? D[0] : vc == 1 ? D[1] : vc == 2 ? D[2] : D[3];
+    double ci[4], cjv[4];
+    const double p = __shfl(dvc, 16 * (c & 3) + c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ci[v] = __shfl(D[v], 16 * g + c);
+      cjv[v] = __shfl(D[v], 16 * (m & 3) + c);
+    }
+    if (!(p > 0.0) || !isfinite(p)) return false;   // the same value in every lane
+    const double d = sqrt(p), rp = 1.0 / p, rd = d * rp;
+    const double cj = mv == 0 ? cjv[0] : mv == 1 ? cjv[1] : mv == 2 ? cjv[2] : cjv[3];
+    const double cjr = cj * rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = g + 4 * v;
+      const double upd = D[v] - ci[v] * cjr;
+      const double col = i > c ? ci[v] * rd : (i == c ? d : D[v]);
+      D[v] = m > c ? (i > c ? upd : D[v]) : (m == c ? col : D[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) D[v] = m > g + 4 * v ? 0.0 : D[v];
+  return true;
+}
+
+// grid: one workgroup per matrix (modes first_mode, first_mode + 1, ...), 512 threads. Tile t of
+// the lower triangle belongs to wavefront t % 8, register slot t / 8; lane (g, m) = (lane / 16,
+// lane % 16) holds rows g + 4 v, column m of its tiles (the MFMA accumulator layout). Step k:
+// (a) the owner of tile (k, k) factors it in registers and publishes it in LDS; (b) the owners
+// of the tiles below it solve them against it (X L_kk^T = T) and publish them; (c) every tile
+// right of column k and on or below the diagonal loses the product of its two panel tiles. L is
+// written once all steps are done. A non-positive or non-finite pivot records CP_ENOTSPD, marks
+// the state done and writes nothing. Entries of L above the diagonal are not written.
+template <int SLOTS>
+__global__ __launch_bounds__(kCholWaves * 64) void k_chol_tiles(int R, const double* __restrict__ Gin,
+                                                              int64_t g_stride, double lambda,
+                                                              double* __restrict__ Lout,
+                                                              int64_t l_stride,
+                                                              double* __restrict__ Dout,
+                                                              int64_t d_stride, int first_mode,
+                                                              CgState* st) {
+  __shared__ double dg[16][17];                        // L_kk of the current step
+  __shared__ double pan[2][kCholMaxNT][16][17];        // the solved panel of a step
+  __shared__ int sbad;
+  const int n = first_mode + blockIdx.x;
+  const double* G = Gin + n * g_stride;
+  double* L = Lout + n * l_stride;
+  double* Dinv = Dout + n * d_stride;
+  const int NT = (R + 15) >> 4, NTT = NT * (NT + 1) / 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
+  if (threadIdx.x == 0) sbad = st->status != CP_OK;
+  __syncthreads();
+  if (sbad) return;
+
+  dv4 T[SLOTS];
+  int TI[SLOTS], TJ[SLOTS];
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    const int t = w + kCholWaves * i;
+    TI[i] = t < NTT ? tile_row(t) : -1;
+    TJ[i] = t < NTT ? t - TI[i] * (TI[i] + 1) / 2 : -1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      T[i][v] = t < NTT ? shifted(G, R, lambda, 16 * TI[i] + g + 4 * v, 16 * TJ[i] + m) : 0.0;
+  }
+
+  for (int k = 0; k < NT; ++k) {
+    const int b = k & 1;
+    const int tkk = k * (k + 1) / 2 + k;
+    if (w == tkk % kCholWaves) {                                             // (a)
+      const int slot = tkk / kCholWaves;
+      dv4 D = T[0];
+#pragma unroll
+      for (int i = 1; i < SLOTS; ++i)
+        if (i == slot) D = T[i];
+      const bool ok = tile_cholesky(D, g, m);
+#pragma unroll
+      for (int i = 0; i < SLOTS; ++i)
+        if (i == slot) T[i] = D;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dg[g + 4 * v][m] = D[v];
+      if (!ok && lane == 0) {
+        st->status = CP_ENOTSPD;
+        st->done = 1;
+        sbad = 1;
+      }
+    }
+    __syncthreads();
+    if (sbad) return;
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {                                        // (b)
+      if (TJ[i] == k && TI[i] > k) {
+        row_forward16(T[i], [&](int c) { return dg[m][c]; }, 1.0 / dg[m][m], g, m);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pan[b][TI[i]][g + 4 * v][m] = T[i][v];
+      }
+    }
+    if (w == (tkk + 1) % kCholWaves) {   // L_kk^-T: the same substitution on the identity
+      dv4 E;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) E[v] = g + 4 * v == m ? 1.0 : 0.0;
+      row_forward16(E, [&](int c) { return dg[m][c]; }, 1.0 / dg[m][m], g, m);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dinv[k * 256 + (g + 4 * v) * 16 + m] = E[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {                                        // (c)
+      if (TJ[i] > k) {
+        const int I = TI[i], J = TJ[i];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int q = 4 * q4 + g;
+          T[i] = mfma64(-pan[b][I][m][q], pan[b][J][m][q], T[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    if (TI[i] < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * TI[i] + g + 4 * v, c = 16 * TJ[i] + m;
+      if (r < R && c < R && c <= r) L[r * R + c] = T[i][v];
+    }
+  }
+}
+
+// Entry (i, j) of L, extended by the identity past R (only i >= j is read).
+template <bool LDSL>
+__device__ __forceinline__ double lget(const double* __restrict__ L, const double* Lt, int R, int i,
+                                       int j) {
+  if (LDSL) {
+    const int I = i >> 4, J = j >> 4;
+    return Lt[(I * (I + 1) / 2 + J) * 272 + (i & 15) * 17 + (j & 15)];
+  }
+  if (i < R && j < R) return L[i * R + j];
+  return i == j ? 1.0 : 0.0;
+}
+
+// grid: ceil(s / 64) workgroups of four wavefronts; wavefront w of workgroup b owns rows
+// 64 b + 16 w .. + 15 of the mode. Each 16-column block of the forward solve Y L^T = M is the
+// product (M_k - sum_{j<k} Y_j L_kj^T) L_kk^-T, and of the back solve A L = Y the product
+// (Y_k - sum_{j>k} A_j L_jk) L_kk^-1: blocked substitution in which the 16 x 16 diagonal blocks
+// act through their inverses (Dinv: L_kk^-T, one 16 x 16 block per k, row-major), so that every
+// step is a chain of FP64 MFMAs. Dynamic LDS: 4 x 16 x (16 NT + 1) doubles for the rows, plus,
+// when LDSL, the NT (NT + 1) / 2 lower tiles of L and the NT blocks of Dinv at 16 x 17 doubles
+// each. Skipped when the state records a failure (the factors keep their values). Writes A in
+// the caller's dtype.
+template <int NT, bool LDSL>
+__global__ __launch_bounds__(256) void k_chol_rows(int R, int64_t s, const double* __restrict__ M,
+                                                   const double* __restrict__ L,
+                                                   const double* __restrict__ Dinv,
+                                                   void* __restrict__ Aout, int dtype,
+                                                   const CgState* st) {
+  constexpr int RP = 16 * NT, YS = RP + 1, NTT = NT * (NT + 1) / 2;
+  extern __shared__ double smem[];
+  if (st->status != CP_OK) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
+  double* Y = smem + w * 16 * YS;
+  double* Lt = smem + 4 * 16 * YS;
+  double* Dt = Lt + NTT * 272;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  if (LDSL) {   // thread t stages entry (t / 16, t % 16) of every tile: all loads in flight
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    double v[NTT + NT];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) {
+      const int i = 16 * tile_row(t) + r, j = 16 * tile_col(t) + c;
+      v[t] = (i < R && j < R) ? L[i * R + j] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) v[NTT + k] = Dinv[k * 256 + threadIdx.x];
+#pragma unroll
+    for (int t = 0; t < NTT + NT; ++t) Lt[t * 272 + r * 17 + c] = v[t];
+  }
+  {   // the wavefront's 16 rows of M, zero past R and past the mode
+    double v[RP / 4];
+#pragma unroll
+    for (int q = 0; q < RP / 4; ++q) {
+      const int e = lane + 64 * q, r = e / RP, c = e - r * RP;
+      const int64_t row = row0 + r;
+      v[q] = (row < s && c < R) ? M[row * R + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RP / 4; ++q) {
+      const int e = lane + 64 * q, r = e / RP, c = e - r * RP;
+      Y[r * YS + c] = v[q];
+    }
+  }
+  if (LDSL) __syncthreads();
+  else wave_lds_sync();
+  // Dinv block k entry (a, b) = (L_kk^-T)[a][b]
+  auto dget = [&](int k, int a, int b) {
+    return LDSL ? Dt[k * 272 + a * 17 + b] : Dinv[k * 256 + a * 16 + b];
+  };
+  // forward: Y L^T = M, block by block
+#pragma unroll 1
+  for (int k = 0; k < NT; ++k) {
+    dv4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = Y[(g + 4 * v) * YS + 16 * k + m];
+#pragma unroll 1
+    for (int jb = 0; jb < k; ++jb) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int q = 16 * jb + 4 * q4 + g;
+        a[q4] = Y[m * YS + q];
+        bv[q4] = lget<LDSL>(L, Lt, R, 16 * k + m, q);
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) acc = mfma64(-a[q4], bv[q4], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Y[(g + 4 * v) * YS + 16 * k + m] = acc[v];
+    wave_lds_sync();
+    dv4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+      y = mfma64(Y[m * YS + 16 * k + 4 * q4 + g], dget(k, 4 * q4 + g, m), y);
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Y[(g + 4 * v) * YS + 16 * k + m] = y[v];
+    wave_lds_sync();
+  }
+  // back: A L = Y, last block first (A overwrites Y block by block)
+#pragma unroll 1
+  for (int k = NT - 1; k >= 0; --k) {
+    dv4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = Y[(g + 4 * v) * YS + 16 * k + m];
+#pragma unroll 1
+    for (int jb = k + 1; jb < NT; ++jb) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int q = 16 * jb + 4 * q4 + g;
+        a[q4] = Y[m * YS + q];
+        bv[q4] = lget<LDSL>(L, Lt, R, q, 16 * k + m);
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) acc = mfma64(-a[q4], bv[q4], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Y[(g + 4 * v) * YS + 16 * k + m] = acc[v];
+    wave_lds_sync();
+    dv4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+      a = mfma64(Y[m * YS + 16 * k + 4 * q4 + g], dget(k, m, 4 * q4 + g), a);
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Y[(g + 4 * v) * YS + 16 * k + m] = a[v];
+    wave_lds_sync();
+  }
+  for (int e = lane; e < 16 * R; e += 64) {
+    const int r = e / R, c = e - r * R;
+    const int64_t row = row0 + r;
+    if (row < s) {
+      if (dtype == CP_F64) ((double*)Aout)[row * R + c] = Y[r * YS + c];
+      else ((float*)Aout)[row * R + c] = (float)Y[r * YS + c];
+    }
+  }
+}
+
+int launch_chol_tiles(int R, const double* G, int64_t g_stride, double lambda, double* L,
+                      int64_t l_stride, double* Dinv, int64_t d_stride, int first_mode, int count,
+                      CgState* st, hipStream_t s) {
+  if (R < 1 || R > kMaxGnRank) return (int)hipErrorInvalidValue;
+  const int NT = (R + 15) / 16, NTT = NT * (NT + 1) / 2;
+  const int slots = (NTT + kCholWaves - 1) / kCholWaves;
+#define CPGN_CHOLT(k)                                                                          \
+  if (slots <= k) {                                                                          \
+    hipLaunchKernelGGL(k_chol_tiles<k>, dim3(count), dim3(kCholWaves * 64), 0, s, R, G,      \
+                       g_stride, lambda, L, l_stride, Dinv, d_stride, first_mode, st);       \
+    return (int)hipGetLastError();                                                           \
+  }
+  CPGN_CHOLT(1) CPGN_CHOLT(2) CPGN_CHOLT(4) CPGN_CHOLT(6) CPGN_CHOLT(9) CPGN_CHOLT(kCholMaxSlots)
+#undef CPGN_CHOLT
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_chol_rows(int R, int64_t s, const double* M, const double* L, const double* Dinv,
+                     void* A, int dtype, const CgState* st, hipStream_t stream) {
+  if (R < 1 || R > kMaxGnRank || s < 1) return (int)hipErrorInvalidValue;
+  const int NT = (R + 15) / 16;
+  const dim3 grid((unsigned)((s + 63) / 64));
+  switch (NT) {
+#define CPGN_CHOLR(k)                                                                           \
+  case k: {                                                                                    \
+    constexpr bool lds = k <= 8;                                                               \
+    const size_t bytes =                                                                       \
+        (size_t)(4 * 16 * (16 * k + 1) + (lds ? (k * (k + 1) / 2 + k) * 272 : 0)) * sizeof(double); \
+    hipLaunchKernelGGL((k_chol_rows<k, lds>), grid, dim3(256), bytes, stream, R, s, M, L, Dinv,  \
+                       A, dtype, st);                                                          \
+    break;                                                                                     \
+  }
+    CPGN_CHOLR(1) CPGN_CHOLR(2) CPGN_CHOLR(3) CPGN_CHOLR(4) CPGN_CHOLR(5) CPGN_CHOLR(6)
+    CPGN_CHOLR(7) CPGN_CHOLR(8) CPGN_CHOLR(9) CPGN_CHOLR(10) CPGN_CHOLR(11) CPGN_CHOLR(12)
+    CPGN_CHOLR(13)
+#undef CPGN_CHOLR
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+}  // namespace cpgn

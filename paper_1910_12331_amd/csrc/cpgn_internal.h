@@ -62,7 +62,7 @@ struct Plan {
   int64_t part_elems = 0;              // MTTKRP partial buffer (elements of compute precision)
   // byte offsets into the workspace
   size_t off_apad = 0, off_fpk_last = 0, off_fpk_prev = 0, off_part = 0, off_p1 = 0;
-  size_t off_m64 = 0, off_a64 = 0, off_s = 0, off_gam = 0, off_pinv = 0;
+  size_t off_m64 = 0, off_a64 = 0, off_s = 0, off_gam = 0, off_pinv = 0, off_dinv = 0;
   size_t off_g = 0, off_v = 0, off_r = 0, off_z = 0, off_w = 0, off_q = 0;
   size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0, off_w1 = 0, off_r1 = 0;
   size_t off_slots = 0;

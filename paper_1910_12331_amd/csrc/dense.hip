@@ -1,9 +1,11 @@
 // FP64 kernels for the small dense parts of one Gauss-Newton step and one ALS sweep
 // (Singh, Ma, Yang, Solomonik, arXiv:1910.12331): Grams S = A^T A and the Hadamard products
 // Gamma(n,p) of eqs. (2) and (6); row-block times R x R products (gradient of Algorithm 1,
-// the implicit J^T J product of eq. (7), the preconditioner apply of Algorithm 2, the ALS
-// solve); the CG vector recurrences with device-resident FP64 scalars; the Cholesky-based
-// explicit inverse (Gamma(n,n) + lambda I)^-1 of Section 3.3.
+// the implicit J^T J product of eq. (7), the preconditioner apply of Algorithm 2); the CG
+// vector recurrences with device-resident FP64 scalars; the explicit inverse
+// (Gamma(n,n) + lambda I)^-1 of the Gauss-Newton preconditioner (Section 3.3), by Gauss-Jordan
+// elimination without pivoting, and the register Cholesky factor of the triangular-solve
+// preconditioner. The ALS solve is in chol.hip.
 //
 // Packed layout: the per-mode [s_n, R] matrices of one kind (factors, gradient, CG vectors)
 // are stored back to back as one [sum_n s_n, R] FP64 array; Dims::off[n] is mode n's first

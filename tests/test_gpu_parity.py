@@ -595,3 +595,20 @@ def test_mode_longer_than_one_row_tile_grid(dt):
     num, den = O.residual(Xh, Ah)
     assert abs(out[0] - num) / num < (1e-12 if dt == torch.float64 else 1e-5)
     gn_compare(p, dt, 1e-3, 0.0, 3, "sensitivity" if dt == torch.float64 else 1e-4)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_als_sweep_not_spd_leaves_factors(dt):
+    """A zero column in every factor but mode 0's makes Gamma(0) singular with an exact zero
+    pivot: the Cholesky factorization reports CP_ENOTSPD and the sweep leaves every factor as it
+    was (the later modes are skipped too)."""
+    p = make_problem((30, 20, 25), 6, workload=0, problem=6, noise=1e-2)
+    A = [a.copy() for a in p.init]
+    A[1][:, 2] = 0.0
+    A[2][:, 2] = 0.0
+    Ad = to_dev(A, dt)
+    before = [a.clone() for a in Ad]
+    status = P.als_sweep(to_dev([p.x], dt)[0], Ad, 0.0)
+    assert int(status.item()) == P._lib.CP_ENOTSPD
+    for a, b in zip(Ad, before):
+        assert torch.equal(a, b)
