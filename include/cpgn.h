@@ -164,6 +164,23 @@ int cp_gn_gradient(const cp_problem* prob, const void* X, const void* const* A, 
                    double* grad_norm_sum_dev, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Objective and gradient together, for a differentiable objective whose forward pass keeps the
+ * gradient for its backward pass: G^(n) = A^(n) Gamma^(n,n) - M^(n) for every mode (as
+ * cp_gn_gradient, the same kernels and bits), and the residual norm of eq. (3) by the expansion
+ * ||X - [[A]]||^2 = ||X||^2 - 2 <M^(1), A^(1)> + sum_{r,z} prod_m S^(m)_{rz} from the same M^(1)
+ * and Grams, so that f costs one extra pass over X (for ||X||^2) and no matrix work. The
+ * expansion cancels as the fit becomes exact: its absolute error in ||X - [[A]]||^2 is about the
+ * MTTKRP's relative accuracy times ||X||^2 (FP32 storage: ~1e-6 ||X||^2), against cp_residual's
+ * direct form. A negative square is clamped to 0.
+ *   G: N device pointers, dims[n] x rank, f_dtype, written.
+ *   res_dev: device double[2]: [0] = ||X - [[A]]||_F by the expansion, [1] = ||X||_F.
+ *   ws: at least cp_workspace_bytes(CP_OP_GN_GRADIENT).
+ */
+int cp_objective_gradient(const cp_problem* prob, const void* X, const void* const* A,
+                          void* const* G, double* res_dev, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
  * Damped Gauss-Newton matrix-vector product, Algorithm 2 with eqs. (5)-(7):
  * Q^(n) = lambda W^(n) + sum_p sum_{l,z} h^(n,p)_{krlz} W^(p)_{lz}, i.e. Q = (J^T J + lambda I) W.
  *   W: N device pointers (input), Q: N device pointers (output), both dims[n] x rank, f_dtype.

@@ -159,6 +159,12 @@ class Workspace:
 _default_ws = Workspace()
 
 
+def release_default_workspace():
+    """Drop the module-level workspace (for a clean shutdown: device memory is then released
+    before interpreter exit instead of by exit-time destructors)."""
+    _default_ws._buf = None
+
+
 def _ws(prob, op, device, ws):
     return (ws or _default_ws).get(prob, op, device)
 
@@ -207,6 +213,22 @@ def gn_gradient(X: torch.Tensor, A: Sequence[torch.Tensor], ws=None):
     _check(L.load().cp_gn_gradient(C.byref(prob), X.data_ptr(), _ptrs(A), _ptrs(G), gsum.data_ptr(),
                                    w, nb, _stream()), "cp_gn_gradient")
     return G, gsum
+
+
+def objective_gradient(X: torch.Tensor, A: Sequence[torch.Tensor], ws=None):
+    """G(n) = A(n) Gamma(n,n) - M(n) for every mode and [||X - [[A]]||_F, ||X||_F] by the expansion
+    from the same MTTKRP and Grams (cp_objective_gradient). Returns (G list, device float64[2])."""
+    _dev(X, "X")
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, factor_dtype(X), R)
+    prob = _problem(X, R)
+    G = [torch.empty_like(a) for a in A]
+    res = torch.empty(2, dtype=torch.float64, device=X.device)
+    w, nb = _ws(prob, L.OP_GN_GRADIENT, X.device, ws)
+    _check(L.load().cp_objective_gradient(C.byref(prob), X.data_ptr(), _ptrs(A), _ptrs(G),
+                                          res.data_ptr(), w, nb, _stream()),
+           "cp_objective_gradient")
+    return G, res
 
 
 def jtj_matvec(A: Sequence[torch.Tensor], W: Sequence[torch.Tensor], lam: float = 0.0, ws=None):

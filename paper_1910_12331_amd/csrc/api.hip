@@ -367,6 +367,31 @@ int cp_gn_gradient(const cp_problem* prob, const void* X, const void* const* A, 
   return hip_status();
 }
 
+int cp_objective_gradient(const cp_problem* prob, const void* X, const void* const* A,
+                          void* const* G, double* res_dev, void* ws, size_t ws_bytes,
+                          void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !res_dev) return CP_EINVAL;
+  if ((rc = check_ptrs(p, A)) || (rc = check_ptrs(p, (const void* const*)G)) ||
+      (rc = check_ws(p, ws, ws_bytes)))
+    return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  launch_prepare_factors_src(p, A, p.dtype, ws, st, true);
+  PerMode<void*> cg{};
+  for (int n = 0; n < p.N; ++n) cg.p[n] = G[n];
+  gradient_core(p, d, X, w, 0.0, cg, nullptr, st);
+  // ||X - [[A]]||^2 = ||X||^2 - 2 <M(0), A(0)> + sum_{r,z} prod_m S(m)[r,z] from the same M(0)
+  // and Grams: one more pass over X, for ||X||^2, with no matrix work
+  int nblocks = 0;
+  launch_sumsq(p, X, w.red_dot, st, &nblocks);
+  launch_fin_residual_expansion(d, nblocks, w.red_dot, w.m64, w.a64, w.S, res_dev, st);
+  return hip_status();
+}
+
 int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* const* W,
                      double lambda, void* const* Q, void* ws, size_t ws_bytes, void* stream) {
   Plan p;

@@ -65,6 +65,39 @@ def test_objective_chain_rule_and_fp32():
         assert rel(a.grad.double().cpu().numpy(), 3.0 * g) < 1e-4
 
 
+@pytest.mark.parametrize("dims,rank", [((12, 10, 8), 3), ((9, 7, 8, 6), 4), ((37, 29, 45), 20)])
+def test_fused_objective_matches_oracle_and_direct_gradient(dims, rank):
+    """method="fused" (cp_objective_gradient): the same gradient bits as the direct form's
+    backward (the same kernels), and f by the expansion within its cancellation bound: the
+    FP64 rounding of ||X||^2, 2 <M, A> and sum prod S, 64 u (||X||^2 + 2 |<M, A>| + sum prod S)
+    in absolute terms, here with a residual of about 0.1 of ||X||."""
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-1)
+    X = dev([p.x], torch.float64)[0]
+    A1 = dev(p.init, torch.float64, grad=True)
+    A2 = dev(p.init, torch.float64, grad=True)
+    f1 = P.cp_objective(X, A1, method="fused")
+    f1.backward()
+    P.cp_objective(X, A2).backward()
+    for a, b in zip(A1, A2):
+        assert torch.equal(a.grad, b.grad)
+    ref = O.objective(p.x, p.init)
+    M0 = O.mttkrp(p.x, p.init, 0)
+    S = O.grams(p.init)
+    had = np.ones_like(S[0])
+    for sm in S:
+        had = had * sm
+    scale = float(np.sum(p.x * p.x)) + 2 * abs(float(np.sum(M0 * p.init[0]))) + abs(float(np.sum(had)))
+    assert abs(float(f1.detach()) - ref) <= 0.5 * 64 * 2.0 ** -53 * scale
+
+
+def test_fused_objective_gradcheck_fp64():
+    p = make_problem((12, 10, 8), 3, workload=0, problem=3, noise=1e-1)
+    X = dev([p.x], torch.float64)[0]
+    A = tuple(dev(p.init, torch.float64, grad=True))
+    assert torch.autograd.gradcheck(lambda *a: P.cp_objective(X, a, method="fused"), A, eps=1e-6,
+                                    atol=1e-6, rtol=1e-6)
+
+
 def test_objective_rejects_gradient_of_x():
     p = make_problem((6, 5, 4), 2, workload=0, problem=2)
     X = torch.tensor(p.x, dtype=torch.float64, device="cuda", requires_grad=True)
