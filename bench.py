@@ -323,38 +323,42 @@ def high_rank_leg(P, torch, stream):
 
 
 def measure_peaks(torch):
-    """HBM stream-copy bandwidth (1 GiB read + 1 GiB written per launch) and register-only MFMA
-    loops (16x16x4 FP32, 16x16x4 FP64, 16x16x32 bf16; 32 accumulators, two wavefronts per SIMD
-    on all 1024 SIMDs), from libcppeaks.so; the best of three runs of 10 launches each."""
+    """HBM stream-copy bandwidth (1 GiB read + 1 GiB written per launch; three launch shapes, the
+    best is reported) and register-only MFMA loops (16x16x4 FP32, 16x16x4 FP64, 16x16x32 bf16;
+    1024 workgroups of four wavefronts), from libcppeaks.so; the best of three runs of 10
+    launches each."""
     import ctypes as C
     path = os.path.join(ROOT, "paper_1910_12331_amd", "libcppeaks.so")
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1910_12331_amd.build`")
     lib = C.CDLL(path)
     lib.cpk_copy_gbs.restype = C.c_double
-    lib.cpk_copy_gbs.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
+    lib.cpk_copy_gbs.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int]
     lib.cpk_mfma_tflops.restype = C.c_double
-    lib.cpk_mfma_tflops.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]
+    lib.cpk_mfma_tflops.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]
     n = 1 << 30
     src = torch.empty(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty(n, dtype=torch.uint8, device="cuda")
     src.fill_(1)
     torch.cuda.synchronize()
-    copy = max(lib.cpk_copy_gbs(src.data_ptr(), dst.data_ptr(), n, 10) for _ in range(3))
+    copies = {f"{b}x256_v{v}": max(lib.cpk_copy_gbs(src.data_ptr(), dst.data_ptr(), n, 10, b, v)
+                                   for _ in range(3))
+              for b, v in ((1024, 0), (65536, 0), (65536, 2))}
+    copy = max(copies.values())
     del src, dst
     out = torch.empty(4096, dtype=torch.float64, device="cuda")
     rates = {}
     for kind, name, iters in ((0, "fp32_16x16x4", 4000), (1, "fp64_16x16x4", 4000),
                               (2, "bf16_16x16x32", 8000)):
-        rates[name] = max(lib.cpk_mfma_tflops(kind, out.data_ptr(), 2048, iters, 10)
+        rates[name] = max(lib.cpk_mfma_tflops(kind, out.data_ptr(), 1024, 256, iters, 10)
                           for _ in range(3))
     log(f"[peaks] copy {copy:.0f} GB/s; MFMA TFLOP/s " +
         ", ".join(f"{k} {v:.1f}" for k, v in rates.items()))
-    return {"hbm_copy_gbs": copy, "mfma_tflops": rates,
+    return {"hbm_copy_gbs": copy, "hbm_copy_configs_gbs": copies, "mfma_tflops": rates,
             "vendor": {"hbm_gbs": PEAK_HBM_GBS, "fp32_tflops": PEAK_FP32_MFMA_TFLOPS,
                        "fp64_tflops": PEAK_FP64_MFMA_TFLOPS, "bf16_tflops": 2500.0},
-            "note": "copy: 2 x bytes / time; MFMA: register-only loops, 32 independent "
-                    "accumulators per wavefront, 2 wavefronts per SIMD"}
+            "note": "copy: 2 x bytes / time; MFMA: register-only loops, 32 (FP64: 16) "
+                    "independent accumulators per wavefront"}
 
 
 def blas_threads():

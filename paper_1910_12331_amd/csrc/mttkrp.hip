@@ -530,7 +530,11 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   const int q = caseB ? p.N - 2 : p.N - 1;
   const int64_t J = p.s[mode];
   g.MB = dt ? (p.dtype == CP_F64 ? 1 : 2) : (p.dtype == CP_F64 ? 2 : 4);
-  (void)vec_ok;
+  // FP32, contraction along X rows: 80-row tiles where they pad the mode less than 64-row ones
+  // (s = 400: 5 tiles and no padding rows, against 7 tiles of which 48 rows are padding)
+  if (!dt && p.dtype == CP_F32 && !caseB && vec_ok && p.xk == 0 &&
+      (J + 79) / 80 * 80 < (J + 63) / 64 * 64)
+    g.MB = 5;
   g.rows_per_tile = 16 * g.MB;
   g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
   g.QC = (p.s[q] + 15) / 16;
@@ -594,6 +598,8 @@ static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipS
       else launch_nb<T, true, 4, false>(NB, grid, st, a);
     } else if (!vec) {
       launch_nb<T, false, 4, false>(NB, grid, st, a);
+    } else if (MB == 5) {
+      launch_nb<T, false, 5, true>(NB, grid, st, a);
     } else {
       launch_nb<T, false, 4, true>(NB, grid, st, a);
     }

@@ -59,7 +59,7 @@ def gpu():
 MTTKRP_CASES = [
     ((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4), ((64, 48, 32), 16),
     ((30, 20, 25), 50), ((24, 20, 18), 100), ((12, 10, 9), 130), ((1, 5, 3), 2), ((5, 1, 3), 2),
-    ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33),
+    ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33), ((230, 17, 12), 20),
 ]
 
 
