@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle's MTTKRP, GN step, ALS sweep and residual at "
                          "300^3 R=50 and 400^3 R=100 on the host and print them as JSON")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="only run the headline loop (--warmup then --steps Gauss-Newton steps with "
+                         "their residuals and run restarts) and exit (for kernel traces)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run each single-mode MTTKRP and one device copy of X of known size "
                          "(the workload the rocprofv3 counter runs are taken on), then exit")
@@ -457,6 +460,42 @@ def cpu_table(shapes=((300, 50), (400, 100)), runs=10, warm=3):
     return out
 
 
+def headline_runs(P, torch, Xd, A0, warmup, steps, target=1e-6):
+    """The timed loop. A step is one Gauss-Newton iteration (Algorithm 1 body: eps_cg 1e-3, at
+    most 20 CG iterations, the damping schedule) followed by the direct relative residual that
+    its stopping test reads on the host. Runs go from the seeded start until the residual reaches
+    the FP32 floor target (1e-6, where the mixed-precision driver leaves FP32 storage); the next
+    step then starts a new run from the same start (factors copied back, schedule reset). Past
+    that floor the FP32 gradient is rounding noise, and a step taken there leaves the converged
+    point. Returns (ms per step, residuals of the timed steps, runs completed in the timed
+    window, the optimizer, the start factors, target)."""
+    A_start = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+    gn = P.GaussNewton(Xd, [a.clone() for a in A_start], P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+    state = dict(runs=0)
+
+    def step():
+        gn.step()
+        r = gn.residual()
+        if r <= target or not np.isfinite(r):
+            for a, a0 in zip(gn.A, A_start):
+                a.copy_(a0)
+            gn.schedule = P.DampingSchedule()
+            state["runs"] += 1
+        return r
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    runs_before = state["runs"]
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed / steps * 1e3, res, state["runs"] - runs_before, gn, A_start, target
+
+
 def trajectory_table(P, torch, Xd, X64, A0, steps):
     """Plain Gauss-Newton steps (damping schedule, eps_cg 1e-3, <= 20 CG iterations) from the
     seeded start with FP32 and with FP64 storage; one JSON line per step with the damping, the
@@ -531,6 +570,11 @@ def main():
     if args.trajectory:
         trajectory_table(P, torch, Xd, X64, A0, args.trajectory)
         return
+    if args.profile_step:
+        ms, res, runs, _, _, _ = headline_runs(P, torch, Xd, A0, args.warmup, args.steps)
+        print(json.dumps({"profile_step": f"{args.warmup} + {args.steps} GN steps with residuals",
+                          "ms_per_step": ms, "runs_completed": runs}), flush=True)
+        return
     if args.profile_kernels:
         ws = P.Workspace()
         for n in range(3):
@@ -597,40 +641,9 @@ def main():
     gn_vs_als = gn_vs_als_leg(P, torch, stream)
     objective = objective_leg(P, torch, Xd, A0, stream)
 
-    # ---- GN steps: warmup, then K timed steps. A step is one Gauss-Newton iteration (Algorithm 1
-    # body) followed by the direct relative residual that its stopping test reads on the host.
-    # Runs go from the seeded start until the residual reaches the FP32 floor target (1e-6, where
-    # the mixed-precision driver leaves FP32 storage); the next step then starts a new run from
-    # the same start (the factors copied back, the damping schedule reset). Past that floor the
-    # FP32 gradient is rounding noise, and a step taken there leaves the converged point.
-    target = 1e-6
-    A_start = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
-    gn = P.GaussNewton(Xd, [a.clone() for a in A_start], P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
-    run_state = dict(runs=0, run_steps=0)
-
-    def headline_step():
-        gn.step()
-        r = gn.residual()
-        run_state["run_steps"] += 1
-        if r <= target or not np.isfinite(r):
-            for a, a0 in zip(gn.A, A_start):
-                a.copy_(a0)
-            gn.schedule = P.DampingSchedule()
-            run_state["runs"] += 1
-            run_state["run_steps"] = 0
-        return r
-
-    for _ in range(args.warmup):
-        headline_step()
-    torch.cuda.synchronize()
-    runs_before = run_state["runs"]
-    res_timed = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res_timed.append(headline_step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = elapsed / args.steps * 1e3
+    # ---- GN steps: warmup, then K timed steps (headline_runs)
+    ms_step, res_timed, runs_in_window, gn, A_start, target = headline_runs(
+        P, torch, Xd, A0, args.warmup, args.steps)
     r_now = res_timed[-1]
     log(f"[bench] GN step + residual: {ms_step:.3f} ms; residuals of the timed steps "
         + " ".join(f"{r:.2e}" for r in res_timed))
@@ -657,7 +670,7 @@ def main():
     if not valid:
         log("[bench] WARNING: a timed step left the converging runs")
     trajectory = dict(start_residual=r_start, target=target, residuals=res_timed,
-                      runs_completed_in_timed_window=run_state["runs"] - runs_before,
+                      runs_completed_in_timed_window=runs_in_window,
                       replay_equals_timed_run=replay_res == res_timed, valid=valid,
                       note="relative residual after each timed step; a run restarts from the "
                            "seeded start once its residual is <= target. valid: all finite, "
