@@ -347,6 +347,214 @@ __global__ __launch_bounds__(256) void k_chol_rows(int R, int64_t s, const doubl
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// P = (G + lambda I)^-1 (or G + lambda diag(G)) for R <= 128, one workgroup of 16 wavefronts
+// per matrix: Gauss-Jordan elimination without pivoting, blocked by 16 x 16 tiles. For an SPD
+// matrix the pivots are those of its Cholesky factorization, so "pivot > 0" tests positive
+// definiteness. The identity-padded matrix (RP = 16 NT rows) lives in LDS. Block step k:
+//   (a) one wavefront inverts the diagonal tile D = M_kk in place by 16 scalar Gauss-Jordan
+//       steps in registers (row and column of each pivot exchanged by lane permutes); for
+//       k > 0 it does so during step k - 1, right after updating that tile in (c);
+//   (b) M_kj <- D^-1 M_kj for j != k (the pivot block row);
+//   (c) M_ij <- M_ij - M_ik M_kj for i, j != k, and M_ik <- -M_ik D^-1 (the pivot block
+//       column, written after a barrier, once every product has read the old M_ik);
+// (b) and (c) are 16 x 16 x 16 products on the FP64 matrix cores. Four workgroup barriers per
+// 16 pivots instead of one per pivot. A non-positive or non-finite pivot records CP_ENOTSPD.
+constexpr int kInvWaves = 16;
+
+// Value of lane c of each quad of lanes (DPP quad permutation), for a double.
+template <int C>
+__device__ __forceinline__ double quad_bcast(double x) {
+  const int2 v = __builtin_bit_cast(int2, x);
+  const int lo = __builtin_amdgcn_mov_dpp(v.x, C * 0x55, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(v.y, C * 0x55, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, int2{lo, hi});
+}
+
+// Value of lane l (uniform) of a double.
+__device__ __forceinline__ double read_lane(double x, int l) {
+  const int2 v = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, int2{__builtin_amdgcn_readlane(v.x, l),
+                                         __builtin_amdgcn_readlane(v.y, l)});
+}
+
+template <int NT>
+__global__ __launch_bounds__(kInvWaves * 64) void k_spd_inv_blk(int R, const double* __restrict__ Gin,
+                                                               int64_t g_stride, double lambda,
+                                                               const double* __restrict__ lam_dev,
+                                                               double* __restrict__ Pout,
+                                                               int64_t p_stride, int first_mode,
+                                                               CgState* st, int diag_damping) {
+  constexpr int RP = 16 * NT, LD = RP + 1;   // odd row stride: column reads hit distinct banks
+  extern __shared__ double M[];               // [RP][LD]
+  __shared__ int sbad;
+  const int n = first_mode + blockIdx.x;
+  const double* G = Gin + n * g_stride;
+  double* P = Pout + n * p_stride;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, g = lane >> 4, m = lane & 15;
+  // every load of the matrix is issued before the first is used (one round trip)
+  constexpr int kInit = (RP * RP + kInvWaves * 64 - 1) / (kInvWaves * 64);
+  double gv[kInit];
+#pragma unroll
+  for (int u = 0; u < kInit; ++u) {
+    const int e = t + u * kInvWaves * 64, i = e / RP, k = e - i * RP;
+    const bool ok = e < RP * RP && i < R && k < R;
+    const double x = G[ok ? i * R + k : 0];
+    gv[u] = ok ? x : 0.0;
+  }
+  if (lam_dev) lambda = *lam_dev;
+  if (t == 0) {
+    sbad = st->status != CP_OK;   // one read: another workgroup may set it meanwhile
+    if (!sbad && (!(lambda >= 0.0) || !isfinite(lambda))) {
+      st->status = CP_EINVAL;
+      st->done = 1;
+      sbad = 1;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kInit; ++u) {
+    const int e = t + u * kInvWaves * 64, i = e / RP, k = e - i * RP;
+    if (e < RP * RP) {
+      // lambda I or lambda diag(G) inside the R x R block, the identity past it
+      const double v = i < R && k < R ? gv[u] + (i == k ? (diag_damping ? lambda * gv[u] : lambda) : 0.0)
+                                      : (i == k ? 1.0 : 0.0);
+      M[i * LD + k] = v;
+    }
+  }
+  __syncthreads();
+  if (sbad) return;
+  auto tile = [&](int I, int J) { return M + (16 * I) * LD + 16 * J; };
+  // C += op(A) B over one 16 x 16 x 16 tile product: A operand A[m][4 q + g] (scaled by sa),
+  // B operand B[4 q + g][m]; C[g + 4 v][m] in element v.
+  auto tprod = [&](const double* A, const double* B, double sa, dv4 c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      c = mfma64(sa * A[m * LD + 4 * q + g], B[(4 * q + g) * LD + m], c);
+    return c;
+  };
+  auto tload = [&](const double* T) {
+    dv4 c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[v] = T[(g + 4 * v) * LD + m];
+    return c;
+  };
+  auto tstore = [&](double* T, dv4 c) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(g + 4 * v) * LD + m] = c[v];
+  };
+  // Wavefront 0 inverts a diagonal tile in place: lane l holds entries (r, 4 (l % 4) + e),
+  // r = l / 4; the row and column of each pivot are exchanged by lane permutes.
+  auto pivot_inv = [&](double* D) {
+    const int r = lane >> 2, cq = 4 * (lane & 3);
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = D[r * LD + cq + e];
+    bool bad = false;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      double rowp[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rowp[e] = __shfl(a[e], 4 * p + (lane & 3));
+      // column p: entry (r, p) sits in lane 4 r + p / 4 of this lane's quad (a quad broadcast);
+      // the pivot in lane 4 p + p / 4 (uniform)
+      const double ap = a[p & 3];
+      double colp;
+      switch (p >> 2) {
+        case 0: colp = quad_bcast<0>(ap); break;
+        case 1: colp = quad_bcast<1>(ap); break;
+        case 2: colp = quad_bcast<2>(ap); break;
+        default: colp = quad_bcast<3>(ap); break;
+      }
+      const double piv = read_lane(ap, 4 * p + (p >> 2));
+      bad = bad || !(piv > 0.0) || !isfinite(piv);
+      // 1 / piv: the hardware reciprocal refined by one Newton step for f(x) = 1/x - piv
+      const double r0 = __builtin_amdgcn_rcp(piv);
+      const double rp = __fma_rn(r0, __fma_rn(-piv, r0, 1.0), r0);
+      const double u = colp * rp;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = cq + e;
+        const double upd = a[e] - u * rowp[e];
+        a[e] = r == p ? (c == p ? rp : rowp[e] * rp) : (c == p ? -u : upd);
+      }
+    }
+    if (bad && lane == 0) sbad = 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) D[r * LD + cq + e] = a[e];
+  };
+  if (wv == 0) pivot_inv(tile(0, 0));
+  __syncthreads();
+  constexpr int NM = NT > 1 ? NT - 1 : 1;
+#pragma unroll 1
+  for (int k = 0; k < NT; ++k) {
+    if (sbad) {   // same value in every thread: uniform exit
+      if (t == 0) {
+        st->status = CP_ENOTSPD;
+        st->done = 1;
+      }
+      return;
+    }
+    const double* Dk = tile(k, k);   // (a) already inverted
+    // (b) the pivot block row, one tile per wavefront
+    for (int j = wv; j < NT - 1; j += kInvWaves) {
+      const int jj = j < k ? j : j + 1;
+      const dv4 c = tprod(Dk, tile(k, jj), 1.0, dv4{0.0, 0.0, 0.0, 0.0});
+      tstore(tile(k, jj), c);
+    }
+    __syncthreads();
+    // (c) wavefront 0 updates the next diagonal tile and inverts it (the next step's (a));
+    // wavefronts 1.. form the pivot block column in registers and update the other trailing
+    // tiles.
+    dv4 colt = {0.0, 0.0, 0.0, 0.0};
+    const int ic = wv - 1 < k ? wv - 1 : wv;
+    const bool has_col = wv >= 1 && wv <= NT - 1;
+    if (wv == 0) {
+      if (k + 1 < NT) {
+        double* T = tile(k + 1, k + 1);
+        tstore(T, tprod(tile(k + 1, k), tile(k, k + 1), -1.0, tload(T)));
+        pivot_inv(T);
+      }
+    } else {
+      if (has_col) colt = tprod(tile(ic, k), Dk, -1.0, colt);
+      const int un = k + 1 < NT ? k * NM + k : -1;   // the next diagonal tile, done above
+      for (int u = wv - 1; u < (NT - 1) * (NT - 1); u += kInvWaves - 1) {
+        if (u == un) continue;
+        const int i = u / NM, j = u - i * NM;
+        const int ii = i < k ? i : i + 1, jj = j < k ? j : j + 1;
+        double* T = tile(ii, jj);
+        tstore(T, tprod(tile(ii, k), tile(k, jj), -1.0, tload(T)));
+      }
+    }
+    __syncthreads();
+    if (has_col) tstore(tile(ic, k), colt);
+    __syncthreads();
+  }
+  for (int e = t; e < R * R; e += kInvWaves * 64) {
+    const int i = e / R, k = e - i * R;
+    P[e] = M[i * LD + k];
+  }
+}
+
+int launch_spd_inv_blk(int R, const double* G, int64_t g_stride, double lambda, double* P,
+                       int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                       bool diag_damping, const double* lam_dev) {
+  const int NT = (R + 15) / 16;
+  const size_t lds = (size_t)16 * NT * (16 * NT + 1) * sizeof(double);
+  switch (NT) {
+#define CPGN_INV(k)                                                                             \
+  case k:                                                                                       \
+    hipLaunchKernelGGL((k_spd_inv_blk<k>), dim3(count), dim3(kInvWaves * 64), lds, s, R, G,   \
+                       g_stride, lambda, lam_dev, P, p_stride, first_mode, st,                  \
+                       diag_damping ? 1 : 0);                                                   \
+    break;
+    CPGN_INV(1) CPGN_INV(2) CPGN_INV(3) CPGN_INV(4) CPGN_INV(5) CPGN_INV(6) CPGN_INV(7)
+    CPGN_INV(8)
+#undef CPGN_INV
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
 int launch_chol_tiles(int R, const double* G, int64_t g_stride, double lambda, double* L,
                       int64_t l_stride, double* Dinv, int64_t d_stride, int first_mode, int count,
                       CgState* st, hipStream_t s) {

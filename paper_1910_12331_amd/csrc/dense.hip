@@ -1042,9 +1042,17 @@ int spd_inv_supported(int R) { return R >= 1 && R <= kMaxGnRank; }
 #ifndef CPGN_SPD_TD
 #define CPGN_SPD_TD 32
 #endif
+int launch_spd_inv_blk(int R, const double* G, int64_t g_stride, double lambda, double* P,
+                       int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                       bool diag_damping, const double* lam_dev);
+
 int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
                    int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
                    bool diag_damping, const double* lam_dev) {
+  // R <= 128: Gauss-Jordan blocked by 16 x 16 tiles on the FP64 matrix cores (chol.hip)
+  if (R <= 128)
+    return launch_spd_inv_blk(R, G, g_stride, lambda, P, p_stride, first_mode, count, st, s,
+                              diag_damping, lam_dev);
   // Thread grid TD x TD, each thread an NBK x NBK block. 32 x 32 (1024 threads) measured faster
   // than 16 x 16 at R = 50, 100 and 128 (the same arithmetic, so the same bits).
   constexpr int TD = CPGN_SPD_TD;
