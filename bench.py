@@ -758,6 +758,7 @@ def main():
         # pick is then timed like the fixed configurations below
         tune = P.autotune_batched(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20),
                                   stream_counts=(1, 2, 4, 8, 16), steps=3)
+        hz = P.device_clock_hz()
         configs = [(1, False), (args.batched_streams, False), (args.batched_streams, True)]
         if (tune.n_streams, tune.graphs) not in configs:
             configs.append((tune.n_streams, tune.graphs))
@@ -769,13 +770,16 @@ def main():
             for _ in range(2):
                 bgn.step()
             bgn.synchronize()
-            per = []
+            # per-problem step latency from device timestamps (the device clock written by a
+            # one-thread kernel on the problem's stream right before and after its step)
+            stamps = torch.zeros((5, 2 * len(devs)), dtype=torch.int64, device="cuda")
             t0 = time.perf_counter()
-            for _ in range(5):
-                ev = bgn.step(timed=True)
+            for k in range(5):
+                bgn.step(stamps=stamps[k])
                 bgn.synchronize()
-                per += [e0.elapsed_time(e1) for e0, e1 in ev]
             el = time.perf_counter() - t0
+            ticks = stamps.view(5, len(devs), 2).cpu().numpy()
+            per = ((ticks[:, :, 1] - ticks[:, :, 0]) / hz * 1e3).ravel()
             key = f"streams_{ns}" + ("_graphs" if graphs else "")
             res[key] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
                             step_ms_p99=float(np.percentile(per, 99)))
@@ -792,7 +796,8 @@ def main():
             f"problem-steps/s in the same timed loop")
         batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
                        note="_graphs: each problem's GN step and damping update replayed from a "
-                            "captured HIP graph", **res)
+                            "captured HIP graph; step_ms_p50/p99: per-problem step latency from "
+                            f"device timestamps ({hz} Hz clock), 5 batch steps", **res)
         kb, kg = f"streams_{args.batched_streams}", f"streams_{args.batched_streams}_graphs"
         log(f"[bench] batched workload: {res[kg]['problem_steps_per_s']:.0f} problem-steps/s on "
             f"{args.batched_streams} streams with graph replay, {res[kb]['problem_steps_per_s']:.0f} "

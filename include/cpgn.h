@@ -290,6 +290,16 @@ int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
 int cp_damping_advance(double* state_dev, void* stream);
 
 /*
+ * Device timestamps for per-problem step latencies (p50/p99) of many problems run on several
+ * streams: enqueues one one-thread kernel on `stream` that writes the device's constant-rate
+ * clock to *dst_dev when it runs, so that two of them around a step bracket the step's execution
+ * on the device. dst_dev: device int64_t, written. cp_device_clock_hz returns the rate of that
+ * clock in *hz (host int64_t) for the current device. CP_EINVAL for a null pointer.
+ */
+int cp_device_timestamp(int64_t* dst_dev, void* stream);
+int cp_device_clock_hz(int64_t* hz);
+
+/*
  * One ALS sweep, Section 2.2: for n = 0..N-1 in order, A^(n) = M^(n) (Gamma^(n) + lambda I)^-1
  * with M^(n) computed from the latest factors: the FP64 Cholesky factor L L^T = Gamma^(n) +
  * lambda I, then Y L^T = M^(n) and A^(n) L = Y by blocked substitution (16-column blocks; the

@@ -19,7 +19,7 @@ LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_als_sweep", "cp_residual",
+           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -90,6 +90,10 @@ def load(path: str = LIB_PATH):
                                       vp, vp, vp, sz, vp]
     lib.cp_damping_advance.restype = i32
     lib.cp_damping_advance.argtypes = [vp, vp]
+    lib.cp_device_timestamp.restype = i32
+    lib.cp_device_timestamp.argtypes = [vp, vp]
+    lib.cp_device_clock_hz.restype = i32
+    lib.cp_device_clock_hz.argtypes = [P(C.c_int64)]
     lib.cp_als_sweep.restype = i32
     lib.cp_als_sweep.argtypes = [P(CpProblem), vp, PTRS, C.c_double, vp, vp, sz, vp]
     lib.cp_residual.restype = i32

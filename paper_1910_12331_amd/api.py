@@ -385,6 +385,22 @@ def damping_advance(state: torch.Tensor):
     return state
 
 
+def device_timestamp(buf: torch.Tensor, index: int):
+    """Enqueue on the current stream a write of the device clock to buf[index] (device int64)."""
+    _dev(buf, "buf", torch.int64)
+    if not 0 <= index < buf.numel():
+        raise IndexError(index)
+    ptr = buf.data_ptr() + index * 8
+    _check(L.load().cp_device_timestamp(ptr, _stream()), "cp_device_timestamp")
+
+
+def device_clock_hz() -> int:
+    """Rate of the clock that device_timestamp writes (ticks per second)."""
+    hz = C.c_int64(0)
+    _check(L.load().cp_device_clock_hz(C.byref(hz)), "cp_device_clock_hz")
+    return int(hz.value)
+
+
 def als_sweep(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float = 0.0, status=None, ws=None):
     """One ALS sweep in place on A (Section 2.2); returns the device int32 status."""
     _dev(X, "X")

@@ -23,6 +23,7 @@ void launch_gn_apply(const Dims&, double*, const double*, const PerMode<void*>&,
                      const CgState*, hipStream_t);
 void launch_gn_stats(const Dims&, int, const double*, const CgState*, cp_gn_stats*, hipStream_t);
 void launch_status_out(const CgState*, int32_t*, hipStream_t);
+void launch_timestamp(int64_t*, hipStream_t);
 int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
                    hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr);
@@ -554,6 +555,22 @@ int cp_damping_advance(double* state_dev, void* stream) {
   if (!state_dev) return CP_EINVAL;
   launch_damping_advance(state_dev, (hipStream_t)stream);
   return hip_status();
+}
+
+int cp_device_timestamp(int64_t* dst_dev, void* stream) {
+  if (!dst_dev) return CP_EINVAL;
+  launch_timestamp(dst_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int cp_device_clock_hz(int64_t* hz) {
+  if (!hz) return CP_EINVAL;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return CP_EHIP;
+  *hz = (int64_t)khz * 1000;
+  return CP_OK;
 }
 
 int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double lambda,

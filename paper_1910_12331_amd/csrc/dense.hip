@@ -345,6 +345,10 @@ __global__ void k_ls_stats(const CgState* st, cp_armijo_stats* out) {
   out->accepted = acc ? 1 : 0;
 }
 
+__global__ void k_timestamp(int64_t* out) {
+  if (threadIdx.x == 0) *out = (int64_t)wall_clock64();
+}
+
 __global__ void k_status_out(const CgState* st, int32_t* out) {
   if (threadIdx.x == 0) *out = st->status;
 }
@@ -1030,6 +1034,10 @@ __global__ void k_damping_advance(double* state) {
 
 void launch_damping_advance(double* state, hipStream_t s) {
   hipLaunchKernelGGL(k_damping_advance, dim3(1), dim3(64), 0, s, state);
+}
+
+void launch_timestamp(int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_timestamp, dim3(1), dim3(64), 0, s, out);
 }
 
 void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {

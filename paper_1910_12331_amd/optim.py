@@ -357,9 +357,12 @@ class BatchedGaussNewton:
             self.graphs.append(g)
         torch.cuda.synchronize()
 
-    def step(self, timed: bool = False):
+    def step(self, timed: bool = False, stamps: torch.Tensor | None = None):
         """One Gauss-Newton step of every problem. With timed=True returns one (start, end) pair
-        of HIP events per problem, recorded on its stream around its step."""
+        of HIP events per problem, recorded on its stream around its step. With stamps (device
+        int64, 2 per problem) the device clock is written to stamps[2 i] and stamps[2 i + 1] by
+        kernels enqueued on problem i's stream right before and after its step
+        (api.device_timestamp; ticks of api.device_clock_hz())."""
         events = []
         for i, opt in enumerate(self.opts):
             s = self.streams[i % len(self.streams)]
@@ -367,11 +370,15 @@ class BatchedGaussNewton:
                 if timed:
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(s)
+                if stamps is not None:
+                    api.device_timestamp(stamps, 2 * i)
                 if self.graphs is not None:
                     self.graphs[i].replay()
                     opt.steps += 1
                 else:
                     opt.step()
+                if stamps is not None:
+                    api.device_timestamp(stamps, 2 * i + 1)
                 if timed:
                     e1.record(s)
                     events.append((e0, e1))

@@ -143,6 +143,8 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_gn_step_devlam(C.byref(p), X, A, C.byref(good0), None, C.c_void_p(0x50000), ws,
                                  need, None) == L.CP_EINVAL
     assert lib.cp_damping_advance(None, None) == L.CP_EINVAL
+    assert lib.cp_device_timestamp(None, None) == L.CP_EINVAL
+    assert lib.cp_device_clock_hz(None) == L.CP_EINVAL
     # storage conversion: negative count, null pointers
     assert lib.cp_tensor_to_bf16(X, -1, 0, M, None) == L.CP_EINVAL
     assert lib.cp_tensor_to_bf16(None, 10, 0, M, None) == L.CP_EINVAL

@@ -170,6 +170,37 @@ def test_batched_streams_match_single_stream_runs():
             assert torch.equal(a, a2)
 
 
+def test_device_timestamps_bracket_batched_steps():
+    """cp_device_timestamp around each problem's step on its stream: the clock rate is positive,
+    every step's end stamp is after its start, the stamps of problems on one stream are ordered
+    as the steps were enqueued, each step's device duration is no longer than the HIP-event time
+    around the same step (plus 20 us for the stamp kernels), and the stamped run ends where an
+    unstamped one does."""
+    from workloads import batched_problems
+    probs = batched_problems(4)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    hz = P.device_clock_hz()
+    assert hz > 0
+    plain = P.BatchedGaussNewton(mk(), n_streams=2)
+    b = P.BatchedGaussNewton(mk(), n_streams=2)
+    stamps = torch.zeros(2 * len(probs), dtype=torch.int64, device="cuda")
+    plain.step()
+    ev = b.step(timed=True, stamps=stamps)
+    plain.synchronize()
+    b.synchronize()
+    t = stamps.view(len(probs), 2).cpu().numpy()
+    assert (t[:, 1] > t[:, 0]).all()
+    for i in range(2, len(probs)):   # problems i - 2 and i share a stream
+        assert t[i, 0] >= t[i - 2, 1]
+    for (e0, e1), (s0, s1) in zip(ev, t):
+        dev_ms = (s1 - s0) / hz * 1e3
+        assert 0.0 < dev_ms <= e0.elapsed_time(e1) + 0.02
+    for op, ob in zip(plain.opts, b.opts):
+        for a, c in zip(op.A, ob.A):
+            assert torch.equal(a, c)
+
+
 # ------------------------------------------------------------------ graph-replayable steps
 def test_device_damping_schedule_matches_host():
     """cp_damping_advance gives bitwise the host schedule's sequence (both directions)."""
