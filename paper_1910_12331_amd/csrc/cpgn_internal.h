@@ -19,15 +19,6 @@ constexpr int kMaxGnRank = 208;
 // Largest grid y (and z) dimension of a launch.
 constexpr int64_t kMaxGridY = 65535;
 constexpr int kNumCU = 256;       // compute units of an MI355X (8 XCDs x 32)
-constexpr int kNumXcd = 8;        // XCDs; workgroup b of a launch runs on XCD b % 8
-
-// Tile of workgroup b in a launch of n workgroups, such that each XCD (which has its own L2)
-// runs a contiguous range of tiles: neighbouring tiles that read the same operand rows then
-// share one L2 instead of fetching them once per XCD. A bijection of [0, n).
-__host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
-  const int q = n / kNumXcd, r = n % kNumXcd, x = b % kNumXcd, j = b / kNumXcd;
-  return x * q + (x < r ? x : r) + j;
-}
 
 // ------------------------------------------------------------------------------------------
 // Matrix-core traits. Lane l of a wavefront supplies A[l%16][l/16] and B[l/16][l%16] to a

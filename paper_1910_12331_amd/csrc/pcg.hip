@@ -57,43 +57,6 @@ struct CgArgs {
   int rb_off[kMaxOrder + 1];
 };
 
-// Mode n of row block rb, its length and its first packed row, selected from the kernel
-// arguments with constant indexes only: every argument is read in the kernel's first batch of
-// scalar loads instead of one dependent load per mode.
-struct BlockMode {
-  int n, rb0;
-  int64_t s, off;
-};
-
-__device__ __forceinline__ BlockMode block_mode(const CgArgs& a, int rb) {
-  BlockMode b{0, 0, a.d.s[0], a.d.off[0]};
-#pragma unroll
-  for (int i = 1; i < kMaxOrder; ++i) {
-    const bool in = i < a.d.N && rb >= a.rb_off[i];
-    b.n = in ? i : b.n;
-    b.rb0 = in ? a.rb_off[i] : b.rb0;
-    b.s = in ? a.d.s[i] : b.s;
-    b.off = in ? a.d.off[i] : b.off;
-  }
-  return b;
-}
-
-__device__ __forceinline__ BlockMode mode_of(const CgArgs& a, int n) {
-  BlockMode b{0, 0, a.d.s[0], a.d.off[0]};
-#pragma unroll
-  for (int i = 1; i < kMaxOrder; ++i) {
-    const bool in = i == n;
-    b.n = in ? i : b.n;
-    b.s = in ? a.d.s[i] : b.s;
-    b.off = in ? a.d.off[i] : b.off;
-  }
-  return b;
-}
-
-__device__ __forceinline__ double* by_parity(double* const (&pair)[2], int k) {
-  return (k & 1) ? pair[1] : pair[0];
-}
-
 // Sums of per-block partials, identical in every thread of the workgroup. The slots are staged
 // in LDS (1024 at a time); each sum is split into 8 contiguous pieces added sequentially by 8
 // threads, and the 8 piece sums are added in order by one thread. This has a shorter critical
@@ -213,20 +176,15 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   __shared__ double Ps[slice_elems(KP)];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);   // slot index: tiles in row-block order
-  const int rb = tile / a.TB, ct = tile - rb * a.TB, c0 = ct * 16;
-  const BlockMode bm = block_mode(a, rb);
-  const int n = bm.n;
-  const int64_t s = bm.s;
-  const int64_t k0 = (int64_t)(rb - bm.rb0) * kCgRows + wv * 16;   // first row of the tile
-  const int64_t rbase = bm.off;
-  const double* Rin = by_parity(a.Rv, it);
-  double* Rout = by_parity(a.Rv, it + 1);
-  const double* W = by_parity(a.W, it + 1);
-  // The kernel's arguments are all loaded here, in one batch of scalar loads.
-  asm volatile("" ::"s"(s), "s"(rbase), "s"(k0), "s"(Rin), "s"(Rout), "s"(W), "s"(a.Q), "s"(a.V),
-               "s"(a.Z), "s"(a.pinv), "s"(a.st), "s"(a.slot_wq), "s"(a.slot_rz), "s"(a.slot_nrm),
-               "s"(a.nslot));
+  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows + wv * 16;   // first row of the tile
+  const int64_t rbase = a.d.off[n];
+  const double* Rin = a.Rv[it & 1];
+  double* Rout = a.Rv[(it + 1) & 1];
+  const double* W = a.W[(it + 1) & 1];
   if (cg_stopped(a.st)) return;
   const double rho = INIT ? 0.0 : a.st->rho[it & 1];
 
@@ -315,8 +273,8 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   double v2[2] = {dot, nrm};
   block_sum(v2);
   if (t == 0) {
-    if constexpr (!CHOL) a.slot_rz[tile] = v2[0];
-    a.slot_nrm[tile] = v2[1];
+    if constexpr (!CHOL) a.slot_rz[blockIdx.x] = v2[0];
+    a.slot_nrm[blockIdx.x] = v2[1];
   }
 }
 
@@ -336,12 +294,12 @@ __global__ __launch_bounds__(64) void k_cg_trsv(CgArgs a, int it) {
   __shared__ double Lp[128 * 129 / 2];
   const int R = a.d.R, t = threadIdx.x;
   const int rb = blockIdx.x;
-  const BlockMode bm = block_mode(a, rb);
-  const int n = bm.n;
-  const int64_t s = bm.s;
-  const int64_t k0 = (int64_t)(rb - bm.rb0) * kCgRows;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows;
   const int rows = (int)(s - k0 < kCgRows ? s - k0 : kCgRows);
-  const double* Rin = INIT ? a.Rv[0] : by_parity(a.Rv, it + 1);
+  const double* Rin = INIT ? a.Rv[0] : a.Rv[(it + 1) & 1];
   // No workgroup of this launch writes the flag, so every lane reads the same value (the
   // workgroup is one wavefront: the early exit is uniform).
   if (__builtin_amdgcn_readfirstlane(__builtin_nontemporal_load(&a.st->done)) != 0) return;
@@ -363,7 +321,7 @@ __global__ __launch_bounds__(64) void k_cg_trsv(CgArgs a, int it) {
         if (i < R && j <= i) Lp[i * (i + 1) / 2 + j] = v[u][h];
       }
   }
-  const int64_t row = (bm.off + k0 + (t < rows ? t : 0)) * R;
+  const int64_t row = (a.d.off[n] + k0 + (t < rows ? t : 0)) * R;
   for (int i0 = 0; i0 < R; i0 += 8) {   // this lane's row of R into Ys (rows past the mode: 0)
     double v[8];
 #pragma unroll
@@ -448,23 +406,17 @@ __global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
   __shared__ double part[kProjWaves][64][4];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R, TB = a.TB;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int p = tile / (TB * TB), rt = (tile / TB) % TB, zt = tile % TB;
+  const int p = blockIdx.x / (TB * TB), rt = (blockIdx.x / TB) % TB, zt = blockIdx.x % TB;
   const int r0 = rt * 16, z0 = zt * 16;
-  const BlockMode pm = mode_of(a, p);
-  const int64_t s = pm.s, base = pm.off;
-  const double* Wold = by_parity(a.W, it);
-  double* Wnew = by_parity(a.W, it + 1);
+  const int64_t s = a.d.s[p], base = a.d.off[p];
+  const double* Wold = a.W[it & 1];
+  double* Wnew = a.W[(it + 1) & 1];
   // Wavefront wv takes the 4-row steps [q0, q1) of this mode's rows.
   const int64_t nsteps = (s + 3) / 4;
   const int64_t per = (nsteps + kProjWaves - 1) / kProjWaves;
   const int64_t q0 = wv * per, q1 = q0 + per < nsteps ? q0 + per : nsteps;
   const bool rok = r0 + m < R, zok = z0 + m < R;
   const bool store_w = rt == 0 && zok;
-  // The kernel's arguments are all loaded here, in one batch of scalar loads.
-  asm volatile("" ::"s"(s), "s"(base), "s"(Wold), "s"(Wnew), "s"(a.A64), "s"(a.Z), "s"(a.B),
-               "s"(a.st), "s"(a.slot_rz), "s"(a.slot_nrm), "s"(a.nslot), "s"(a.d.N),
-               "s"(a.rb_off[1]), "s"(a.rb_off[2]), "s"(a.rb_off[3]));
   if (cg_stopped(a.st)) return;
   // The first batch of rows is requested before the scalars it waits for.
   ProjBatch b;
@@ -512,18 +464,13 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R, N = a.d.N;
   const int64_t RR = (int64_t)R * R;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);   // slot index: tiles in row-block order
-  const int rb = tile / a.TB, ct = tile - rb * a.TB, c0 = ct * 16;
-  const BlockMode bm = block_mode(a, rb);
-  const int n = bm.n;
-  const int64_t s = bm.s;
-  const int64_t k0 = (int64_t)(rb - bm.rb0) * kCgRows + wv * 16;
-  const int64_t rbase = bm.off;
-  const double* W = by_parity(a.W, it + 1);
-  // The kernel's arguments are all loaded here, in one batch of scalar loads.
-  asm volatile("" ::"s"(s), "s"(rbase), "s"(k0), "s"(W), "s"(a.A64), "s"(a.gam), "s"(a.B),
-               "s"(a.Q), "s"(a.lam_dev), "s"(a.st), "s"(a.slot_wq), "s"(a.d.N),
-               "s"(a.diag_damping));
+  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  int n = 0;
+  while (rb >= a.rb_off[n + 1]) ++n;
+  const int64_t s = a.d.s[n];
+  const int64_t k0 = (int64_t)(rb - a.rb_off[n]) * kCgRows + wv * 16;
+  const int64_t rbase = a.d.off[n];
+  const double* W = a.W[(it + 1) & 1];
   if (cg_stopped(a.st)) return;
 
   const bool rowok = k0 + m < s;
@@ -602,7 +549,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   }
   double v1[1] = {dot};
   block_sum(v1);
-  if (t == 0) a.slot_wq[tile] = v1[0];
+  if (t == 0) a.slot_wq[blockIdx.x] = v1[0];
 }
 
 // After the last enqueued iteration: the state for cg_maxiter completed iterations.
