@@ -759,36 +759,42 @@ def main():
         tune = P.autotune_batched(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20),
                                   stream_counts=(1, 2, 4, 8, 16), steps=3)
         hz = P.device_clock_hz()
-        configs = [(1, False), (args.batched_streams, False), (args.batched_streams, True)]
-        if (tune.n_streams, tune.graphs) not in configs:
-            configs.append((tune.n_streams, tune.graphs))
-        for ns, graphs in configs:
+        bs = args.batched_streams
+        configs = [(1, False, False), (bs, False, False), (bs, True, False), (bs, False, True),
+                   (bs, True, True)]
+        if (tune.n_streams, tune.graphs, tune.batch_cg) not in configs:
+            configs.append((tune.n_streams, tune.graphs, tune.batch_cg))
+        cname = lambda ns, g, b: f"streams_{ns}" + ("_graphs" if g else "") + ("_batchcg" if b else "")
+        for ns, graphs, bcg in configs:
             cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
             torch.cuda.synchronize()
             bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns,
-                                       graphs=graphs)
+                                       graphs=graphs, batch_cg=bcg)
             for _ in range(2):
                 bgn.step()
             bgn.synchronize()
             # per-problem step latency from device timestamps (the device clock written by a
-            # one-thread kernel on the problem's stream right before and after its step)
+            # one-thread kernel on the problem's stream right before and after its step; not
+            # part of the single graph of a batched-CG step)
+            stamped = not (graphs and bcg)
             stamps = torch.zeros((5, 2 * len(devs)), dtype=torch.int64, device="cuda")
             t0 = time.perf_counter()
             for k in range(5):
-                bgn.step(stamps=stamps[k])
+                bgn.step(stamps=stamps[k] if stamped else None)
                 bgn.synchronize()
             el = time.perf_counter() - t0
-            ticks = stamps.view(5, len(devs), 2).cpu().numpy()
-            per = ((ticks[:, :, 1] - ticks[:, :, 0]) / hz * 1e3).ravel()
-            key = f"streams_{ns}" + ("_graphs" if graphs else "")
-            res[key] = dict(problem_steps_per_s=64 * 5 / el, step_ms_p50=float(np.percentile(per, 50)),
-                            step_ms_p99=float(np.percentile(per, 99)))
+            rec = dict(problem_steps_per_s=64 * 5 / el)
+            if stamped:
+                ticks = stamps.view(5, len(devs), 2).cpu().numpy()
+                per = ((ticks[:, :, 1] - ticks[:, :, 0]) / hz * 1e3).ravel()
+                rec.update(step_ms_p50=float(np.percentile(per, 50)),
+                           step_ms_p99=float(np.percentile(per, 99)))
+            res[cname(ns, graphs, bcg)] = rec
             del bgn, cur
-        kt = f"streams_{tune.n_streams}" + ("_graphs" if tune.graphs else "")
+        kt = cname(tune.n_streams, tune.graphs, tune.batch_cg)
         res["autotuned"] = dict(choice=kt, problem_steps_per_s=res[kt]["problem_steps_per_s"],
                                 sweep_problem_steps_per_s={
-                                    f"streams_{k[0]}" + ("_graphs" if k[1] else ""): v
-                                    for k, v in tune.table.items()},
+                                    cname(*k): v for k, v in tune.table.items()},
                                 note="sweep: 3 steps per configuration without per-problem "
                                      "events; problem_steps_per_s: the timed loop of the fixed "
                                      "configurations")
@@ -796,13 +802,19 @@ def main():
             f"problem-steps/s in the same timed loop")
         batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
                        note="_graphs: each problem's GN step and damping update replayed from a "
-                            "captured HIP graph; step_ms_p50/p99: per-problem step latency from "
+                            "captured HIP graph; _batchcg: CG of all problems in shared launches "
+                            "(with _graphs: the whole batch step as one graph); "
+                            "step_ms_p50/p99: per-problem step latency from "
                             f"device timestamps ({hz} Hz clock), 5 batch steps", **res)
-        kb, kg = f"streams_{args.batched_streams}", f"streams_{args.batched_streams}_graphs"
-        log(f"[bench] batched workload: {res[kg]['problem_steps_per_s']:.0f} problem-steps/s on "
-            f"{args.batched_streams} streams with graph replay, {res[kb]['problem_steps_per_s']:.0f} "
-            f"without, {res['streams_1']['problem_steps_per_s']:.0f} on one stream; per-problem step "
-            f"p50 {res[kg]['step_ms_p50']:.3f} ms, p99 {res[kg]['step_ms_p99']:.3f} ms (graphs)")
+        kb, kg = cname(bs, False, False), cname(bs, True, False)
+        kc, kcg = cname(bs, False, True), cname(bs, True, True)
+        log(f"[bench] batched workload: {res[kcg]['problem_steps_per_s']:.0f} problem-steps/s on "
+            f"{bs} streams with batched CG and one graph per batch step, "
+            f"{res[kc]['problem_steps_per_s']:.0f} with batched CG eagerly, "
+            f"{res[kg]['problem_steps_per_s']:.0f} with per-problem graphs, "
+            f"{res[kb]['problem_steps_per_s']:.0f} eager, "
+            f"{res['streams_1']['problem_steps_per_s']:.0f} on one stream; per-problem step "
+            f"p50 {res[kc]['step_ms_p50']:.3f} ms, p99 {res[kc]['step_ms_p99']:.3f} ms (batched CG)")
         del devs
 
     # ---- order-4 workload in bfloat16 / split bfloat16 / FP32 / FP64 storage

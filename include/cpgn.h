@@ -290,6 +290,32 @@ int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
 int cp_damping_advance(double* state_dev, void* stream);
 
 /*
+ * A Gauss-Newton step (Algorithm 1) split in three calls, so that the CG iterations (Algorithm 2)
+ * of many independent problems share launches; for each problem the three calls together do
+ * exactly what cp_gn_step_devlam does (the same kernels on the same data: bitwise the same
+ * factors and stats). R <= 128, explicit-inverse preconditioner (no CP_GN_CHOL_PRECOND).
+ *   cp_gn_step_begin  everything before CG on `stream`: prepared factors, the gradient of
+ *                     Algorithm 1, the preconditioner of Section 3.3 (lambda_dev: device
+ *                     damping as in cp_gn_step_devlam, or NULL for params->lambda), and the
+ *                     problem's CG arguments, stored in its workspace `ws`.
+ *   cp_gn_cg_batch    CG initialisation, cg_maxiter iterations and the final state of `count`
+ *                     (<= CP_MAX_CG_BATCH) problems whose steps have begun: probs[i] and ws[i]
+ *                     (ws_bytes[i] bytes) as given to cp_gn_step_begin; three launches per
+ *                     iteration for the whole batch. Every problem stops at its own test.
+ *   cp_gn_step_end    A += V and the step's stats (device) for one problem.
+ * Stream order: begin of a problem, then the batch, then its end (join and fork the streams with
+ * events when problems begin on several streams).
+ */
+#define CP_MAX_CG_BATCH 128
+int cp_gn_step_begin(const cp_problem* prob, const void* X, void* const* A,
+                     const cp_gn_params* params, const double* lambda_dev, void* ws,
+                     size_t ws_bytes, void* stream);
+int cp_gn_cg_batch(int count, const cp_problem* probs, void* const* ws, const size_t* ws_bytes,
+                   int cg_maxiter, void* stream);
+int cp_gn_step_end(const cp_problem* prob, void* const* A, cp_gn_stats* stats, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/*
  * Device timestamps for per-problem step latencies (p50/p99) of many problems run on several
  * streams: enqueues one one-thread kernel on `stream` that writes the device's constant-rate
  * clock to *dst_dev when it runs, so that two of them around a step bracket the step's execution

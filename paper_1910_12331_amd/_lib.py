@@ -19,7 +19,7 @@ LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
+           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_gn_step_begin", "cp_gn_cg_batch", "cp_gn_step_end", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -50,6 +50,7 @@ class CpArmijoStats(C.Structure):
 
 
 PTRS = C.c_void_p * MAX_ORDER
+MAX_CG_BATCH = 128
 _lib = None
 
 
@@ -90,6 +91,12 @@ def load(path: str = LIB_PATH):
                                       vp, vp, vp, sz, vp]
     lib.cp_damping_advance.restype = i32
     lib.cp_damping_advance.argtypes = [vp, vp]
+    lib.cp_gn_step_begin.restype = i32
+    lib.cp_gn_step_begin.argtypes = [P(CpProblem), vp, PTRS, P(CpGnParams), vp, vp, sz, vp]
+    lib.cp_gn_cg_batch.restype = i32
+    lib.cp_gn_cg_batch.argtypes = [i32, P(CpProblem), P(vp), P(sz), i32, vp]
+    lib.cp_gn_step_end.restype = i32
+    lib.cp_gn_step_end.argtypes = [P(CpProblem), PTRS, vp, vp, sz, vp]
     lib.cp_device_timestamp.restype = i32
     lib.cp_device_timestamp.argtypes = [vp, vp]
     lib.cp_device_clock_hz.restype = i32

@@ -8,7 +8,7 @@ fallback, and a missing library raises.
 from __future__ import annotations
 
 import ctypes as C
-from typing import Sequence
+from typing import NamedTuple, Sequence
 
 import torch
 
@@ -375,6 +375,60 @@ def gn_step_devlam(X, A: Sequence[torch.Tensor], lam_dev: torch.Tensor, cg_tol: 
     _check(L.load().cp_gn_step_devlam(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),
                                       lam_dev.data_ptr(), stats.data_ptr(), w, nb, _stream()),
            "cp_gn_step_devlam")
+    return stats
+
+
+class BegunStep(NamedTuple):
+    """A Gauss-Newton step whose part before CG is enqueued (gn_step_begin): the problem, its
+    workspace (pointer and size) and the factors the step updates."""
+    prob: object
+    ws_ptr: int
+    ws_bytes: int
+    A: list
+
+
+def gn_step_begin(X, A: Sequence[torch.Tensor], lam: float | None = None, lam_dev=None,
+                  cg_tol: float = 1e-3, cg_maxiter: int = 20, ws=None,
+                  damping: str = "identity") -> BegunStep:
+    """The part of a Gauss-Newton step before CG on the current stream (cp_gn_step_begin), with
+    the damping lam (host) or lam_dev (a one-element float64 GPU tensor read when it runs)."""
+    if damping not in ("identity", "diagonal"):
+        raise ValueError("damping must be 'identity' or 'diagonal'")
+    if (lam is None) == (lam_dev is None):
+        raise ValueError("give exactly one of lam and lam_dev")
+    _dev(X, "X")
+    if lam_dev is not None:
+        _dev(lam_dev, "lam_dev", torch.float64)
+    R = int(A[0].shape[1])
+    _factors(A, X.shape, factor_dtype(X), R)
+    prob = _problem(X, R)
+    prm = L.CpGnParams(float(lam) if lam is not None else 0.0, float(cg_tol), int(cg_maxiter),
+                       _gn_flags(damping, "inverse"))
+    w, nb = _ws(prob, L.OP_GN_STEP, X.device, ws)
+    _check(L.load().cp_gn_step_begin(C.byref(prob), X.data_ptr(), _ptrs(A), C.byref(prm),
+                                     lam_dev.data_ptr() if lam_dev is not None else None, w, nb,
+                                     _stream()), "cp_gn_step_begin")
+    return BegunStep(prob, w, nb, list(A))
+
+
+def gn_cg_batch(steps: Sequence[BegunStep], cg_maxiter: int = 20):
+    """CG of every begun step in shared launches on the current stream (cp_gn_cg_batch)."""
+    n = len(steps)
+    if not 1 <= n <= L.MAX_CG_BATCH:
+        raise ValueError(f"1 to {L.MAX_CG_BATCH} steps per batch")
+    probs = (L.CpProblem * n)(*[s.prob for s in steps])
+    wss = (C.c_void_p * n)(*[s.ws_ptr for s in steps])
+    nbs = (C.c_size_t * n)(*[s.ws_bytes for s in steps])
+    _check(L.load().cp_gn_cg_batch(n, probs, wss, nbs, int(cg_maxiter), _stream()),
+           "cp_gn_cg_batch")
+
+
+def gn_step_end(step: BegunStep, stats=None):
+    """A += V and the step's stats for one begun step, on the current stream (cp_gn_step_end)."""
+    if stats is None:
+        stats = stats_buffer(step.A[0].device)
+    _check(L.load().cp_gn_step_end(C.byref(step.prob), _ptrs(step.A), stats.data_ptr(),
+                                   step.ws_ptr, step.ws_bytes, _stream()), "cp_gn_step_end")
     return stats
 
 

@@ -9,6 +9,8 @@
 
 #include "cpgn_internal.h"
 
+#include <vector>
+
 namespace cpgn {
 
 // Launchers defined in the other translation units.
@@ -49,6 +51,12 @@ size_t cg_slot_bytes(const Plan&);
 int launch_cg(const Plan&, const Dims&, const double*, const double*, const double*, double*,
               double*, double*, double*, double*, double*, double*, double*, void*, CgState*,
               double, int, bool, hipStream_t, const double* lam_dev = nullptr, bool chol = false);
+size_t cg_args_bytes();
+void launch_cg_store(const Plan& p, const Dims& d, const double* A64, const double* gam,
+                     const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
+                     double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
+                     bool diag_damping, const double* lam_dev, void* dst, hipStream_t s);
+int launch_cg_batch(int count, const Plan* plans, void* const* args, int maxiter, hipStream_t s);
 
 void launch_rowmm(const Dims&, const RowMM&, const CgState*, hipStream_t);
 int launch_chol_tiles(int, const double*, int64_t, double, double*, int64_t, double*, int64_t, int,
@@ -151,6 +159,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_w1 = take(vec);
   p->off_r1 = take(vec);
   p->off_slots = take(cg_slot_bytes(*p));
+  p->off_cgargs = take(cg_args_bytes());
   p->off_krp = take((size_t)krp * 4);
   p->bytes = off;
   // the T pass launches one grid row per row tile of s0 s1 (at most 65535); the contraction of
@@ -421,6 +430,35 @@ int cp_gn_jtj_matvec(const cp_problem* prob, const void* const* A, const void* c
 // One Gauss-Newton step; the damping is prm->lambda, or *lam_dev read on the device.
 // One Gauss-Newton step: the direction V of Algorithm 1, then either the full step A += V or,
 // with ls, the Armijo search along V (Section 5).
+// Checks of the Gauss-Newton parameters shared by every step entry point.
+static int gn_params_ok(const Plan& p, const cp_gn_params* prm, const double* lam_dev) {
+  if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
+  if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
+      (prm->flags & ~(CP_GN_DIAG_DAMPING | CP_GN_CHOL_PRECOND)) != 0)
+    return CP_EINVAL;
+  if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
+  if ((prm->flags & CP_GN_CHOL_PRECOND) && p.R > 128) return CP_EUNSUPPORTED;
+  return CP_OK;
+}
+
+// The part of a step before CG: prepared factors, gradient (Algorithm 1), preconditioner.
+static void gn_pre_cg(const Plan& p, const Dims& d, const Ws& w, const void* X, void* const* A,
+                      const cp_gn_params* prm, const double* lam_dev, void* ws, hipStream_t st) {
+  const int64_t RR = (int64_t)p.R * p.R;
+  const double lam = lam_dev ? 0.0 : prm->lambda;
+  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
+  PerMode<void*> none{};
+  gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
+  // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
+  const bool diag = (prm->flags & CP_GN_DIAG_DAMPING) != 0;
+  if (prm->flags & CP_GN_CHOL_PRECOND)   // Cholesky factors, applied by triangular solves in CG
+    launch_spd_chol(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
+                    lam_dev);
+  else
+    launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
+                   lam_dev);
+}
+
 static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
                         const cp_gn_params* prm, const double* lam_dev, cp_gn_stats* stats,
                         void* ws, size_t ws_bytes, void* stream,
@@ -433,32 +471,16 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
              !(ls->shrink > 0.0 && ls->shrink < 1.0) || ls->max_trials < 0 ||
              ls->max_trials > 64 || (ls->flags & ~CP_LS_F0_GIVEN) != 0))
     return CP_EINVAL;
-  if (!lam_dev && (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))) return CP_EINVAL;
-  if (!(prm->cg_tol >= 0.0) || !isfinite(prm->cg_tol) || prm->cg_maxiter < 0 ||
-      (prm->flags & ~(CP_GN_DIAG_DAMPING | CP_GN_CHOL_PRECOND)) != 0)
-    return CP_EINVAL;
-  if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
-  if ((prm->flags & CP_GN_CHOL_PRECOND) && p.R > 128) return CP_EUNSUPPORTED;
+  if ((rc = gn_params_ok(p, prm, lam_dev))) return rc;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);
   const Ws w = carve(p, ws);
-  const int64_t RR = (int64_t)p.R * p.R;
   const int nb = rowmm_blocks(d);
   const double lam = lam_dev ? 0.0 : prm->lambda;
-
-  launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true);
-  PerMode<void*> none{};
-  gradient_core(p, d, X, w, prm->cg_tol, none, nullptr, st);
-  // Preconditioner P_inv(n) = (Gamma(n,n) + lambda I)^-1.
   const bool diag = (prm->flags & CP_GN_DIAG_DAMPING) != 0;
   const bool chol = (prm->flags & CP_GN_CHOL_PRECOND) != 0;
-  if (chol)   // Cholesky factors in place of the inverse, applied by triangular solves in CG
-    launch_spd_chol(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
-                    lam_dev);
-  else
-    launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
-                   lam_dev);
+  gn_pre_cg(p, d, w, X, A, prm, lam_dev, ws, st);
   // CG: three launches per iteration, scalars kept on the device.
   launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
             (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, lam,
@@ -502,6 +524,61 @@ int cp_gn_step_devlam(const cp_problem* prob, const void* X, void* const* A,
                       void* ws, size_t ws_bytes, void* stream) {
   if (!lambda_dev) return CP_EINVAL;
   return gn_step_impl(prob, X, A, prm, lambda_dev, stats, ws, ws_bytes, stream);
+}
+
+int cp_gn_step_begin(const cp_problem* prob, const void* X, void* const* A,
+                     const cp_gn_params* prm, const double* lambda_dev, void* ws, size_t ws_bytes,
+                     void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!X || !prm) return CP_EINVAL;
+  if ((rc = gn_params_ok(p, prm, lambda_dev))) return rc;
+  if (p.R > 128 || (prm->flags & CP_GN_CHOL_PRECOND)) return CP_EUNSUPPORTED;
+  if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  gn_pre_cg(p, d, w, X, A, prm, lambda_dev, ws, st);
+  launch_cg_store(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
+                  (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st,
+                  lambda_dev ? 0.0 : prm->lambda, (prm->flags & CP_GN_DIAG_DAMPING) != 0,
+                  lambda_dev, w.base + p.off_cgargs, st);
+  return hip_status();
+}
+
+int cp_gn_cg_batch(int count, const cp_problem* probs, void* const* ws, const size_t* ws_bytes,
+                   int cg_maxiter, void* stream) {
+  if (count < 1 || count > CP_MAX_CG_BATCH || !probs || !ws || !ws_bytes || cg_maxiter < 0)
+    return CP_EINVAL;
+  std::vector<Plan> plans((size_t)count);
+  std::vector<void*> args((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    int rc = make_plan(&probs[i], &plans[i]);
+    if (rc) return rc;
+    if (plans[i].R > 128) return CP_EUNSUPPORTED;
+    if ((rc = check_ws(plans[i], ws[i], ws_bytes[i]))) return rc;
+    args[i] = (char*)ws[i] + plans[i].off_cgargs;
+  }
+  launch_cg_batch(count, plans.data(), args.data(), cg_maxiter, (hipStream_t)stream);
+  return hip_status();
+}
+
+int cp_gn_step_end(const cp_problem* prob, void* const* A, cp_gn_stats* stats, void* ws,
+                   size_t ws_bytes, void* stream) {
+  Plan p;
+  int rc = make_plan(prob, &p);
+  if (rc) return rc;
+  if (!stats) return CP_EINVAL;
+  if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims d = make_dims(p);
+  const Ws w = carve(p, ws);
+  PerMode<void*> aout{};
+  for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
+  launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, st);
+  launch_gn_stats(d, rowmm_blocks(d), w.red_nrm, w.st, stats, st);
+  return hip_status();
 }
 
 }  // extern "C"

@@ -18,6 +18,7 @@ constexpr int kRedSlots = 1024;   // max blocks contributing to one deterministi
 constexpr int kMaxGnRank = 208;
 // Largest grid y (and z) dimension of a launch.
 constexpr int64_t kMaxGridY = 65535;
+constexpr int kMaxCgBatch = 128;   // problems per batched CG launch (their table is a kernel argument)
 constexpr int kNumCU = 256;       // compute units of an MI355X (8 XCDs x 32)
 
 // ------------------------------------------------------------------------------------------
@@ -66,6 +67,7 @@ struct Plan {
   size_t off_g = 0, off_v = 0, off_r = 0, off_z = 0, off_w = 0, off_q = 0;
   size_t off_bp = 0, off_y = 0, off_red = 0, off_state = 0, off_w1 = 0, off_r1 = 0;
   size_t off_slots = 0;
+  size_t off_cgargs = 0;                // the CG kernel arguments, for batched CG launches
   size_t off_krp = 0;                  // outer Khatri-Rao tables of the bfloat16 MTTKRP
   size_t bytes = 0;
   size_t t_bytes = 0;                  // ALS dimension tree (order 3): T = X x_3 A(2), after `bytes`

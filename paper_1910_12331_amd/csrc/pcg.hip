@@ -136,7 +136,8 @@ __device__ __forceinline__ bool cg_stopped(const CgState* st) {
 // Records the CG state before iteration `it` (it iterations done) and decides whether to stop.
 // Called by every workgroup with identical inputs; workgroup 0 writes.
 __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, double rho_old,
-                                         double rsum, double gsum, double eps, double& beta) {
+                                         double rsum, double gsum, double eps, double& beta,
+                                         bool writer) {
   beta = it == 0 ? 0.0 : rho / rho_old;
   bool stop = false;
   int status = CP_OK;
@@ -146,7 +147,7 @@ __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, do
   } else if (!(rsum > eps * gsum)) {
     stop = true;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (writer && threadIdx.x == 0) {
     CgState* st = a.st;
     st->rho[it & 1] = rho;
     st->rz = rho;
@@ -170,13 +171,13 @@ __device__ __forceinline__ bool cg_check(const CgArgs& a, int it, double rho, do
 // CHOL: the preconditioner is applied afterwards by k_cg_trsv (triangular solves); this kernel
 // then writes V, R_new and the norm partials only.
 template <int KB, bool INIT, bool EVEN, bool CHOL>
-__global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
+__device__ __forceinline__ void cg_update_body(const CgArgs& a, int it, int bid) {
   constexpr int KQ = 4 * KB;    // MFMA steps (k values per lane)
   constexpr int KP = 16 * KB;   // padded contraction length
   __shared__ double Ps[slice_elems(KP)];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R;
-  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  const int rb = bid / a.TB, ct = bid - rb * a.TB, c0 = ct * 16;
   int n = 0;
   while (rb >= a.rb_off[n + 1]) ++n;
   const int64_t s = a.d.s[n];
@@ -232,14 +233,14 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
     if (!isfinite(wq)) status = CP_ENONFINITE;
     else if (!(wq > 0.0)) status = CP_EBREAKDOWN;
     if (status != CP_OK) {
-      if (blockIdx.x == 0 && t == 0) {
+      if (bid == 0 && t == 0) {
         a.st->status = status;
         a.st->done = 1;
       }
       return;
     }
     alpha = rho / wq;
-    if (blockIdx.x == 0 && t == 0) a.st->alpha = alpha;
+    if (bid == 0 && t == 0) a.st->alpha = alpha;
 #pragma unroll
     for (int j = 0; j < KQ; ++j) ro[j] = __fma_rn(-alpha, qo[j], ro[j]);
   }
@@ -273,9 +274,14 @@ __global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
   double v2[2] = {dot, nrm};
   block_sum(v2);
   if (t == 0) {
-    if constexpr (!CHOL) a.slot_rz[blockIdx.x] = v2[0];
-    a.slot_nrm[blockIdx.x] = v2[1];
+    if constexpr (!CHOL) a.slot_rz[bid] = v2[0];
+    a.slot_nrm[bid] = v2[1];
   }
+}
+
+template <int KB, bool INIT, bool EVEN, bool CHOL>
+__global__ __launch_bounds__(256) void k_cg_update(CgArgs a, int it) {
+  cg_update_body<KB, INIT, EVEN, CHOL>(a, it, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -402,11 +408,11 @@ __device__ __forceinline__ void proj_load(ProjBatch& b, const CgArgs& a, const d
   }
 }
 
-__global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
+__device__ __forceinline__ void cg_proj_body(const CgArgs& a, int it, int bid) {
   __shared__ double part[kProjWaves][64][4];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R, TB = a.TB;
-  const int p = blockIdx.x / (TB * TB), rt = (blockIdx.x / TB) % TB, zt = blockIdx.x % TB;
+  const int p = bid / (TB * TB), rt = (bid / TB) % TB, zt = bid % TB;
   const int r0 = rt * 16, z0 = zt * 16;
   const int64_t s = a.d.s[p], base = a.d.off[p];
   const double* Wold = a.W[it & 1];
@@ -424,7 +430,7 @@ __global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(it + 1) & 1];
   double rho, rsum, beta;
   reduce_rz(a, rho, rsum);
-  if (cg_check(a, it, rho, rho_old, rsum, gsum, eps, beta)) return;
+  if (cg_check(a, it, rho, rho_old, rsum, gsum, eps, beta, bid == 0)) return;
 
   dv4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t qb = q0; qb < q1; qb += kProjSteps) {
@@ -451,12 +457,14 @@ __global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) {
   }
 }
 
+__global__ __launch_bounds__(512) void k_cg_proj(CgArgs a, int it) { cg_proj_body(a, it, blockIdx.x); }
+
 // ---------------------------------------------------------------------------------------------
 // k_cg_matvec<KB>: one 64 x 16 block of Q(n) = lambda W + W Gamma(n,n) + A Y(n)^T and its
 // partial <W,Q>. grid: nslot workgroups of 256 threads.
 // ---------------------------------------------------------------------------------------------
 template <int KB, bool EVEN>
-__global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
+__device__ __forceinline__ void cg_matvec_body(const CgArgs& a, int it, int bid) {
   constexpr int KQ = 4 * KB;
   constexpr int KP = 16 * KB;
   __shared__ double Gs[slice_elems(KP)];   // Gamma(n,n)[k][c0 + c]
@@ -464,7 +472,7 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
   const int R = a.d.R, N = a.d.N;
   const int64_t RR = (int64_t)R * R;
-  const int rb = blockIdx.x / a.TB, ct = blockIdx.x - rb * a.TB, c0 = ct * 16;
+  const int rb = bid / a.TB, ct = bid - rb * a.TB, c0 = ct * 16;
   int n = 0;
   while (rb >= a.rb_off[n + 1]) ++n;
   const int64_t s = a.d.s[n];
@@ -549,18 +557,25 @@ __global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
   }
   double v1[1] = {dot};
   block_sum(v1);
-  if (t == 0) a.slot_wq[blockIdx.x] = v1[0];
+  if (t == 0) a.slot_wq[bid] = v1[0];
+}
+
+template <int KB, bool EVEN>
+__global__ __launch_bounds__(256) void k_cg_matvec(CgArgs a, int it) {
+  cg_matvec_body<KB, EVEN>(a, it, blockIdx.x);
 }
 
 // After the last enqueued iteration: the state for cg_maxiter completed iterations.
-__global__ __launch_bounds__(512) void k_cg_final(CgArgs a, int maxiter) {
+__device__ __forceinline__ void cg_final_body(const CgArgs& a, int maxiter) {
   if (cg_stopped(a.st)) return;
   const double gsum = a.st->gsum, eps = a.st->eps, rho_old = a.st->rho[(maxiter + 1) & 1];
   double rho, rsum, beta;
   reduce_rz(a, rho, rsum);
-  cg_check(a, maxiter, rho, rho_old, rsum, gsum, eps, beta);
+  cg_check(a, maxiter, rho, rho_old, rsum, gsum, eps, beta, true);
   if (threadIdx.x == 0) a.st->done = 1;
 }
+
+__global__ __launch_bounds__(512) void k_cg_final(CgArgs a, int maxiter) { cg_final_body(a, maxiter); }
 
 int cg_tiles(const Plan& p) { return (p.R + 15) / 16; }
 
@@ -602,12 +617,10 @@ static void launch_kb(const CgArgs& a, int N, int maxiter, hipStream_t s, bool c
   else launch_kb<KB, false, false>(a, N, maxiter, s);
 }
 
-// Enqueues CG initialisation, cg_maxiter iterations and the final state. R = -G must be in R0.
-int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
-              const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
-              double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
-              int maxiter, bool diag_damping, hipStream_t s, const double* lam_dev, bool chol) {
-  if (chol && p.R > 128) return (int)hipErrorInvalidValue;
+static CgArgs make_cg_args(const Plan& p, const Dims& d, const double* A64, const double* gam,
+                           const double* pinv, double* V, double* R0, double* R1, double* Z,
+                           double* W0, double* W1, double* Q, double* B, void* slots, CgState* st,
+                           double lambda, bool diag_damping, const double* lam_dev) {
   CgArgs a{};
   a.d = d;
   a.A64 = A64;
@@ -633,6 +646,17 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
   a.slot_wq = (double*)slots;
   a.slot_rz = a.slot_wq + a.nslot;
   a.slot_nrm = a.slot_rz + a.nslot;
+  return a;
+}
+
+// Enqueues CG initialisation, cg_maxiter iterations and the final state. R = -G must be in R0.
+int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam,
+              const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
+              double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
+              int maxiter, bool diag_damping, hipStream_t s, const double* lam_dev, bool chol) {
+  if (chol && p.R > 128) return (int)hipErrorInvalidValue;
+  const CgArgs a = make_cg_args(p, d, A64, gam, pinv, V, R0, R1, Z, W0, W1, Q, B, slots, st,
+                                lambda, diag_damping, lam_dev);
   switch (a.TB) {
     case 1: launch_kb<1>(a, p.N, maxiter, s, chol); break;
     case 2: launch_kb<2>(a, p.N, maxiter, s, chol); break;
@@ -648,6 +672,115 @@ int launch_cg(const Plan& p, const Dims& d, const double* A64, const double* gam
     case 11: launch_kb<11>(a, p.N, maxiter, s, chol); break;
     case 12: launch_kb<12>(a, p.N, maxiter, s, chol); break;
     case 13: launch_kb<13>(a, p.N, maxiter, s, chol); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched CG: the iterations of many independent problems in shared launches. Each problem's
+// CgArgs sits in its own workspace (written by launch_cg_store when its step begins); a launch
+// covers the workgroups of every problem back to back, and workgroup b finds its problem q as the
+// one with off[q] <= b < off[q + 1]. Every problem runs the bodies above on its own state, with
+// the column-block count of the largest rank in the batch (extra blocks are zero: the results
+// are bitwise those of the problem's own launches); a problem whose CG has stopped returns at
+// once, as in its own launches.
+// ---------------------------------------------------------------------------------------------
+struct CgBatch {
+  const CgArgs* args[kMaxCgBatch];
+  int off[kMaxCgBatch + 1];    // workgroups before each problem: update and matvec launches
+  int offp[kMaxCgBatch + 1];   // the same for the projection launch
+  int n;
+};
+
+__global__ void k_cg_store(CgArgs a, CgArgs* dst) {
+  if (threadIdx.x == 0) *dst = a;
+}
+
+size_t cg_args_bytes() { return sizeof(CgArgs); }
+
+void launch_cg_store(const Plan& p, const Dims& d, const double* A64, const double* gam,
+                     const double* pinv, double* V, double* R0, double* R1, double* Z, double* W0,
+                     double* W1, double* Q, double* B, void* slots, CgState* st, double lambda,
+                     bool diag_damping, const double* lam_dev, void* dst, hipStream_t s) {
+  const CgArgs a = make_cg_args(p, d, A64, gam, pinv, V, R0, R1, Z, W0, W1, Q, B, slots, st,
+                                lambda, diag_damping, lam_dev);
+  hipLaunchKernelGGL(k_cg_store, dim3(1), dim3(64), 0, s, a, (CgArgs*)dst);
+}
+
+// Problem of this workgroup and its workgroup index within that problem (uniform).
+__device__ __forceinline__ int batch_find(const int* off, int n, int& local) {
+  __shared__ int sq;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    if (off[q] <= (int)blockIdx.x && (int)blockIdx.x < off[q + 1]) sq = q;
+  __syncthreads();
+  const int q = sq;
+  local = (int)blockIdx.x - off[q];
+  return q;
+}
+
+template <int KB, bool INIT, bool EVEN>
+__global__ __launch_bounds__(256) void k_cg_update_batch(CgBatch b, int it) {
+  int bid;
+  const int q = batch_find(b.off, b.n, bid);
+  cg_update_body<KB, INIT, EVEN, false>(*b.args[q], it, bid);
+}
+
+__global__ __launch_bounds__(512) void k_cg_proj_batch(CgBatch b, int it) {
+  int bid;
+  const int q = batch_find(b.offp, b.n, bid);
+  cg_proj_body(*b.args[q], it, bid);
+}
+
+template <int KB, bool EVEN>
+__global__ __launch_bounds__(256) void k_cg_matvec_batch(CgBatch b, int it) {
+  int bid;
+  const int q = batch_find(b.off, b.n, bid);
+  cg_matvec_body<KB, EVEN>(*b.args[q], it, bid);
+}
+
+__global__ __launch_bounds__(512) void k_cg_final_batch(CgBatch b, int maxiter) {
+  cg_final_body(*b.args[blockIdx.x], maxiter);
+}
+
+template <int KB, bool EVEN>
+static void launch_batch_kb(const CgBatch& b, int maxiter, hipStream_t s) {
+  const dim3 gu((unsigned)b.off[b.n]), gp((unsigned)b.offp[b.n]);
+  hipLaunchKernelGGL((k_cg_update_batch<KB, true, EVEN>), gu, dim3(256), 0, s, b, 0);
+  for (int it = 0; it < maxiter; ++it) {
+    hipLaunchKernelGGL(k_cg_proj_batch, gp, dim3(512), 0, s, b, it);
+    hipLaunchKernelGGL((k_cg_matvec_batch<KB, EVEN>), gu, dim3(256), 0, s, b, it);
+    hipLaunchKernelGGL((k_cg_update_batch<KB, false, EVEN>), gu, dim3(256), 0, s, b, it);
+  }
+  hipLaunchKernelGGL(k_cg_final_batch, dim3((unsigned)b.n), dim3(512), 0, s, b, maxiter);
+}
+
+// plans[i], args[i] (device CgArgs written by launch_cg_store) of count <= kMaxCgBatch problems,
+// all with R <= 128 and the explicit-inverse preconditioner.
+int launch_cg_batch(int count, const Plan* plans, void* const* args, int maxiter, hipStream_t s) {
+  if (count < 1 || count > kMaxCgBatch) return (int)hipErrorInvalidValue;
+  CgBatch b{};
+  b.n = count;
+  int tb = 1;
+  bool even = true;
+  for (int i = 0; i < count; ++i) {
+    const Plan& p = plans[i];
+    const int t = cg_tiles(p);
+    tb = t > tb ? t : tb;
+    even = even && p.R % 2 == 0;
+    b.args[i] = (const CgArgs*)args[i];
+    b.off[i + 1] = b.off[i] + cg_row_blocks(p) * t;
+    b.offp[i + 1] = b.offp[i] + p.N * t * t;
+  }
+  switch (tb) {
+#define CPGN_CGB(k)                                                                  \
+  case k:                                                                            \
+    if (even) launch_batch_kb<k, true>(b, maxiter, s);                               \
+    else launch_batch_kb<k, false>(b, maxiter, s);                                   \
+    break;
+    CPGN_CGB(1) CPGN_CGB(2) CPGN_CGB(3) CPGN_CGB(4) CPGN_CGB(5) CPGN_CGB(6) CPGN_CGB(7)
+    CPGN_CGB(8)
+#undef CPGN_CGB
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

@@ -320,13 +320,23 @@ class BatchedGaussNewton:
 
     With graphs=True one Gauss-Newton step of each problem, together with its damping update
     (read and advanced on the device), is captured once as a HIP graph and replayed per step: the
-    host then issues one graph launch per problem instead of every kernel launch of the step."""
+    host then issues one graph launch per problem instead of every kernel launch of the step.
+
+    With batch_cg=True the CG iterations of all problems share launches (cp_gn_cg_batch): each
+    problem's step begins on its stream (gradient and preconditioner), the streams join, CG runs
+    for the whole batch on the current stream (three launches per iteration instead of three per
+    iteration and problem), and the streams fork again for the updates. The iterates are bitwise
+    those of the per-problem steps. With graphs=True as well, the whole batch step (all streams)
+    is captured as one graph."""
 
     def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8,
-                 graphs: bool = False):
+                 graphs: bool = False, batch_cg: bool = False):
         cfg = config or GNConfig()
         if graphs and cfg.line_search is not None:
             raise ValueError("graph replay covers the plain Gauss-Newton step only")
+        if batch_cg and (cfg.line_search is not None or cfg.preconditioner != "inverse"):
+            raise ValueError("batched CG covers the plain step with the explicit inverse")
+        self.batch_cg = batch_cg
         self.cfg = cfg
         torch.cuda.current_stream().synchronize()   # inputs were written on the current stream
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
@@ -335,8 +345,71 @@ class BatchedGaussNewton:
             with torch.cuda.stream(self.streams[i % len(self.streams)]):
                 self.opts.append(GaussNewton(X, A, replace(cfg, schedule=None)))
         self.graphs = None
-        if graphs:
+        self.batch_graph = None
+        if graphs and batch_cg:
+            self._capture_batch()
+        elif graphs:
             self._capture()
+
+    def _batch_step(self, lam_states=None, stamps=None):
+        """Enqueue one batched step of every problem: begin on each problem's stream, CG of all
+        on the current stream, end on each problem's stream (events fork and join the streams)."""
+        main = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(main)
+        begun = []
+        for i, opt in enumerate(self.opts):
+            s = self.streams[i % len(self.streams)]
+            s.wait_event(fork)
+            with torch.cuda.stream(s):
+                if stamps is not None:
+                    api.device_timestamp(stamps, 2 * i)
+                if lam_states is not None:
+                    begun.append(api.gn_step_begin(opt.X, opt.A, lam_dev=lam_states[i][0:1],
+                                                   cg_tol=self.cfg.cg_tol,
+                                                   cg_maxiter=self.cfg.cg_maxiter, ws=opt.ws,
+                                                   damping=self.cfg.damping))
+                else:
+                    begun.append(api.gn_step_begin(opt.X, opt.A, lam=opt.schedule.value,
+                                                   cg_tol=self.cfg.cg_tol,
+                                                   cg_maxiter=self.cfg.cg_maxiter, ws=opt.ws,
+                                                   damping=self.cfg.damping))
+        for s in self.streams[:len(self.opts)]:
+            join = torch.cuda.Event()
+            join.record(s)
+            main.wait_event(join)
+        for k in range(0, len(begun), api.L.MAX_CG_BATCH):
+            api.gn_cg_batch(begun[k:k + api.L.MAX_CG_BATCH], self.cfg.cg_maxiter)
+        fork2 = torch.cuda.Event()
+        fork2.record(main)
+        for i, opt in enumerate(self.opts):
+            s = self.streams[i % len(self.streams)]
+            s.wait_event(fork2)
+            with torch.cuda.stream(s):
+                api.gn_step_end(begun[i], stats=opt.stats_buf)
+                if lam_states is not None:
+                    api.damping_advance(lam_states[i])
+                if stamps is not None:
+                    api.device_timestamp(stamps, 2 * i + 1)
+        for s in self.streams[:len(self.opts)]:
+            join = torch.cuda.Event()
+            join.record(s)
+            main.wait_event(join)
+
+    def _capture_batch(self):
+        self.lam_state = []
+        for opt in self.opts:
+            self.lam_state.append(opt.schedule.to_device(opt.X.device))
+            prob = api._problem(opt.X, int(opt.A[0].shape[1]))
+            api._ws(prob, api.L.OP_GN_STEP, opt.X.device, opt.ws)
+        torch.cuda.synchronize()
+        cap = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cap):
+            self._batch_step(lam_states=self.lam_state)
+        self.batch_graph = g
+        self.graphs = []   # the per-problem schedules live on the device (see synchronize)
+        torch.cuda.synchronize()
 
     def _capture(self):
         self.lam_state, self.graphs = [], []
@@ -363,6 +436,20 @@ class BatchedGaussNewton:
         int64, 2 per problem) the device clock is written to stamps[2 i] and stamps[2 i + 1] by
         kernels enqueued on problem i's stream right before and after its step
         (api.device_timestamp; ticks of api.device_clock_hz())."""
+        if self.batch_cg:
+            if timed:
+                raise ValueError("a batched step has one span per problem: use stamps")
+            if self.batch_graph is not None:
+                if stamps is not None:
+                    raise ValueError("stamps are not part of the captured batch graph")
+                self.batch_graph.replay()
+            else:
+                self._batch_step(stamps=stamps)
+            for opt in self.opts:
+                if self.batch_graph is None:
+                    opt.schedule.advance()
+                opt.steps += 1
+            return []
         events = []
         for i, opt in enumerate(self.opts):
             s = self.streams[i % len(self.streams)]
@@ -385,6 +472,7 @@ class BatchedGaussNewton:
         return events
 
     def synchronize(self):
+        torch.cuda.current_stream().synchronize()
         for s in self.streams:
             s.synchronize()
         if self.graphs is not None:   # keep the host schedules in step with the device ones
@@ -401,12 +489,14 @@ class BatchedGaussNewton:
 
 @dataclass
 class BatchedTuning:
-    """The launch configuration chosen for a batch: HIP streams, graph replay, the throughput
-    it measured and the whole sweep (problem-steps/s per (n_streams, graphs))."""
+    """The launch configuration chosen for a batch: HIP streams, graph replay, batched CG, the
+    throughput it measured and the whole sweep (problem-steps/s per (n_streams, graphs,
+    batch_cg))."""
     n_streams: int
     graphs: bool
     problem_steps_per_s: float
     table: dict
+    batch_cg: bool = False
 
 
 _TUNING_CACHE: dict = {}
@@ -426,10 +516,10 @@ def batch_key(problems) -> tuple:
     return (len(problems), tuple(dtypes), tuple(ranks), tuple(sizes))
 
 
-def _time_batched(problems, config, n_streams, graphs, steps) -> float:
+def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False) -> float:
     cur = [(X, [a.clone() for a in A]) for X, A in problems]   # the caller's factors stay as is
     torch.cuda.synchronize()
-    bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs)
+    bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs, batch_cg=batch_cg)
     bgn.step()
     bgn.synchronize()
     torch.cuda.synchronize()
@@ -442,23 +532,33 @@ def _time_batched(problems, config, n_streams, graphs, steps) -> float:
 
 
 def autotune_batched(problems, config: GNConfig | None = None, stream_counts=(1, 2, 4, 8, 16),
-                     graphs=(False, True), steps: int = 3, timer=None, cache=_TUNING_CACHE):
-    """Sweep-based tuning of the batched runner: every (n_streams, graphs) pair runs `steps`
-    Gauss-Newton steps of the whole batch on copies of its factors, timed by the wall clock, and
-    the fastest is returned (the first one on a tie). The result is cached per batch_key, so a
-    batch of a shape seen before is not timed again. The iterates do not depend on the choice
-    (the kernels are deterministic), only the throughput does."""
+                     graphs=(False, True), steps: int = 3, timer=None, cache=_TUNING_CACHE,
+                     batch_cg=(False, True)):
+    """Sweep-based tuning of the batched runner: every (n_streams, graphs, batch_cg) triple runs
+    `steps` Gauss-Newton steps of the whole batch on copies of its factors, timed by the wall
+    clock, and the fastest is returned (the first one on a tie). batch_cg=True (CG of all
+    problems in shared launches) is swept only where it applies (plain step, explicit-inverse
+    preconditioner, ranks <= 128). The result is cached per batch_key, so a batch of a shape seen
+    before is not timed again. The iterates do not depend on the choice (the kernels are
+    deterministic and the batched CG gives the per-problem bits), only the throughput does."""
     key = batch_key(problems)
     if cache is not None and key in cache:
         return cache[key]
+    cfg = config or GNConfig()
+    can_batch = (cfg.line_search is None and cfg.preconditioner == "inverse"
+                 and max(int(A[0].shape[1]) for _, A in problems) <= 128)
     timer = timer or _time_batched
     table = {}
     for ns in stream_counts:
         for g in graphs:
-            table[(int(ns), bool(g))] = len(problems) * steps / timer(problems, config, ns, g, steps)
+            for b in batch_cg:
+                if b and not can_batch:
+                    continue
+                table[(int(ns), bool(g), bool(b))] = len(problems) * steps / timer(
+                    problems, config, ns, g, steps, bool(b))
     best = max(table, key=table.get)
     out = BatchedTuning(n_streams=best[0], graphs=best[1], problem_steps_per_s=table[best],
-                        table=table)
+                        table=table, batch_cg=best[2])
     if cache is not None:
         cache[key] = out
     return out

@@ -144,6 +144,15 @@ def test_call_validation_without_launch(lib):
                                  need, None) == L.CP_EINVAL
     assert lib.cp_damping_advance(None, None) == L.CP_EINVAL
     assert lib.cp_device_timestamp(None, None) == L.CP_EINVAL
+    # split step: batch size and null arrays are rejected before any launch
+    wsa = (C.c_void_p * 1)(ws)
+    nba = (C.c_size_t * 1)(need)
+    assert lib.cp_gn_cg_batch(0, C.byref(p), wsa, nba, 20, None) == L.CP_EINVAL
+    assert lib.cp_gn_cg_batch(L.MAX_CG_BATCH + 1, C.byref(p), wsa, nba, 20, None) == L.CP_EINVAL
+    assert lib.cp_gn_cg_batch(1, C.byref(p), None, nba, 20, None) == L.CP_EINVAL
+    assert lib.cp_gn_cg_batch(1, C.byref(p), wsa, nba, -1, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_begin(C.byref(p), None, A, C.byref(good0), None, ws, need, None) == L.CP_EINVAL
+    assert lib.cp_gn_step_end(C.byref(p), A, None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_device_clock_hz(None) == L.CP_EINVAL
     # storage conversion: negative count, null pointers
     assert lib.cp_tensor_to_bf16(X, -1, 0, M, None) == L.CP_EINVAL

@@ -201,6 +201,81 @@ def test_device_timestamps_bracket_batched_steps():
             assert torch.equal(a, c)
 
 
+def test_batched_cg_steps_match_per_problem_steps():
+    """Steps split in begin / batched CG / end (cp_gn_step_begin, cp_gn_cg_batch, cp_gn_step_end)
+    give bitwise the factors and stats of each problem's own cp_gn_step over three steps, for
+    uneven problems (modes 60..200, ranks 8..64, so the batch runs with the largest rank's column
+    blocks), and the first step matches the oracle."""
+    from workloads import batched_problems
+    probs = batched_problems(6)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    ref = [P.GaussNewton(X, A) for X, A in mk()]
+    bat = P.BatchedGaussNewton(mk(), n_streams=3, batch_cg=True)
+    for k in range(3):
+        for g in ref:
+            g.step()
+        bat.step()
+        bat.synchronize()
+        torch.cuda.synchronize()
+        for g, ob in zip(ref, bat.opts):
+            assert g.stats() == ob.stats(), k
+            for a, b in zip(g.A, ob.A):
+                assert torch.equal(a, b), k
+        if k == 0:
+            for p, ob in zip(probs[:2], bat.opts[:2]):
+                xs = p.x.astype(np.float32).astype(np.float64)
+                As = [a.astype(np.float32).astype(np.float64) for a in p.init]
+                its = ob.stats()["cg_iters"]
+                r, _ = O.gn_step(xs, As, 1e-4, 0.0, its)
+                for a, b in zip(ob.A, r):
+                    assert rel(a.double().cpu().numpy(), b) < 1e-4
+
+
+def test_batched_cg_single_problem_matches_gn_step_fp64():
+    """One FP64 problem through begin / batch of one / end equals cp_gn_step bitwise (factors and
+    stats), with the host damping and with the device damping."""
+    p = make_problem((30, 25, 20), 7, workload=1, problem=3)
+    X = torch.tensor(p.x, device="cuda")
+    for devlam in (False, True):
+        A1 = [torch.tensor(a, device="cuda") for a in p.init]
+        A2 = [a.clone() for a in A1]
+        s1 = P.gn_step(X, A1, 3e-3, 1e-3, 20)
+        if devlam:
+            lam = torch.tensor([3e-3], dtype=torch.float64, device="cuda")
+            st = P.gn_step_begin(X, A2, lam_dev=lam, cg_tol=1e-3, cg_maxiter=20)
+        else:
+            st = P.gn_step_begin(X, A2, lam=3e-3, cg_tol=1e-3, cg_maxiter=20)
+        P.gn_cg_batch([st], 20)
+        s2 = P.gn_step_end(st)
+        torch.cuda.synchronize()
+        assert P.read_stats(s1) == P.read_stats(s2)
+        for a, b in zip(A1, A2):
+            assert torch.equal(a, b)
+
+
+def test_batched_cg_graph_replays_match_eager():
+    """The whole batched step captured as one graph (all streams) and replayed three times, with
+    eager work between replays, gives bitwise the eager batched iterates and schedules."""
+    from workloads import batched_problems
+    probs = batched_problems(5)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    eager = P.BatchedGaussNewton(mk(), n_streams=2, batch_cg=True)
+    graph = P.BatchedGaussNewton(mk(), n_streams=2, batch_cg=True, graphs=True)
+    for k in range(3):
+        eager.step()
+        eager.synchronize()
+        graph.step()
+        graph.synchronize()
+        _ = graph.residuals()
+        torch.cuda.synchronize()
+        for oe, og in zip(eager.opts, graph.opts):
+            assert og.schedule.value == oe.schedule.value
+            for a, b in zip(oe.A, og.A):
+                assert torch.equal(a, b), k
+
+
 # ------------------------------------------------------------------ graph-replayable steps
 def test_device_damping_schedule_matches_host():
     """cp_damping_advance gives bitwise the host schedule's sequence (both directions)."""
@@ -270,11 +345,12 @@ def test_autotuned_batched_run_matches_single_stream():
     before = [[a.clone() for a in A] for _, A in probs]
     cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20)
     tune = P.autotune_batched(probs, cfg, stream_counts=(1, 4), steps=2, cache={})
-    assert (tune.n_streams, tune.graphs) in tune.table and len(tune.table) == 4
+    assert (tune.n_streams, tune.graphs, tune.batch_cg) in tune.table and len(tune.table) == 8
     for (_, A), B in zip(probs, before):
         assert all(torch.equal(a, b) for a, b in zip(A, B))
     tuned = [(X, [a.clone() for a in A]) for X, A in probs]
-    bgn = P.BatchedGaussNewton(tuned, cfg, n_streams=tune.n_streams, graphs=tune.graphs)
+    bgn = P.BatchedGaussNewton(tuned, cfg, n_streams=tune.n_streams, graphs=tune.graphs,
+                               batch_cg=tune.batch_cg)
     for _ in range(3):
         bgn.step()
     bgn.synchronize()

@@ -102,21 +102,28 @@ def test_autotune_batched_picks_fastest_and_caches():
     probs = [(torch.zeros(60, 70, 90), [torch.zeros(60, 8), torch.zeros(70, 8), torch.zeros(90, 8)]),
              (torch.zeros(130, 70, 90), [torch.zeros(130, 40), torch.zeros(70, 40),
                                          torch.zeros(90, 40)])]
-    secs = {(1, False): 4.0, (1, True): 3.0, (4, False): 2.0, (4, True): 1.0, (8, False): 1.5,
-            (8, True): 1.0}
+    secs = {(1, False, False): 4.0, (1, True, False): 3.0, (4, False, False): 2.0,
+            (4, True, False): 1.0, (8, False, False): 1.5, (8, True, False): 1.0,
+            (1, False, True): 2.5, (1, True, True): 2.5, (4, False, True): 0.8,
+            (4, True, True): 0.5, (8, False, True): 0.9, (8, True, True): 0.5}
     calls = []
 
-    def timer(problems, config, ns, graphs, steps):
-        calls.append((ns, graphs))
+    def timer(problems, config, ns, graphs, steps, batch_cg):
+        calls.append((ns, graphs, batch_cg))
         assert problems is probs and steps == 3
-        return secs[(ns, graphs)]
+        return secs[(ns, graphs, batch_cg)]
 
     cache = {}
     out = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
-    assert (out.n_streams, out.graphs) == (4, True)           # first of the two fastest
-    assert out.problem_steps_per_s == 2 * 3 / 1.0 and len(out.table) == 6
-    assert len(calls) == 6
+    assert (out.n_streams, out.graphs, out.batch_cg) == (4, True, True)   # first of the fastest
+    assert out.problem_steps_per_s == 2 * 3 / 0.5 and len(out.table) == 12
+    assert len(calls) == 12
     again = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
-    assert again is out and len(calls) == 6                   # served from the cache
+    assert again is out and len(calls) == 12                  # served from the cache
+    # batched CG is not swept where it does not apply (the Cholesky preconditioner)
+    calls.clear()
+    cfg = optim.GNConfig(preconditioner="cholesky")
+    out2 = optim.autotune_batched(probs, cfg, stream_counts=(1, 4, 8), timer=timer, cache={})
+    assert not out2.batch_cg and len(calls) == 6 and all(not c[2] for c in calls)
     # the bucket: ranks 8 and 40 -> 8 and 64, largest modes 90 and 130 -> 128 and 256
     assert optim.batch_key(probs) == (2, ("torch.float32",), (8, 64), (128, 256))
