@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle's MTTKRP, GN step, ALS sweep and residual at "
                          "300^3 R=50 and 400^3 R=100 on the host and print them as JSON")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="only run the 64-problem batched workload with batched CG (8 streams, one "
+                         "graph per batch step): --warmup then --steps batch steps (for kernel "
+                         "traces)")
     ap.add_argument("--profile-step", action="store_true",
                     help="only run the headline loop (--warmup then --steps Gauss-Newton steps with "
                          "their residuals and run restarts) and exit (for kernel traces)")
@@ -561,6 +565,27 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_bf16": "3 x cp_mttkrp per mode, 80^4 R=64, bfloat16 and split"}),
               flush=True)
+        return
+    if args.profile_batched:
+        from workloads import batched_problems
+        devs = [(torch.tensor(q.x, dtype=torch.float32, device="cuda"),
+                 [torch.tensor(a, dtype=torch.float32, device="cuda") for a in q.init])
+                for q in batched_problems(64)]
+        bgn = P.BatchedGaussNewton(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=8,
+                                   graphs=True, batch_cg=True)
+        for _ in range(args.warmup):
+            bgn.step()
+        bgn.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bgn.step()
+            bgn.synchronize()
+        ms = (time.perf_counter() - t0) / max(1, args.steps) * 1e3
+        print(json.dumps({"profile_batched": f"{args.warmup} + {args.steps} batch steps of 64 "
+                          "problems, batched CG, 8 streams, one graph per batch step",
+                          "ms_per_batch_step": ms}), flush=True)
+        del bgn, devs
+        shutdown()
         return
     log(f"[bench] device {dev_name}; building {s}^3 rank-{R} planted FP32 tensor")
     X64, A0, Xd = make_inputs(s, R, np.float32)
