@@ -116,7 +116,9 @@ def event_samples(fn, reps, stream):
 
 
 def mttkrp_times(P, Xd, A, reps, stream):
-    """Median and mean duration of one cp_mttkrp call per mode."""
+    """Per mode: median and mean duration of one cp_mttkrp call (factor preparation, main kernel,
+    partial-tile reduction), and median and mean duration of its main kernel alone, from HIP
+    events that cp_mttkrp_marked records on the stream right around that kernel's launch."""
     import torch
     ws = P.Workspace()
     s, R = Xd.shape[0], A[0].shape[1]
@@ -126,7 +128,17 @@ def mttkrp_times(P, Xd, A, reps, stream):
         for _ in range(3):
             P.mttkrp(Xd, A, n, out=M, ws=ws)
         ts = event_samples(lambda: P.mttkrp(Xd, A, n, out=M, ws=ws), reps, stream)
-        out[n] = (float(np.median(ts)), float(np.mean(ts)))
+        marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(reps)]
+        for e0, e1 in marks:   # creates the HIP events
+            e0.record(stream)
+            e1.record(stream)
+        for mk in marks:
+            P.mttkrp(Xd, A, n, out=M, ws=ws, marks=mk)
+        marks[-1][1].synchronize()
+        tk = [e0.elapsed_time(e1) / 1e3 for e0, e1 in marks]
+        out[n] = (float(np.median(ts)), float(np.mean(ts)), float(np.median(tk)),
+                  float(np.mean(tk)))
     return out
 
 
@@ -618,9 +630,11 @@ def main():
     mt32 = mttkrp_times(P, Xd, A, args.mttkrp_reps, stream)
     mt = {n: v[0] for n, v in mt32.items()}
     mt_tf = {n: flops / t / 1e12 for n, t in mt.items()}
-    mean_t = sum(v[1] for v in mt32.values()) / 3
-    log(f"[bench] MTTKRP FP32 per-mode median ms {[round(t * 1e3, 4) for t in mt.values()]}, "
-        f"TFLOP/s {[round(v, 1) for v in mt_tf.values()]}")
+    mean_t = sum(v[3] for v in mt32.values()) / 3        # main kernel alone, mean over modes
+    mean_call = sum(v[1] for v in mt32.values()) / 3     # whole cp_mttkrp call
+    log(f"[bench] MTTKRP FP32 per-mode median ms per call {[round(t * 1e3, 4) for t in mt.values()]}"
+        f", TFLOP/s {[round(v, 1) for v in mt_tf.values()]}; main kernel median ms "
+        f"{[round(v[2] * 1e3, 4) for v in mt32.values()]}")
     X64d = torch.from_numpy(X64).cuda()
     A64m = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A0]
     mt64 = mttkrp_times(P, X64d, A64m, args.mttkrp_reps, stream)
@@ -877,12 +891,23 @@ def main():
                      "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": flops / mean_t / 1e12 / PEAK_FP32_MFMA_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "cp_mttkrp FP32 single mode (mean over modes and calls)"},
+                     "kernel": "k_mttkrp, the main kernel of cp_mttkrp, FP32 single mode: HIP "
+                               "events recorded on its stream around its launch (mean over modes "
+                               "and calls)",
+                     "per_call": {"achieved": flops / mean_call / 1e12,
+                                  "frac": flops / mean_call / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                                  "note": "whole cp_mttkrp call: factor preparation, main "
+                                          "kernel, partial-tile reduction"}},
         "mttkrp_fp32": {f"mode{n}": {"median_ms": v[0] * 1e3, "mean_ms": v[1] * 1e3,
-                                     "tflops_median": flops / v[0] / 1e12} for n, v in mt32.items()},
+                                     "tflops_median": flops / v[0] / 1e12,
+                                     "kernel_median_ms": v[2] * 1e3, "kernel_mean_ms": v[3] * 1e3}
+                        for n, v in mt32.items()},
         "mttkrp_fp64": {f"mode{n}": {"median_ms": v[0] * 1e3, "mean_ms": v[1] * 1e3,
                                      "tflops_median": flops / v[0] / 1e12,
-                                     "frac_fp64_peak": flops / v[0] / 1e12 / PEAK_FP64_MFMA_TFLOPS}
+                                     "frac_fp64_peak": flops / v[0] / 1e12 / PEAK_FP64_MFMA_TFLOPS,
+                                     "kernel_median_ms": v[2] * 1e3,
+                                     "kernel_frac_fp64_peak":
+                                         flops / v[2] / 1e12 / PEAK_FP64_MFMA_TFLOPS}
                         for n, v in mt64.items()},
         "mttkrp_all_modes": {
             "fp32_median_ms": tall32 * 1e3, "fp64_median_ms": tall64 * 1e3,

@@ -144,6 +144,17 @@ int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int m
               void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * cp_mttkrp with its main kernel bracketed for timing: the HIP events `kernel_begin` and
+ * `kernel_end` (hipEvent_t, created by the caller; either may be NULL) are recorded on `stream`
+ * right before the first and after the last launch of the MTTKRP kernel proper, so that
+ * hipEventElapsedTime gives that kernel's duration without the factor preparation before it and
+ * the partial-tile reduction after it. Same result, arguments and errors as cp_mttkrp.
+ */
+int cp_mttkrp_marked(const cp_problem* prob, const void* X, const void* const* A, int mode,
+                     void* M, void* ws, size_t ws_bytes, void* stream, void* kernel_begin,
+                     void* kernel_end);
+
+/*
  * All-mode MTTKRP: M^(n) = X_(n) P^(n) (Section 2.2, eq. (1)) for every mode n at one point, the
  * contractions that form the gradient of Algorithm 1. For an order-3 tensor, modes 0 and 1 come
  * from one pass over X (a dimension tree, Section 2.2: the partial contraction with A^(2) is

@@ -18,7 +18,7 @@ GN_CHOL_PRECOND = 2
 LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
-EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
+EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_marked", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
            "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_gn_step_begin", "cp_gn_cg_batch", "cp_gn_step_end", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.cp_workspace_bytes.argtypes = [P(CpProblem), i32, P(sz)]
     lib.cp_mttkrp.restype = i32
     lib.cp_mttkrp.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
+    lib.cp_mttkrp_marked.restype = i32
+    lib.cp_mttkrp_marked.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp, vp, vp]
     lib.cp_mttkrp_all.restype = i32
     lib.cp_mttkrp_all.argtypes = [P(CpProblem), vp, PTRS, PTRS, vp, sz, vp]
     lib.cp_gn_gradient.restype = i32

@@ -169,8 +169,12 @@ def _ws(prob, op, device, ws):
     return (ws or _default_ws).get(prob, op, device)
 
 
-def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=None):
-    """M = X_(mode) P^(mode) (Section 2.2, eq. (1)); returns a dims[mode] x R tensor."""
+def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=None,
+           marks=None):
+    """M = X_(mode) P^(mode) (Section 2.2, eq. (1)); returns a dims[mode] x R tensor.
+    marks: optional (begin, end) pair of torch.cuda.Event (enable_timing=True, recorded once
+    before so that the HIP events exist), recorded around the main MTTKRP kernel only
+    (cp_mttkrp_marked): begin.elapsed_time(end) is that kernel's duration."""
     _dev(X, "X")
     R = int(A[0].shape[1])
     _factors(A, X.shape, factor_dtype(X), R)
@@ -179,8 +183,17 @@ def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=N
         out = torch.empty((X.shape[mode], R), dtype=factor_dtype(X), device=X.device)
     _dev(out, "out", factor_dtype(X), (X.shape[mode], R))
     w, nb = _ws(prob, L.OP_MTTKRP, X.device, ws)
-    _check(L.load().cp_mttkrp(C.byref(prob), X.data_ptr(), _ptrs(A), int(mode), out.data_ptr(), w, nb,
-                              _stream()), "cp_mttkrp")
+    lib = L.load()
+    if marks is None:
+        _check(lib.cp_mttkrp(C.byref(prob), X.data_ptr(), _ptrs(A), int(mode), out.data_ptr(), w,
+                             nb, _stream()), "cp_mttkrp")
+    else:
+        ev0, ev1 = marks
+        if not ev0.cuda_event or not ev1.cuda_event:
+            raise ValueError("mttkrp marks: record each event once before passing it")
+        _check(lib.cp_mttkrp_marked(C.byref(prob), X.data_ptr(), _ptrs(A), int(mode),
+                                    out.data_ptr(), w, nb, _stream(), C.c_void_p(ev0.cuda_event),
+                                    C.c_void_p(ev1.cuda_event)), "cp_mttkrp_marked")
     return out
 
 

@@ -324,17 +324,26 @@ int cp_workspace_bytes(const cp_problem* prob, int op, size_t* bytes) {
   return CP_OK;
 }
 
-int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int mode, void* M,
-              void* ws, size_t ws_bytes, void* stream) {
+int cp_mttkrp_marked(const cp_problem* prob, const void* X, const void* const* A, int mode,
+                     void* M, void* ws, size_t ws_bytes, void* stream, void* kernel_begin,
+                     void* kernel_end) {
   Plan p;
   int rc = make_plan(prob, &p);
   if (rc) return rc;
   if (!X || !M || mode < 0 || mode >= p.N) return CP_EINVAL;
   if ((rc = check_ptrs(p, A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
+  KernelMarks mk;
+  mk.before = (hipEvent_t)kernel_begin;
+  mk.after = (hipEvent_t)kernel_end;
   launch_prepare_factors_src(p, A, p.dtype, ws, st, false, 1u << mode);
-  launch_mttkrp(p, X, mode, ws, nullptr, M, st);
+  launch_mttkrp(p, X, mode, ws, nullptr, M, st, mk);
   return hip_status();
+}
+
+int cp_mttkrp(const cp_problem* prob, const void* X, const void* const* A, int mode, void* M,
+              void* ws, size_t ws_bytes, void* stream) {
+  return cp_mttkrp_marked(prob, X, A, mode, M, ws, ws_bytes, stream, nullptr, nullptr);
 }
 
 int cp_mttkrp_all(const cp_problem* prob, const void* X, const void* const* A, void* const* M,

@@ -128,8 +128,13 @@ Dims make_dims(const Plan& p);
 // Launch helpers (return hipError_t as int).
 int launch_prepare_factors(const Plan& p, const void* const* A, void* ws, hipStream_t st,
                            bool also_a64);
+// Events recorded on the stream right before the first and after the last launch of the main
+// MTTKRP kernel (not the factor preparation or the partial-tile reduction); either may be null.
+struct KernelMarks {
+  hipEvent_t before = nullptr, after = nullptr;
+};
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64_out,
-                  void* m_out_fdtype, hipStream_t st);
+                  void* m_out_fdtype, hipStream_t st, KernelMarks mk = {});
 // Work decomposition of one MTTKRP launch (shared by the workspace plan and the launcher).
 struct MttkrpGeom {
   int MB;                 // 16-row blocks per wavefront tile

@@ -638,7 +638,7 @@ static bool vec_ok(const Plan& p, int mode, const void* X) {
 template <typename T>
 static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, double* m64,
                            void* mout, bool dt, double* m64_outer, void* mout_outer,
-                           hipStream_t st) {
+                           hipStream_t st, KernelMarks mk = {}) {
   const bool vec = vec_ok(p, mode, X);
   const MttkrpGeom G = mttkrp_geom(p, mode, vec, dt);
   const bool caseB = mode == p.N - 1;
@@ -675,6 +675,10 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
   a.NBt = p.NBt;
   a.nsplit = (int)(4 * G.SW);
   a.dt = dt ? 1 : 0;
+  if (mk.before) {
+    const hipError_t e = hipEventRecord(mk.before, st);
+    if (e != hipSuccess) return (int)e;
+  }
   for (int cb0 = 0; cb0 < p.NBt; cb0 += 8) {
     const int NB = p.NBt - cb0 < 8 ? p.NBt - cb0 : 8;
     a.cb0 = cb0;
@@ -683,6 +687,10 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
       const int64_t nrt = G.RT - rt0 < kMaxGridY ? G.RT - rt0 : kMaxGridY;
       launch_variant<T>(caseB, vec, G.MB, NB, dim3((unsigned)G.SW, (unsigned)nrt), st, a);
     }
+  }
+  if (mk.after) {
+    const hipError_t e = hipEventRecord(mk.after, st);
+    if (e != hipSuccess) return (int)e;
   }
   hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(reduce_grid(a.J, p.R)), dim3(1024), 0, st,
                      (const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);
@@ -700,7 +708,7 @@ void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int R
 }
 
 int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
-                       hipStream_t st);
+                       hipStream_t st, KernelMarks mk);
 
 // Order 3: T = X x_3 A(2) as the [s0 s1][Rp] matrix (compute precision), for the ALS dimension
 // tree. It is the mode-0 MTTKRP of X viewed as the two-way tensor [s0 s1, s2]: one workgroup per
@@ -799,11 +807,13 @@ void launch_ttm_contract(const Plan& p, const void* T, const double* F, int mode
 }
 
 int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
-                  hipStream_t st) {
-  if (p.xk != 0) return launch_mttkrp_bf16(p, X, mode, ws, m64, mout, st);
+                  hipStream_t st, KernelMarks mk) {
+  if (p.xk != 0) return launch_mttkrp_bf16(p, X, mode, ws, m64, mout, st, mk);
   if (p.dtype == CP_F32)
-    return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st);
-  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st);
+    return launch_mttkrp_t<float>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st,
+                                  mk);
+  return launch_mttkrp_t<double>(p, X, mode, (char*)ws, m64, mout, false, nullptr, nullptr, st,
+                                 mk);
 }
 
 // Order 3, one pass over X: M(0) and, through the dimension tree, M(1). Each mode's result goes

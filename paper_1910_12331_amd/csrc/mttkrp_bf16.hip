@@ -417,7 +417,7 @@ int64_t bf16_krp_offset(const Plan& p, int mode) {
 }
 
 int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double* m64, void* mout,
-                       hipStream_t st) {
+                       hipStream_t st, KernelMarks mk) {
   char* ws = (char*)wsv;
   const bool caseB = mode == p.N - 1;
   const int q = caseB ? p.N - 2 : p.N - 1;
@@ -441,6 +441,10 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
   a.Rp = p.Rp;
   a.NBt = p.NBt;
   a.nsplit = (int)((caseB ? BfTile<true>::W : BfTile<false>::W) * G.SW);
+  if (mk.before) {
+    const hipError_t e = hipEventRecord(mk.before, st);
+    if (e != hipSuccess) return (int)e;
+  }
   for (int cb0 = 0; cb0 < p.NBt; cb0 += kBfNB) {
     const int NB = p.NBt - cb0 < kBfNB ? p.NBt - cb0 : kBfNB;
     a.cb0 = cb0;
@@ -456,6 +460,10 @@ int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* wsv, double
       if (caseB) bf_launch<true>(x3, vec, NB, grid, lds, st, a);
       else bf_launch<false>(x3, vec, NB, grid, lds, st, a);
     }
+  }
+  if (mk.after) {
+    const hipError_t e = hipEventRecord(mk.after, st);
+    if (e != hipSuccess) return (int)e;
   }
   launch_mttkrp_reduce_f32(a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, CP_F32, st);
   return (int)hipGetLastError();

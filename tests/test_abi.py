@@ -132,6 +132,12 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, ws, need - 1, None) == L.CP_EWORKSPACE
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, C.c_void_p(0x40010), need, None) == L.CP_EINVAL
     assert lib.cp_mttkrp(C.byref(p), X, A, 0, M, None, need, None) == L.CP_EINVAL
+    # the marked form validates the same way before recording anything
+    assert lib.cp_mttkrp_marked(C.byref(p), X, A, 3, M, ws, need, None, None, None) == L.CP_EINVAL
+    assert lib.cp_mttkrp_marked(C.byref(p), None, A, 0, M, ws, need, None, None,
+                                None) == L.CP_EINVAL
+    assert lib.cp_mttkrp_marked(C.byref(p), X, A, 0, M, ws, need - 1, None, None,
+                                None) == L.CP_EWORKSPACE
     # all-mode MTTKRP: null output pointer, null tensor, small workspace
     Ms = fake_ptrs()
     Ms[2] = 0

@@ -139,6 +139,18 @@ def test_mttkrp_400_fp32_closed_form():
         M = P.mttkrp(Xd, Ad, n)
         # X itself is rounded to FP32 (relative 6e-8 per entry) on top of the FP32 contraction
         assert rel(host([M])[0], ref) < 2e-5
+        # cp_mttkrp_marked (the bench's roofline timing): same bits, and the bracketed main
+        # kernel lies inside the HIP-event time of the whole call
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for e in ev:
+            e.record()
+        ev[0].record()
+        M2 = P.mttkrp(Xd, Ad, n, marks=(ev[1], ev[2]))
+        ev[3].record()
+        ev[3].synchronize()
+        assert torch.equal(M2, M)
+        t_kernel, t_call = ev[1].elapsed_time(ev[2]), ev[0].elapsed_time(ev[3])
+        assert 0.0 < t_kernel <= t_call, (t_kernel, t_call)
 
 
 # ------------------------------------------------------------------------------------ gradient
