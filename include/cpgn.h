@@ -327,6 +327,43 @@ int cp_gn_step_end(const cp_problem* prob, void* const* A, cp_gn_stats* stats, v
                    size_t ws_bytes, void* stream);
 
 /*
+ * A batch program: one Gauss-Newton step (Algorithm 1, CG of Algorithm 2) of `count` independent
+ * problems in shared launches. cp_gn_batch_create records, once, the launches that
+ * cp_gn_step_begin and cp_gn_step_end make for each problem (and a cp_damping_advance when
+ * damping_state[i] is given), with their arguments; cp_gn_batch_step then enqueues, for each
+ * position in the step, one launch per kernel that runs the workgroups of every problem at that
+ * position (a workgroup finds its problem from a table of workgroup offsets), with the CG of all
+ * problems in between as cp_gn_cg_batch does. Each problem computes exactly what its three split
+ * calls compute (bitwise the same factors, stats and damping), in about 40 launches per step
+ * for the whole batch instead of about 20 per problem plus the shared CG.
+ *   count: >= 1. probs[i], X[i], ws[i] (ws_bytes[i] >= cp_workspace_bytes(CP_OP_GN_STEP)): as
+ *     for cp_gn_step_begin. A: count * CP_MAX_ORDER device pointers, A[i * CP_MAX_ORDER + n] the
+ *     factor n of problem i (read and overwritten by each step). params: HOST pointer, shared by
+ *     all problems (CP_GN_CHOL_PRECOND not supported). lambda_dev: NULL (params->lambda for all)
+ *     or count device pointers (an entry may be NULL: params->lambda). damping_state: NULL or
+ *     count device double[5] schedules (entries may be NULL) advanced after each step as by
+ *     cp_damping_advance. stats: count device pointers to cp_gn_stats.
+ *   table: caller-owned device memory for the recorded arguments, table_bytes long (16-byte
+ *     aligned); *table_needed (host) receives the size required. With table NULL or too small
+ *     the call returns CP_EWORKSPACE after setting *table_needed, and creates nothing.
+ *   *out (host) receives the program. It refers to every pointer above (none is copied): they
+ *     must stay valid and keep their sizes while the program is used. The recorded arguments are
+ *     copied into `table` synchronously before the call returns.
+ * Errors: CP_EINVAL (null or inconsistent arguments), CP_EUNSUPPORTED (rank above 128, bfloat16
+ * storage, or the Cholesky preconditioner), CP_EWORKSPACE (workspace or table too small), or a
+ * HIP error of the table copy. cp_gn_batch_step enqueues one step on `stream` (CP_EINVAL for a
+ * null program); cp_gn_batch_destroy releases the host-side program (not the caller's memory).
+ */
+typedef struct cp_gn_batch cp_gn_batch;
+int cp_gn_batch_create(int count, const cp_problem* probs, const void* const* X, void* const* A,
+                       const cp_gn_params* params, double* const* lambda_dev,
+                       double* const* damping_state, cp_gn_stats* const* stats,
+                       void* const* ws, const size_t* ws_bytes, void* table, size_t table_bytes,
+                       size_t* table_needed, cp_gn_batch** out);
+int cp_gn_batch_step(cp_gn_batch* program, void* stream);
+int cp_gn_batch_destroy(cp_gn_batch* program);
+
+/*
  * Device timestamps for per-problem step latencies (p50/p99) of many problems run on several
  * streams: enqueues one one-thread kernel on `stream` that writes the device's constant-rate
  * clock to *dst_dev when it runs, so that two of them around a step bracket the step's execution

@@ -19,7 +19,7 @@ LS_F0_GIVEN = 1
 RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_marked", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
-           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_gn_step_begin", "cp_gn_cg_batch", "cp_gn_step_end", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
+           "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_gn_step_begin", "cp_gn_cg_batch", "cp_gn_step_end", "cp_gn_batch_create", "cp_gn_batch_step", "cp_gn_batch_destroy", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
            "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
 
 
@@ -99,6 +99,13 @@ def load(path: str = LIB_PATH):
     lib.cp_gn_cg_batch.argtypes = [i32, P(CpProblem), P(vp), P(sz), i32, vp]
     lib.cp_gn_step_end.restype = i32
     lib.cp_gn_step_end.argtypes = [P(CpProblem), PTRS, vp, vp, sz, vp]
+    lib.cp_gn_batch_create.restype = i32
+    lib.cp_gn_batch_create.argtypes = [i32, P(CpProblem), P(vp), P(vp), P(CpGnParams), P(vp),
+                                       P(vp), P(vp), P(vp), P(sz), vp, sz, P(sz), P(vp)]
+    lib.cp_gn_batch_step.restype = i32
+    lib.cp_gn_batch_step.argtypes = [vp, vp]
+    lib.cp_gn_batch_destroy.restype = i32
+    lib.cp_gn_batch_destroy.argtypes = [vp]
     lib.cp_device_timestamp.restype = i32
     lib.cp_device_timestamp.argtypes = [vp, vp]
     lib.cp_device_clock_hz.restype = i32

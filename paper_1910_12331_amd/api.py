@@ -445,6 +445,77 @@ def gn_step_end(step: BegunStep, stats=None):
     return stats
 
 
+class GNBatchProgram:
+    """One Gauss-Newton step of many problems in shared launches (cp_gn_batch_create /
+    cp_gn_batch_step): each problem's launches before and after CG are recorded once, and a step
+    runs one launch per kernel and position in the step for the whole batch, with the CG of all
+    problems in between. Each problem's factors, stats and damping come out bitwise as from
+    gn_step_begin / gn_cg_batch / gn_step_end.
+
+    problems: sequence of (X, A, ws, stats, lam_state): ws a Workspace, stats a stats_buffer,
+    lam_state a float64[5] damping state on the device (read as lambda and advanced after each
+    step) or None (then lam is used). The tensors must stay alive and unmoved while the program
+    is used; the program keeps references to them."""
+
+    def __init__(self, problems, lam: float = 0.0, cg_tol: float = 1e-3, cg_maxiter: int = 20,
+                 damping: str = "identity"):
+        n = len(problems)
+        if n < 1:
+            raise ValueError("at least one problem")
+        self._keep = []
+        probs = (L.CpProblem * n)()
+        Xs = (C.c_void_p * n)()
+        As = (C.c_void_p * (n * L.MAX_ORDER))()
+        lams = (C.c_void_p * n)()
+        states = (C.c_void_p * n)()
+        stats = (C.c_void_p * n)()
+        wss = (C.c_void_p * n)()
+        nbs = (C.c_size_t * n)()
+        for i, (X, A, ws, st, lam_state) in enumerate(problems):
+            _dev(X, "X")
+            R = int(A[0].shape[1])
+            _factors(A, X.shape, factor_dtype(X), R)
+            probs[i] = _problem(X, R)
+            Xs[i] = X.data_ptr()
+            for m, a in enumerate(A):
+                As[i * L.MAX_ORDER + m] = a.data_ptr()
+            if lam_state is not None:
+                _dev(lam_state, "lam_state", torch.float64, (5,))
+                lams[i] = states[i] = lam_state.data_ptr()
+            stats[i] = st.data_ptr()
+            wss[i], nbs[i] = ws.get(probs[i], L.OP_GN_STEP, X.device)
+            self._keep.append((X, list(A), ws, st, lam_state))
+        prm = L.CpGnParams(float(lam), float(cg_tol), int(cg_maxiter), _gn_flags(damping, "inverse"))
+        lib = L.load()
+        need = C.c_size_t(0)
+        handle = C.c_void_p(None)
+        args = [n, probs, Xs, As, C.byref(prm), lams, states, stats, wss, nbs]
+        rc = lib.cp_gn_batch_create(*args, None, 0, C.byref(need), C.byref(handle))
+        if rc != L.CP_EWORKSPACE:
+            _check(rc, "cp_gn_batch_create")
+        self.table = torch.empty(int(need.value) + 16, dtype=torch.uint8, device=problems[0][0].device)
+        base = (self.table.data_ptr() + 15) // 16 * 16
+        _check(lib.cp_gn_batch_create(*args, base, int(need.value), C.byref(need), C.byref(handle)),
+               "cp_gn_batch_create")
+        self._handle = handle
+        self._lib = lib
+
+    def step(self):
+        """Enqueue one Gauss-Newton step of every problem on the current stream."""
+        _check(self._lib.cp_gn_batch_step(self._handle, _stream()), "cp_gn_batch_step")
+
+    def close(self):
+        if self._handle is not None and self._handle.value:
+            self._lib.cp_gn_batch_destroy(self._handle)
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def damping_advance(state: torch.Tensor):
     """Advance a device damping state {lambda, lower, upper, mu, decreasing} (float64[5]) once."""
     _dev(state, "state", torch.float64, (5,))

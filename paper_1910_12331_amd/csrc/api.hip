@@ -7,7 +7,7 @@
 
 #include <mutex>
 
-#include "cpgn_internal.h"
+#include "batch.h"
 
 #include <vector>
 
@@ -728,6 +728,174 @@ int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int
     launch_fin_residual_expansion(d, nblocks, w.red_dot, w.m64, w.a64, w.S, out_dev, st);
   }
   return hip_status();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Batch program: the launches of one Gauss-Newton step of many problems, recorded per problem
+// once and run as one launch per (kernel, position in the step) for the whole batch.
+// ---------------------------------------------------------------------------------------------
+namespace cpgn {
+
+thread_local std::vector<BatchRec>* t_batch_rec = nullptr;
+
+// One batched launch: the members' records are in the device table at tab.blk[i].
+struct BatchLaunch {
+  void (*launch)(const BatchTab&, unsigned, size_t, hipStream_t) = nullptr;
+  BatchTab tab{};
+  unsigned blocks = 0;
+  size_t lds = 0;
+};
+
+// Records the launches that `fn` makes on the calling thread (none runs).
+template <class F>
+static std::vector<BatchRec> record(F&& fn) {
+  std::vector<BatchRec> recs;
+  t_batch_rec = &recs;
+  fn();
+  t_batch_rec = nullptr;
+  return recs;
+}
+
+// Level-synchronous schedule of per-problem chains: the j-th launches of all chains form level
+// j; within a level, launches of the same kernel are merged (at most kMaxBatch members each).
+// A chain's launch j + 1 runs after its launch j because levels are enqueued in order on one
+// stream. Member records are appended to `bytes` (16-byte aligned); blk[] holds offsets into it
+// until the table's device address is known.
+static std::vector<BatchLaunch> schedule(const std::vector<std::vector<BatchRec>>& chains,
+                                         std::vector<unsigned char>& bytes) {
+  std::vector<BatchLaunch> out;
+  size_t depth = 0;
+  for (const auto& c : chains) depth = c.size() > depth ? c.size() : depth;
+  for (size_t j = 0; j < depth; ++j) {
+    std::vector<int> todo;
+    for (int i = 0; i < (int)chains.size(); ++i)
+      if (j < chains[i].size()) todo.push_back(i);
+    while (!todo.empty()) {
+      const BatchRec& head = chains[todo[0]][j];
+      BatchLaunch L;
+      L.launch = head.launch;
+      std::vector<int> rest;
+      for (int i : todo) {
+        const BatchRec& r = chains[i][j];
+        if (r.launch != head.launch || L.tab.n == kMaxBatch) {
+          rest.push_back(i);
+          continue;
+        }
+        const size_t at = (bytes.size() + 15) / 16 * 16;
+        bytes.resize(at + r.blk.size());
+        memcpy(bytes.data() + at, r.blk.data(), r.blk.size());
+        L.tab.blk[L.tab.n] = (const unsigned char*)(uintptr_t)at;
+        L.tab.off[L.tab.n] = (int)L.blocks;
+        L.blocks += r.blocks;
+        L.lds = r.lds > L.lds ? r.lds : L.lds;
+        ++L.tab.n;
+      }
+      L.tab.off[L.tab.n] = (int)L.blocks;
+      out.push_back(L);
+      todo.swap(rest);
+    }
+  }
+  return out;
+}
+
+}  // namespace cpgn
+
+struct cp_gn_batch {
+  std::vector<cpgn::BatchLaunch> pre, post;
+  std::vector<cpgn::Plan> plans;
+  std::vector<void*> cgargs;
+  int cg_maxiter = 0;
+};
+
+extern "C" {
+
+int cp_gn_batch_create(int count, const cp_problem* probs, const void* const* X, void* const* A,
+                       const cp_gn_params* prm, double* const* lambda_dev,
+                       double* const* damping_state, cp_gn_stats* const* stats,
+                       void* const* ws, const size_t* ws_bytes, void* table, size_t table_bytes,
+                       size_t* table_needed, cp_gn_batch** out) {
+  if (count < 1 || !probs || !X || !A || !prm || !stats || !ws || !ws_bytes || !table_needed ||
+      !out)
+    return CP_EINVAL;
+  if (prm->flags & CP_GN_CHOL_PRECOND) return CP_EUNSUPPORTED;
+  std::vector<Plan> plans((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    Plan& p = plans[i];
+    int rc = make_plan(&probs[i], &p);
+    if (rc) return rc;
+    const double* lam = lambda_dev ? lambda_dev[i] : nullptr;
+    if (!X[i] || !stats[i]) return CP_EINVAL;
+    if ((rc = gn_params_ok(p, prm, lam))) return rc;
+    if (p.R > 128 || p.xk != 0) return CP_EUNSUPPORTED;
+    if ((rc = check_ptrs(p, (const void* const*)(A + (size_t)i * CP_MAX_ORDER))) ||
+        (rc = check_ws(p, ws[i], ws_bytes[i])))
+      return rc;
+  }
+  // Record each problem's launches: before CG (cp_gn_step_begin), after CG (cp_gn_step_end and
+  // the damping update). Nothing is launched while recording.
+  std::vector<std::vector<BatchRec>> pre((size_t)count), post((size_t)count);
+  std::vector<void*> cgargs((size_t)count);
+  const hipStream_t none = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const Plan& p = plans[i];
+    const Dims d = make_dims(p);
+    const Ws w = carve(p, ws[i]);
+    void* const* Ai = A + (size_t)i * CP_MAX_ORDER;
+    const double* lam = lambda_dev ? lambda_dev[i] : nullptr;
+    pre[i] = record([&] {
+      gn_pre_cg(p, d, w, X[i], Ai, prm, lam, ws[i], none);
+      launch_cg_store(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z,
+                      w.w, (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st,
+                      lam ? 0.0 : prm->lambda, (prm->flags & CP_GN_DIAG_DAMPING) != 0, lam,
+                      w.base + p.off_cgargs, none);
+    });
+    post[i] = record([&] {
+      PerMode<void*> aout{};
+      for (int n = 0; n < p.N; ++n) aout.p[n] = Ai[n];
+      launch_gn_apply(d, w.a64, w.v, aout, p.dtype, w.red_nrm, w.st, none);
+      launch_gn_stats(d, rowmm_blocks(d), w.red_nrm, w.st, stats[i], none);
+      if (damping_state && damping_state[i]) launch_damping_advance(damping_state[i], none);
+    });
+    cgargs[i] = w.base + p.off_cgargs;
+  }
+  std::vector<unsigned char> bytes;
+  std::vector<BatchLaunch> lpre = schedule(pre, bytes), lpost = schedule(post, bytes);
+  *table_needed = bytes.size();
+  if (!table || table_bytes < bytes.size() || ((uintptr_t)table % 16) != 0) return CP_EWORKSPACE;
+  for (auto* ls : {&lpre, &lpost})
+    for (BatchLaunch& L : *ls)
+      for (int k = 0; k < L.tab.n; ++k)
+        L.tab.blk[k] = (const unsigned char*)table + (uintptr_t)L.tab.blk[k];
+  if (hipMemcpy(table, bytes.data(), bytes.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return hip_status();
+  cp_gn_batch* b = new cp_gn_batch;
+  b->pre = std::move(lpre);
+  b->post = std::move(lpost);
+  b->plans = std::move(plans);
+  b->cgargs = std::move(cgargs);
+  b->cg_maxiter = prm->cg_maxiter;
+  *out = b;
+  return CP_OK;
+}
+
+int cp_gn_batch_step(cp_gn_batch* b, void* stream) {
+  if (!b) return CP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  for (const BatchLaunch& L : b->pre) L.launch(L.tab, L.blocks, L.lds, st);
+  const int count = (int)b->plans.size();
+  for (int k = 0; k < count; k += kMaxCgBatch) {
+    const int n = count - k < kMaxCgBatch ? count - k : kMaxCgBatch;
+    launch_cg_batch(n, b->plans.data() + k, b->cgargs.data() + k, b->cg_maxiter, st);
+  }
+  for (const BatchLaunch& L : b->post) L.launch(L.tab, L.blocks, L.lds, st);
+  return hip_status();
+}
+
+int cp_gn_batch_destroy(cp_gn_batch* b) {
+  delete b;
+  return CP_OK;
 }
 
 }  // extern "C"

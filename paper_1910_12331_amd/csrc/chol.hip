@@ -16,6 +16,7 @@
 //                 nothing but L, which a workgroup stages in LDS when it fits (R <= 128).
 //                 k_chol_tiles forms those 16 x 16 inverses by the same substitution on the
 //                 identity, beside the panel of each step.
+#include "batch.h"
 #include "mfma64.h"
 
 namespace cpgn {
@@ -379,16 +380,16 @@ __device__ __forceinline__ double read_lane(double x, int l) {
 }
 
 template <int NT>
-__global__ __launch_bounds__(kInvWaves * 64) void k_spd_inv_blk(int R, const double* __restrict__ Gin,
-                                                               int64_t g_stride, double lambda,
-                                                               const double* __restrict__ lam_dev,
-                                                               double* __restrict__ Pout,
-                                                               int64_t p_stride, int first_mode,
-                                                               CgState* st, int diag_damping) {
+__device__ __forceinline__ void spd_inv_blk_body(int R, const double* __restrict__ Gin,
+                                                 int64_t g_stride, double lambda,
+                                                 const double* __restrict__ lam_dev,
+                                                 double* __restrict__ Pout, int64_t p_stride,
+                                                 int first_mode, CgState* st, int diag_damping,
+                                                 dim3 bid) {
   constexpr int RP = 16 * NT, LD = RP + 1;   // odd row stride: column reads hit distinct banks
   extern __shared__ double M[];               // [RP][LD]
   __shared__ int sbad;
-  const int n = first_mode + blockIdx.x;
+  const int n = first_mode + bid.x;
   const double* G = Gin + n * g_stride;
   double* P = Pout + n * p_stride;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, g = lane >> 4, m = lane & 15;
@@ -535,6 +536,38 @@ __global__ __launch_bounds__(kInvWaves * 64) void k_spd_inv_blk(int R, const dou
   }
 }
 
+template <int NT>
+struct KSpdInvBlk {
+  struct Args {
+    int R;
+    const double* G;
+    int64_t g_stride;
+    double lambda;
+    const double* lam_dev;
+    double* P;
+    int64_t p_stride;
+    int first_mode;
+    CgState* st;
+    int diag_damping;
+  };
+  static constexpr int kThreads = kInvWaves * 64, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3) {
+    spd_inv_blk_body<NT>(a.R, a.G, a.g_stride, a.lambda, a.lam_dev, a.P, a.p_stride,
+                         a.first_mode, a.st, a.diag_damping, bid);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+template <int NT>
+__global__ __launch_bounds__(kInvWaves * 64) void k_spd_inv_blk(typename KSpdInvBlk<NT>::Args a) {
+  KSpdInvBlk<NT>::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+template <int NT>
+void KSpdInvBlk<NT>::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL((k_spd_inv_blk<NT>), grid, dim3(kThreads), lds, s, a);
+}
+
 int launch_spd_inv_blk(int R, const double* G, int64_t g_stride, double lambda, double* P,
                        int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
                        bool diag_damping, const double* lam_dev) {
@@ -543,9 +576,9 @@ int launch_spd_inv_blk(int R, const double* G, int64_t g_stride, double lambda, 
   switch (NT) {
 #define CPGN_INV(k)                                                                             \
   case k:                                                                                       \
-    hipLaunchKernelGGL((k_spd_inv_blk<k>), dim3(count), dim3(kInvWaves * 64), lds, s, R, G,   \
-                       g_stride, lambda, lam_dev, P, p_stride, first_mode, st,                  \
-                       diag_damping ? 1 : 0);                                                   \
+    dispatch<KSpdInvBlk<k>>(dim3(count), lds, s,                                                \
+                            {R, G, g_stride, lambda, lam_dev, P, p_stride, first_mode, st,       \
+                             diag_damping ? 1 : 0});                                             \
     break;
     CPGN_INV(1) CPGN_INV(2) CPGN_INV(3) CPGN_INV(4) CPGN_INV(5) CPGN_INV(6) CPGN_INV(7)
     CPGN_INV(8)

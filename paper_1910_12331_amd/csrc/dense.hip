@@ -11,7 +11,7 @@
 // are stored back to back as one [sum_n s_n, R] FP64 array; Dims::off[n] is mode n's first
 // row. Every reduction writes one partial per workgroup and is finished by a single
 // workgroup in a fixed order, so results do not depend on scheduling.
-#include "cpgn_internal.h"
+#include "batch.h"
 
 namespace cpgn {
 
@@ -41,20 +41,38 @@ __device__ __forceinline__ bool state_done(const CgState* st) {
 }
 
 // Gam[n][p] = Hadamard product of S(m) over m not in {n, p} (all-ones when empty), eq. (6).
-__global__ void k_gamma(Dims d, const double* __restrict__ S, double* __restrict__ Gam) {
-  const int R = d.R, N = d.N;
-  const int64_t RR = (int64_t)R * R;
-  const int64_t total = (int64_t)N * N * RR;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = idx % RR;
-    const int np = (int)(idx / RR);
-    const int n = np / N, p = np % N;
-    double v = 1.0;
-    for (int m = 0; m < N; ++m)
-      if (m != n && m != p) v *= S[m * RR + e];
-    Gam[idx] = v;
+struct KGamma {
+  struct Args {
+    Dims d;
+    const double* S;
+    double* Gam;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3 gdim) {
+    const Dims& d = a.d;
+    const double* __restrict__ S = a.S;
+    double* __restrict__ Gam = a.Gam;
+    const int R = d.R, N = d.N;
+    const int64_t RR = (int64_t)R * R;
+    const int64_t total = (int64_t)N * N * RR;
+    for (int64_t idx = bid.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gdim.x * blockDim.x) {
+      const int64_t e = idx % RR;
+      const int np = (int)(idx / RR);
+      const int n = np / N, p = np % N;
+      double v = 1.0;
+      for (int m = 0; m < N; ++m)
+        if (m != n && m != p) v *= S[m * RR + e];
+      Gam[idx] = v;
+    }
   }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(256) void k_gamma(KGamma::Args a) { KGamma::run(a, CPGN_BID, CPGN_GDIM); }
+
+void KGamma::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_gamma, grid, dim3(kThreads), lds, s, a);
 }
 
 // Y(n)[r][z] = sum_{p != n} Gam[n][p][r][z] * B(p)[r][z]  (the R x R core of eq. (7)).
@@ -149,23 +167,42 @@ __device__ double sum_slots(const double* red, int nblocks) {
 }
 
 // Gradient norms: gsum = sum_n sqrt(sum_b nrm[n][b]); resets the CG state.
-__global__ void k_fin_grad(int N, int nblocks, const double* red_nrm, CgState* st, double eps,
-                           double* gsum_out) {
-  double g = 0.0;
-  for (int n = 0; n < N; ++n) g += sqrt(sum_slots(red_nrm + n * kRedSlots, nblocks));
-  if (threadIdx.x == 0) {
-    st->gsum = g;
-    st->rsum = g;
-    st->eps = eps;
-    st->alpha = 0.0;
-    st->beta = 0.0;
-    st->rz = 0.0;
-    st->upd2 = 0.0;
-    st->iters = 0;
-    st->status = isfinite(g) ? CP_OK : CP_ENONFINITE;
-    st->done = st->status != CP_OK ? 1 : 0;
-    if (gsum_out) *gsum_out = g;
+struct KFinGrad {
+  struct Args {
+    int N, nblocks;
+    const double* red_nrm;
+    CgState* st;
+    double eps;
+    double* gsum_out;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3, dim3) {
+    double g = 0.0;
+    for (int n = 0; n < a.N; ++n) g += sqrt(sum_slots(a.red_nrm + n * kRedSlots, a.nblocks));
+    if (threadIdx.x == 0) {
+      CgState* st = a.st;
+      st->gsum = g;
+      st->rsum = g;
+      st->eps = a.eps;
+      st->alpha = 0.0;
+      st->beta = 0.0;
+      st->rz = 0.0;
+      st->upd2 = 0.0;
+      st->iters = 0;
+      st->status = isfinite(g) ? CP_OK : CP_ENONFINITE;
+      st->done = st->status != CP_OK ? 1 : 0;
+      if (a.gsum_out) *a.gsum_out = g;
+    }
   }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(256) void k_fin_grad(KFinGrad::Args a) {
+  KFinGrad::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+void KFinGrad::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_fin_grad, grid, dim3(kThreads), lds, s, a);
 }
 
 __global__ void k_state_reset(CgState* st) {
@@ -179,42 +216,82 @@ __global__ void k_state_reset(CgState* st) {
 }
 
 // A64 += V (when the step did not fail), write the caller's factors, ||V||, and the stats.
-__global__ __launch_bounds__(256) void k_gn_apply(Dims d, double* __restrict__ A64,
-                                                  const double* __restrict__ V,
-                                                  PerMode<void*> Aout, int dtype, double* red_nrm,
-                                                  const CgState* st) {
-  const int n = blockIdx.y;
-  const bool ok = st->status == CP_OK;
-  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
-  double nrm = 0.0, dummy = 0.0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const double v = ok ? V[base + e] : 0.0;
-    nrm += v * v;
-    if (ok) {
-      const double a = A64[base + e] + v;
-      A64[base + e] = a;
-      if (dtype == CP_F64) ((double*)Aout.p[n])[e] = a;
-      else ((float*)Aout.p[n])[e] = (float)a;
+struct KGnApply {
+  struct Args {
+    Dims d;
+    double* A64;
+    const double* V;
+    PerMode<void*> Aout;
+    int dtype;
+    double* red_nrm;
+    const CgState* st;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3 gdim) {
+    const Dims& d = a.d;
+    double* __restrict__ A64 = a.A64;
+    const double* __restrict__ V = a.V;
+    const int n = bid.y;
+    const bool ok = a.st->status == CP_OK;
+    const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+    double nrm = 0.0, dummy = 0.0;
+    for (int64_t e = bid.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (int64_t)gdim.x * blockDim.x) {
+      const double v = ok ? V[base + e] : 0.0;
+      nrm += v * v;
+      if (ok) {
+        const double x = A64[base + e] + v;
+        A64[base + e] = x;
+        if (a.dtype == CP_F64) ((double*)a.Aout.p[n])[e] = x;
+        else ((float*)a.Aout.p[n])[e] = (float)x;
+      }
     }
+    block_sum2(nrm, dummy);
+    if (threadIdx.x == 0) a.red_nrm[n * kRedSlots + bid.x] = nrm;
   }
-  block_sum2(nrm, dummy);
-  if (threadIdx.x == 0) red_nrm[n * kRedSlots + blockIdx.x] = nrm;
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(256) void k_gn_apply(KGnApply::Args a) {
+  KGnApply::run(a, CPGN_BID, CPGN_GDIM);
 }
 
-__global__ void k_gn_stats(int N, int nblocks, const double* red_nrm, const CgState* st,
-                           cp_gn_stats* out) {
-  double u = 0.0;
-  for (int n = 0; n < N; ++n) u += sum_slots(red_nrm + n * kRedSlots, nblocks);
-  if (threadIdx.x == 0) {
-    out->status = st->status;
-    out->cg_iters = st->iters;
-    out->grad_norm_sum = st->gsum;
-    out->cg_res_norm_sum = st->rsum;
-    out->alpha_last = st->alpha;
-    out->beta_last = st->beta;
-    out->update_norm = sqrt(u);
+void KGnApply::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_gn_apply, grid, dim3(kThreads), lds, s, a);
+}
+
+struct KGnStats {
+  struct Args {
+    int N, nblocks;
+    const double* red_nrm;
+    const CgState* st;
+    cp_gn_stats* out;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3, dim3) {
+    double u = 0.0;
+    for (int n = 0; n < a.N; ++n) u += sum_slots(a.red_nrm + n * kRedSlots, a.nblocks);
+    if (threadIdx.x == 0) {
+      const CgState* st = a.st;
+      cp_gn_stats* out = a.out;
+      out->status = st->status;
+      out->cg_iters = st->iters;
+      out->grad_norm_sum = st->gsum;
+      out->cg_res_norm_sum = st->rsum;
+      out->alpha_last = st->alpha;
+      out->beta_last = st->beta;
+      out->update_norm = sqrt(u);
+    }
   }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(256) void k_gn_stats(KGnStats::Args a) {
+  KGnStats::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+void KGnStats::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_gn_stats, grid, dim3(kThreads), lds, s, a);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -961,8 +1038,7 @@ void launch_gram2(const Dims& d, const double* X, const double* Y, double* C, in
 }
 
 void launch_gamma(const Dims& d, const double* S, double* Gam, hipStream_t s) {
-  hipLaunchKernelGGL(k_gamma, dim3(grid1((int64_t)d.N * d.N * d.R * d.R, 256)), dim3(256), 0, s,
-                     d, S, Gam);
+  dispatch<KGamma>(dim3(grid1((int64_t)d.N * d.N * d.R * d.R, 256)), 0, s, {d, S, Gam});
 }
 
 void launch_ycore(const Dims& d, const double* Gam, const double* B, double* Y, const CgState* st,
@@ -995,8 +1071,7 @@ void launch_to64(const Dims& d, const PerMode<const void*>& src, int dtype, doub
 
 void launch_fin_grad(const Dims& d, int nblocks, const double* red_nrm, CgState* st, double eps,
                      double* gsum_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_grad, dim3(1), dim3(256), 0, s, d.N, nblocks, red_nrm, st, eps,
-                     gsum_out);
+  dispatch<KFinGrad>(dim3(1), 0, s, {d.N, nblocks, red_nrm, st, eps, gsum_out});
 }
 
 void launch_state_reset(CgState* st, hipStream_t s) {
@@ -1006,34 +1081,50 @@ void launch_state_reset(CgState* st, hipStream_t s) {
 void launch_gn_apply(const Dims& d, double* A64, const double* V, const PerMode<void*>& Aout,
                      int dtype, double* red_nrm, const CgState* st, hipStream_t s) {
   dim3 grid(rowmm_blocks(d), d.N);
-  hipLaunchKernelGGL(k_gn_apply, grid, dim3(256), 0, s, d, A64, V, Aout, dtype, red_nrm, st);
+  dispatch<KGnApply>(grid, 0, s, {d, A64, V, Aout, dtype, red_nrm, st});
 }
 
 void launch_gn_stats(const Dims& d, int nblocks, const double* red_nrm, const CgState* st,
                      cp_gn_stats* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gn_stats, dim3(1), dim3(256), 0, s, d.N, nblocks, red_nrm, st, out);
+  dispatch<KGnStats>(dim3(1), 0, s, {d.N, nblocks, red_nrm, st, out});
 }
 
 // Damping schedule of Section 3.2 on the device: state = {value, lower, upper, mu, decreasing}.
 // One thread; the same IEEE operations as the host schedule, so both give the same sequence.
-__global__ void k_damping_advance(double* state) {
-  if (threadIdx.x != 0) return;
-  double v = state[0];
-  const double lower = state[1], upper = state[2], mu = state[3];
-  bool dec = state[4] != 0.0;
-  if (dec) {
-    v = v / mu;
-    if (v <= lower) dec = false;
-  } else {
-    v = v * mu;
-    if (v >= upper) dec = true;
+struct KDampingAdvance {
+  struct Args {
+    double* state;
+  };
+  static constexpr int kThreads = 64, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3, dim3) {
+    if (threadIdx.x != 0) return;
+    double* state = a.state;
+    double v = state[0];
+    const double lower = state[1], upper = state[2], mu = state[3];
+    bool dec = state[4] != 0.0;
+    if (dec) {
+      v = v / mu;
+      if (v <= lower) dec = false;
+    } else {
+      v = v * mu;
+      if (v >= upper) dec = true;
+    }
+    state[0] = v;
+    state[4] = dec ? 1.0 : 0.0;
   }
-  state[0] = v;
-  state[4] = dec ? 1.0 : 0.0;
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(64) void k_damping_advance(KDampingAdvance::Args a) {
+  KDampingAdvance::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+void KDampingAdvance::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_damping_advance, grid, dim3(kThreads), lds, s, a);
 }
 
 void launch_damping_advance(double* state, hipStream_t s) {
-  hipLaunchKernelGGL(k_damping_advance, dim3(1), dim3(64), 0, s, state);
+  dispatch<KDampingAdvance>(dim3(1), 0, s, {state});
 }
 
 void launch_timestamp(int64_t* out, hipStream_t s) {

@@ -5,6 +5,7 @@
 //                 (the gradient G = A Gamma(n,n) - M of Algorithm 1, the ALS solve
 //                 M P_inv(n), and the rows of the implicit product of eq. (7)), with per-block
 //                 partial sums of <Out, D> and ||Out||^2 for the scalar reductions.
+#include "batch.h"
 #include "mfma64.h"
 
 namespace cpgn {
@@ -14,16 +15,15 @@ constexpr int kGramSteps = 16;   // 4-row MFMA steps loaded per batch and wavefr
 
 // grid: (TB * TB, 1, number of modes), 512 threads. The eight wavefronts split the rows of the
 // mode; their partial tiles are added in wavefront order.
-__global__ __launch_bounds__(512) void k_gram_mfma(Dims d, const double* __restrict__ Xp,
-                                                   const double* __restrict__ Yp,
-                                                   double* __restrict__ C, int mode_only,
-                                                   const CgState* st) {
+__device__ __forceinline__ void gram_body(const Dims& d, const double* __restrict__ Xp,
+                                          const double* __restrict__ Yp, double* __restrict__ C,
+                                          int mode_only, const CgState* st, dim3 bid) {
   if (st && st->done) return;   // written only by earlier launches
   __shared__ double part[kGramWaves][64][4];
-  const int n = mode_only >= 0 ? mode_only : blockIdx.z;
+  const int n = mode_only >= 0 ? mode_only : bid.z;
   const int R = d.R, TB = (R + 15) / 16;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
-  const int r0 = 16 * (blockIdx.x / TB), z0 = 16 * (blockIdx.x % TB);
+  const int r0 = 16 * (bid.x / TB), z0 = 16 * (bid.x % TB);
   const int64_t s = d.s[n], base = d.off[n];
   const int64_t nsteps = (s + 3) / 4;
   const int64_t per = (nsteps + kGramWaves - 1) / kGramWaves;
@@ -57,11 +57,33 @@ __global__ __launch_bounds__(512) void k_gram_mfma(Dims d, const double* __restr
   }
 }
 
+struct KGram {
+  struct Args {
+    Dims d;
+    const double* X;
+    const double* Y;
+    double* C;
+    int mode_only;
+    const CgState* st;
+  };
+  static constexpr int kThreads = 512, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3) {
+    gram_body(a.d, a.X, a.Y, a.C, a.mode_only, a.st, bid);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__global__ __launch_bounds__(512) void k_gram_mfma(KGram::Args a) { KGram::run(a, CPGN_BID, CPGN_GDIM); }
+
+void KGram::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_gram_mfma, grid, dim3(kThreads), lds, s, a);
+}
+
 void launch_gram_mfma(const Dims& d, const double* X, const double* Y, double* C, int mode_only,
                       const CgState* st, hipStream_t s) {
   const int TB = (d.R + 15) / 16;
   dim3 grid(TB * TB, 1, mode_only >= 0 ? 1 : d.N);
-  hipLaunchKernelGGL(k_gram_mfma, grid, dim3(512), 0, s, d, X, Y, C, mode_only, st);
+  dispatch<KGram>(grid, 0, s, {d, X, Y, C, mode_only, st});
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -70,18 +92,19 @@ void launch_gram_mfma(const Dims& d, const double* X, const double* Y, double* C
 // suffice for any number of rows.
 // ---------------------------------------------------------------------------------------------
 template <int KB, bool EVEN>
-__global__ __launch_bounds__(256) void k_rowmm_mfma(Dims d, RowMM a, const CgState* st) {
+__device__ __forceinline__ void rowmm_body(const Dims& d, const RowMM& a, const CgState* st,
+                                           dim3 bid, dim3 gdim) {
   constexpr int KQ = 4 * KB;
   constexpr int KP = 16 * KB;
   __shared__ double T1s[slice_elems(KP)];   // T1(n)[k][c0 + c]
   __shared__ double T2s[slice_elems(KP)];   // T2(n)[c0 + c][k]
   if (st && (st->done || (a.skip_if_status && st->status != 0))) return;   // earlier launches
-  const int n = a.mode_only >= 0 ? a.mode_only : blockIdx.y;
+  const int n = a.mode_only >= 0 ? a.mode_only : bid.y;
   const int R = d.R, TB = (R + 15) / 16;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, m = lane & 15, g = lane >> 4;
-  const int ct = blockIdx.x % TB, c0 = ct * 16;
+  const int ct = bid.x % TB, c0 = ct * 16;
   const int64_t s = d.s[n], base = d.off[n];
-  const int64_t nrb = (s + 63) / 64, rstride = gridDim.x / TB;
+  const int64_t nrb = (s + 63) / 64, rstride = gdim.x / TB;
   const double* T1 = a.t1 ? a.t1 + n * a.t1_stride : nullptr;
   const double* T2 = a.t2 ? a.t2 + n * a.t2_stride : nullptr;
 #pragma unroll
@@ -99,7 +122,7 @@ __global__ __launch_bounds__(256) void k_rowmm_mfma(Dims d, RowMM a, const CgSta
   __syncthreads();
   const bool colok = c0 + m < R;
   double dot = 0.0, nrm = 0.0;
-  for (int64_t rb = blockIdx.x / TB; rb < nrb; rb += rstride) {
+  for (int64_t rb = bid.x / TB; rb < nrb; rb += rstride) {
     const int64_t k0 = rb * 64 + wv * 16;
     const bool rowok = k0 + m < s;
     dv4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -137,10 +160,34 @@ __global__ __launch_bounds__(256) void k_rowmm_mfma(Dims d, RowMM a, const CgSta
     double v2[2] = {dot, nrm};
     block_sum(v2);
     if (t == 0) {
-      if (a.red_dot) a.red_dot[n * kRedSlots + blockIdx.x] = v2[0];
-      if (a.red_nrm) a.red_nrm[n * kRedSlots + blockIdx.x] = v2[1];
+      if (a.red_dot) a.red_dot[n * kRedSlots + bid.x] = v2[0];
+      if (a.red_nrm) a.red_nrm[n * kRedSlots + bid.x] = v2[1];
     }
   }
+}
+
+template <int KB, bool EVEN>
+struct KRowmm {
+  struct Args {
+    Dims d;
+    RowMM a;
+    const CgState* st;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& x, dim3 bid, dim3 gdim) {
+    rowmm_body<KB, EVEN>(x.d, x.a, x.st, bid, gdim);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& x);
+};
+
+template <int KB, bool EVEN>
+__global__ __launch_bounds__(256) void k_rowmm_mfma(typename KRowmm<KB, EVEN>::Args x) {
+  KRowmm<KB, EVEN>::run(x, CPGN_BID, CPGN_GDIM);
+}
+
+template <int KB, bool EVEN>
+void KRowmm<KB, EVEN>::direct(dim3 grid, size_t lds, hipStream_t s, const Args& x) {
+  hipLaunchKernelGGL((k_rowmm_mfma<KB, EVEN>), grid, dim3(kThreads), lds, s, x);
 }
 
 // Partial-sum slots per mode used by k_rowmm_mfma: TB column tiles x up to kRedSlots / TB row
@@ -156,8 +203,8 @@ int rowmm_mfma_blocks(const Dims& d) {
 template <int KB>
 static void launch_rowmm_kb(const Dims& d, const RowMM& a, const CgState* st, hipStream_t s) {
   dim3 grid(rowmm_mfma_blocks(d), a.mode_only >= 0 ? 1 : d.N);
-  if (d.R % 2 == 0) hipLaunchKernelGGL((k_rowmm_mfma<KB, true>), grid, dim3(256), 0, s, d, a, st);
-  else hipLaunchKernelGGL((k_rowmm_mfma<KB, false>), grid, dim3(256), 0, s, d, a, st);
+  if (d.R % 2 == 0) dispatch<KRowmm<KB, true>>(grid, 0, s, {d, a, st});
+  else dispatch<KRowmm<KB, false>>(grid, 0, s, {d, a, st});
 }
 
 // R <= 128 only.

@@ -17,7 +17,7 @@
 // wavefronts of a workgroup are summed through LDS in a fixed order and each workgroup writes
 // one partial tile; a second kernel adds the partials in a fixed order in FP64, so results
 // are bitwise reproducible.
-#include "cpgn_internal.h"
+#include "batch.h"
 
 namespace cpgn {
 
@@ -153,7 +153,7 @@ __host__ __device__ __forceinline__ int64_t owner_split(int64_t t, int64_t nitem
 }
 
 template <typename T, bool CASE_B, int MB, int NB, bool VEC, bool DT>
-__device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
+__device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a, dim3 bid) {
   // FP64 with many column blocks keeps a single F buffer (registers); F is L2-resident.
   constexpr bool PF = sizeof(T) == 4 || NB <= 4;
   typedef typename Mfma<T>::v4 v4;
@@ -161,8 +161,8 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, m = lane & 15;
-  const int split = blockIdx.x * 4 + wave;
-  const int64_t rt = a.rt0 + blockIdx.y;
+  const int split = bid.x * 4 + wave;
+  const int64_t rt = a.rt0 + bid.y;
   const int64_t j0 = rt * 16 * MB;
   const int64_t it0 = a.nitems * split / a.nsplit;
   const int64_t it1 = a.nitems * (split + 1) / a.nsplit;
@@ -337,7 +337,7 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
   }
   __syncthreads();
   if (wave == 0) {
-    T* P = (T*)a.part + (int64_t)blockIdx.x * a.Jpad * a.Rp;
+    T* P = (T*)a.part + (int64_t)bid.x * a.Jpad * a.Rp;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -359,13 +359,37 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs& a) {
 // twice the registers), also two wavefronts per SIMD.
 template <typename T, bool CASE_B, int MB, int NB, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_mttkrp(MttkrpArgs a) {
-  mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a);
+  mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a, CPGN_BID);
 }
 
 template <typename T, int MB, int NB>
 __global__ __launch_bounds__(256, 2) void k_mttkrp_tree(MttkrpArgs a) {
-  mttkrp_body<T, false, MB, NB, true, true>(a);
+  mttkrp_body<T, false, MB, NB, true, true>(a, CPGN_BID);
 }
+
+template <typename T, bool CASE_B, int MB, int NB, bool VEC>
+struct KMttkrp {
+  using Args = MttkrpArgs;
+  static constexpr int kThreads = 256, kMinBlocks = 2;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3) {
+    mttkrp_body<T, CASE_B, MB, NB, VEC, false>(a, bid);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+    hipLaunchKernelGGL((k_mttkrp<T, CASE_B, MB, NB, VEC>), grid, dim3(kThreads), lds, s, a);
+  }
+};
+
+template <typename T, int MB, int NB>
+struct KMttkrpTree {
+  using Args = MttkrpArgs;
+  static constexpr int kThreads = 256, kMinBlocks = 2;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3) {
+    mttkrp_body<T, false, MB, NB, true, true>(a, bid);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+    hipLaunchKernelGGL((k_mttkrp_tree<T, MB, NB>), grid, dim3(kThreads), lds, s, a);
+  }
+};
 
 // M[j, r] = sum over partial tiles, in FP64, in a fixed order. A workgroup of 16 wavefronts owns
 // 64 consecutive outputs (flattened over j, r < R; one coalesced load per tile and wavefront);
@@ -374,14 +398,14 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp_tree(MttkrpArgs a) {
 constexpr int kRedWaves = 16;
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_mttkrp_reduce(const T* __restrict__ part, int nparts,
-                                                        int64_t Jpad, int Rp, int64_t J, int R,
-                                                        double* __restrict__ m64, void* mout,
-                                                        int mout_dtype) {
+__device__ __forceinline__ void mttkrp_reduce_body(const T* __restrict__ part, int nparts,
+                                                   int64_t Jpad, int Rp, int64_t J, int R,
+                                                   double* __restrict__ m64, void* mout,
+                                                   int mout_dtype, dim3 bid) {
   __shared__ double sh[kRedWaves][kWave];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = J * R;
-  const int64_t idx = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t idx = (int64_t)bid.x * kWave + lane;
   const bool ok = idx < n;
   const int64_t j = ok ? idx / R : 0;
   const int r = ok ? (int)(idx - j * R) : 0;
@@ -408,6 +432,37 @@ __global__ __launch_bounds__(1024) void k_mttkrp_reduce(const T* __restrict__ pa
       }
     }
   }
+}
+
+template <typename T>
+struct KMttReduce {
+  struct Args {
+    const T* part;
+    int nparts;
+    int64_t Jpad;
+    int Rp;
+    int64_t J;
+    int R;
+    double* m64;
+    void* mout;
+    int mout_dtype;
+  };
+  static constexpr int kThreads = 1024, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3) {
+    mttkrp_reduce_body<T>(a.part, a.nparts, a.Jpad, a.Rp, a.J, a.R, a.m64, a.mout, a.mout_dtype,
+                          bid);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mttkrp_reduce(typename KMttReduce<T>::Args a) {
+  KMttReduce<T>::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+template <typename T>
+void KMttReduce<T>::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_mttkrp_reduce<T>, grid, dim3(kThreads), lds, s, a);
 }
 
 static unsigned reduce_grid(int64_t J, int R) { return (unsigned)((J * R + kWave - 1) / kWave); }
@@ -444,10 +499,10 @@ __device__ __forceinline__ double src_at(const PrepArgs& a, int mode, int64_t i,
 }
 
 template <typename T>
-__global__ void k_prepare(PrepArgs a) {
+__device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 gdim) {
   const int64_t total = a.seg[a.N + 3];
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t idx = bid.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gdim.x * blockDim.x) {
     if (idx < a.seg[a.N]) {
       int mode = 0;
       while (idx >= a.seg[mode + 1]) ++mode;
@@ -514,6 +569,26 @@ __global__ void k_prepare(PrepArgs a) {
   }
 }
 
+template <typename T>
+struct KPrepare {
+  using Args = PrepArgs;
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3 gdim) {
+    prepare_body<T>(a, bid, gdim);
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prepare(PrepArgs a) {
+  prepare_body<T>(a, CPGN_BID, CPGN_GDIM);
+}
+
+template <typename T>
+void KPrepare<T>::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_prepare<T>, grid, dim3(kThreads), lds, s, a);
+}
+
 // ------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------
@@ -558,7 +633,7 @@ static void launch_nb(int NB, dim3 grid, hipStream_t st, const MttkrpArgs& a) {
   switch (NB) {
 #define CPGN_NB(k)                                                                         \
   case k:                                                                                  \
-    hipLaunchKernelGGL((k_mttkrp<T, CASE_B, MB, k, VEC>), grid, dim3(256), 0, st, a); \
+    dispatch<KMttkrp<T, CASE_B, MB, k, VEC>>(grid, 0, st, a);                          \
     break;
     CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4) CPGN_NB(5) CPGN_NB(6) CPGN_NB(7) CPGN_NB(8)
 #undef CPGN_NB
@@ -570,7 +645,7 @@ template <typename T, int MB>
 static void launch_tree_nb(int NB, dim3 grid, hipStream_t st, const MttkrpArgs& a) {
   switch (NB) {
 #define CPGN_NB(k)                                                                      \
-  case k: hipLaunchKernelGGL((k_mttkrp_tree<T, MB, k>), grid, dim3(256), 0, st, a); break;
+  case k: dispatch<KMttkrpTree<T, MB, k>>(grid, 0, st, a); break;
     CPGN_NB(1) CPGN_NB(2) CPGN_NB(3) CPGN_NB(4) CPGN_NB(5) CPGN_NB(6) CPGN_NB(7) CPGN_NB(8)
 #undef CPGN_NB
     default: break;
@@ -608,24 +683,67 @@ static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipS
 
 // M(o)[o][r] = sum over row tiles and over the wavefronts that shared o (fixed order).
 template <typename T>
-__global__ void k_dt_reduce(const T* __restrict__ p1, int64_t RT, int64_t O, int64_t HS, int Rp,
-                            int R, int64_t QC, int64_t nitems, int64_t S, double* __restrict__ m64,
-                            void* mout, int mout_dtype) {
+struct KDtReduce {
+  struct Args {
+    const T* p1;
+    int64_t RT, O, HS;
+    int Rp, R;
+    int64_t QC, nitems, S;
+    double* m64;
+    void* mout;
+    int mout_dtype;
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3 gdim);
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+template <typename T>
+__device__ __forceinline__ void KDtReduce<T>::run(const Args& a, dim3 bid, dim3 gdim) {
+  const T* __restrict__ p1 = a.p1;
+  const int64_t RT = a.RT, O = a.O, HS = a.HS, QC = a.QC, nitems = a.nitems, S = a.S;
+  const int Rp = a.Rp, R = a.R;
+  double* __restrict__ m64 = a.m64;
+  void* mout = a.mout;
+  const int mout_dtype = a.mout_dtype;
   const int64_t n = O * R;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t idx = bid.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gdim.x * blockDim.x) {
     const int64_t o = idx / R;
     const int r = (int)(idx - o * R);
     const int64_t h_n = owner_split((o + 1) * QC - 1, nitems, S) - owner_split(o * QC, nitems, S) + 1;
+    // Terms k = rt h_n + h in order; each batch of 8 is loaded before it is added, so the loads
+    // of a batch are in flight together (same sum, same order as one term at a time).
+    const int64_t K = RT * h_n;
     double s = 0.0;
-    for (int64_t rt = 0; rt < RT; ++rt)
-      for (int64_t h = 0; h < h_n; ++h) s += (double)p1[((rt * O + o) * HS + h) * Rp + r];
+    for (int64_t k0 = 0; k0 < K; k0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t k = k0 + u < K ? k0 + u : K - 1;
+        const int64_t rt = k / h_n, h = k - rt * h_n;
+        v[u] = p1[((rt * O + o) * HS + h) * Rp + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < K) s += (double)v[u];
+    }
     if (m64) m64[idx] = s;
     if (mout) {
       if (mout_dtype == CP_F64) ((double*)mout)[idx] = s;
       else ((float*)mout)[idx] = (float)s;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dt_reduce(typename KDtReduce<T>::Args a) {
+  KDtReduce<T>::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+template <typename T>
+void KDtReduce<T>::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_dt_reduce<T>, grid, dim3(kThreads), lds, s, a);
 }
 
 static bool vec_ok(const Plan& p, int mode, const void* X) {
@@ -692,19 +810,19 @@ static int launch_mttkrp_t(const Plan& p, const void* X, int mode, char* ws, dou
     const hipError_t e = hipEventRecord(mk.after, st);
     if (e != hipSuccess) return (int)e;
   }
-  hipLaunchKernelGGL(k_mttkrp_reduce<T>, dim3(reduce_grid(a.J, p.R)), dim3(1024), 0, st,
-                     (const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype);
+  dispatch<KMttReduce<T>>(dim3(reduce_grid(a.J, p.R)), 0, st,
+                          {(const T*)a.part, (int)G.SW, a.Jpad, p.Rp, a.J, p.R, m64, mout, p.dtype});
   if (dt)
-    hipLaunchKernelGGL(k_dt_reduce<T>, dim3(grid_for(G.O * p.R)), dim3(256), 0, st,
-                       (const T*)a.p1, G.RT, G.O, G.HS, p.Rp, p.R, G.QC, G.nitems,
-                       (int64_t)a.nsplit, m64_outer, mout_outer, p.dtype);
+    dispatch<KDtReduce<T>>(dim3(grid_for(G.O * p.R)), 0, st,
+                           {(const T*)a.p1, G.RT, G.O, G.HS, p.Rp, p.R, G.QC, G.nitems,
+                            (int64_t)a.nsplit, m64_outer, mout_outer, p.dtype});
   return (int)hipGetLastError();
 }
 
 void launch_mttkrp_reduce_f32(const float* part, int nparts, int64_t Jpad, int Rp, int64_t J,
                               int R, double* m64, void* mout, int mout_dtype, hipStream_t st) {
-  hipLaunchKernelGGL(k_mttkrp_reduce<float>, dim3(reduce_grid(J, R)), dim3(1024), 0, st, part,
-                     nparts, Jpad, Rp, J, R, m64, mout, mout_dtype);
+  dispatch<KMttReduce<float>>(dim3(reduce_grid(J, R)), 0, st,
+                              {part, nparts, Jpad, Rp, J, R, m64, mout, mout_dtype});
 }
 
 int launch_mttkrp_bf16(const Plan& p, const void* X, int mode, void* ws, double* m64, void* mout,
@@ -879,8 +997,8 @@ int launch_prepare_factors_src(const Plan& p, const void* const* src, int src_dt
     a.seg[p.N + 3] = a.seg[p.N + 2] + a.krp_seg[p.N];
   }
   const int grid = grid_for(a.seg[p.N + 3]);
-  if (p.dtype == CP_F32) hipLaunchKernelGGL(k_prepare<float>, dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(k_prepare<double>, dim3(grid), dim3(256), 0, st, a);
+  if (p.dtype == CP_F32) dispatch<KPrepare<float>>(dim3(grid), 0, st, a);
+  else dispatch<KPrepare<double>>(dim3(grid), 0, st, a);
   return (int)hipGetLastError();
 }
 

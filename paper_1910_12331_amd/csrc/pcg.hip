@@ -27,6 +27,7 @@
 // contraction (K = R padded to 16 KB): its operands are loaded straight from memory into
 // registers, all in one batch, while the shared 16-column slice of the R x R operand goes
 // through LDS.
+#include "batch.h"
 #include "mfma64.h"
 
 namespace cpgn {
@@ -693,8 +694,24 @@ struct CgBatch {
   int n;
 };
 
-__global__ void k_cg_store(CgArgs a, CgArgs* dst) {
-  if (threadIdx.x == 0) *dst = a;
+struct KCgStore {
+  struct Args {
+    CgArgs a;
+    CgArgs* dst;
+  };
+  static constexpr int kThreads = 64, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& x, dim3, dim3) {
+    if (threadIdx.x == 0) *x.dst = x.a;
+  }
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& x);
+};
+
+__global__ __launch_bounds__(64) void k_cg_store(KCgStore::Args x) {
+  KCgStore::run(x, CPGN_BID, CPGN_GDIM);
+}
+
+void KCgStore::direct(dim3 grid, size_t lds, hipStream_t s, const Args& x) {
+  hipLaunchKernelGGL(k_cg_store, grid, dim3(kThreads), lds, s, x);
 }
 
 size_t cg_args_bytes() { return sizeof(CgArgs); }
@@ -705,7 +722,7 @@ void launch_cg_store(const Plan& p, const Dims& d, const double* A64, const doub
                      bool diag_damping, const double* lam_dev, void* dst, hipStream_t s) {
   const CgArgs a = make_cg_args(p, d, A64, gam, pinv, V, R0, R1, Z, W0, W1, Q, B, slots, st,
                                 lambda, diag_damping, lam_dev);
-  hipLaunchKernelGGL(k_cg_store, dim3(1), dim3(64), 0, s, a, (CgArgs*)dst);
+  dispatch<KCgStore>(dim3(1), 0, s, {a, (CgArgs*)dst});
 }
 
 // Problem of this workgroup and its workgroup index within that problem (uniform).

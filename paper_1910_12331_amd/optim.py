@@ -327,16 +327,25 @@ class BatchedGaussNewton:
     for the whole batch on the current stream (three launches per iteration instead of three per
     iteration and problem), and the streams fork again for the updates. The iterates are bitwise
     those of the per-problem steps. With graphs=True as well, the whole batch step (all streams)
-    is captured as one graph."""
+    is captured as one graph.
+
+    With fused=True (implies batch_cg) every part of the step shares launches: a batch program
+    (api.GNBatchProgram, cp_gn_batch_create) records each problem's launches before and after CG
+    once, and a step runs one launch per kernel and position in the step for all problems, on
+    the current stream, with the damping schedules advanced on the device. Same iterates again;
+    with graphs=True the program's launches are captured as one graph."""
 
     def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8,
-                 graphs: bool = False, batch_cg: bool = False):
+                 graphs: bool = False, batch_cg: bool = False, fused: bool = False):
         cfg = config or GNConfig()
         if graphs and cfg.line_search is not None:
             raise ValueError("graph replay covers the plain Gauss-Newton step only")
+        batch_cg = batch_cg or fused
         if batch_cg and (cfg.line_search is not None or cfg.preconditioner != "inverse"):
             raise ValueError("batched CG covers the plain step with the explicit inverse")
         self.batch_cg = batch_cg
+        self.fused = fused
+        self.program = None
         self.cfg = cfg
         torch.cuda.current_stream().synchronize()   # inputs were written on the current stream
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
@@ -346,10 +355,27 @@ class BatchedGaussNewton:
                 self.opts.append(GaussNewton(X, A, replace(cfg, schedule=None)))
         self.graphs = None
         self.batch_graph = None
-        if graphs and batch_cg:
+        if fused:
+            self._build_program(graphs)
+        elif graphs and batch_cg:
             self._capture_batch()
         elif graphs:
             self._capture()
+
+    def _build_program(self, graphs: bool):
+        self.lam_state = [opt.schedule.to_device(opt.X.device) for opt in self.opts]
+        torch.cuda.synchronize()
+        self.program = api.GNBatchProgram(
+            [(opt.X, opt.A, opt.ws, opt.stats_buf, st) for opt, st in zip(self.opts, self.lam_state)],
+            cg_tol=self.cfg.cg_tol, cg_maxiter=self.cfg.cg_maxiter, damping=self.cfg.damping)
+        self.graphs = []   # the schedules live on the device (see synchronize)
+        if graphs:
+            cap = torch.cuda.Stream()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                self.program.step()
+            self.batch_graph = g
+            torch.cuda.synchronize()
 
     def _batch_step(self, lam_states=None, stamps=None):
         """Enqueue one batched step of every problem: begin on each problem's stream, CG of all
@@ -439,14 +465,18 @@ class BatchedGaussNewton:
         if self.batch_cg:
             if timed:
                 raise ValueError("a batched step has one span per problem: use stamps")
+            if self.fused and stamps is not None:
+                raise ValueError("stamps are not part of a batch program")
             if self.batch_graph is not None:
                 if stamps is not None:
                     raise ValueError("stamps are not part of the captured batch graph")
                 self.batch_graph.replay()
+            elif self.program is not None:
+                self.program.step()
             else:
                 self._batch_step(stamps=stamps)
             for opt in self.opts:
-                if self.batch_graph is None:
+                if self.batch_graph is None and self.program is None:
                     opt.schedule.advance()
                 opt.steps += 1
             return []

@@ -160,6 +160,28 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_gn_step_begin(C.byref(p), None, A, C.byref(good0), None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_step_end(C.byref(p), A, None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_device_clock_hz(None) == L.CP_EINVAL
+    # batch program: argument checks, then the table-size query (recording only, no launch)
+    n2 = 2
+    probs2 = (L.CpProblem * n2)(p, p)
+    X2 = (C.c_void_p * n2)(0x10000, 0x11000)
+    A2 = (C.c_void_p * (n2 * L.MAX_ORDER))(*([0x1000, 0x2000, 0x3000] + [0] * (L.MAX_ORDER - 3)) * 2)
+    st2 = (C.c_void_p * n2)(0x50000, 0x51000)
+    ws2 = (C.c_void_p * n2)(0x40000, 0x40000 + (need + 4095) // 4096 * 4096)
+    nb2 = (C.c_size_t * n2)(need, need)
+    needed, h = C.c_size_t(0), C.c_void_p(None)
+    args = lambda cnt, prm=good0, st=st2: [cnt, probs2, X2, A2, C.byref(prm), None, None, st, ws2,
+                                          nb2, None, 0, C.byref(needed), C.byref(h)]
+    assert lib.cp_gn_batch_create(*args(0)) == L.CP_EINVAL
+    assert lib.cp_gn_batch_create(*args(n2, st=None)) == L.CP_EINVAL
+    chol = L.CpGnParams(0.0, 1e-3, 20, L.GN_CHOL_PRECOND)
+    assert lib.cp_gn_batch_create(*args(n2, prm=chol)) == L.CP_EUNSUPPORTED
+    assert lib.cp_gn_batch_create(*args(n2)) == L.CP_EWORKSPACE and needed.value > 0
+    assert not h.value   # nothing created
+    assert lib.cp_gn_batch_step(None, None) == L.CP_EINVAL
+    big = L.CpProblem(p.order, 130, p.dims, p.x_dtype, p.f_dtype)
+    probs3 = (L.CpProblem * n2)(big, big)
+    assert lib.cp_gn_batch_create(n2, probs3, X2, A2, C.byref(good0), None, None, st2, ws2, nb2,
+                                  None, 0, C.byref(needed), C.byref(h)) == L.CP_EUNSUPPORTED
     # storage conversion: negative count, null pointers
     assert lib.cp_tensor_to_bf16(X, -1, 0, M, None) == L.CP_EINVAL
     assert lib.cp_tensor_to_bf16(None, 10, 0, M, None) == L.CP_EINVAL

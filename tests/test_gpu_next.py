@@ -276,6 +276,84 @@ def test_batched_cg_graph_replays_match_eager():
                 assert torch.equal(a, b), k
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_batch_program_steps_match_per_problem_steps(dt):
+    """The batch program (cp_gn_batch_create / cp_gn_batch_step: every part of the step in shared
+    launches) gives bitwise the factors, stats and device damping schedules of each problem's own
+    cp_gn_step over three steps, for uneven problems (modes 60..200 with and without vector
+    loads, ranks 8..64), and the first step matches the oracle."""
+    from workloads import batched_problems
+    probs = batched_problems(7)
+    mk = lambda: [(torch.tensor(p.x, dtype=dt, device="cuda"),
+                   [torch.tensor(a, dtype=dt, device="cuda") for a in p.init]) for p in probs]
+    ref = [P.GaussNewton(X, A) for X, A in mk()]
+    bat = P.BatchedGaussNewton(mk(), fused=True)
+    assert bat.program is not None
+    for k in range(3):
+        for g in ref:
+            g.step()
+        bat.step()
+        bat.synchronize()
+        torch.cuda.synchronize()
+        for g, ob in zip(ref, bat.opts):
+            assert g.stats() == ob.stats(), k
+            assert ob.schedule.value == g.schedule.value, k
+            for a, b in zip(g.A, ob.A):
+                assert torch.equal(a, b), k
+        if k == 0:
+            for p, ob in zip(probs[:2], bat.opts[:2]):
+                xs = p.x.astype(np.float32).astype(np.float64) if dt == torch.float32 else p.x
+                As = [a.astype(np.float32).astype(np.float64) if dt == torch.float32 else a
+                      for a in p.init]
+                r, _ = O.gn_step(xs, As, 1e-4, 0.0, ob.stats()["cg_iters"])
+                for a, b in zip(ob.A, r):
+                    assert rel(a.double().cpu().numpy(), b) < (1e-4 if dt == torch.float32 else 1e-9)
+
+
+def test_batch_program_graph_replays_match_eager():
+    """The batch program captured as one graph and replayed three times, with eager work between
+    the replays, gives bitwise the eager program's iterates and schedules."""
+    from workloads import batched_problems
+    probs = batched_problems(5)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init]) for p in probs]
+    eager = P.BatchedGaussNewton(mk(), fused=True)
+    graph = P.BatchedGaussNewton(mk(), fused=True, graphs=True)
+    for k in range(3):
+        eager.step()
+        eager.synchronize()
+        graph.step()
+        graph.synchronize()
+        _ = graph.residuals()
+        torch.cuda.synchronize()
+        for oe, og in zip(eager.opts, graph.opts):
+            assert og.schedule.value == oe.schedule.value
+            assert og.stats() == oe.stats()
+            for a, b in zip(oe.A, og.A):
+                assert torch.equal(a, b), k
+
+
+def test_batch_program_many_problems_split_into_groups():
+    """More problems than one batched launch holds (130 > 128 members): the program splits its
+    launches and the CG batches, and every problem still matches its own step bitwise."""
+    rng = np.random.default_rng(5)
+    shapes = [(6 + i % 5, 5 + i % 3, 7 + i % 4) for i in range(130)]
+    data = [(rng.standard_normal(sh), [rng.standard_normal((n, 3)) for n in sh]) for sh in shapes]
+    mk = lambda: [(torch.tensor(x, dtype=torch.float64, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float64, device="cuda") for a in A]) for x, A in data]
+    ref = [P.GaussNewton(X, A) for X, A in mk()]
+    bat = P.BatchedGaussNewton(mk(), fused=True)
+    for g in ref:
+        g.step()
+    bat.step()
+    bat.synchronize()
+    torch.cuda.synchronize()
+    for g, ob in zip(ref, bat.opts):
+        assert g.stats() == ob.stats()
+        for a, b in zip(g.A, ob.A):
+            assert torch.equal(a, b)
+
+
 # ------------------------------------------------------------------ graph-replayable steps
 def test_device_damping_schedule_matches_host():
     """cp_damping_advance gives bitwise the host schedule's sequence (both directions)."""
