@@ -66,9 +66,8 @@ def parse():
                     help="only time the oracle's MTTKRP, GN step, ALS sweep and residual at "
                          "300^3 R=50 and 400^3 R=100 on the host and print them as JSON")
     ap.add_argument("--profile-batched", action="store_true",
-                    help="only run the 64-problem batched workload with batched CG (8 streams, one "
-                         "graph per batch step): --warmup then --steps batch steps (for kernel "
-                         "traces)")
+                    help="only run the 64-problem batched workload as a batch program replayed "
+                         "from one graph: --warmup then --steps batch steps (for kernel traces)")
     ap.add_argument("--profile-step", action="store_true",
                     help="only run the headline loop (--warmup then --steps Gauss-Newton steps with "
                          "their residuals and run restarts) and exit (for kernel traces)")
@@ -583,8 +582,8 @@ def main():
         devs = [(torch.tensor(q.x, dtype=torch.float32, device="cuda"),
                  [torch.tensor(a, dtype=torch.float32, device="cuda") for a in q.init])
                 for q in batched_problems(64)]
-        bgn = P.BatchedGaussNewton(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=8,
-                                   graphs=True, batch_cg=True)
+        bgn = P.BatchedGaussNewton(devs, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), graphs=True,
+                                   fused=True)
         for _ in range(args.warmup):
             bgn.step()
         bgn.synchronize()
@@ -594,7 +593,7 @@ def main():
             bgn.synchronize()
         ms = (time.perf_counter() - t0) / max(1, args.steps) * 1e3
         print(json.dumps({"profile_batched": f"{args.warmup} + {args.steps} batch steps of 64 "
-                          "problems, batched CG, 8 streams, one graph per batch step",
+                          "problems, batch program replayed from one graph",
                           "ms_per_batch_step": ms}), flush=True)
         del bgn, devs
         shutdown()
@@ -799,23 +798,29 @@ def main():
                                   stream_counts=(1, 2, 4, 8, 16), steps=3)
         hz = P.device_clock_hz()
         bs = args.batched_streams
-        configs = [(1, False, False), (bs, False, False), (bs, True, False), (bs, False, True),
-                   (bs, True, True)]
-        if (tune.n_streams, tune.graphs, tune.batch_cg) not in configs:
-            configs.append((tune.n_streams, tune.graphs, tune.batch_cg))
-        cname = lambda ns, g, b: f"streams_{ns}" + ("_graphs" if g else "") + ("_batchcg" if b else "")
-        for ns, graphs, bcg in configs:
+        configs = [(1, False, False, False), (bs, False, False, False), (bs, True, False, False),
+                   (bs, False, True, False), (bs, True, True, False), (1, False, True, True),
+                   (1, True, True, True)]
+        tk = (tune.n_streams, tune.graphs, tune.batch_cg, tune.fused)
+        if tk not in configs:
+            configs.append(tk)
+
+        def cname(ns, g, b, f):
+            if f:
+                return "program" + ("_graph" if g else "")
+            return f"streams_{ns}" + ("_graphs" if g else "") + ("_batchcg" if b else "")
+        for ns, graphs, bcg, fus in configs:
             cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
             torch.cuda.synchronize()
             bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns,
-                                       graphs=graphs, batch_cg=bcg)
+                                       graphs=graphs, batch_cg=bcg, fused=fus)
             for _ in range(2):
                 bgn.step()
             bgn.synchronize()
             # per-problem step latency from device timestamps (the device clock written by a
             # one-thread kernel on the problem's stream right before and after its step; not
-            # part of the single graph of a batched-CG step)
-            stamped = not (graphs and bcg)
+            # part of the single graph of a batched-CG step or of a batch program)
+            stamped = not (graphs and bcg) and not fus
             stamps = torch.zeros((5, 2 * len(devs)), dtype=torch.int64, device="cuda")
             t0 = time.perf_counter()
             for k in range(5):
@@ -828,9 +833,9 @@ def main():
                 per = ((ticks[:, :, 1] - ticks[:, :, 0]) / hz * 1e3).ravel()
                 rec.update(step_ms_p50=float(np.percentile(per, 50)),
                            step_ms_p99=float(np.percentile(per, 99)))
-            res[cname(ns, graphs, bcg)] = rec
+            res[cname(ns, graphs, bcg, fus)] = rec
             del bgn, cur
-        kt = cname(tune.n_streams, tune.graphs, tune.batch_cg)
+        kt = cname(*tk)
         res["autotuned"] = dict(choice=kt, problem_steps_per_s=res[kt]["problem_steps_per_s"],
                                 sweep_problem_steps_per_s={
                                     cname(*k): v for k, v in tune.table.items()},
@@ -842,12 +847,17 @@ def main():
         batched = dict(workload="64 FP32 problems, modes U{60..200}, rank U{8,16,32,64}, noise 1e-4",
                        note="_graphs: each problem's GN step and damping update replayed from a "
                             "captured HIP graph; _batchcg: CG of all problems in shared launches "
-                            "(with _graphs: the whole batch step as one graph); "
+                            "(with _graphs: the whole batch step as one graph); program: the batch "
+                            "program (every part of the step in shared launches, one stream; "
+                            "_graph: replayed from one captured graph); "
                             "step_ms_p50/p99: per-problem step latency from "
                             f"device timestamps ({hz} Hz clock), 5 batch steps", **res)
-        kb, kg = cname(bs, False, False), cname(bs, True, False)
-        kc, kcg = cname(bs, False, True), cname(bs, True, True)
-        log(f"[bench] batched workload: {res[kcg]['problem_steps_per_s']:.0f} problem-steps/s on "
+        kb, kg = cname(bs, False, False, False), cname(bs, True, False, False)
+        kc, kcg = cname(bs, False, True, False), cname(bs, True, True, False)
+        kp, kpg = cname(1, False, True, True), cname(1, True, True, True)
+        log(f"[bench] batched workload: batch program {res[kpg]['problem_steps_per_s']:.0f} "
+            f"problem-steps/s from one graph, {res[kp]['problem_steps_per_s']:.0f} eagerly; "
+            f"{res[kcg]['problem_steps_per_s']:.0f} on "
             f"{bs} streams with batched CG and one graph per batch step, "
             f"{res[kc]['problem_steps_per_s']:.0f} with batched CG eagerly, "
             f"{res[kg]['problem_steps_per_s']:.0f} with per-problem graphs, "

@@ -498,8 +498,10 @@ __device__ __forceinline__ double src_at(const PrepArgs& a, int mode, int64_t i,
                                : (double)((const float*)a.src[mode])[i * a.R + r];
 }
 
-template <typename T>
-__device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 gdim) {
+// I: index type of the element arithmetic (32-bit when every index fits, which makes the
+// divisions by Rp and NBt several times cheaper; same values either way).
+template <typename T, typename I>
+__device__ __forceinline__ void prepare_impl(const PrepArgs& a, dim3 bid, dim3 gdim) {
   const int64_t total = a.seg[a.N + 3];
   for (int64_t idx = bid.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gdim.x * blockDim.x) {
@@ -507,7 +509,7 @@ __device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 g
       int mode = 0;
       while (idx >= a.seg[mode + 1]) ++mode;
       const int64_t e = idx - a.seg[mode];
-      const int64_t i = e / a.Rp;
+      const int64_t i = (int64_t)((I)e / (I)a.Rp);
       const int c = (int)(e - i * a.Rp);
       const double v = c < a.R ? src_at<T>(a, mode, i, c) : 0.0;
       ((T*)a.apad[mode])[e] = (T)v;
@@ -520,8 +522,8 @@ __device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 g
         const int t = (int)(e & 3);
         const int lane = (int)((e >> 2) & 63);
         const int64_t rest = e >> 8;
-        const int cb = (int)(rest % a.NBt);
-        const int64_t chunk = rest / a.NBt;
+        const int64_t chunk = (int64_t)((I)rest / (I)a.NBt);
+        const int cb = (int)(rest - chunk * a.NBt);
         const int64_t row = 16 * chunk + 4 * (lane >> 4) + t;
         const int col = 16 * cb + (lane & 15);
         const double v = (row < a.s[q] && col < a.R) ? src_at<T>(a, q, row, col) : 0.0;
@@ -530,8 +532,8 @@ __device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 g
         const int t = (int)(e & 7);
         const int lane = (int)((e >> 3) & 63);
         const int64_t rest = e >> 9;
-        const int cb = (int)(rest % a.NBt);
-        const int64_t chunk = rest / a.NBt;
+        const int64_t chunk = (int64_t)((I)rest / (I)a.NBt);
+        const int cb = (int)(rest - chunk * a.NBt);
         const int64_t row = 32 * chunk + 8 * (lane >> 4) + t;
         const int col = 16 * cb + (lane & 15);
         const float v = (row < a.s[q] && col < a.R) ? (float)src_at<T>(a, q, row, col) : 0.0f;
@@ -543,7 +545,7 @@ __device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 g
       while (e0 >= a.krp_seg[n + 1]) ++n;
       const int64_t e = e0 - a.krp_seg[n];
       const int q = n == a.N - 1 ? a.N - 2 : a.N - 1;
-      const int64_t o = e / a.Rp;
+      const int64_t o = (int64_t)((I)e / (I)a.Rp);
       const int c = (int)(e - o * a.Rp);
       double v = c < a.R ? 1.0 : 0.0;
       if (a.small32) {
@@ -567,6 +569,12 @@ __device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 g
       a.krp[a.krp_dst[n] + e] = (float)v;
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void prepare_body(const PrepArgs& a, dim3 bid, dim3 gdim) {
+  if (a.seg[a.N + 3] < ((int64_t)1 << 31)) prepare_impl<T, uint32_t>(a, bid, gdim);
+  else prepare_impl<T, int64_t>(a, bid, gdim);
 }
 
 template <typename T>
@@ -615,10 +623,13 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   g.QC = (p.s[q] + 15) / 16;
   g.O = p.total / J / p.s[q];
   g.nitems = g.O * g.QC;
-  // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane).
+  // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane), but at
+  // least 16 items per wavefront: with fewer, the first loads of a workgroup, its reduction
+  // through LDS and its partial tile cost more than its products (small modes; many such
+  // problems then share launches in a batch program).
   const int64_t wgs = (int64_t)kNumCU * 2;
   int64_t sw = wgs / g.RT;
-  const int64_t max_sw = (g.nitems + 7) / 8;
+  const int64_t max_sw = (g.nitems + 63) / 64;
   if (sw > max_sw) sw = max_sw;
   if (sw > kRedSlots) sw = kRedSlots;
   if (sw < 1) sw = 1;

@@ -43,8 +43,10 @@ class DampingSchedule:
         return torch.tensor([self.value, self.lower, self.upper, self.mu,
                              1.0 if self.decreasing else 0.0], dtype=torch.float64, device=device)
 
-    def load_device(self, state: torch.Tensor):
-        v = state.cpu().tolist()
+    def load_device(self, state):
+        """Take the state back from its device array (or from the same five values on the
+        host)."""
+        v = state.cpu().tolist() if isinstance(state, torch.Tensor) else list(state)
         self.value, self.lower, self.upper, self.mu = v[0], v[1], v[2], v[3]
         self.decreasing = v[4] != 0.0
 
@@ -362,8 +364,13 @@ class BatchedGaussNewton:
         elif graphs:
             self._capture()
 
+    def _device_states(self):
+        """The problems' damping states as rows of one device array (one copy reads them all)."""
+        self.lam_all = torch.stack([opt.schedule.to_device(opt.X.device) for opt in self.opts])
+        self.lam_state = [self.lam_all[i] for i in range(len(self.opts))]
+
     def _build_program(self, graphs: bool):
-        self.lam_state = [opt.schedule.to_device(opt.X.device) for opt in self.opts]
+        self._device_states()
         torch.cuda.synchronize()
         self.program = api.GNBatchProgram(
             [(opt.X, opt.A, opt.ws, opt.stats_buf, st) for opt, st in zip(self.opts, self.lam_state)],
@@ -423,9 +430,8 @@ class BatchedGaussNewton:
             main.wait_event(join)
 
     def _capture_batch(self):
-        self.lam_state = []
+        self._device_states()
         for opt in self.opts:
-            self.lam_state.append(opt.schedule.to_device(opt.X.device))
             prob = api._problem(opt.X, int(opt.A[0].shape[1]))
             api._ws(prob, api.L.OP_GN_STEP, opt.X.device, opt.ws)
         torch.cuda.synchronize()
@@ -438,10 +444,11 @@ class BatchedGaussNewton:
         torch.cuda.synchronize()
 
     def _capture(self):
-        self.lam_state, self.graphs = [], []
+        self._device_states()
+        self.graphs = []
         for i, opt in enumerate(self.opts):
             s = self.streams[i % len(self.streams)]
-            state = opt.schedule.to_device(opt.X.device)
+            state = self.lam_state[i]
             # allocate the workspace before capture (nothing may be allocated inside it)
             prob = api._problem(opt.X, int(opt.A[0].shape[1]))
             api._ws(prob, api.L.OP_GN_STEP, opt.X.device, opt.ws)
@@ -452,7 +459,6 @@ class BatchedGaussNewton:
                                    stats=opt.stats_buf, ws=opt.ws, damping=self.cfg.damping,
                                    preconditioner=self.cfg.preconditioner)
                 api.damping_advance(state)
-            self.lam_state.append(state)
             self.graphs.append(g)
         torch.cuda.synchronize()
 
@@ -506,8 +512,8 @@ class BatchedGaussNewton:
         for s in self.streams:
             s.synchronize()
         if self.graphs is not None:   # keep the host schedules in step with the device ones
-            for opt, state in zip(self.opts, self.lam_state):
-                opt.schedule.load_device(state)
+            for opt, row in zip(self.opts, self.lam_all.cpu().tolist()):
+                opt.schedule.load_device(row)
 
     def residuals(self):
         out = []
@@ -520,13 +526,14 @@ class BatchedGaussNewton:
 @dataclass
 class BatchedTuning:
     """The launch configuration chosen for a batch: HIP streams, graph replay, batched CG, the
-    throughput it measured and the whole sweep (problem-steps/s per (n_streams, graphs,
-    batch_cg))."""
+    batch program, the throughput it measured and the whole sweep (problem-steps/s per
+    (n_streams, graphs, batch_cg, fused))."""
     n_streams: int
     graphs: bool
     problem_steps_per_s: float
     table: dict
     batch_cg: bool = False
+    fused: bool = False
 
 
 _TUNING_CACHE: dict = {}
@@ -546,10 +553,12 @@ def batch_key(problems) -> tuple:
     return (len(problems), tuple(dtypes), tuple(ranks), tuple(sizes))
 
 
-def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False) -> float:
+def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False,
+                  fused=False) -> float:
     cur = [(X, [a.clone() for a in A]) for X, A in problems]   # the caller's factors stay as is
     torch.cuda.synchronize()
-    bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs, batch_cg=batch_cg)
+    bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs, batch_cg=batch_cg,
+                             fused=fused)
     bgn.step()
     bgn.synchronize()
     torch.cuda.synchronize()
@@ -563,32 +572,40 @@ def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False) ->
 
 def autotune_batched(problems, config: GNConfig | None = None, stream_counts=(1, 2, 4, 8, 16),
                      graphs=(False, True), steps: int = 3, timer=None, cache=_TUNING_CACHE,
-                     batch_cg=(False, True)):
-    """Sweep-based tuning of the batched runner: every (n_streams, graphs, batch_cg) triple runs
-    `steps` Gauss-Newton steps of the whole batch on copies of its factors, timed by the wall
-    clock, and the fastest is returned (the first one on a tie). batch_cg=True (CG of all
-    problems in shared launches) is swept only where it applies (plain step, explicit-inverse
-    preconditioner, ranks <= 128). The result is cached per batch_key, so a batch of a shape seen
-    before is not timed again. The iterates do not depend on the choice (the kernels are
-    deterministic and the batched CG gives the per-problem bits), only the throughput does."""
+                     batch_cg=(False, True), fused=(False, True)):
+    """Sweep-based tuning of the batched runner: every (n_streams, graphs, batch_cg, fused)
+    configuration runs `steps` Gauss-Newton steps of the whole batch on copies of its factors,
+    timed by the wall clock, and the fastest is returned (the first one on a tie). batch_cg=True
+    (CG of all problems in shared launches) is swept only where it applies (plain step,
+    explicit-inverse preconditioner, ranks <= 128); fused=True (the whole step as a batch
+    program, on one stream: n_streams 1) where that applies as well and no tensor is stored in
+    bfloat16. The result is cached per batch_key, so a batch of a shape seen before is not timed
+    again. The iterates do not depend on the choice (the kernels are deterministic and the
+    batched launches give the per-problem bits), only the throughput does."""
     key = batch_key(problems)
     if cache is not None and key in cache:
         return cache[key]
     cfg = config or GNConfig()
     can_batch = (cfg.line_search is None and cfg.preconditioner == "inverse"
                  and max(int(A[0].shape[1]) for _, A in problems) <= 128)
+    can_fuse = can_batch and all(isinstance(X, torch.Tensor) for X, _ in problems)
     timer = timer or _time_batched
     table = {}
+    for g in graphs:
+        for f in fused:
+            if f and can_fuse:
+                table[(1, bool(g), True, True)] = len(problems) * steps / timer(
+                    problems, config, 1, g, steps, True, True)
     for ns in stream_counts:
         for g in graphs:
             for b in batch_cg:
                 if b and not can_batch:
                     continue
-                table[(int(ns), bool(g), bool(b))] = len(problems) * steps / timer(
-                    problems, config, ns, g, steps, bool(b))
+                table[(int(ns), bool(g), bool(b), False)] = len(problems) * steps / timer(
+                    problems, config, ns, g, steps, bool(b), False)
     best = max(table, key=table.get)
     out = BatchedTuning(n_streams=best[0], graphs=best[1], problem_steps_per_s=table[best],
-                        table=table, batch_cg=best[2])
+                        table=table, batch_cg=best[2], fused=best[3])
     if cache is not None:
         cache[key] = out
     return out

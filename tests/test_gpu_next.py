@@ -423,12 +423,13 @@ def test_autotuned_batched_run_matches_single_stream():
     before = [[a.clone() for a in A] for _, A in probs]
     cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20)
     tune = P.autotune_batched(probs, cfg, stream_counts=(1, 4), steps=2, cache={})
-    assert (tune.n_streams, tune.graphs, tune.batch_cg) in tune.table and len(tune.table) == 8
+    key = (tune.n_streams, tune.graphs, tune.batch_cg, tune.fused)
+    assert key in tune.table and len(tune.table) == 10
     for (_, A), B in zip(probs, before):
         assert all(torch.equal(a, b) for a, b in zip(A, B))
     tuned = [(X, [a.clone() for a in A]) for X, A in probs]
     bgn = P.BatchedGaussNewton(tuned, cfg, n_streams=tune.n_streams, graphs=tune.graphs,
-                               batch_cg=tune.batch_cg)
+                               batch_cg=tune.batch_cg, fused=tune.fused)
     for _ in range(3):
         bgn.step()
     bgn.synchronize()

@@ -102,28 +102,38 @@ def test_autotune_batched_picks_fastest_and_caches():
     probs = [(torch.zeros(60, 70, 90), [torch.zeros(60, 8), torch.zeros(70, 8), torch.zeros(90, 8)]),
              (torch.zeros(130, 70, 90), [torch.zeros(130, 40), torch.zeros(70, 40),
                                          torch.zeros(90, 40)])]
-    secs = {(1, False, False): 4.0, (1, True, False): 3.0, (4, False, False): 2.0,
-            (4, True, False): 1.0, (8, False, False): 1.5, (8, True, False): 1.0,
-            (1, False, True): 2.5, (1, True, True): 2.5, (4, False, True): 0.8,
-            (4, True, True): 0.5, (8, False, True): 0.9, (8, True, True): 0.5}
+    secs = {(1, False, False, False): 4.0, (1, True, False, False): 3.0,
+            (4, False, False, False): 2.0, (4, True, False, False): 1.0,
+            (8, False, False, False): 1.5, (8, True, False, False): 1.0,
+            (1, False, True, False): 2.5, (1, True, True, False): 2.5,
+            (4, False, True, False): 0.8, (4, True, True, False): 0.5,
+            (8, False, True, False): 0.9, (8, True, True, False): 0.5,
+            (1, False, True, True): 0.6, (1, True, True, True): 0.5}
     calls = []
 
-    def timer(problems, config, ns, graphs, steps, batch_cg):
-        calls.append((ns, graphs, batch_cg))
+    def timer(problems, config, ns, graphs, steps, batch_cg, fused):
+        calls.append((ns, graphs, batch_cg, fused))
         assert problems is probs and steps == 3
-        return secs[(ns, graphs, batch_cg)]
+        return secs[(ns, graphs, batch_cg, fused)]
 
     cache = {}
     out = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
-    assert (out.n_streams, out.graphs, out.batch_cg) == (4, True, True)   # first of the fastest
-    assert out.problem_steps_per_s == 2 * 3 / 0.5 and len(out.table) == 12
-    assert len(calls) == 12
+    # the first of the fastest (0.5 s) in sweep order: the graphed batch program
+    assert (out.n_streams, out.graphs, out.batch_cg, out.fused) == (1, True, True, True)
+    assert out.problem_steps_per_s == 2 * 3 / 0.5 and len(out.table) == 14
+    assert len(calls) == 14
     again = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
-    assert again is out and len(calls) == 12                  # served from the cache
-    # batched CG is not swept where it does not apply (the Cholesky preconditioner)
+    assert again is out and len(calls) == 14                  # served from the cache
+    # without the batch program the batched CG on 4 streams with graphs wins
+    out1 = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache={},
+                                  fused=(False,))
+    assert (out1.n_streams, out1.graphs, out1.batch_cg, out1.fused) == (4, True, True, False)
+    # neither batched CG nor the batch program is swept where they do not apply (the Cholesky
+    # preconditioner)
     calls.clear()
     cfg = optim.GNConfig(preconditioner="cholesky")
     out2 = optim.autotune_batched(probs, cfg, stream_counts=(1, 4, 8), timer=timer, cache={})
-    assert not out2.batch_cg and len(calls) == 6 and all(not c[2] for c in calls)
+    assert not out2.batch_cg and not out2.fused and len(calls) == 6
+    assert all(not c[2] and not c[3] for c in calls)
     # the bucket: ranks 8 and 40 -> 8 and 64, largest modes 90 and 130 -> 128 and 256
     assert optim.batch_key(probs) == (2, ("torch.float32",), (8, 64), (128, 256))
