@@ -52,6 +52,15 @@ __device__ __forceinline__ int batch_member(const BatchTab& t, int& local) {
 // note for them is expected.)
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
+// The arguments are read in place through a no-alias pointer (the table is never written while
+// kernels run), so the compiler keeps uniform reads scalar and reorders them freely around the
+// body's stores; a private copy would put any array indexed at run time in scratch memory.
+template <class K>
+__device__ __forceinline__ void batched_run(const typename K::Args* __restrict__ a, dim3 bid,
+                                            dim3 gdim) {
+  K::run(*a, bid, gdim);
+}
+
 template <class K>
 __global__ __launch_bounds__(K::kThreads, K::kMinBlocks) void k_batched(BatchTab t) {
   int local;
@@ -59,10 +68,9 @@ __global__ __launch_bounds__(K::kThreads, K::kMinBlocks) void k_batched(BatchTab
   const unsigned char* blk = t.blk[q];
   const uint32_t* g = (const uint32_t*)blk;
   const uint32_t gx = g[0], gy = g[1], gz = g[2];
-  // A private copy: the body's argument reads then cannot alias its own stores.
-  const typename K::Args a = *(const typename K::Args*)(blk + kBatchHeader);
   const uint32_t l = (uint32_t)local;
-  K::run(a, dim3(l % gx, (l / gx) % gy, l / (gx * gy)), dim3(gx, gy, gz));
+  batched_run<K>((const typename K::Args*)(blk + kBatchHeader),
+                 dim3(l % gx, (l / gx) % gy, l / (gx * gy)), dim3(gx, gy, gz));
 }
 #pragma clang diagnostic pop
 
