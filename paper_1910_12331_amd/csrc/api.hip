@@ -28,7 +28,18 @@ void launch_status_out(const CgState*, int32_t*, hipStream_t);
 void launch_timestamp(int64_t*, hipStream_t);
 int spd_inv_supported(int);
 int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
-                   hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr);
+                   hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr,
+                   double* tmp = nullptr);
+int als_supported(int);
+void launch_cgw_zero(const Dims&, double*, const CgState*, hipStream_t);
+void launch_cgw_check(const Dims&, const double*, const double*, CgState*, int, bool,
+                      hipStream_t);
+void launch_cgw_dir(const Dims&, const double*, double*, const CgState*, int, hipStream_t);
+void launch_cgw_damp(const Dims&, const double*, double*, const double*, double, const double*,
+                     bool, double*, const CgState*, hipStream_t);
+void launch_cgw_alpha(const Dims&, const double*, CgState*, int, hipStream_t);
+void launch_cgw_update(const Dims&, double*, double*, const double*, const double*, double*,
+                       const CgState*, hipStream_t);
 int launch_spd_chol(int, const double*, int64_t, double, double*, int64_t, int, int, CgState*,
                     hipStream_t, bool diag_damping, const double* lam_dev);
 void launch_damping_advance(double*, hipStream_t);
@@ -154,7 +165,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_q = take(vec);
   p->off_bp = take((size_t)p->N * RR * 8);
   p->off_y = take((size_t)p->N * RR * 8);
-  p->off_red = take((size_t)2 * p->N * kRedSlots * 8);
+  p->off_red = take((size_t)3 * p->N * kRedSlots * 8);
   p->off_state = take(sizeof(CgState));
   p->off_w1 = take(vec);
   p->off_r1 = take(vec);
@@ -186,7 +197,8 @@ Dims make_dims(const Plan& p) {
 // Pointers into a carved workspace.
 struct Ws {
   char* base;
-  double *m64, *a64, *S, *gam, *pinv, *g, *v, *r, *z, *w, *q, *bp, *y, *red_dot, *red_nrm;
+  double *m64, *a64, *S, *gam, *pinv, *g, *v, *r, *z, *w, *q, *bp, *y, *red_dot, *red_nrm,
+      *red_wq;
   CgState* st;
 };
 
@@ -208,6 +220,7 @@ static Ws carve(const Plan& p, void* ws) {
   w.y = (double*)(w.base + p.off_y);
   w.red_dot = (double*)(w.base + p.off_red);
   w.red_nrm = w.red_dot + (size_t)p.N * kRedSlots;
+  w.red_wq = w.red_nrm + (size_t)p.N * kRedSlots;
   w.st = (CgState*)(w.base + p.off_state);
   return w;
 }
@@ -463,9 +476,48 @@ static void gn_pre_cg(const Plan& p, const Dims& d, const Ws& w, const void* X, 
   if (prm->flags & CP_GN_CHOL_PRECOND)   // Cholesky factors, applied by triangular solves in CG
     launch_spd_chol(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
                     lam_dev);
-  else
+  else   // (above kMaxGnRank the inverse works in global memory, with Y's buffer as scratch)
     launch_spd_inv(p.R, w.gam, (int64_t)(p.N + 1) * RR, lam, w.pinv, RR, 0, p.N, w.st, st, diag,
-                   lam_dev);
+                   lam_dev, w.y);
+}
+
+// CG of Algorithm 2 for R > kMaxGnRank (the fixed-rank CG kernels hold operand rows of up to
+// kMaxGnRank values in registers): the same iteration from the generic product kernels, with
+// the scalars on the device (see the k_cgw_* kernels).
+static void cg_wide(const Plan& p, const Dims& d, const Ws& w, double lam, const double* lam_dev,
+                    bool diag, int maxiter, hipStream_t st) {
+  const int64_t RR = (int64_t)p.R * p.R;
+  launch_cgw_zero(d, w.v, w.st, st);
+  RowMM z{};   // Z = R P_inv and the partials of <Z, R>
+  z.l1 = w.r;
+  z.t1 = w.pinv;
+  z.t1_stride = RR;
+  z.out = w.z;
+  z.dotw = w.r;
+  z.red_dot = w.red_dot;
+  z.mode_only = -1;
+  RowMM q{};   // Q0 = W Gamma(n,n) + A(n) Y(n)^T, eq. (7)
+  q.l1 = w.w;
+  q.t1 = w.gam;
+  q.t1_stride = (int64_t)(p.N + 1) * RR;
+  q.l2 = w.a64;
+  q.t2 = w.y;
+  q.t2_stride = RR;
+  q.out = w.q;
+  q.mode_only = -1;
+  launch_rowmm(d, z, w.st, st);
+  for (int it = 0; it < maxiter; ++it) {
+    launch_cgw_check(d, w.red_dot, w.red_nrm, w.st, it, false, st);
+    launch_cgw_dir(d, w.z, w.w, w.st, it, st);
+    launch_gram2(d, w.a64, w.w, w.bp, -1, w.st, st);
+    launch_ycore(d, w.gam, w.bp, w.y, w.st, st);
+    launch_rowmm(d, q, w.st, st);
+    launch_cgw_damp(d, w.w, w.q, w.gam, lam, lam_dev, diag, w.red_wq, w.st, st);
+    launch_cgw_alpha(d, w.red_wq, w.st, it, st);
+    launch_cgw_update(d, w.v, w.r, w.w, w.q, w.red_nrm, w.st, st);
+    launch_rowmm(d, z, w.st, st);
+  }
+  launch_cgw_check(d, w.red_dot, w.red_nrm, w.st, maxiter, true, st);
 }
 
 static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
@@ -491,9 +543,12 @@ static int gn_step_impl(const cp_problem* prob, const void* X, void* const* A,
   const bool chol = (prm->flags & CP_GN_CHOL_PRECOND) != 0;
   gn_pre_cg(p, d, w, X, A, prm, lam_dev, ws, st);
   // CG: three launches per iteration, scalars kept on the device.
-  launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
-            (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, lam,
-            prm->cg_maxiter, diag, st, lam_dev, chol);
+  if (p.R > kMaxGnRank)
+    cg_wide(p, d, w, lam, lam_dev, diag, prm->cg_maxiter, st);
+  else
+    launch_cg(p, d, w.a64, w.gam, w.pinv, w.v, w.r, (double*)(w.base + p.off_r1), w.z, w.w,
+              (double*)(w.base + p.off_w1), w.q, w.bp, w.base + p.off_slots, w.st, lam,
+              prm->cg_maxiter, diag, st, lam_dev, chol);
   PerMode<void*> aout{};
   for (int n = 0; n < p.N; ++n) aout.p[n] = A[n];
   if (!ls) {
@@ -665,7 +720,7 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
   int rc = make_plan(prob, &p);
   if (rc) return rc;
   if (!X || !(lambda >= 0.0) || !isfinite(lambda)) return CP_EINVAL;
-  if (!spd_inv_supported(p.R)) return CP_EUNSUPPORTED;
+  if (!als_supported(p.R)) return CP_EUNSUPPORTED;
   if ((rc = check_ptrs(p, (const void* const*)A)) || (rc = check_ws(p, ws, ws_bytes))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Dims d = make_dims(p);

@@ -629,4 +629,157 @@ int launch_chol_rows(int R, int64_t s, const double* M, const double* L, const d
   return (int)hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// SPD inverse for R > kMaxGnRank (the matrix no longer fits a workgroup's registers or LDS):
+// Gauss-Jordan in place on P = G(n,n) + lambda D in global memory, blocked by 16 x 16 tiles, two
+// launches per block step k (K = ceil(R / 16) steps). With M = [[D, B], [C, E]] (block k first),
+// one step gives [[D^-1, D^-1 B], [-C D^-1, E - C D^-1 B]]:
+//   k_inv_big_row   one workgroup per tile j of block row k (and mode): inverts D (16 x 16 in LDS,
+//                   Gauss-Jordan on pivots that must be positive, else CP_ENOTSPD), writes the
+//                   new row tile D^-1 P[k][j] (j != k), saves the old column tile C[j] = P[j][k]
+//                   and, for j = k, D^-1 to a buffer.
+//   k_inv_big_rest  one workgroup per tile (i, j), i != k: P[i][j] -= C[i] P[k][j] (j != k, the
+//                   new row), P[i][k] = -C[i] D^-1; and P[k][k] = D^-1.
+// tmp holds, per mode, C (K x 16 x 16) and D^-1 (16 x 16).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_inv_big_init(int R, const double* __restrict__ G,
+                                                      int64_t g_stride, double lambda,
+                                                      const double* __restrict__ lam_dev,
+                                                      double* __restrict__ P, int64_t p_stride,
+                                                      int first_mode, int diag_damping) {
+  const int n = first_mode + blockIdx.y;
+  const double lam = lam_dev ? *lam_dev : lambda;
+  const double* Gn = G + n * g_stride;
+  double* Pn = P + n * p_stride;
+  const int64_t RR = (int64_t)R * R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < RR;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / R, j = e - i * R;
+    double v = Gn[e];
+    if (i == j) v += diag_damping ? lam * v : lam;
+    Pn[e] = v;
+  }
+}
+
+// Inverse of the diagonal tile of block k into Ds (LDS, [16][17]); 256 threads, thread (r, c).
+// Rows and columns past R hold the identity. Returns false (uniformly) on a pivot that is not
+// positive and finite.
+__device__ __forceinline__ bool inv_diag_tile(const double* Pn, int R, int k, double (*Ds)[17]) {
+  __shared__ int bad;
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  const int gi = 16 * k + r, gj = 16 * k + c;
+  Ds[r][c] = (gi < R && gj < R) ? Pn[(int64_t)gi * R + gj] : (r == c ? 1.0 : 0.0);
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int p = 0; p < 16; ++p) {
+    const double piv = Ds[p][p];
+    const double prow = Ds[p][c], fcol = Ds[r][p];
+    __syncthreads();
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (t == 0) bad = 1;
+    } else {
+      const double rp = (c == p ? 1.0 : prow) / piv;   // row p of the in-place inverse
+      if (r == p) Ds[r][c] = rp;
+      else Ds[r][c] = (c == p ? 0.0 : Ds[r][c]) - fcol * rp;
+    }
+    __syncthreads();
+  }
+  return bad == 0;
+}
+
+__global__ __launch_bounds__(256) void k_inv_big_row(int R, double* __restrict__ P,
+                                                     int64_t p_stride, int first_mode, int k,
+                                                     double* __restrict__ tmp, int64_t t_stride,
+                                                     CgState* st) {
+  __shared__ double Ds[16][17];
+  __shared__ double T[16][17];
+  if (st && st->status != CP_OK) return;   // an earlier step failed: the result is not used
+  const int n = first_mode + blockIdx.y, j = blockIdx.x;
+  const int K = (R + 15) / 16;
+  double* Pn = P + n * p_stride;
+  double* C = tmp + n * t_stride;          // [K][16][16]
+  double* Dinv = C + (int64_t)K * 256;     // [16][16]
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  const bool ok = inv_diag_tile(Pn, R, k, Ds);
+  if (!ok) {
+    if (j == 0 && t == 0 && st) {
+      st->status = CP_ENOTSPD;
+      st->done = 1;
+    }
+    return;
+  }
+  if (j == k) {
+    Dinv[r * 16 + c] = Ds[r][c];
+    return;
+  }
+  // column tile j of block column k (old values) and row tile (k, j) of P
+  const int gi = 16 * j + r, gk = 16 * k + c;
+  C[(int64_t)j * 256 + t] = (gi < R && gk < R) ? Pn[(int64_t)gi * R + gk] : 0.0;
+  const int rk = 16 * k + r, cj = 16 * j + c;
+  T[r][c] = (rk < R && cj < R) ? Pn[(int64_t)rk * R + cj] : 0.0;
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v = fma(Ds[r][q], T[q][c], v);
+  if (rk < R && cj < R) Pn[(int64_t)rk * R + cj] = v;
+}
+
+__global__ __launch_bounds__(256) void k_inv_big_rest(int R, double* __restrict__ P,
+                                                      int64_t p_stride, int first_mode, int k,
+                                                      const double* __restrict__ tmp,
+                                                      int64_t t_stride, const CgState* st) {
+  __shared__ double Ci[16][17];
+  __shared__ double Rk[16][17];
+  if (st && st->status != CP_OK) return;
+  const int K = (R + 15) / 16;
+  const int n = first_mode + blockIdx.z, i = blockIdx.y, j = blockIdx.x;
+  double* Pn = P + n * p_stride;
+  const double* C = tmp + n * t_stride;
+  const double* Dinv = C + (int64_t)K * 256;
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  const int gi = 16 * i + r, gj = 16 * j + c;
+  if (i == k) {
+    if (j == k && gi < R && gj < R) Pn[(int64_t)gi * R + gj] = Dinv[t];
+    return;
+  }
+  Ci[r][c] = C[(int64_t)i * 256 + t];
+  if (j == k) {
+    Rk[r][c] = Dinv[t];
+  } else {
+    const int rk = 16 * k + r;
+    Rk[r][c] = (rk < R && gj < R) ? Pn[(int64_t)rk * R + gj] : 0.0;
+  }
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v = fma(Ci[r][q], Rk[q][c], v);
+  if (gi < R && gj < R) {
+    const int64_t e = (int64_t)gi * R + gj;
+    Pn[e] = j == k ? -v : Pn[e] - v;
+  }
+}
+
+// Workspace of launch_spd_inv_big per mode (doubles).
+int64_t spd_inv_big_tmp(int R) { return (int64_t)((R + 15) / 16) * 256 + 256; }
+
+int launch_spd_inv_big(int R, const double* G, int64_t g_stride, double lambda, double* P,
+                       int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                       bool diag_damping, const double* lam_dev, double* tmp) {
+  const int K = (R + 15) / 16;
+  const int64_t ts = spd_inv_big_tmp(R);
+  const int64_t RR = (int64_t)R * R;
+  int g = (int)((RR + 255) / 256);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_inv_big_init, dim3(g, count), dim3(256), 0, s, R, G, g_stride, lambda,
+                     lam_dev, P, p_stride, first_mode, diag_damping ? 1 : 0);
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL(k_inv_big_row, dim3(K, count), dim3(256), 0, s, R, P, p_stride,
+                       first_mode, k, tmp, ts, st);
+    hipLaunchKernelGGL(k_inv_big_rest, dim3(K, K, count), dim3(256), 0, s, R, P, p_stride,
+                       first_mode, k, tmp, ts, st);
+  }
+  return (int)hipGetLastError();
+}
+
 }  // namespace cpgn

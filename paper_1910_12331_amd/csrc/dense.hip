@@ -1136,7 +1136,15 @@ void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
 }
 
 // GN and ALS need R <= kMaxGnRank (the inverse is register-resident in one workgroup).
-int spd_inv_supported(int R) { return R >= 1 && R <= kMaxGnRank; }
+// The Gauss-Newton step takes any rank: up to kMaxGnRank the inverse is register- or
+// LDS-resident in one workgroup, above it blocked in global memory. The ALS sweep's Cholesky
+// factor is held by one workgroup: R <= kMaxGnRank.
+int spd_inv_supported(int R) { return R >= 1; }
+int als_supported(int R) { return R >= 1 && R <= kMaxGnRank; }
+
+int launch_spd_inv_big(int R, const double* G, int64_t g_stride, double lambda, double* P,
+                       int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
+                       bool diag_damping, const double* lam_dev, double* tmp);
 
 #ifndef CPGN_SPD_TD
 #define CPGN_SPD_TD 32
@@ -1147,7 +1155,12 @@ int launch_spd_inv_blk(int R, const double* G, int64_t g_stride, double lambda, 
 
 int launch_spd_inv(int R, const double* G, int64_t g_stride, double lambda, double* P,
                    int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,
-                   bool diag_damping, const double* lam_dev) {
+                   bool diag_damping, const double* lam_dev, double* tmp) {
+  if (R > kMaxGnRank) {
+    if (!tmp) return (int)hipErrorInvalidValue;
+    return launch_spd_inv_big(R, G, g_stride, lambda, P, p_stride, first_mode, count, st, s,
+                              diag_damping, lam_dev, tmp);
+  }
   // R <= 128: Gauss-Jordan blocked by 16 x 16 tiles on the FP64 matrix cores (chol.hip)
   if (R <= 128)
     return launch_spd_inv_blk(R, G, g_stride, lambda, P, p_stride, first_mode, count, st, s,
@@ -1330,6 +1343,168 @@ void launch_ls_final(const Dims& d, const double* A64, const double* V, const Pe
   dim3 grid(rowmm_blocks(d), d.N);
   hipLaunchKernelGGL(k_ls_final, grid, dim3(256), 0, s, d, A64, V, Aout, dtype, red_nrm, st);
   hipLaunchKernelGGL(k_ls_stats, dim3(1), dim3(64), 0, s, st, out);
+}
+
+}  // namespace cpgn
+
+namespace cpgn {
+
+// ---------------------------------------------------------------------------------------------
+// CG of Algorithm 2 for R > kMaxGnRank, composed from the generic product kernels (Grams, the
+// R x R core of eq. (7), row products) and the small kernels below; all scalars stay on the
+// device, and every kernel returns at once when the state is done, as in the fixed-rank CG. Per
+// iteration: check (rho = <R,Z>, the stop test, beta), W = Z + beta W, Q = (J^T J + lambda D) W,
+// alpha = rho / <W,Q>, V += alpha W and R -= alpha Q, Z = R P_inv. Partial sums are per block and
+// mode, added in a fixed order.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cgw_zero(Dims d, double* __restrict__ V,
+                                                  const CgState* st) {
+  if (state_done(st)) return;
+  const int n = blockIdx.y;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    V[base + e] = 0.0;
+}
+
+// Before iteration `it` (it iterations done): rho = sum <R,Z>, rsum = sum_n ||R(n)|| (gsum before
+// the first iteration, R = -G), the stop test, beta = rho / rho_old.
+__global__ __launch_bounds__(256) void k_cgw_check(int N, int nblocks, const double* red_rz,
+                                                   const double* red_rr, CgState* st, int it,
+                                                   int final_check) {
+  if (state_done(st)) return;
+  double rho = 0.0, rsum = 0.0;
+  for (int n = 0; n < N; ++n) rho += sum_slots(red_rz + n * kRedSlots, nblocks);
+  if (it == 0) {
+    rsum = st->gsum;
+  } else {
+    for (int n = 0; n < N; ++n) rsum += sqrt(sum_slots(red_rr + n * kRedSlots, nblocks));
+  }
+  if (threadIdx.x != 0) return;
+  const double beta = it == 0 ? 0.0 : rho / st->rho[(it + 1) & 1];
+  bool stop = false;
+  int status = CP_OK;
+  if (!isfinite(rho) || !isfinite(rsum)) {
+    status = CP_ENONFINITE;
+    stop = true;
+  } else if (!(rsum > st->eps * st->gsum)) {
+    stop = true;
+  }
+  st->rho[it & 1] = rho;
+  st->rz = rho;
+  st->rsum = rsum;
+  st->iters = it;
+  if (it > 0) st->beta = beta;
+  if (stop || final_check) {
+    st->status = status;
+    st->done = 1;
+  }
+}
+
+// W = Z + beta W (beta = 0 before the first iteration).
+__global__ __launch_bounds__(256) void k_cgw_dir(Dims d, const double* __restrict__ Z,
+                                                 double* __restrict__ W, const CgState* st,
+                                                 int it) {
+  if (state_done(st)) return;
+  const double beta = it == 0 ? 0.0 : st->beta;
+  const int n = blockIdx.y;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    W[base + e] = it == 0 ? Z[base + e] : __fma_rn(beta, W[base + e], Z[base + e]);
+}
+
+// Q = lambda_c W + Q0 (lambda_c = lambda, or lambda Gamma(n,n)[c][c] for the diagonal damping)
+// and the partials of <W, Q>.
+__global__ __launch_bounds__(256) void k_cgw_damp(Dims d, const double* __restrict__ W,
+                                                  double* __restrict__ Q,
+                                                  const double* __restrict__ gam, double lambda,
+                                                  const double* __restrict__ lam_dev, int diag,
+                                                  double* red_wq, const CgState* st) {
+  if (state_done(st)) return;
+  const int n = blockIdx.y, R = d.R, N = d.N;
+  const double lam = lam_dev ? *lam_dev : lambda;
+  const double* Gnn = gam + (int64_t)n * (N + 1) * R * R;
+  const int64_t base = d.off[n] * R, cnt = d.s[n] * R;
+  double dot = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % R);
+    const double lc = diag ? lam * Gnn[(int64_t)c * (R + 1)] : lam;
+    const double w = W[base + e];
+    const double q = __fma_rn(lc, w, Q[base + e]);
+    Q[base + e] = q;
+    dot += w * q;
+  }
+  block_sum2(dot, dummy);
+  if (threadIdx.x == 0) red_wq[n * kRedSlots + blockIdx.x] = dot;
+}
+
+// alpha = rho / sum <W, Q>; a non-positive or non-finite denominator stops CG with a status.
+__global__ __launch_bounds__(256) void k_cgw_alpha(int N, int nblocks, const double* red_wq,
+                                                   CgState* st, int it) {
+  if (state_done(st)) return;
+  double wq = 0.0;
+  for (int n = 0; n < N; ++n) wq += sum_slots(red_wq + n * kRedSlots, nblocks);
+  if (threadIdx.x != 0) return;
+  int status = CP_OK;
+  if (!isfinite(wq)) status = CP_ENONFINITE;
+  else if (!(wq > 0.0)) status = CP_EBREAKDOWN;
+  if (status != CP_OK) {
+    st->status = status;
+    st->done = 1;
+    return;
+  }
+  st->alpha = st->rho[it & 1] / wq;
+}
+
+// V += alpha W, R -= alpha Q, and the partials of ||R||^2.
+__global__ __launch_bounds__(256) void k_cgw_update(Dims d, double* __restrict__ V,
+                                                    double* __restrict__ Rv,
+                                                    const double* __restrict__ W,
+                                                    const double* __restrict__ Q, double* red_rr,
+                                                    const CgState* st) {
+  if (state_done(st)) return;
+  const double alpha = st->alpha;
+  const int n = blockIdx.y;
+  const int64_t base = d.off[n] * d.R, cnt = d.s[n] * d.R;
+  double nrm = 0.0, dummy = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    V[base + e] = __fma_rn(alpha, W[base + e], V[base + e]);
+    const double r = __fma_rn(-alpha, Q[base + e], Rv[base + e]);
+    Rv[base + e] = r;
+    nrm += r * r;
+  }
+  block_sum2(nrm, dummy);
+  if (threadIdx.x == 0) red_rr[n * kRedSlots + blockIdx.x] = nrm;
+}
+
+void launch_cgw_zero(const Dims& d, double* V, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_zero, dim3(rowmm_blocks(d), d.N), dim3(256), 0, s, d, V, st);
+}
+void launch_cgw_check(const Dims& d, const double* red_rz, const double* red_rr, CgState* st,
+                      int it, bool final_check, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_check, dim3(1), dim3(256), 0, s, d.N, rowmm_blocks(d), red_rz, red_rr,
+                     st, it, final_check ? 1 : 0);
+}
+void launch_cgw_dir(const Dims& d, const double* Z, double* W, const CgState* st, int it,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_dir, dim3(rowmm_blocks(d), d.N), dim3(256), 0, s, d, Z, W, st, it);
+}
+void launch_cgw_damp(const Dims& d, const double* W, double* Q, const double* gam, double lambda,
+                     const double* lam_dev, bool diag, double* red_wq, const CgState* st,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_damp, dim3(rowmm_blocks(d), d.N), dim3(256), 0, s, d, W, Q, gam,
+                     lambda, lam_dev, diag ? 1 : 0, red_wq, st);
+}
+void launch_cgw_alpha(const Dims& d, const double* red_wq, CgState* st, int it, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_alpha, dim3(1), dim3(256), 0, s, d.N, rowmm_blocks(d), red_wq, st, it);
+}
+void launch_cgw_update(const Dims& d, double* V, double* Rv, const double* W, const double* Q,
+                       double* red_rr, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgw_update, dim3(rowmm_blocks(d), d.N), dim3(256), 0, s, d, V, Rv, W, Q,
+                     red_rr, st);
 }
 
 }  // namespace cpgn

@@ -220,19 +220,18 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_residual(C.byref(p), X, A, 0, None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_jtj_matvec(C.byref(p), A, A, -1.0, A, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_gradient(C.byref(p), X, A, L.PTRS(), None, ws, need, None) == L.CP_EINVAL
-    # ranks whose R x R inverse does not fit in one workgroup's registers (R > 208) are refused
-    # by GN and ALS
+    # the ALS sweep's Cholesky factor is held by one workgroup: R <= 208 (Gauss-Newton takes
+    # any rank: above 208 its inverse and CG work in global memory)
     pr = prob(rank=209)
     _, need2 = ws_bytes(lib, pr)
-    assert lib.cp_gn_step(C.byref(pr), X, A, C.byref(good), st, ws, need2, None) == L.CP_EUNSUPPORTED
     assert lib.cp_als_sweep(C.byref(pr), X, A, 0.0, None, ws, need2, None) == L.CP_EUNSUPPORTED
     # the triangular-solve preconditioner keeps its operands in 64 KB of LDS: R <= 128
     pc = prob(rank=129)
     _, need3 = ws_bytes(lib, pc)
     chol = L.CpGnParams(1e-3, 1e-3, 20, L.GN_CHOL_PRECOND)
     assert lib.cp_gn_step(C.byref(pc), X, A, C.byref(chol), st, ws, need3, None) == L.CP_EUNSUPPORTED
-    assert lib.cp_gn_step_armijo(C.byref(pr), X, A, C.byref(good), C.byref(ok_ls), st, ls_st, ws,
-                                 need2, None) == L.CP_EUNSUPPORTED
+    assert lib.cp_gn_step_armijo(C.byref(pc), X, A, C.byref(chol), C.byref(ok_ls), st, ls_st, ws,
+                                 need3, None) == L.CP_EUNSUPPORTED
 
 
 def test_status_strings(lib):

@@ -274,6 +274,24 @@ def test_gn_step_high_rank_rank_exceeds_mode_size(dims, rank, damping):
     gn_compare(p, torch.float64, 1e-2, 1e-3, 20, "sensitivity", damping=damping)
 
 
+@pytest.mark.parametrize("damping", ["identity", "diagonal"])
+@pytest.mark.parametrize("dims,rank", [((30, 28, 26), 230), ((40, 36, 24, 6), 300)])
+def test_gn_step_rank_above_208(dims, rank, damping):
+    """Ranks above 208 (Section 5's Cyclops runs go to R = 2000): the preconditioner inverse is
+    blocked Gauss-Jordan in global memory and CG runs from the generic product kernels. CG with
+    the tolerance test, both damping forms, FP64, against the oracle's step."""
+    p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
+    gn_compare(p, torch.float64, 1e-2, 1e-3, 20, "sensitivity", damping=damping)
+
+
+@pytest.mark.parametrize("maxiter", [0, 1, 7])
+def test_gn_step_rank_above_208_fixed_iterations(maxiter):
+    """R = 257 (17 blocks of 16 columns, the last one ragged) with exactly 0, 1 and 7 CG
+    iterations (eps_cg = 0) against the oracle's step."""
+    p = make_problem((20, 18, 22), 257, workload=0, problem=7, noise=1e-2)
+    gn_compare(p, torch.float64, 5e-2, 0.0, maxiter, "sensitivity")
+
+
 @pytest.mark.parametrize("dims,rank", [((60, 50, 70), 150), ((150, 150, 150), 200)])
 def test_als_sweep_high_rank(dims, rank):
     """ALS above R = 128 (each mode takes its own pass over X; the inverse has 13 register
