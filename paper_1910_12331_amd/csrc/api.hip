@@ -31,6 +31,10 @@ int launch_spd_inv(int, const double*, int64_t, double, double*, int64_t, int, i
                    hipStream_t, bool diag_damping = false, const double* lam_dev = nullptr,
                    double* tmp = nullptr);
 int als_supported(int);
+int launch_als_solve_big(int R, int64_t s, const double* G, int64_t g_stride, double lambda,
+                         double* L, int64_t l_stride, double* Dinv, double* stage, int mode,
+                         const double* M, double* Y, double* A64, void* Aout, int dtype,
+                         CgState* st, hipStream_t hs);
 void launch_cgw_zero(const Dims&, double*, const CgState*, hipStream_t);
 void launch_cgw_check(const Dims&, const double*, const double*, CgState*, int, bool,
                       hipStream_t);
@@ -747,10 +751,15 @@ int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double l
     // A(n) L = Y by substitution (skipped, factors unchanged, when a pivot is not positive)
     double* dinv = (double*)(w.base + p.off_dinv);
     const int64_t dstride = (int64_t)((p.R + 15) / 16) * 256;
-    launch_chol_tiles(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, dinv, dstride, n,
-                      1, w.st, st);
-    launch_chol_rows(p.R, p.s[n], m64n, w.pinv + n * RR, dinv + n * dstride, A[n], p.dtype, w.st,
-                     st);
+    if (p.R > kMaxGnRank) {   // L in global memory, tiles streamed (the Y and CG buffers as scratch)
+      launch_als_solve_big(p.R, p.s[n], w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR,
+                           dinv + n * dstride, w.y, n, m64n, w.z, w.v, A[n], p.dtype, w.st, st);
+    } else {
+      launch_chol_tiles(p.R, w.gam, (int64_t)(p.N + 1) * RR, lambda, w.pinv, RR, dinv, dstride,
+                        n, 1, w.st, st);
+      launch_chol_rows(p.R, p.s[n], m64n, w.pinv + n * RR, dinv + n * dstride, A[n], p.dtype,
+                       w.st, st);
+    }
     // refresh the padded/packed copies, the FP64 copy and the Gram of the updated mode
     launch_prepare_factors_src(p, (const void* const*)A, p.dtype, ws, st, true, 1u << (n + 1));
     launch_gram2(d, w.a64, w.a64, w.S, n, nullptr, st);

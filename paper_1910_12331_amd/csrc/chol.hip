@@ -782,4 +782,181 @@ int launch_spd_inv_big(int R, const double* G, int64_t g_stride, double lambda, 
   return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// ALS solve for R > kMaxGnRank: A(n) = M (L L^T)^-1 with L L^T = Gamma(n) + lambda I, all in
+// global memory, blocked by 16 x 16 tiles (K = ceil(R / 16)).
+//   Cholesky, right-looking, two launches per block column k:
+//     k_cholb_panel  one workgroup per tile row i >= k: factors the diagonal tile A_kk = L_kk
+//                    L_kk^T in LDS (pivots must be positive, else CP_ENOTSPD) and inverts L_kk;
+//                    row k stores L_kk (staged) and L_kk^-1, rows i > k store L_ik = A_ik L_kk^-T.
+//     k_cholb_trail  one workgroup per tile (i, j), k < j <= i: A_ij -= L_ik L_jk^T; and the
+//                    staged L_kk into place.
+//   Substitution, one launch per block column: Y L^T = M forward (Y_k = (M_k - sum_{j<k} Y_j
+//   L_kj^T) L_kk^-T), then A L = Y backward (A_k = (Y_k - sum_{j>k} A_j L_jk) L_kk^-1); 16 rows
+//   x 16 columns per workgroup. Skipped (factors unchanged) when the factorization failed.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cholb_init(int R, const double* __restrict__ G,
+                                                    int64_t g_stride, double lambda,
+                                                    double* __restrict__ L, int64_t l_stride,
+                                                    int mode) {
+  const double* Gn = G + mode * g_stride;
+  double* Ln = L + mode * l_stride;
+  const int64_t RR = (int64_t)R * R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < RR;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / R, j = e - i * R;
+    Ln[e] = Gn[e] + (i == j ? lambda : 0.0);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cholb_panel(int R, double* __restrict__ L,
+                                                     int64_t l_stride, int mode, int k,
+                                                     double* __restrict__ stage,
+                                                     double* __restrict__ Dinv, CgState* st) {
+  __shared__ double A[16][17], X[16][17], T[16][17];
+  __shared__ int bad;
+  if (st->status != CP_OK) return;
+  double* Ln = L + mode * l_stride;
+  const int i = k + blockIdx.x;
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  const int gr = 16 * k + r, gc = 16 * k + c;
+  A[r][c] = (gr < R && gc < R) ? Ln[(int64_t)gr * R + gc] : (r == c ? 1.0 : 0.0);
+  X[r][c] = 0.0;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int p = 0; p < 16; ++p) {   // A_kk = L L^T, column p at a time (lower triangle)
+    const double d = A[p][p];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (t == 0) bad = 1;
+      break;
+    }
+    const double l = sqrt(d);
+    const double arp = A[r][p], acp = A[c][p];
+    __syncthreads();
+    if (c == p && r >= p) A[r][p] = r == p ? l : arp / l;
+    else if (r > p && c > p && c <= r) A[r][c] -= (arp / l) * (acp / l);
+    __syncthreads();
+  }
+  __syncthreads();
+  if (bad) {
+    if (blockIdx.x == 0 && t == 0) st->status = CP_ENOTSPD;
+    return;
+  }
+  for (int p = 0; p < 16; ++p) {   // X = L_kk^-1 (lower), row p from rows < p
+    if (r == p && c <= p) {
+      double v = c == p ? 1.0 : 0.0;
+      for (int q = c; q < p; ++q) v -= A[p][q] * X[q][c];
+      X[p][c] = v / A[p][p];
+    }
+    __syncthreads();
+  }
+  if (i == k) {
+    stage[t] = c <= r ? A[r][c] : 0.0;
+    Dinv[(int64_t)k * 256 + t] = X[r][c];
+    return;
+  }
+  const int ir = 16 * i + r;
+  T[r][c] = (ir < R && gc < R) ? Ln[(int64_t)ir * R + gc] : 0.0;
+  __syncthreads();
+  double v = 0.0;   // L_ik = A_ik L_kk^-T: sum_q A_ik[r][q] X[c][q]
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v = fma(T[r][q], X[c][q], v);
+  if (ir < R && gc < R) Ln[(int64_t)ir * R + gc] = v;
+}
+
+__global__ __launch_bounds__(256) void k_cholb_trail(int R, double* __restrict__ L,
+                                                     int64_t l_stride, int mode, int k,
+                                                     const double* __restrict__ stage,
+                                                     const CgState* st) {
+  __shared__ double Li[16][17], Lj[16][17];
+  if (st->status != CP_OK) return;
+  const int i = blockIdx.y, j = blockIdx.x;
+  double* Ln = L + mode * l_stride;
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  if (i == k && j == k) {
+    const int gr = 16 * k + r, gc = 16 * k + c;
+    if (gr < R && gc < R) Ln[(int64_t)gr * R + gc] = stage[t];
+    return;
+  }
+  if (!(j > k && j <= i)) return;
+  const int ir = 16 * i + r, jr = 16 * j + r, kc = 16 * k + c;
+  Li[r][c] = (ir < R && kc < R) ? Ln[(int64_t)ir * R + kc] : 0.0;
+  Lj[r][c] = (jr < R && kc < R) ? Ln[(int64_t)jr * R + kc] : 0.0;
+  __syncthreads();
+  double v = 0.0;   // (L_ik L_jk^T)[r][c] = sum_q L_ik[r][q] L_jk[c][q]
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v = fma(Li[r][q], Lj[c][q], v);
+  const int gc = 16 * j + c;
+  if (ir < R && gc < R) Ln[(int64_t)ir * R + gc] -= v;
+}
+
+// Forward (back = 0) or backward (back = 1) substitution for block column k over 16 rows of the
+// mode per workgroup. fwd: In = M, Out = Y; back: In = Y, Out = A (FP64) and Acast.
+__global__ __launch_bounds__(256) void k_cholb_solve(int R, int64_t s, const double* __restrict__ In,
+                                                     const double* __restrict__ L,
+                                                     const double* __restrict__ Dinv, int k,
+                                                     int back, double* __restrict__ Out,
+                                                     void* __restrict__ Acast, int dtype,
+                                                     const CgState* st) {
+  __shared__ double U[16][17], D[16][17];
+  if (st->status != CP_OK) return;
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
+  const int64_t row = (int64_t)blockIdx.x * 16 + r;
+  const int col = 16 * k + c;
+  D[r][c] = Dinv[(int64_t)k * 256 + t];
+  double u = 0.0;
+  if (row < s && col < R) {
+    u = In[row * R + col];
+    const double* Orow = Out + row * R;
+    if (!back) {
+      for (int q = 0; q < 16 * k; ++q) u -= Orow[q] * L[(int64_t)col * R + q];
+    } else {
+      for (int q = 16 * (k + 1); q < R; ++q) u -= Orow[q] * L[(int64_t)q * R + col];
+    }
+  }
+  U[r][c] = u;
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)   // fwd: Y_k = U L_kk^-T; back: A_k = U L_kk^-1
+    v = fma(U[r][q], back ? D[q][c] : D[c][q], v);
+  if (row < s && col < R) {
+    Out[row * R + col] = v;
+    if (back) {
+      if (dtype == CP_F64) ((double*)Acast)[row * R + col] = v;
+      else ((float*)Acast)[row * R + col] = (float)v;
+    }
+  }
+}
+
+// A = M (G_n + lambda I)^-1 for one mode n, R > kMaxGnRank. L: R x R per mode (l_stride),
+// Dinv: K x 256 doubles, stage: 256 doubles, Y and A64: s x R doubles of scratch.
+int launch_als_solve_big(int R, int64_t s, const double* G, int64_t g_stride, double lambda,
+                         double* L, int64_t l_stride, double* Dinv, double* stage, int mode,
+                         const double* M, double* Y, double* A64, void* Aout, int dtype,
+                         CgState* st, hipStream_t hs) {
+  const int K = (R + 15) / 16;
+  const int64_t RR = (int64_t)R * R;
+  int g = (int)((RR + 255) / 256);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_cholb_init, dim3(g), dim3(256), 0, hs, R, G, g_stride, lambda, L,
+                     l_stride, mode);
+  double* Ln = L + mode * l_stride;
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL(k_cholb_panel, dim3(K - k), dim3(256), 0, hs, R, L, l_stride, mode, k,
+                       stage, Dinv, st);
+    hipLaunchKernelGGL(k_cholb_trail, dim3(K, K), dim3(256), 0, hs, R, L, l_stride, mode, k,
+                       stage, (const CgState*)st);
+  }
+  const dim3 rows((unsigned)((s + 15) / 16));
+  for (int k = 0; k < K; ++k)
+    hipLaunchKernelGGL(k_cholb_solve, rows, dim3(256), 0, hs, R, s, M, (const double*)Ln,
+                       (const double*)Dinv, k, 0, Y, nullptr, dtype, (const CgState*)st);
+  for (int k = K - 1; k >= 0; --k)
+    hipLaunchKernelGGL(k_cholb_solve, rows, dim3(256), 0, hs, R, s, (const double*)Y,
+                       (const double*)Ln, (const double*)Dinv, k, 1, A64, Aout, dtype,
+                       (const CgState*)st);
+  return (int)hipGetLastError();
+}
+
 }  // namespace cpgn

@@ -1136,11 +1136,10 @@ void launch_status_out(const CgState* st, int32_t* out, hipStream_t s) {
 }
 
 // GN and ALS need R <= kMaxGnRank (the inverse is register-resident in one workgroup).
-// The Gauss-Newton step takes any rank: up to kMaxGnRank the inverse is register- or
-// LDS-resident in one workgroup, above it blocked in global memory. The ALS sweep's Cholesky
-// factor is held by one workgroup: R <= kMaxGnRank.
+// Any rank: up to kMaxGnRank the Gauss-Newton inverse and the ALS Cholesky factor are register-
+// or LDS-resident in one workgroup, above it they are blocked in global memory.
 int spd_inv_supported(int R) { return R >= 1; }
-int als_supported(int R) { return R >= 1 && R <= kMaxGnRank; }
+int als_supported(int R) { return R >= 1; }
 
 int launch_spd_inv_big(int R, const double* G, int64_t g_stride, double lambda, double* P,
                        int64_t p_stride, int first_mode, int count, CgState* st, hipStream_t s,

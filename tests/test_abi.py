@@ -220,11 +220,6 @@ def test_call_validation_without_launch(lib):
     assert lib.cp_residual(C.byref(p), X, A, 0, None, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_jtj_matvec(C.byref(p), A, A, -1.0, A, ws, need, None) == L.CP_EINVAL
     assert lib.cp_gn_gradient(C.byref(p), X, A, L.PTRS(), None, ws, need, None) == L.CP_EINVAL
-    # the ALS sweep's Cholesky factor is held by one workgroup: R <= 208 (Gauss-Newton takes
-    # any rank: above 208 its inverse and CG work in global memory)
-    pr = prob(rank=209)
-    _, need2 = ws_bytes(lib, pr)
-    assert lib.cp_als_sweep(C.byref(pr), X, A, 0.0, None, ws, need2, None) == L.CP_EUNSUPPORTED
     # the triangular-solve preconditioner keeps its operands in 64 KB of LDS: R <= 128
     pc = prob(rank=129)
     _, need3 = ws_bytes(lib, pc)

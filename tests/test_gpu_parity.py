@@ -292,10 +292,13 @@ def test_gn_step_rank_above_208_fixed_iterations(maxiter):
     gn_compare(p, torch.float64, 5e-2, 0.0, maxiter, "sensitivity")
 
 
-@pytest.mark.parametrize("dims,rank", [((60, 50, 70), 150), ((150, 150, 150), 200)])
+@pytest.mark.parametrize("dims,rank", [((60, 50, 70), 150), ((150, 150, 150), 200),
+                                       ((30, 28, 26), 230), ((40, 36, 24, 6), 300)])
 def test_als_sweep_high_rank(dims, rank):
-    """ALS above R = 128 (each mode takes its own pass over X; the inverse has 13 register
-    blocks at R = 200), held to 10x the oracle's own spread under a 1e-15 input perturbation."""
+    """ALS above R = 128 (each mode takes its own pass over X; the Cholesky factor has 13
+    register blocks at R = 200, and above R = 208 it is blocked in global memory with the
+    substitutions one block column per launch), held to 10x the oracle's own spread under a
+    1e-15 input perturbation."""
     p = make_problem(dims, rank, workload=0, problem=rank, noise=1e-2)
     Ad = to_dev(p.init, torch.float64)
     status = P.als_sweep(to_dev([p.x], torch.float64)[0], Ad, 1e-2)
