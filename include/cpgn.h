@@ -31,9 +31,10 @@
  *     non-finite values) are written as a status code into device memory (the `status` field
  *     of cp_gn_stats, or `status_dev`); the caller reads it after synchronising the stream.
  *     On such a failure the factors are left unchanged.
- *   - The Gauss-Newton steps and cp_als_sweep need rank <= 208 (their R x R inverse is held in
- *     one workgroup's registers, and so are the CG operand rows) and return CP_EUNSUPPORTED
- *     otherwise; the other calls take any rank.
+ *   - Every call takes any rank. Up to 208 the R x R inverse (Gauss-Newton), the Cholesky
+ *     factor (ALS) and the CG operand rows are held by one workgroup; above 208 they are blocked
+ *     by 16 x 16 tiles in global memory (more launches per step). The triangular-solve
+ *     preconditioner (CP_GN_CHOL_PRECOND) and the split and batched steps need rank <= 128.
  *
  * Precision
  *   - x_dtype equals f_dtype, CP_F64 or CP_F32; or f_dtype = CP_F32 and x_dtype = CP_BF16 or
@@ -286,7 +287,7 @@ typedef struct cp_armijo_stats {
  *   ||alpha V||). ls_stats: DEVICE pointer to one cp_armijo_stats.
  *   ws: at least cp_workspace_bytes(CP_OP_GN_STEP).
  *   Errors: CP_EINVAL for null pointers or parameters out of range (before any launch);
- *   rank > 208: CP_EUNSUPPORTED.
+ *   CP_GN_CHOL_PRECOND above rank 128: CP_EUNSUPPORTED.
  */
 int cp_gn_step_armijo(const cp_problem* prob, const void* X, void* const* A,
                       const cp_gn_params* params, const cp_armijo_params* ls, cp_gn_stats* stats,
@@ -384,7 +385,8 @@ int cp_device_clock_hz(int64_t* hz);
  * workspace of the other operations, the sweep takes one pass per mode.
  *   A: N device pointers, read and overwritten in place. lambda >= 0 (0 = plain ALS).
  *   status_dev: device int32 receiving CP_OK or CP_ENOTSPD (a pivot <= 0: that mode and the ones
- *   after it keep their factors; may be NULL). Rank <= 208 (CP_EUNSUPPORTED above).
+ *   after it keep their factors; may be NULL). Any rank: above 208 the Cholesky factor and the
+ *   substitutions are blocked by 16 x 16 tiles in global memory, one launch per block column.
  */
 int cp_als_sweep(const cp_problem* prob, const void* X, void* const* A, double lambda,
                  int32_t* status_dev, void* ws, size_t ws_bytes, void* stream);
