@@ -310,6 +310,33 @@ def test_batch_program_steps_match_per_problem_steps(dt):
                     assert rel(a.double().cpu().numpy(), b) < (1e-4 if dt == torch.float32 else 1e-9)
 
 
+def test_batch_program_mixed_orders_dtypes_diagonal_damping():
+    """One batch program over problems of orders 3 and 4, FP32 and FP64, ranks 5 to 40, with the
+    diagonal damping: the launches of different kernel instantiations share levels, and every
+    problem still gives bitwise the factors and stats of its own steps (two steps)."""
+    rng = np.random.default_rng(11)
+    shapes = [((23, 19, 31), 5, torch.float32), ((12, 9, 11, 8), 7, torch.float64),
+              ((40, 36, 20), 40, torch.float64), ((10, 13, 8, 9), 12, torch.float32),
+              ((64, 30, 17), 20, torch.float32), ((25, 25, 25), 33, torch.float64)]
+    data = [(rng.standard_normal(sh), [rng.standard_normal((n, R)) for n in sh], dt)
+            for sh, R, dt in shapes]
+    mk = lambda: [(torch.tensor(x, dtype=dt, device="cuda"),
+                   [torch.tensor(a, dtype=dt, device="cuda") for a in A]) for x, A, dt in data]
+    cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20, damping="diagonal")
+    ref = [P.GaussNewton(X, A, cfg) for X, A in mk()]
+    bat = P.BatchedGaussNewton(mk(), cfg, fused=True)
+    for k in range(2):
+        for g in ref:
+            g.step()
+        bat.step()
+        bat.synchronize()
+        torch.cuda.synchronize()
+        for g, ob in zip(ref, bat.opts):
+            assert g.stats() == ob.stats(), k
+            for a, b in zip(g.A, ob.A):
+                assert torch.equal(a, b), k
+
+
 def test_batch_program_graph_replays_match_eager():
     """The batch program captured as one graph and replayed three times, with eager work between
     the replays, gives bitwise the eager program's iterates and schedules."""
