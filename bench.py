@@ -790,11 +790,35 @@ def main():
         del Aar
         log(f"[bench] time to 1e-8 with Armijo control (FP64): {armijo_s:.3f} s in {len(har)} "
             f"steps (r={har[-1]:.2e})")
+        # precision ladder with the bfloat16 rungs: bfloat16 -> split bfloat16 -> FP32 -> FP64
+        # storage of the same tensor (conversions made before the timed region; one untimed run
+        # first so that the timed one reuses cached workspace allocations)
+        Xb, Xs = P.to_bf16(X32d), P.to_bf16(X32d, split=True)
+        lad_cfg = P.GNConfig(cg_tol=1e-3, cg_maxiter=20)
+        P.gn_ladder_to_target([Xb, Xs, X32d, X64d], [torch.tensor(a, dtype=torch.float32,
+                                                                 device="cuda") for a in A0],
+                              1e-8, lad_cfg)
+        Alad = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in A0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hlad = P.gn_ladder_to_target([Xb, Xs, X32d, X64d], Alad, 1e-8, lad_cfg)
+        ladder_s = time.perf_counter() - t0
+        del Xb, Xs, Alad
+        lad_rungs = {}
+        for name, _, acc in hlad:
+            lad_rungs[name] = lad_rungs.get(name, 0) + 1
+        log(f"[bench] time to 1e-8 with the bfloat16 ladder: {ladder_s:.3f} s, steps per rung "
+            f"{lad_rungs} (r={hlad[-1][1]:.2e})")
         ttt = dict(fp64_seconds=fp64_s, fp64_steps=len(h64), fp64_residual=h64[-1],
                    fp64_armijo_seconds=armijo_s, fp64_armijo_steps=len(har),
                    fp64_armijo_residual=har[-1],
                    mixed_seconds=mixed_s, mixed_steps_fp32=n32, mixed_steps_fp64=len(hmx) - n32,
                    mixed_residual=hmx[-1][1], speedup=fp64_s / mixed_s,
+                   ladder_bf16_seconds=ladder_s, ladder_bf16_steps_per_rung=lad_rungs,
+                   ladder_bf16_residual=hlad[-1][1],
+                   ladder_note="bfloat16 -> split bfloat16 -> FP32 -> FP64 storage "
+                               "(gn_ladder_to_target: a rung is left when a step raises the "
+                               "residual or the residual nears the rung's floor)",
                    fp64_gn_step_20cg_ms=t20_64 * 1e3)
         log(f"[bench] time to 1e-8: FP64 {fp64_s:.3f} s in {len(h64)} steps (r={h64[-1]:.2e}); "
             f"mixed {mixed_s:.3f} s in {n32} FP32 + {len(hmx) - n32} FP64 steps (r={hmx[-1][1]:.2e})")
