@@ -146,8 +146,8 @@ def mttkrp_times(P, Xd, A, reps, stream):
 # counter reads for a device copy of X (256 MB read + 256 MB written), so 1.0 = exact bytes.
 # Valid only for the kernel source it was taken on.
 MTTKRP_TRAFFIC = {
-    "source_sha256": "58c628ee16ff4044d3e8d0d68d6eeb9761e8fb5a831f6cfa764e49fb3fe4f330",
-    "bytes_per_launch": 319321704,   # mean over the three modes of the main kernel
+    "source_sha256": "83ec1f1bbf7f442a18d72f40d7761af39a9b3bee847775f123c8a456ea5dfef3",
+    "bytes_per_launch": 319329780,   # mean over the three modes of the main kernel
 }
 
 
@@ -840,22 +840,25 @@ def main():
                                   stream_counts=(1, 2, 4, 8, 16), steps=3)
         hz = P.device_clock_hz()
         bs = args.batched_streams
-        configs = [(1, False, False, False), (bs, False, False, False), (bs, True, False, False),
-                   (bs, False, True, False), (bs, True, True, False), (1, False, True, True),
-                   (1, True, True, True)]
-        tk = (tune.n_streams, tune.graphs, tune.batch_cg, tune.fused)
+        configs = [(1, False, False, False, None), (bs, False, False, False, None),
+                   (bs, True, False, False, None), (bs, False, True, False, None),
+                   (bs, True, True, False, None), (1, False, True, True, None),
+                   (1, True, True, True, None)]
+        tk = (tune.n_streams, tune.graphs, tune.batch_cg, tune.fused, tune.tiles)
         if tk not in configs:
             configs.append(tk)
 
-        def cname(ns, g, b, f):
+        def cname(ns, g, b, f, t=None):
             if f:
-                return "program" + ("_graph" if g else "")
-            return f"streams_{ns}" + ("_graphs" if g else "") + ("_batchcg" if b else "")
-        for ns, graphs, bcg, fus in configs:
+                name = "program" + ("_graph" if g else "")
+            else:
+                name = f"streams_{ns}" + ("_graphs" if g else "") + ("_batchcg" if b else "")
+            return name if t is None else name + "_tiles_{}_{}_{}".format(*t)
+        for ns, graphs, bcg, fus, tls in configs:
             cur = [(X_, [a.clone() for a in A_]) for X_, A_ in devs]
             torch.cuda.synchronize()
             bgn = P.BatchedGaussNewton(cur, P.GNConfig(cg_tol=1e-3, cg_maxiter=20), n_streams=ns,
-                                       graphs=graphs, batch_cg=bcg, fused=fus)
+                                       graphs=graphs, batch_cg=bcg, fused=fus, tiles=tls)
             for _ in range(2):
                 bgn.step()
             bgn.synchronize()
@@ -875,14 +878,20 @@ def main():
                 per = ((ticks[:, :, 1] - ticks[:, :, 0]) / hz * 1e3).ravel()
                 rec.update(step_ms_p50=float(np.percentile(per, 50)),
                            step_ms_p99=float(np.percentile(per, 99)))
-            res[cname(ns, graphs, bcg, fus)] = rec
+            res[cname(ns, graphs, bcg, fus, tls)] = rec
             del bgn, cur
         kt = cname(*tk)
         res["autotuned"] = dict(choice=kt, problem_steps_per_s=res[kt]["problem_steps_per_s"],
                                 sweep_problem_steps_per_s={
                                     cname(*k): v for k, v in tune.table.items()},
+                                tile_sweep_problem_steps_per_s={
+                                    "tiles_{}_{}_{}".format(*t): v
+                                    for t, v in tune.tile_table.items()},
                                 note="sweep: 3 steps per configuration without per-problem "
-                                     "events; problem_steps_per_s: the timed loop of the fixed "
+                                     "events, then MTTKRP tile shapes (min items per wavefront, "
+                                     "workgroups per CU, FP32 row tile in 16-row blocks; 0 = "
+                                     "default) on the best configuration; "
+                                     "problem_steps_per_s: the timed loop of the fixed "
                                      "configurations")
         log(f"[bench] batched autotuner picks {kt}: {res[kt]['problem_steps_per_s']:.0f} "
             f"problem-steps/s in the same timed loop")

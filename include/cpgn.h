@@ -411,6 +411,34 @@ int cp_residual(const cp_problem* prob, const void* X, const void* const* A, int
  */
 int cp_tensor_to_bf16(const float* X, int64_t n, int split, void* out, void* stream);
 
+/*
+ * Tile shape of the FP32/FP64 MTTKRP launches (Section 2.2's contraction; not a step of the
+ * method). A tuning choice for many small problems, where the best split of a mode's work over
+ * wavefronts depends on the shapes: every setting computes the same contraction, but the
+ * partial sums are added in a different order, so results agree to rounding, not bitwise, across
+ * settings (bitwise for one setting). Zero fields take the defaults.
+ *   mttkrp_min_items: least (outer index, 16-wide inner chunk) items per wavefront before a row
+ *     tile's items are split over more wavefronts; 1..4096, default 16.
+ *   mttkrp_wg_per_cu: workgroups per compute unit one launch aims for; 1..8, default 2.
+ *   mttkrp_row_block: 16-row blocks per row tile of the FP32 kernel for modes whose inner index
+ *     runs along X rows (n < N-1, 16-byte aligned rows); 2, 4 or 5, default automatic (5 where
+ *     80-row tiles pad the mode less than 64-row ones, else 4). Other kernels keep their tiles.
+ *   reserved: must be 0.
+ * cp_set_tuning applies to the calling host thread: to the workspace sizes, launches and batch
+ * programs of calls made from it afterwards (a batch program keeps the setting of its
+ * cp_gn_batch_create). A workspace sized under one setting can be too small for another
+ * (CP_EWORKSPACE). t == NULL restores the defaults. CP_EINVAL for a field out of range.
+ * cp_get_tuning writes the calling thread's setting (zeros for defaults) to *t (host).
+ */
+typedef struct {
+  int32_t mttkrp_min_items;
+  int32_t mttkrp_wg_per_cu;
+  int32_t mttkrp_row_block;
+  int32_t reserved;
+} cp_tuning;
+int cp_set_tuning(const cp_tuning* t);
+int cp_get_tuning(cp_tuning* t);
+
 /* Static description of a status code. */
 const char* cp_status_string(int status);
 

@@ -20,7 +20,7 @@ RESIDUAL_DIRECT, RESIDUAL_EXPANSION = 0, 1
 
 EXPORTS = ["cp_workspace_bytes", "cp_mttkrp", "cp_mttkrp_marked", "cp_mttkrp_all", "cp_gn_gradient", "cp_objective_gradient", "cp_gn_jtj_matvec", "cp_gn_step",
            "cp_gn_step_devlam", "cp_gn_step_noalloc", "cp_gn_step_armijo", "cp_damping_advance", "cp_gn_step_begin", "cp_gn_cg_batch", "cp_gn_step_end", "cp_gn_batch_create", "cp_gn_batch_step", "cp_gn_batch_destroy", "cp_device_timestamp", "cp_device_clock_hz", "cp_als_sweep", "cp_residual",
-           "cp_tensor_to_bf16", "cp_status_string", "cp_abi_version"]
+           "cp_tensor_to_bf16", "cp_set_tuning", "cp_get_tuning", "cp_status_string", "cp_abi_version"]
 
 
 class CpProblem(C.Structure):
@@ -47,6 +47,11 @@ class CpArmijoParams(C.Structure):
 class CpArmijoStats(C.Structure):
     _fields_ = [("alpha", C.c_double), ("f0", C.c_double), ("f", C.c_double), ("gv", C.c_double),
                 ("x_norm", C.c_double), ("trials", C.c_int32), ("accepted", C.c_int32)]
+
+
+class CpTuning(C.Structure):
+    _fields_ = [("mttkrp_min_items", C.c_int32), ("mttkrp_wg_per_cu", C.c_int32),
+                ("mttkrp_row_block", C.c_int32), ("reserved", C.c_int32)]
 
 
 PTRS = C.c_void_p * MAX_ORDER
@@ -116,6 +121,10 @@ def load(path: str = LIB_PATH):
     lib.cp_residual.argtypes = [P(CpProblem), vp, PTRS, i32, vp, vp, sz, vp]
     lib.cp_tensor_to_bf16.restype = i32
     lib.cp_tensor_to_bf16.argtypes = [vp, C.c_int64, i32, vp, vp]
+    lib.cp_set_tuning.restype = i32
+    lib.cp_set_tuning.argtypes = [P(CpTuning)]
+    lib.cp_get_tuning.restype = i32
+    lib.cp_get_tuning.argtypes = [P(CpTuning)]
     if lib.cp_abi_version() != 1:
         raise RuntimeError("libcpgn.so ABI version mismatch")
     _lib = lib

@@ -8,6 +8,7 @@ fallback, and a missing library raises.
 from __future__ import annotations
 
 import ctypes as C
+import contextlib
 from typing import NamedTuple, Sequence
 
 import torch
@@ -537,6 +538,48 @@ def device_clock_hz() -> int:
     hz = C.c_int64(0)
     _check(L.load().cp_device_clock_hz(C.byref(hz)), "cp_device_clock_hz")
     return int(hz.value)
+
+
+class Tiles(NamedTuple):
+    """MTTKRP tile shape (cp_tuning): least items per wavefront, workgroups per compute unit a
+    launch aims for, FP32 row tile in 16-row blocks (2, 4 or 5). 0 takes the default
+    (16, 2, automatic)."""
+    min_items: int = 0
+    wg_per_cu: int = 0
+    row_block: int = 0
+
+
+def set_tiles(t: Tiles | None):
+    """Set the calling thread's MTTKRP tile shape for the calls made from it afterwards
+    (cp_set_tuning); None restores the defaults."""
+    lib = L.load()
+    if t is None:
+        _check(lib.cp_set_tuning(None), "cp_set_tuning")
+        return
+    ct = L.CpTuning(int(t.min_items), int(t.wg_per_cu), int(t.row_block), 0)
+    _check(lib.cp_set_tuning(C.byref(ct)), "cp_set_tuning")
+
+
+def get_tiles() -> Tiles:
+    """The calling thread's MTTKRP tile shape (cp_get_tuning; zeros are defaults)."""
+    ct = L.CpTuning()
+    _check(L.load().cp_get_tuning(C.byref(ct)), "cp_get_tuning")
+    return Tiles(ct.mttkrp_min_items, ct.mttkrp_wg_per_cu, ct.mttkrp_row_block)
+
+
+@contextlib.contextmanager
+def tiles(t: Tiles | None):
+    """Run a block under MTTKRP tile shape t (None: leave the current one) and restore the
+    previous shape afterwards."""
+    if t is None:
+        yield
+        return
+    prev = get_tiles()
+    set_tiles(t)
+    try:
+        yield
+    finally:
+        set_tiles(prev)
 
 
 def als_sweep(X: torch.Tensor, A: Sequence[torch.Tensor], lam: float = 0.0, status=None, ws=None):

@@ -84,6 +84,9 @@ void launch_ttm_contract(const Plan&, const void*, const double*, int, double*, 
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// MTTKRP tile shape of the plans made on this host thread (cp_set_tuning; zeros: defaults).
+static thread_local cp_tuning t_tuning = {0, 0, 0, 0};
+
 int make_plan(const cp_problem* prob, Plan* p) {
   if (!prob || !p) return CP_EINVAL;
   if (prob->order < 2 || prob->order > kMaxOrder || prob->rank < 1) return CP_EINVAL;
@@ -93,6 +96,9 @@ int make_plan(const cp_problem* prob, Plan* p) {
                     (prob->x_dtype == CP_BF16 || prob->x_dtype == CP_BF16X3);
   if (!native && !bf16) return CP_EUNSUPPORTED;
   *p = Plan{};
+  if (t_tuning.mttkrp_min_items) p->mt_min_items = t_tuning.mttkrp_min_items;
+  if (t_tuning.mttkrp_wg_per_cu) p->mt_wg_per_cu = t_tuning.mttkrp_wg_per_cu;
+  p->mt_row_block = t_tuning.mttkrp_row_block;
   p->N = prob->order;
   p->R = prob->rank;
   if (p->R > (1 << 20)) return CP_EINVAL;
@@ -315,6 +321,27 @@ using namespace cpgn;
 extern "C" {
 
 int cp_abi_version(void) { return CP_ABI_VERSION; }
+
+int cp_set_tuning(const cp_tuning* t) {
+  if (!t) {
+    t_tuning = cp_tuning{0, 0, 0, 0};
+    return CP_OK;
+  }
+  if (t->mttkrp_min_items < 0 || t->mttkrp_min_items > 4096) return CP_EINVAL;
+  if (t->mttkrp_wg_per_cu < 0 || t->mttkrp_wg_per_cu > 8) return CP_EINVAL;
+  if (t->mttkrp_row_block != 0 && t->mttkrp_row_block != 2 && t->mttkrp_row_block != 4 &&
+      t->mttkrp_row_block != 5)
+    return CP_EINVAL;
+  if (t->reserved != 0) return CP_EINVAL;
+  t_tuning = *t;
+  return CP_OK;
+}
+
+int cp_get_tuning(cp_tuning* t) {
+  if (!t) return CP_EINVAL;
+  *t = t_tuning;
+  return CP_OK;
+}
 
 const char* cp_status_string(int s) {
   switch (s) {

@@ -71,6 +71,10 @@ struct Plan {
   size_t off_krp = 0;                  // outer Khatri-Rao tables of the bfloat16 MTTKRP
   size_t bytes = 0;
   size_t t_bytes = 0;                  // ALS dimension tree (order 3): T = X x_3 A(2), after `bytes`
+  // MTTKRP tile shape (cp_tuning of the calling thread when the plan was made)
+  int mt_min_items = 16;               // least items per wavefront
+  int mt_wg_per_cu = 2;                // workgroups per compute unit a launch aims for
+  int mt_row_block = 0;                // FP32 row tile in 16-row blocks (0: automatic)
 };
 
 // Device-resident CG state (FP64 scalars never leave the device during a step).

@@ -614,10 +614,12 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   const int64_t J = p.s[mode];
   g.MB = dt ? (p.dtype == CP_F64 ? 1 : 2) : (p.dtype == CP_F64 ? 2 : 4);
   // FP32, contraction along X rows: 80-row tiles where they pad the mode less than 64-row ones
-  // (s = 400: 5 tiles and no padding rows, against 7 tiles of which 48 rows are padding)
-  if (!dt && p.dtype == CP_F32 && !caseB && vec_ok && p.xk == 0 &&
-      (J + 79) / 80 * 80 < (J + 63) / 64 * 64)
-    g.MB = 5;
+  // (s = 400: 5 tiles and no padding rows, against 7 tiles of which 48 rows are padding), or
+  // the tile the plan's tuning names (32, 64 or 80 rows)
+  if (!dt && p.dtype == CP_F32 && !caseB && vec_ok && p.xk == 0) {
+    if (p.mt_row_block != 0) g.MB = p.mt_row_block;
+    else if ((J + 79) / 80 * 80 < (J + 63) / 64 * 64) g.MB = 5;
+  }
   g.rows_per_tile = 16 * g.MB;
   g.RT = (J + g.rows_per_tile - 1) / g.rows_per_tile;
   g.QC = (p.s[q] + 15) / 16;
@@ -626,10 +628,11 @@ MttkrpGeom mttkrp_geom(const Plan& p, int mode, bool vec_ok, bool dt) {
   // One resident round of 4-wave workgroups: two per CU (<= 256 registers per lane), but at
   // least 16 items per wavefront: with fewer, the first loads of a workgroup, its reduction
   // through LDS and its partial tile cost more than its products (small modes; many such
-  // problems then share launches in a batch program).
-  const int64_t wgs = (int64_t)kNumCU * 2;
+  // problems then share launches in a batch program). Both figures come from the plan's tuning.
+  const int64_t wgs = (int64_t)kNumCU * p.mt_wg_per_cu;
   int64_t sw = wgs / g.RT;
-  const int64_t max_sw = (g.nitems + 63) / 64;
+  const int64_t per_wg = 4 * (int64_t)p.mt_min_items;
+  const int64_t max_sw = (g.nitems + per_wg - 1) / per_wg;
   if (sw > max_sw) sw = max_sw;
   if (sw > kRedSlots) sw = kRedSlots;
   if (sw < 1) sw = 1;
@@ -686,6 +689,8 @@ static void launch_variant(bool caseB, bool vec, int MB, int NB, dim3 grid, hipS
       launch_nb<T, false, 4, false>(NB, grid, st, a);
     } else if (MB == 5) {
       launch_nb<T, false, 5, true>(NB, grid, st, a);
+    } else if (MB == 2) {
+      launch_nb<T, false, 2, true>(NB, grid, st, a);
     } else {
       launch_nb<T, false, 4, true>(NB, grid, st, a);
     }
@@ -722,22 +727,28 @@ __device__ __forceinline__ void KDtReduce<T>::run(const Args& a, dim3 bid, dim3 
        idx += (int64_t)gdim.x * blockDim.x) {
     const int64_t o = idx / R;
     const int r = (int)(idx - o * R);
-    const int64_t h_n = owner_split((o + 1) * QC - 1, nitems, S) - owner_split(o * QC, nitems, S) + 1;
+    const int64_t w0 = owner_split(o * QC, nitems, S);
+    const int64_t h_n = owner_split((o + 1) * QC - 1, nitems, S) - w0 + 1;
     // Terms k = rt h_n + h in order; each batch of 8 is loaded before it is added, so the loads
-    // of a batch are in flight together (same sum, same order as one term at a time).
+    // of a batch are in flight together (same sum, same order as one term at a time). Slot h
+    // belongs to split w0 + h; with more splits than items a split between two owners of o can
+    // be empty and never writes its slot, so such terms are skipped.
     const int64_t K = RT * h_n;
     double s = 0.0;
     for (int64_t k0 = 0; k0 < K; k0 += 8) {
       T v[8];
+      bool use[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t k = k0 + u < K ? k0 + u : K - 1;
         const int64_t rt = k / h_n, h = k - rt * h_n;
+        const int64_t w = w0 + h;
+        use[u] = k0 + u < K && nitems * w / S < nitems * (w + 1) / S;
         v[u] = p1[((rt * O + o) * HS + h) * Rp + r];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (k0 + u < K) s += (double)v[u];
+        if (use[u]) s += (double)v[u];
     }
     if (m64) m64[idx] = s;
     if (mout) {

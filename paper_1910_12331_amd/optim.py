@@ -5,7 +5,7 @@ from __future__ import annotations
 
 import math
 import time
-from dataclasses import dataclass, replace
+from dataclasses import dataclass, field, replace
 
 import torch
 
@@ -335,10 +335,20 @@ class BatchedGaussNewton:
     (api.GNBatchProgram, cp_gn_batch_create) records each problem's launches before and after CG
     once, and a step runs one launch per kernel and position in the step for all problems, on
     the current stream, with the damping schedules advanced on the device. Same iterates again;
-    with graphs=True the program's launches are captured as one graph."""
+    with graphs=True the program's launches are captured as one graph.
+
+    tiles (api.Tiles) sets the MTTKRP tile shape of every launch the runner makes (workspaces,
+    eager steps, captured graphs and the batch program); the iterates then agree with the
+    default shape's to rounding, and bitwise with single-problem runs under the same shape."""
 
     def __init__(self, problems, config: GNConfig | None = None, n_streams: int = 8,
-                 graphs: bool = False, batch_cg: bool = False, fused: bool = False):
+                 graphs: bool = False, batch_cg: bool = False, fused: bool = False,
+                 tiles: api.Tiles | None = None):
+        self.tiles = tiles
+        with api.tiles(tiles):
+            self._init(problems, config, n_streams, graphs, batch_cg, fused)
+
+    def _init(self, problems, config, n_streams, graphs, batch_cg, fused):
         cfg = config or GNConfig()
         if graphs and cfg.line_search is not None:
             raise ValueError("graph replay covers the plain Gauss-Newton step only")
@@ -468,6 +478,10 @@ class BatchedGaussNewton:
         int64, 2 per problem) the device clock is written to stamps[2 i] and stamps[2 i + 1] by
         kernels enqueued on problem i's stream right before and after its step
         (api.device_timestamp; ticks of api.device_clock_hz())."""
+        with api.tiles(self.tiles):
+            return self._step(timed, stamps)
+
+    def _step(self, timed, stamps):
         if self.batch_cg:
             if timed:
                 raise ValueError("a batched step has one span per problem: use stamps")
@@ -517,23 +531,35 @@ class BatchedGaussNewton:
 
     def residuals(self):
         out = []
-        for i, opt in enumerate(self.opts):
-            with torch.cuda.stream(self.streams[i % len(self.streams)]):
-                out.append(opt.residual())
+        with api.tiles(self.tiles):
+            for i, opt in enumerate(self.opts):
+                with torch.cuda.stream(self.streams[i % len(self.streams)]):
+                    out.append(opt.residual())
         return out
 
 
 @dataclass
 class BatchedTuning:
-    """The launch configuration chosen for a batch: HIP streams, graph replay, batched CG, the
-    batch program, the throughput it measured and the whole sweep (problem-steps/s per
-    (n_streams, graphs, batch_cg, fused))."""
+    """The configuration chosen for a batch: HIP streams, graph replay, batched CG, the batch
+    program and the MTTKRP tile shape (None: the default), the throughput it measured, the launch
+    sweep (problem-steps/s per (n_streams, graphs, batch_cg, fused), default tiles) and the tile
+    sweep (problem-steps/s per api.Tiles, chosen launch configuration)."""
     n_streams: int
     graphs: bool
     problem_steps_per_s: float
     table: dict
     batch_cg: bool = False
     fused: bool = False
+    tiles: api.Tiles | None = None
+    tile_table: dict = field(default_factory=dict)
+
+
+# MTTKRP tile shapes the autotuner tries, one field at a time from the default (16 items per
+# wavefront, 2 workgroups per CU, automatic row tile)
+TILE_CANDIDATES = (("min_items", (4, 8, 32, 64)), ("wg_per_cu", (1, 4)), ("row_block", (2, 4)))
+# a tile shape replaces the best one so far only when it is this much faster (timing noise of a
+# few-step sweep)
+TILE_MARGIN = 1.03
 
 
 _TUNING_CACHE: dict = {}
@@ -554,11 +580,11 @@ def batch_key(problems) -> tuple:
 
 
 def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False,
-                  fused=False) -> float:
+                  fused=False, tiles=None) -> float:
     cur = [(X, [a.clone() for a in A]) for X, A in problems]   # the caller's factors stay as is
     torch.cuda.synchronize()
     bgn = BatchedGaussNewton(cur, config, n_streams=n_streams, graphs=graphs, batch_cg=batch_cg,
-                             fused=fused)
+                             fused=fused, tiles=tiles)
     bgn.step()
     bgn.synchronize()
     torch.cuda.synchronize()
@@ -572,16 +598,22 @@ def _time_batched(problems, config, n_streams, graphs, steps, batch_cg=False,
 
 def autotune_batched(problems, config: GNConfig | None = None, stream_counts=(1, 2, 4, 8, 16),
                      graphs=(False, True), steps: int = 3, timer=None, cache=_TUNING_CACHE,
-                     batch_cg=(False, True), fused=(False, True)):
+                     batch_cg=(False, True), fused=(False, True), tile_sweep: bool = True):
     """Sweep-based tuning of the batched runner: every (n_streams, graphs, batch_cg, fused)
     configuration runs `steps` Gauss-Newton steps of the whole batch on copies of its factors,
     timed by the wall clock, and the fastest is returned (the first one on a tie). batch_cg=True
     (CG of all problems in shared launches) is swept only where it applies (plain step,
     explicit-inverse preconditioner, ranks <= 128); fused=True (the whole step as a batch
     program, on one stream: n_streams 1) where that applies as well and no tensor is stored in
-    bfloat16. The result is cached per batch_key, so a batch of a shape seen before is not timed
-    again. The iterates do not depend on the choice (the kernels are deterministic and the
-    batched launches give the per-problem bits), only the throughput does."""
+    bfloat16. The launch configurations do not change the iterates (the kernels are
+    deterministic and the batched launches give the per-problem bits), only the throughput.
+
+    With tile_sweep (FP32/FP64 tensors only) the chosen configuration is then timed under other
+    MTTKRP tile shapes (api.Tiles), one field of TILE_CANDIDATES at a time starting from the
+    default; a shape is kept when it beats the best so far by TILE_MARGIN. The tile shape changes
+    the order of the MTTKRP's partial sums, so iterates under the chosen shape agree with the
+    default's to rounding. The result is cached per batch_key, so a batch of a shape seen before
+    is not timed again."""
     key = batch_key(problems)
     if cache is not None and key in cache:
         return cache[key]
@@ -604,8 +636,28 @@ def autotune_batched(problems, config: GNConfig | None = None, stream_counts=(1,
                 table[(int(ns), bool(g), bool(b), False)] = len(problems) * steps / timer(
                     problems, config, ns, g, steps, bool(b), False)
     best = max(table, key=table.get)
-    out = BatchedTuning(n_streams=best[0], graphs=best[1], problem_steps_per_s=table[best],
-                        table=table, batch_cg=best[2], fused=best[3])
+    rate = table[best]
+    chosen = None
+    tile_table = {}
+    if tile_sweep and all(isinstance(X, torch.Tensor) and X.dtype in (torch.float32, torch.float64)
+                          for X, _ in problems):
+        cur = api.Tiles()
+        tile_table[cur] = rate
+        for name, values in TILE_CANDIDATES:
+            base = cur
+            for v in values:
+                t = base._replace(**{name: v})
+                if t in tile_table:
+                    continue
+                tile_table[t] = len(problems) * steps / timer(
+                    problems, config, best[0], best[1], steps, best[2], best[3], tiles=t)
+                if tile_table[t] > tile_table[cur] * TILE_MARGIN:
+                    cur = t
+        if cur != api.Tiles():
+            chosen, rate = cur, tile_table[cur]
+    out = BatchedTuning(n_streams=best[0], graphs=best[1], problem_steps_per_s=rate,
+                        table=table, batch_cg=best[2], fused=best[3], tiles=chosen,
+                        tile_table=tile_table)
     if cache is not None:
         cache[key] = out
     return out

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import threading
 
 import pytest
 
@@ -50,6 +51,8 @@ def test_struct_layout_matches_header(tmp_path):
         'printf("%zu %zu %zu %zu %zu\\n", sizeof(cp_armijo_params), offsetof(cp_armijo_params,'
         ' max_trials), sizeof(cp_armijo_stats), offsetof(cp_armijo_stats, x_norm),'
         " offsetof(cp_armijo_stats, accepted));\n"
+        'printf("%zu %zu %zu\\n", sizeof(cp_tuning), offsetof(cp_tuning, mttkrp_row_block),'
+        " offsetof(cp_tuning, reserved));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -64,6 +67,9 @@ def test_struct_layout_matches_header(tmp_path):
     assert c == [C.sizeof(L.CpArmijoParams), L.CpArmijoParams.max_trials.offset,
                  C.sizeof(L.CpArmijoStats), L.CpArmijoStats.x_norm.offset,
                  L.CpArmijoStats.accepted.offset]
+    d = list(map(int, lines[3].split()))
+    assert d == [C.sizeof(L.CpTuning), L.CpTuning.mttkrp_row_block.offset,
+                 L.CpTuning.reserved.offset]
 
 
 def prob(dims=(8, 9, 10), rank=5, dt=L.CP_F64):
@@ -90,6 +96,39 @@ def test_workspace_queries(lib):
     assert ws_bytes(lib, prob(), 17)[0] == L.CP_EINVAL
     big = ws_bytes(lib, prob((400, 400, 400), 100, L.CP_F32))[1]
     assert big < 64 << 20   # the workspace stays small next to the tensor
+
+
+def test_tuning_validation_and_workspace_sizes(lib):
+    """cp_set_tuning checks its fields, keeps the setting per thread and resets on NULL; the
+    MTTKRP partial tiles in the workspace follow the split it sets (host planning only)."""
+    p = prob((400, 400, 400), 100, L.CP_F32)
+    base = ws_bytes(lib, p)[1]
+    got = L.CpTuning()
+    try:
+        for bad in [(-1, 0, 0, 0), (4097, 0, 0, 0), (0, 9, 0, 0), (0, -1, 0, 0), (0, 0, 3, 0),
+                    (0, 0, 1, 0), (0, 0, 0, 1)]:
+            assert lib.cp_set_tuning(C.byref(L.CpTuning(*bad))) == L.CP_EINVAL, bad
+        assert lib.cp_get_tuning(C.byref(got)) == 0
+        assert (got.mttkrp_min_items, got.mttkrp_wg_per_cu, got.mttkrp_row_block) == (0, 0, 0)
+        assert lib.cp_get_tuning(None) == L.CP_EINVAL
+        assert lib.cp_set_tuning(C.byref(L.CpTuning(8, 4, 2, 0))) == 0
+        assert lib.cp_get_tuning(C.byref(got)) == 0
+        assert (got.mttkrp_min_items, got.mttkrp_wg_per_cu, got.mttkrp_row_block) == (8, 4, 2)
+        # twice the workgroups per launch: more partial tiles than the default split
+        assert ws_bytes(lib, p)[1] > base
+        assert lib.cp_set_tuning(C.byref(L.CpTuning(4096, 1, 0, 0))) == 0
+        assert ws_bytes(lib, p)[1] <= base
+        # the setting belongs to the thread that made it
+        seen = []
+        t = threading.Thread(target=lambda: seen.append(ws_bytes(lib, p)[1]))
+        t.start()
+        t.join()
+        assert seen == [base]
+        assert lib.cp_set_tuning(C.byref(L.CpTuning(16, 2, 0, 0))) == 0   # the defaults
+        assert ws_bytes(lib, p)[1] == base
+    finally:
+        assert lib.cp_set_tuning(None) == 0
+    assert ws_bytes(lib, p)[1] == base
 
 
 @pytest.mark.parametrize("mut,code", [

@@ -310,6 +310,45 @@ def test_batch_program_steps_match_per_problem_steps(dt):
                     assert rel(a.double().cpu().numpy(), b) < (1e-4 if dt == torch.float32 else 1e-9)
 
 
+def test_batched_runs_under_tile_shape_match_single_problem_runs():
+    """Batch runners given an MTTKRP tile shape (the batch program replayed from one graph, and
+    eager steps on three streams) give bitwise the factors and stats of each problem's own steps
+    under the same shape (api.tiles), the first step matches the oracle, and the calling thread's
+    shape is the default again outside the runners."""
+    from workloads import batched_problems
+    probs = batched_problems(5)
+    T = P.Tiles(8, 4, 2)
+    mk = lambda: [(torch.tensor(p.x, dtype=torch.float32, device="cuda"),
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in p.init])
+                  for p in probs]
+    with P.tiles(T):
+        ref = [P.GaussNewton(X, A) for X, A in mk()]
+    bat = P.BatchedGaussNewton(mk(), fused=True, graphs=True, tiles=T)
+    eag = P.BatchedGaussNewton(mk(), n_streams=3, tiles=T)
+    assert P.get_tiles() == P.Tiles()
+    for k in range(3):
+        with P.tiles(T):
+            for g in ref:
+                g.step()
+        bat.step()
+        eag.step()
+        bat.synchronize()
+        eag.synchronize()
+        torch.cuda.synchronize()
+        assert P.get_tiles() == P.Tiles()
+        for g, ob, oe in zip(ref, bat.opts, eag.opts):
+            assert g.stats() == ob.stats() == oe.stats(), k
+            for a, b, c in zip(g.A, ob.A, oe.A):
+                assert torch.equal(a, b) and torch.equal(a, c), k
+        if k == 0:
+            for p, ob in zip(probs[:2], bat.opts[:2]):
+                xs = p.x.astype(np.float32).astype(np.float64)
+                As = [a.astype(np.float32).astype(np.float64) for a in p.init]
+                r, _ = O.gn_step(xs, As, 1e-4, 0.0, ob.stats()["cg_iters"])
+                for a, b in zip(ob.A, r):
+                    assert rel(a.double().cpu().numpy(), b) < 1e-4
+
+
 def test_batch_program_mixed_orders_dtypes_diagonal_damping():
     """One batch program over problems of orders 3 and 4, FP32 and FP64, ranks 5 to 40, with the
     diagonal damping: the launches of different kernel instantiations share levels, and every
@@ -452,19 +491,24 @@ def test_autotuned_batched_run_matches_single_stream():
     tune = P.autotune_batched(probs, cfg, stream_counts=(1, 4), steps=2, cache={})
     key = (tune.n_streams, tune.graphs, tune.batch_cg, tune.fused)
     assert key in tune.table and len(tune.table) == 10
+    # the tile sweep: the default and 8 shapes, one field at a time
+    assert len(tune.tile_table) == 9 and P.Tiles() in tune.tile_table
+    assert tune.tiles is None or tune.tiles in tune.tile_table
+    assert P.get_tiles() == P.Tiles()
     for (_, A), B in zip(probs, before):
         assert all(torch.equal(a, b) for a, b in zip(A, B))
     tuned = [(X, [a.clone() for a in A]) for X, A in probs]
     bgn = P.BatchedGaussNewton(tuned, cfg, n_streams=tune.n_streams, graphs=tune.graphs,
-                               batch_cg=tune.batch_cg, fused=tune.fused)
+                               batch_cg=tune.batch_cg, fused=tune.fused, tiles=tune.tiles)
     for _ in range(3):
         bgn.step()
     bgn.synchronize()
     for (X, A), (_, At) in zip(probs, tuned):
         ref = [a.clone() for a in A]
-        opt = P.GaussNewton(X, ref, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
-        for _ in range(3):
-            opt.step()
+        with P.tiles(tune.tiles):
+            opt = P.GaussNewton(X, ref, P.GNConfig(cg_tol=1e-3, cg_maxiter=20))
+            for _ in range(3):
+                opt.step()
         torch.cuda.synchronize()
         assert all(torch.equal(a, b) for a, b in zip(At, ref))
 

@@ -92,6 +92,66 @@ def test_mttkrp_all_matches_oracle(dims, rank, dt):
         assert rel(host([M])[0], ref) < TOL[dt], (n, rel(host([M])[0], ref))
 
 
+TILE_SHAPES = [P.Tiles(4), P.Tiles(64, 1), P.Tiles(1, 8), P.Tiles(row_block=2),
+               P.Tiles(row_block=4), P.Tiles(row_block=5), P.Tiles(8, 4, 2)]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims,rank", [((150, 37, 60), 20), ((45, 33, 28, 20), 9),
+                                       ((70, 3, 66), 33)])
+def test_mttkrp_tile_shapes_match_oracle(dims, rank, dt):
+    """Every MTTKRP tile shape (cp_set_tuning: items per wavefront, workgroups per compute unit,
+    FP32 row tile) computes the contraction of Section 2.2: single-mode and all-mode calls
+    against the oracle, on modes of several row tiles with a ragged tail, with and without
+    vector loads (a last mode of 66); the defaults set explicitly give the default's bits, and
+    the thread's setting is restored afterwards."""
+    rng = np.random.default_rng(sum(dims) + rank + 5)
+    X = rng.standard_normal(dims)
+    A = rnd_factors(dims, rank, 11 + rank)
+    Xh, Ah = rounded([X], dt)[0], rounded(A, dt)
+    Xd, Ad = to_dev([X], dt)[0], to_dev(A, dt)
+    N = len(dims)
+    base = [P.mttkrp(Xd, Ad, n) for n in range(N)]
+    with P.tiles(P.Tiles(16, 2, 0)):
+        for n in range(N):
+            assert torch.equal(P.mttkrp(Xd, Ad, n), base[n]), n
+    refs = [O.mttkrp(Xh, Ah, n) for n in range(N)]
+    for t in TILE_SHAPES:
+        with P.tiles(t):
+            for n in range(N):
+                M = host([P.mttkrp(Xd, Ad, n)])[0]
+                assert rel(M, refs[n]) < TOL[dt], (t, n, rel(M, refs[n]))
+            for n, M in enumerate(P.mttkrp_all(Xd, Ad)):
+                M = host([M])[0]
+                assert rel(M, refs[n]) < TOL[dt], (t, "all", n, rel(M, refs[n]))
+    assert P.get_tiles() == P.Tiles()
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dims", [(40, 1, 32), (40, 1, 20), (33, 2, 48)])
+def test_mttkrp_all_tree_with_more_splits_than_items(dims, dt):
+    """Dimension tree (order 3, mode 0 with vector loads) where the contraction has fewer items
+    than wavefronts (a middle mode of 1 or 2): a wavefront without items between two that share
+    an outer index writes no partial, and the reduction must not read its slot. The workspace is
+    filled with NaN first, so a stale slot would show."""
+    rank = 5
+    rng = np.random.default_rng(sum(dims) + 77)
+    X = rng.standard_normal(dims)
+    A = rnd_factors(dims, rank, 78)
+    Xh, Ah = rounded([X], dt)[0], rounded(A, dt)
+    Xd, Ad = to_dev([X], dt)[0], to_dev(A, dt)
+    for t in [None, P.Tiles(1, 8)]:
+        with P.tiles(t):
+            ws = P.Workspace()
+            ws.get(P.api._problem(Xd, rank), P._lib.OP_MTTKRP_ALL, Xd.device)
+            ws._buf.fill_(255)   # all-ones bytes: NaN in FP32 and FP64
+            Ms = P.mttkrp_all(Xd, Ad, ws=ws)
+        for n, M in enumerate(Ms):
+            M = host([M])[0]
+            ref = O.mttkrp(Xh, Ah, n)
+            assert np.isfinite(M).all() and rel(M, ref) < TOL[dt], (t, n, rel(M, ref))
+
+
 def test_mttkrp_all_400_fp32_closed_form():
     """The bench's all-mode launch shape (400^3, R = 100, FP32, dimension tree for modes 0 and 1)
     against the planted closed form on every output."""

@@ -5,7 +5,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from paper_1910_12331_amd import optim  # noqa: E402
+from paper_1910_12331_amd import api, optim  # noqa: E402
 
 
 class FakeTensor:
@@ -109,31 +109,49 @@ def test_autotune_batched_picks_fastest_and_caches():
             (4, False, True, False): 0.8, (4, True, True, False): 0.5,
             (8, False, True, False): 0.9, (8, True, True, False): 0.5,
             (1, False, True, True): 0.6, (1, True, True, True): 0.5}
+    T = api.Tiles
+    # tile sweep on the chosen configuration: 8 items per wavefront wins its field (0.45 s), one
+    # workgroup per CU is faster by less than the margin (0.44 s), 32-row tiles win theirs
+    tile_secs = {T(4): 0.49, T(8): 0.45, T(32): 0.6, T(64): 0.7, T(8, 1): 0.44, T(8, 4): 0.5,
+                 T(8, 0, 2): 0.40, T(8, 0, 4): 0.45}
     calls = []
 
-    def timer(problems, config, ns, graphs, steps, batch_cg, fused):
-        calls.append((ns, graphs, batch_cg, fused))
+    def timer(problems, config, ns, graphs, steps, batch_cg, fused, tiles=None):
+        calls.append((ns, graphs, batch_cg, fused, tiles))
         assert problems is probs and steps == 3
+        if tiles is not None:
+            assert (ns, graphs, batch_cg, fused) == best_launch
+            return tile_secs.get(tiles, 1.0) if best_launch == (1, True, True, True) else 1.0
         return secs[(ns, graphs, batch_cg, fused)]
 
     cache = {}
+    best_launch = (1, True, True, True)
     out = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
     # the first of the fastest (0.5 s) in sweep order: the graphed batch program
-    assert (out.n_streams, out.graphs, out.batch_cg, out.fused) == (1, True, True, True)
-    assert out.problem_steps_per_s == 2 * 3 / 0.5 and len(out.table) == 14
-    assert len(calls) == 14
+    assert (out.n_streams, out.graphs, out.batch_cg, out.fused) == best_launch
+    assert len(out.table) == 14 and out.table[best_launch] == 2 * 3 / 0.5
+    assert out.tiles == T(8, 0, 2) and out.problem_steps_per_s == 2 * 3 / 0.40
+    assert len(out.tile_table) == 9 and out.tile_table[T()] == 2 * 3 / 0.5
+    assert len(calls) == 14 + 8
+    assert [c[4] for c in calls[14:]] == [T(4), T(8), T(32), T(64), T(8, 1), T(8, 4), T(8, 0, 2),
+                                          T(8, 0, 4)]
     again = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache=cache)
-    assert again is out and len(calls) == 14                  # served from the cache
-    # without the batch program the batched CG on 4 streams with graphs wins
+    assert again is out and len(calls) == 22                  # served from the cache
+    # without the batch program the batched CG on 4 streams with graphs wins; no tile shape
+    # beats the default there (every tile timing is 1 s)
+    best_launch = (4, True, True, False)
     out1 = optim.autotune_batched(probs, stream_counts=(1, 4, 8), timer=timer, cache={},
                                   fused=(False,))
-    assert (out1.n_streams, out1.graphs, out1.batch_cg, out1.fused) == (4, True, True, False)
+    assert (out1.n_streams, out1.graphs, out1.batch_cg, out1.fused) == best_launch
+    assert out1.tiles is None and out1.problem_steps_per_s == 2 * 3 / 0.5
     # neither batched CG nor the batch program is swept where they do not apply (the Cholesky
-    # preconditioner)
+    # preconditioner); no tile sweep when it is switched off
     calls.clear()
     cfg = optim.GNConfig(preconditioner="cholesky")
-    out2 = optim.autotune_batched(probs, cfg, stream_counts=(1, 4, 8), timer=timer, cache={})
+    out2 = optim.autotune_batched(probs, cfg, stream_counts=(1, 4, 8), timer=timer, cache={},
+                                  tile_sweep=False)
     assert not out2.batch_cg and not out2.fused and len(calls) == 6
-    assert all(not c[2] and not c[3] for c in calls)
+    assert all(not c[2] and not c[3] and c[4] is None for c in calls)
+    assert out2.tiles is None and out2.tile_table == {}
     # the bucket: ranks 8 and 40 -> 8 and 64, largest modes 90 and 130 -> 128 and 256
     assert optim.batch_key(probs) == (2, ("torch.float32",), (8, 64), (128, 256))
