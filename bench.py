@@ -146,8 +146,8 @@ def mttkrp_times(P, Xd, A, reps, stream):
 # counter reads for a device copy of X (256 MB read + 256 MB written), so 1.0 = exact bytes.
 # Valid only for the kernel source it was taken on.
 MTTKRP_TRAFFIC = {
-    "source_sha256": "83ec1f1bbf7f442a18d72f40d7761af39a9b3bee847775f123c8a456ea5dfef3",
-    "bytes_per_launch": 319329780,   # mean over the three modes of the main kernel
+    "source_sha256": "ab5caa02142650bb57cea8447d799319475c2c1ced977a737199165accc866bd",
+    "bytes_per_launch": 320028905,   # mean over the three modes of the main kernel
 }
 
 
@@ -185,6 +185,21 @@ def order4_leg(P, torch, reps, stream):
             modes[f"mode{n}"] = dict(median_ms=t * 1e3, tflops=flops / t / 1e12,
                                      x_read_gbs=float(np.prod(dims)) * xbytes[name] / t / 1e9,
                                      rel_err_vs_fp64_storage=err)
+        # all four modes at one point (cp_mttkrp_all): FP32/FP64 storage takes modes 0..2 from
+        # one pass over X (dimension tree + outer-mode contraction) and mode 3 from a second;
+        # the bfloat16 forms take one pass per mode
+        Ms = [torch.empty((dims[n], R), dtype=A[0].dtype, device="cuda") for n in range(4)]
+        for _ in range(3):
+            P.mttkrp_all(X, A, out=Ms, ws=ws)
+        ta = float(np.median(event_samples(lambda: P.mttkrp_all(X, A, out=Ms, ws=ws), reps,
+                                           stream)))
+        modes["all"] = dict(median_ms=ta * 1e3, passes_over_x=2 if name in ("f32", "f64") else 4,
+                            sum_of_single_mode_ms=sum(modes[f"mode{n}"]["median_ms"]
+                                                      for n in range(4)),
+                            rel_err_vs_fp64_storage=max(
+                                float(torch.linalg.norm(Ms[n].double() - M64[n])
+                                      / torch.linalg.norm(M64[n])) for n in range(4)))
+        del Ms
         # GN steps from the same start and damping schedule; the first eight steps' direct
         # residual against the FP64 master tensor, and the step time (20 CG iterations)
         Ag = [a.clone() for a in A]
@@ -194,13 +209,26 @@ def order4_leg(P, torch, reps, stream):
             gn.step()
             r = P.residual(X64, [a.double() for a in gn.A], ws=ws).cpu()
             traj.append(float(r[0] / r[1]))
+        # each timed step starts from the same factors (restored outside the events), so every
+        # sample is the same work: 20 CG iterations from the start point
         At = [a.clone() for a in A]
         sb = P.stats_buffer(X64.device)
         ws2 = P.Workspace()
-        for _ in range(2):
+        samples = []
+        for k in range(7):
+            for a, a0 in zip(At, A):
+                a.copy_(a0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             P.gn_step(X, At, 1e-4, 0.0, 20, stats=sb, ws=ws2)
-        tstep = event_time(lambda: P.gn_step(X, At, 1e-4, 0.0, 20, stats=sb, ws=ws2), 5, stream)
-        out[name] = dict(mttkrp=modes, gn_step_20cg_ms=tstep * 1e3, residual_first_steps=traj)
+            e1.record(stream)
+            e1.synchronize()
+            if k >= 2:
+                samples.append(e0.elapsed_time(e1))
+        sst = P.read_stats(sb)
+        out[name] = dict(mttkrp=modes, gn_step_20cg_ms=float(np.median(samples)),
+                         gn_step_cg_iters=sst["cg_iters"], gn_step_status=sst["status"],
+                         residual_first_steps=traj)
         del Ag, gn, At
     # time to relative residual 2e-3 (twice the noise level) from the same start: FP64 storage
     # alone, and the precision ladder bfloat16 -> split bfloat16 -> FP64
@@ -231,6 +259,9 @@ def order4_leg(P, torch, reps, stream):
             abs(a - b) / b for a, b in zip(out[name]["residual_first_steps"], out["f64"]["residual_first_steps"])]
     log("[bench] 80^4 R=64 MTTKRP per mode (ms): " + "; ".join(
         f"{k} " + " ".join(f"{v['mttkrp'][f'mode{n}']['median_ms']:.4f}" for n in range(4)) for k, v in out.items()))
+    log("[bench] 80^4 R=64 all-mode MTTKRP (ms, against the sum of single modes): " + "; ".join(
+        f"{k} {v['mttkrp']['all']['median_ms']:.4f} ({v['mttkrp']['all']['sum_of_single_mode_ms']:.4f})"
+        for k, v in out.items()))
     log("[bench] 80^4 MTTKRP rel. error vs FP64 storage (mode 0): " + ", ".join(
         f"{k} {v['mttkrp']['mode0']['rel_err_vs_fp64_storage']:.2e}" for k, v in out.items()))
     del X64, X32, forms, M64
@@ -739,6 +770,10 @@ def main():
     for _ in range(2):
         P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20)
     t20 = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20), 5, stream)
+    s20 = P.read_stats(sb)
+    if s20["status"] != 0 or s20["cg_iters"] != 20:
+        log(f"[bench] WARNING: the 20-iteration step timing ended with status {s20['status']}, "
+            f"{s20['cg_iters']} CG iterations")
     t0cg = event_time(lambda: P.gn_step(Xd, A20, 1e-4, 0.0, 0, stats=sb, ws=ws20), 5, stream)
     # the same with the preconditioner applied by Cholesky triangular solves (Section 3.3)
     P.gn_step(Xd, A20, 1e-4, 0.0, 20, stats=sb, ws=ws20, preconditioner="cholesky")

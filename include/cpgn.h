@@ -15,7 +15,8 @@
  *     dims[n] x rank matrix (rank contiguous). Modes may have different sizes, hence the
  *     per-mode pointers.
  *   - Every buffer, including the workspace `ws`, is allocated and owned by the caller. The
- *     library allocates nothing, keeps no mutable global state and is re-entrant per stream.
+ *     library allocates nothing and is re-entrant per stream; its only mutable state is each
+ *     host thread's MTTKRP tile shape (cp_set_tuning) and cp_gn_step_noalloc's scratch array.
  *     Query the workspace size with cp_workspace_bytes; the workspace must be 256-byte
  *     aligned. Its contents need not be initialised and are clobbered.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every call only
@@ -157,9 +158,12 @@ int cp_mttkrp_marked(const cp_problem* prob, const void* X, const void* const* A
 
 /*
  * All-mode MTTKRP: M^(n) = X_(n) P^(n) (Section 2.2, eq. (1)) for every mode n at one point, the
- * contractions that form the gradient of Algorithm 1. For an order-3 tensor, modes 0 and 1 come
- * from one pass over X (a dimension tree, Section 2.2: the partial contraction with A^(2) is
- * shared) and mode 2 from a second pass; other orders take one pass per mode.
+ * contractions that form the gradient of Algorithm 1. For an FP32/FP64 tensor of order >= 3
+ * whose last mode is a multiple of 4 (16-byte aligned X), modes 0 .. N-2 come from one pass over
+ * X (a dimension tree, Section 2.2: the partial contraction with A^(N-1) is shared; above order 3
+ * the middle modes are formed from its FP64 per-outer-index sums, while those take at most a
+ * quarter of X's bytes) and mode N-1 from a second pass; otherwise one pass per mode. The
+ * gradient (cp_gn_gradient, cp_gn_step) forms its MTTKRPs the same way.
  *   M: N device pointers, M[n] is dims[n] x rank, f_dtype, written.
  */
 int cp_mttkrp_all(const cp_problem* prob, const void* X, const void* const* A, void* const* M,

@@ -199,8 +199,9 @@ def mttkrp(X: torch.Tensor, A: Sequence[torch.Tensor], mode: int, out=None, ws=N
 
 
 def mttkrp_all(X, A: Sequence[torch.Tensor], out=None, ws=None):
-    """M(n) for every mode at one point (order 3: modes 0 and 1 from one pass over X through a
-    dimension tree). Returns the list of dims[n] x R tensors."""
+    """M(n) for every mode at one point (FP32/FP64 order >= 3 with the last mode a multiple of
+    4: modes 0 .. N-2 from one pass over X through a dimension tree). Returns the list of
+    dims[n] x R tensors."""
     _dev(X, "X")
     R = int(A[0].shape[1])
     fd = factor_dtype(X)

@@ -122,6 +122,15 @@ int make_plan(const cp_problem* prob, Plan* p) {
   int64_t part = p->qc_last * 16 * p->Rp;   // residual's packed last factor reuses this region
   int64_t p1 = 0;
   int64_t krp = 0;
+  // Dimension tree for modes 0 .. N-2: order 3 always; higher orders while the tree partials
+  // and Pm (FP64, one row per outer index) take at most a quarter of X's bytes
+  const int64_t n_outer_idx = p->total / (p->s[0] * p->s[p->N - 1]);
+  if (p->xk == 0 && p->N == 3) p->tree = true;
+  if (p->xk == 0 && p->N >= 4) {
+    const MttkrpGeom g = mttkrp_geom(*p, 0, true, true);
+    const double extra = (double)g.RT * g.O * g.HS * p->Rp * p->esz + (double)n_outer_idx * p->R * 8;
+    p->tree = extra <= 0.25 * (double)p->total * p->esz;
+  }
   for (int n = 0; n < p->N && p->xk != 0; ++n) {
     const MttkrpGeom g = mttkrp_geom_bf16(*p, n);
     const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
@@ -131,7 +140,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   for (int n = 0; n < p->N && p->xk == 0; ++n) {
     for (int v = 0; v < 4; ++v) {   // geometry of every launch form (vector loads, tree)
       const bool dt = v >= 2;
-      if (dt && !(n == 0 && p->N == 3)) continue;
+      if (dt && !(n == 0 && p->tree)) continue;
       const MttkrpGeom g = mttkrp_geom(*p, n, (v & 1) == 1, dt);
       const int64_t e = g.SW * g.RT * g.rows_per_tile * p->Rp;
       part = e > part ? e : part;
@@ -182,6 +191,7 @@ int make_plan(const cp_problem* prob, Plan* p) {
   p->off_slots = take(cg_slot_bytes(*p));
   p->off_cgargs = take(cg_args_bytes());
   p->off_krp = take((size_t)krp * 4);
+  if (p->tree && p->N >= 4) p->off_pm = take((size_t)n_outer_idx * p->R * 8);
   p->bytes = off;
   // the T pass launches one grid row per row tile of s0 s1 (at most 65535); the contraction of
   // T keeps one output row's R values in one workgroup's lanes (R <= 128)
@@ -260,17 +270,16 @@ static void gradient_core(const Plan& p, const Dims& d, const void* X, const Ws&
                           const PerMode<void*>& cast_g, double* gsum_out, hipStream_t st) {
   launch_gram2(d, w.a64, w.a64, w.S, -1, nullptr, st);
   launch_gamma(d, w.S, w.gam, st);
-  if (p.N == 3) {
-    // dimension tree: one pass over X gives M(0) and M(1), a second one M(2)
-    launch_mttkrp_pair01(p, X, w.base, w.m64, w.m64 + p.s[0] * p.R, st);
-    launch_mttkrp(p, X, 2, w.base, w.m64 + (p.s[0] + p.s[1]) * p.R, nullptr, st);
-  } else {
-    int64_t off = 0;
-    for (int n = 0; n < p.N; ++n) {
-      launch_mttkrp(p, X, n, w.base, w.m64 + off * p.R, nullptr, st);
-      off += p.s[n];
-    }
+  // modes 0 .. N-2 (the dimension tree: one pass over X where it applies), then mode N-1
+  double* m64[kMaxOrder];
+  void* mout[kMaxOrder] = {};
+  int64_t off = 0;
+  for (int n = 0; n < p.N; ++n) {
+    m64[n] = w.m64 + off * p.R;
+    off += p.s[n];
   }
+  launch_mttkrp_lead(p, X, w.base, m64, mout, st);
+  launch_mttkrp(p, X, p.N - 1, w.base, m64[p.N - 1], nullptr, st);
   const int64_t RR = (int64_t)p.R * p.R;
   RowMM a{};
   a.in = w.m64;
@@ -401,13 +410,11 @@ int cp_mttkrp_all(const cp_problem* prob, const void* X, const void* const* A, v
     return rc;
   hipStream_t st = (hipStream_t)stream;
   launch_prepare_factors_src(p, A, p.dtype, ws, st, false);
-  if (p.N == 3) {
-    // dimension tree: one pass over X gives M(0) and M(1), a second one M(2)
-    launch_mttkrp_pair01(p, X, ws, nullptr, nullptr, st, M[0], M[1]);
-    launch_mttkrp(p, X, 2, ws, nullptr, M[2], st);
-  } else {
-    for (int n = 0; n < p.N; ++n) launch_mttkrp(p, X, n, ws, nullptr, M[n], st);
-  }
+  // modes 0 .. N-2 (the dimension tree: one pass over X where it applies), then mode N-1
+  double* m64[kMaxOrder] = {};
+  int rc2 = launch_mttkrp_lead(p, X, ws, m64, M, st);
+  if (!rc2) rc2 = launch_mttkrp(p, X, p.N - 1, ws, nullptr, M[p.N - 1], st);
+  if (rc2) return rc2;
   return hip_status();
 }
 

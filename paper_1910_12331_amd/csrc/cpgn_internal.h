@@ -71,6 +71,10 @@ struct Plan {
   size_t off_krp = 0;                  // outer Khatri-Rao tables of the bfloat16 MTTKRP
   size_t bytes = 0;
   size_t t_bytes = 0;                  // ALS dimension tree (order 3): T = X x_3 A(2), after `bytes`
+  // Dimension tree for modes 0 .. N-2 (FP32/FP64 storage): order 3 always, higher orders while
+  // its partials (and the FP64 outer-mode product Pm at off_pm) stay small next to X
+  bool tree = false;
+  size_t off_pm = 0;
   // MTTKRP tile shape (cp_tuning of the calling thread when the plan was made)
   int mt_min_items = 16;               // least items per wavefront
   int mt_wg_per_cu = 2;                // workgroups per compute unit a launch aims for
@@ -159,7 +163,7 @@ __host__ __device__ __forceinline__ uint16_t to_bf16_rne(float f) {
 __host__ __device__ __forceinline__ float bf16_to_float(uint32_t h) {
   return __builtin_bit_cast(float, h << 16);
 }
-int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
-                         hipStream_t st, void* mout_0 = nullptr, void* mout_1 = nullptr);
+int launch_mttkrp_lead(const Plan& p, const void* X, void* ws, double* const* m64,
+                       void* const* mout, hipStream_t st);
 
 }  // namespace cpgn

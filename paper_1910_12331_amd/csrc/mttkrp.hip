@@ -956,17 +956,110 @@ int launch_mttkrp(const Plan& p, const void* X, int mode, void* ws, double* m64,
                                  mk);
 }
 
-// Order 3, one pass over X: M(0) and, through the dimension tree, M(1). Each mode's result goes
-// to its FP64 buffer and/or its caller-precision buffer (either may be null).
-int launch_mttkrp_pair01(const Plan& p, const void* X, void* ws, double* m64_0, double* m64_1,
-                         hipStream_t st, void* mout_0, void* mout_1) {
-  if (p.N != 3 || p.xk != 0 || !vec_ok(p, 0, X)) {
-    const int rc = launch_mttkrp(p, X, 0, ws, m64_0, mout_0, st);
-    return rc ? rc : launch_mttkrp(p, X, 1, ws, m64_1, mout_1, st);
+// Order >= 4 dimension tree, second half: the tree pass leaves, for every outer index o =
+// (i_1, ..., i_{N-2}) (row-major), Pm[o][r] = sum over i_0, i_{N-1} of X A(0) A(N-1) in FP64.
+// Outer mode m's MTTKRP is then M(m)[i, r] = sum over the o with o_m = i of Pm[o][r] times the
+// other outer factors' entries: one thread per output element, terms in increasing o.
+struct KOuterContract {
+  struct Args {
+    const double* pm;                 // [O][R]
+    int64_t O;
+    int R, Rp, n_outer, dtype;        // dtype of apad and of mout
+    int64_t size[kMaxOrder];          // outer sizes s_1 .. s_{N-2}
+    int64_t first[kMaxOrder + 1];     // output elements before outer mode d (prefix of s_d R)
+    const void* apad[kMaxOrder];      // padded factors of the outer modes [s][Rp]
+    double* m64[kMaxOrder];           // FP64 outputs [s][R] (may be null)
+    void* mout[kMaxOrder];            // compute-precision outputs [s][R] (may be null)
+  };
+  static constexpr int kThreads = 256, kMinBlocks = 1;
+  static __device__ __forceinline__ void run(const Args& a, dim3 bid, dim3 gdim);
+  static void direct(dim3 grid, size_t lds, hipStream_t s, const Args& a);
+};
+
+__device__ __forceinline__ void KOuterContract::run(const Args& a, dim3 bid, dim3 gdim) {
+  const int64_t total = a.first[a.n_outer];
+  for (int64_t idx = bid.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gdim.x * blockDim.x) {
+    int d = 0;
+    while (idx >= a.first[d + 1]) ++d;
+    const int64_t e = idx - a.first[d];
+    const int64_t i = e / a.R;
+    const int r = (int)(e - i * a.R);
+    int64_t stride = 1;   // distance between consecutive i_d in o
+    for (int k = a.n_outer - 1; k > d; --k) stride *= a.size[k];
+    const int64_t outer = a.O / (a.size[d] * stride);
+    double s = 0.0;
+    for (int64_t hi = 0; hi < outer; ++hi)
+      for (int64_t lo = 0; lo < stride; ++lo) {
+        const int64_t o = (hi * a.size[d] + i) * stride + lo;
+        double w = 1.0;
+        int64_t rem = o;
+        for (int k = a.n_outer - 1; k >= 0; --k) {
+          const int64_t ik = rem % a.size[k];
+          rem /= a.size[k];
+          if (k == d) continue;
+          w *= a.dtype == CP_F64 ? ((const double*)a.apad[k])[ik * a.Rp + r]
+                                 : (double)((const float*)a.apad[k])[ik * a.Rp + r];
+        }
+        s += a.pm[o * a.R + r] * w;
+      }
+    if (a.m64[d]) a.m64[d][e] = s;
+    if (a.mout[d]) {
+      if (a.dtype == CP_F64) ((double*)a.mout[d])[e] = s;
+      else ((float*)a.mout[d])[e] = (float)s;
+    }
   }
-  if (p.dtype == CP_F32)
-    return launch_mttkrp_t<float>(p, X, 0, (char*)ws, m64_0, mout_0, true, m64_1, mout_1, st);
-  return launch_mttkrp_t<double>(p, X, 0, (char*)ws, m64_0, mout_0, true, m64_1, mout_1, st);
+}
+
+__global__ __launch_bounds__(256) void k_outer_contract(KOuterContract::Args a) {
+  KOuterContract::run(a, CPGN_BID, CPGN_GDIM);
+}
+
+void KOuterContract::direct(dim3 grid, size_t lds, hipStream_t s, const Args& a) {
+  hipLaunchKernelGGL(k_outer_contract, grid, dim3(kThreads), lds, s, a);
+}
+
+// Modes 0 .. N-2 at one point. With the dimension tree (FP32/FP64 storage, vector loads along
+// the last mode, and Plan::tree) one pass over X gives M(0) and the outer modes' partials: for
+// order 3 these are M(1) itself, for higher orders Pm, contracted by k_outer_contract. Otherwise
+// one pass per mode. Each mode's result goes to its FP64 buffer and/or its caller-precision
+// buffer (either may be null).
+int launch_mttkrp_lead(const Plan& p, const void* X, void* ws, double* const* m64,
+                       void* const* mout, hipStream_t st) {
+  if (!p.tree || p.xk != 0 || !vec_ok(p, 0, X)) {
+    for (int n = 0; n + 1 < p.N; ++n) {
+      const int rc = launch_mttkrp(p, X, n, ws, m64[n], mout[n], st);
+      if (rc) return rc;
+    }
+    return CP_OK;
+  }
+  double* pm = p.N == 3 ? m64[1] : (double*)((char*)ws + p.off_pm);
+  void* pm_out = p.N == 3 ? mout[1] : nullptr;
+  int rc = p.dtype == CP_F32
+               ? launch_mttkrp_t<float>(p, X, 0, (char*)ws, m64[0], mout[0], true, pm, pm_out, st)
+               : launch_mttkrp_t<double>(p, X, 0, (char*)ws, m64[0], mout[0], true, pm, pm_out,
+                                         st);
+  if (rc || p.N == 3) return rc;
+  KOuterContract::Args a{};
+  a.pm = pm;
+  a.O = p.total / (p.s[0] * p.s[p.N - 1]);
+  a.R = p.R;
+  a.Rp = p.Rp;
+  a.n_outer = p.N - 2;
+  a.dtype = p.dtype;
+  int64_t off = p.s[0];
+  a.first[0] = 0;
+  for (int d = 0; d < a.n_outer; ++d) {
+    const int m = d + 1;
+    a.size[d] = p.s[m];
+    a.first[d + 1] = a.first[d] + p.s[m] * p.R;
+    a.apad[d] = (char*)ws + p.off_apad + off * p.Rp * p.esz;
+    off += p.s[m];
+    a.m64[d] = m64[m];
+    a.mout[d] = mout[m];
+  }
+  dispatch<KOuterContract>(dim3(grid_for(a.first[a.n_outer])), 0, st, a);
+  return (int)hipGetLastError();
 }
 
 // Source factors may be the caller's buffers (compute precision) or FP64 copies.

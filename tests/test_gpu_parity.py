@@ -59,7 +59,8 @@ def gpu():
 MTTKRP_CASES = [
     ((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4), ((64, 48, 32), 16),
     ((30, 20, 25), 50), ((24, 20, 18), 100), ((12, 10, 9), 130), ((1, 5, 3), 2), ((5, 1, 3), 2),
-    ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33), ((230, 17, 12), 20),
+    ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33), ((230, 17, 12), 20), ((20, 9, 7, 32), 12),
+    ((9, 5, 6, 4, 8), 7), ((6, 4, 3, 5, 2, 12), 5),
 ]
 
 
@@ -128,12 +129,13 @@ def test_mttkrp_tile_shapes_match_oracle(dims, rank, dt):
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("dims", [(40, 1, 32), (40, 1, 20), (33, 2, 48)])
+@pytest.mark.parametrize("dims", [(40, 1, 32), (40, 1, 20), (33, 2, 48), (40, 1, 1, 32),
+                                  (20, 9, 7, 32)])
 def test_mttkrp_all_tree_with_more_splits_than_items(dims, dt):
-    """Dimension tree (order 3, mode 0 with vector loads) where the contraction has fewer items
-    than wavefronts (a middle mode of 1 or 2): a wavefront without items between two that share
-    an outer index writes no partial, and the reduction must not read its slot. The workspace is
-    filled with NaN first, so a stale slot would show."""
+    """Dimension tree (mode 0 with vector loads) where the contraction has fewer items than
+    wavefronts (middle modes of 1 or 2): a wavefront without items between two that share an
+    outer index writes no partial, and the reduction must not read its slot. The workspace is
+    filled with NaN first, so a stale slot (or an unwritten Pm row of order 4) would show."""
     rank = 5
     rng = np.random.default_rng(sum(dims) + 77)
     X = rng.standard_normal(dims)
@@ -215,7 +217,7 @@ def test_mttkrp_400_fp32_closed_form():
 
 # ------------------------------------------------------------------------------------ gradient
 GRAD_CASES = [((40, 40, 40), 5), ((23, 18, 31), 6), ((9, 7, 8, 6), 3), ((11, 13), 4),
-              ((30, 25, 20), 50)]
+              ((30, 25, 20), 50), ((20, 9, 7, 32), 12), ((9, 5, 6, 4, 8), 7)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -312,6 +314,15 @@ def als_sensitivity_tol(Xh, Ah, lam, seed=2):
 @pytest.mark.parametrize("maxiter", [0, 1, 5, 10])
 def test_gn_step_fixed_iterations_fp64(maxiter):
     p = make_problem((40, 40, 40), 5, workload=1)
+    gn_compare(p, torch.float64, 1e-4, 0.0, maxiter, 1e-12)
+
+
+@pytest.mark.parametrize("maxiter", [0, 1, 5])
+@pytest.mark.parametrize("dims", [(24, 10, 9, 16), (9, 5, 6, 4, 8)])
+def test_gn_step_fixed_iterations_dimension_tree_orders_4_5_fp64(dims, maxiter):
+    """Orders 4 and 5 with the last mode a multiple of 4: the gradient's modes 0 .. N-2 come
+    from one pass over X (dimension tree and the outer-mode contraction)."""
+    p = make_problem(dims, 6, workload=1)
     gn_compare(p, torch.float64, 1e-4, 0.0, maxiter, 1e-12)
 
 
