@@ -114,13 +114,22 @@ def test_mttkrp_within_bound(dims, rank, split):
 
 
 @pytest.mark.parametrize("split", [False, True], ids=["bf16", "bf16x3"])
-def test_mttkrp_all_within_bound(split):
-    dims, rank = (28, 22, 24, 16), 20
+@pytest.mark.parametrize("dims,rank", [((28, 22, 24, 16), 20), ((40, 33, 32), 24),
+                                       ((6, 5, 7, 4, 8), 5), ((30, 1, 1, 32), 9),
+                                       ((28, 22, 24, 18), 20)])
+def test_mttkrp_all_within_bound(dims, rank, split):
+    """All modes at one point (one pass per mode for a bfloat16 tensor), orders 3 to 5, middle
+    modes of 1, a last mode that rules out vector loads. The workspace is filled with NaN first,
+    so a partial or table entry left unwritten would show."""
     p = make_problem(dims, rank, workload=4, problem=21, kind="lognorm", noise=1e-3)
     planes, xv = stored(p, split)
     A = f32(p.init)
     absA = [np.abs(a) for a in A]
-    Ms = P.mttkrp_all(dev_x(planes, split), dev_f(A))
+    X = dev_x(planes, split)
+    ws = P.Workspace()
+    ws.get(P.api._problem(X, rank), P._lib.OP_MTTKRP_ALL, X.device)
+    ws._buf.fill_(255)
+    Ms = P.mttkrp_all(X, dev_f(A), ws=ws)
     for n, M in enumerate(Ms):
         ref = O.mttkrp(xv, A, n)
         bound = gamma(dims, n, split) * O.mttkrp(np.abs(xv), absA, n) + 1e-30
@@ -183,11 +192,13 @@ def test_residual_matches_oracle(split):
 
 
 @pytest.mark.parametrize("split", [False, True], ids=["bf16", "bf16x3"])
-def test_gradient_vs_fp64_master(split):
+@pytest.mark.parametrize("dims", [(24, 22, 20, 18), (24, 22, 20, 16)])
+def test_gradient_vs_fp64_master(dims, split):
     """Error of the GPU gradient against the FP64 oracle on the FP64 master tensor, within the
     bound that storage rounding plus the MTTKRP bound give: elementwise
-    |G_gpu - G| <= MTTKRP(|X_stored - X|, |A|) + gamma MTTKRP(|X_stored|, |A|) + 2^-23 |G_gpu|."""
-    dims, rank = (24, 22, 20, 18), 16
+    |G_gpu - G| <= MTTKRP(|X_stored - X|, |A|) + gamma MTTKRP(|X_stored|, |A|) + 2^-23 |G_gpu|.
+    Last modes of 18 and 16 (scalar and vector loads along the inner index)."""
+    rank = 16
     p = make_problem(dims, rank, workload=4, problem=5, kind="lognorm", noise=1e-3)
     planes, xv = stored(p, split)
     A = f32(p.init)
