@@ -731,20 +731,25 @@ __device__ __forceinline__ void KDtReduce<T>::run(const Args& a, dim3 bid, dim3 
     const int64_t h_n = owner_split((o + 1) * QC - 1, nitems, S) - w0 + 1;
     // Terms k = rt h_n + h in order; each batch of 8 is loaded before it is added, so the loads
     // of a batch are in flight together (same sum, same order as one term at a time). Slot h
-    // belongs to split w0 + h; with more splits than items a split between two owners of o can
-    // be empty and never writes its slot, so such terms are skipped.
+    // belongs to split w0 + h. Only with more splits than items can a split between two owners
+    // of o be empty; it never writes its slot, so such terms are skipped (uniform test).
     const int64_t K = RT * h_n;
+    const bool may_be_empty = S > nitems;
     double s = 0.0;
     for (int64_t k0 = 0; k0 < K; k0 += 8) {
       T v[8];
       bool use[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int64_t k = k0 + u < K ? k0 + u : K - 1;
-        const int64_t rt = k / h_n, h = k - rt * h_n;
-        const int64_t w = w0 + h;
-        use[u] = k0 + u < K && nitems * w / S < nitems * (w + 1) / S;
-        v[u] = p1[((rt * O + o) * HS + h) * Rp + r];
+        // K = row tiles x slots < 2^31 (both index the partial buffer): 32-bit division
+        const int k = (int)(k0 + u < K ? k0 + u : K - 1);
+        const int rt = k / (int)h_n, h = k - rt * (int)h_n;
+        use[u] = k0 + u < K;
+        if (may_be_empty) {
+          const int64_t w = w0 + h;
+          use[u] = use[u] && nitems * w / S < nitems * (w + 1) / S;
+        }
+        v[u] = p1[(((int64_t)rt * O + o) * HS + h) * Rp + r];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
