@@ -435,8 +435,15 @@ def test_gn_step_cholesky_preconditioner_fp32():
 
 
 def test_cholesky_and_inverse_preconditioners_agree_on_gpu():
-    """Both forms apply the same operator: the steps agree to rounding."""
+    """Both forms apply the same operator: the steps agree to rounding. Bound: 10x the sum of the
+    oracle's own difference between the two forms and its spread under 1e-15 input
+    perturbations (at least 1e-12)."""
     p = make_problem((60, 50, 40), 20, workload=0, problem=20, noise=1e-3)
+    ref = [O.flatten_factors([b - a for a, b in
+                              zip(p.init, O.gn_step(p.x, p.init, 1e-3, 1e-3, 20, "identity", pc)[0])])
+           for pc in ("inverse", "cholesky")]
+    forms = float(np.linalg.norm(ref[1] - ref[0]) / np.linalg.norm(ref[0]))
+    tol = max(1e-12, 10 * (forms + oracle_sensitivity(p.x, p.init, 1e-3, 1e-3, 20)))
     X = to_dev([p.x], torch.float64)[0]
     out = []
     for pc in ("inverse", "cholesky"):
@@ -444,7 +451,7 @@ def test_cholesky_and_inverse_preconditioners_agree_on_gpu():
         st = P.read_stats(P.gn_step(X, Ad, 1e-3, 1e-3, 20, preconditioner=pc))
         out.append((st, [a - b for a, b in zip(host(Ad), p.init)]))
     assert out[0][0]["cg_iters"] == out[1][0]["cg_iters"]
-    assert rel(O.flatten_factors(out[1][1]), O.flatten_factors(out[0][1])) < 1e-11
+    assert rel(O.flatten_factors(out[1][1]), O.flatten_factors(out[0][1])) < tol
 
 
 def test_gn_step_cholesky_preconditioner_not_spd_leaves_factors():
