@@ -182,6 +182,33 @@ def test_mttkrp_config2_full_size_fp64():
         assert rel(host([M])[0], O.mttkrp(p.x, p.init, n)) < 1e-12
 
 
+@pytest.mark.parametrize("tiles", [P.Tiles(4, 1, 4), P.Tiles(64, 4, 2)],
+                         ids=["4items-1wg-64rows", "64items-4wg-32rows"])
+def test_mttkrp_400_fp32_closed_form_tile_shapes(tiles):
+    """The bench's 400^3 R = 100 FP32 shape under other MTTKRP tile shapes (single-mode and
+    all-mode calls, several launches' worth of splits and row tiles) against the planted closed
+    form M(n) = B(n) (Hadamard_{m != n} B(m)^T A(m)) in FP64."""
+    rng = np.random.default_rng(3002)
+    B = [rng.standard_normal((400, 100)).astype(np.float32).astype(np.float64) for _ in range(3)]
+    X = planted_tensor(B).astype(np.float32)
+    A = [rng.standard_normal((400, 100)).astype(np.float32).astype(np.float64) for _ in range(3)]
+    Xd = torch.from_numpy(X).cuda()
+    del X
+    Ad = to_dev(A, torch.float32)
+    refs = []
+    for n in range(3):
+        cross = np.ones((100, 100))
+        for m in range(3):
+            if m != n:
+                cross *= B[m].T @ A[m]
+        refs.append(B[n] @ cross)
+    with P.tiles(tiles):
+        for n in range(3):
+            assert rel(host([P.mttkrp(Xd, Ad, n)])[0], refs[n]) < 2e-5, n
+        for n, M in enumerate(P.mttkrp_all(Xd, Ad)):
+            assert rel(host([M])[0], refs[n]) < 2e-5, ("all", n)
+
+
 def test_mttkrp_400_fp32_closed_form():
     """400^3, R = 100 FP32 planted tensor: M(n) = B(n) (Hadamard_{m != n} B(m)^T A(m)) holds at
     any size; checked against that closed form (FP64) on the FP32-rounded factors."""
