@@ -60,7 +60,7 @@ MTTKRP_CASES = [
     ((40, 40, 40), 5), ((37, 29, 51), 7), ((9, 7, 8, 6), 3), ((13, 17), 4), ((64, 48, 32), 16),
     ((30, 20, 25), 50), ((24, 20, 18), 100), ((12, 10, 9), 130), ((1, 5, 3), 2), ((5, 1, 3), 2),
     ((6, 5, 7, 3, 4), 9), ((70, 3, 66), 33), ((230, 17, 12), 20), ((20, 9, 7, 32), 12),
-    ((9, 5, 6, 4, 8), 7), ((6, 4, 3, 5, 2, 12), 5),
+    ((9, 5, 6, 4, 8), 7), ((6, 4, 3, 5, 2, 12), 5), ((40, 2, 3, 2, 2, 2, 2, 16), 5),
 ]
 
 
@@ -244,7 +244,8 @@ def test_mttkrp_400_fp32_closed_form():
 
 # ------------------------------------------------------------------------------------ gradient
 GRAD_CASES = [((40, 40, 40), 5), ((23, 18, 31), 6), ((9, 7, 8, 6), 3), ((11, 13), 4),
-              ((30, 25, 20), 50), ((20, 9, 7, 32), 12), ((9, 5, 6, 4, 8), 7)]
+              ((30, 25, 20), 50), ((20, 9, 7, 32), 12), ((9, 5, 6, 4, 8), 7),
+              ((40, 2, 3, 2, 2, 2, 2, 16), 5)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
